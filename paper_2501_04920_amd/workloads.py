@@ -1,0 +1,83 @@
+"""Synthetic workloads: lattice-unit parameter sets and initial droplets.
+
+This module only *chooses inputs*.  It holds none of the lattice Boltzmann
+arithmetic; both the GPU library and the CPU oracle receive the same plain
+dictionaries from here.
+
+The paper's parameter table is missing, so the lattice values are chosen
+from the dimensionless groups the paper does print (Eq. 23-24; W0 = 5.6893 and
+beta = 0.5643 at d = 2 mm, Sec. 6; zeta = 0.001 and M_phi = 0.1, Sec. 6;
+vartheta = 0.3, Sec. 4.2) with this recipe, lattice units dx = dt = 1, the
+electrode gap d = ny and c0 = 1:
+
+    dpsi    = ny * sqrt(Ca_E * zeta / (eps_v * R))          (Ca_E of Eq. 23)
+    mu_bar  = U * ny / dpsi                                   (drift speed U)
+    v_th    = alpha * dpsi    (D = v_th mu, so D = alpha mu_bar dpsi: alpha of Eq. 23)
+    q       = W0 * eps_v * dpsi / (c0 * ny**2)                (W0 of Eq. 23)
+    gamma_v = (beta**2 / W0) * ny / dpsi                      (O and beta, Eq. 23-24)
+
+with U = 0.01, alpha = 0.01, eps_v = 1 and eta = 0.1 (tau_f = 0.8) unless a
+configuration says otherwise.
+"""
+from __future__ import annotations
+
+import math
+
+W0_2MM = 5.6893     # conduction number at d = 2 mm, 1 kV (Fig. 10 caption)
+BETA_2MM = 0.5643   # voltage-independent number at d = 2 mm (Sec. 6)
+
+
+def lattice_params(n: int, radius: float, *, Ca_E=0.5, eps_r=2.0, mu_r=1.0, rho_r=1.0,
+                   eta_r=1.0, W=4.0, W0=W0_2MM, beta=BETA_2MM, U=0.01, alpha=0.01,
+                   zeta=1e-3, M_phi=0.1, eta_v=0.1, eps_v=1.0, m_ratio=1.0, nx=None):
+    """Lattice parameters of a droplet of radius ``radius`` between electrodes
+    ``n`` rows apart (grid nx x n, nx = n by default)."""
+    dpsi = n * math.sqrt(Ca_E * zeta / (eps_v * radius))
+    mu_bar = U * n / dpsi
+    mu_v = mu_bar / math.sqrt(m_ratio)          # mu_bar = sqrt(mu+ mu-)
+    v_th = alpha * dpsi
+    q = W0 * eps_v * dpsi / (1.0 * n * n)
+    gamma_v = (beta * beta / W0) * n / dpsi
+    return dict(nx=nx or n, ny=n, walls=0, reaction=1, poisson_form=1, flow=1, ion_force=1,
+                poisson_iters=0, rho_v=1.0, rho_r=rho_r, eta_v=eta_v, eta_r=eta_r,
+                M_phi=M_phi, W=W, zeta=zeta, theta=0.3, dpsi=dpsi, eps_v=eps_v,
+                eps_r=eps_r, mu_v=mu_v, mu_r=mu_r, m_ratio=m_ratio, v_th=v_th, c0=1.0,
+                q=q, gamma_v=gamma_v, s_free=1.0)
+
+
+def droplet(n: int, radius: float, noise=1e-4, seed=0, nx=None):
+    nx = nx or n
+    return dict(xc=(nx - 1) / 2.0, yc=(n - 1) / 2.0, radius=radius, noise=noise, seed=seed)
+
+
+def config1():
+    """FP64 parity case: 128^2, R = 20, W = 4, eps_r = 2, mu_r = 1, Ca_E = 0.5,
+    2000 steps after a 2000-sweep Poisson pre-solve."""
+    return dict(name="droplet-128-fp64", params=lattice_params(128, 20.0),
+                droplet=droplet(128, 20.0), presolve=2000, steps=2000)
+
+
+def config2_points():
+    """FP32 cases: 512^2, R = 80, W = 4, eps_r x mu_r x Ca_E in
+    {0.5, 2} x {0.5, 2} x {0.25, 1.0}, 20k steps."""
+    pts = []
+    for eps_r in (0.5, 2.0):
+        for mu_r in (0.5, 2.0):
+            for ca in (0.25, 1.0):
+                pts.append(dict(name="droplet-512-eps%g-mu%g-ca%g" % (eps_r, mu_r, ca),
+                                params=lattice_params(512, 80.0, Ca_E=ca, eps_r=eps_r, mu_r=mu_r),
+                                droplet=droplet(512, 80.0), presolve=0, steps=20000))
+    return pts
+
+
+def config3():
+    """Throughput case: 2048^2, R = 320, W = 5 (groups of the 128^2 case)."""
+    return dict(name="droplet-2048", params=lattice_params(2048, 320.0, W=5.0),
+                droplet=droplet(2048, 320.0), presolve=0, steps=50000)
+
+
+def scaled(n: int, *, W=4.0, **groups):
+    """The droplet case at grid n with radius n / 6.4 (as in the 128^2 case)."""
+    r = n / 6.4
+    return dict(name="droplet-%d" % n, params=lattice_params(n, r, W=W, **groups),
+                droplet=droplet(n, r), presolve=0, steps=0)
