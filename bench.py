@@ -1,0 +1,233 @@
+"""Throughput of the fused five-equation phase-field EHD lattice Boltzmann
+sweep on one MI355X.
+
+A step is one pass of the whole method over the grid (all five LB equations
+per cell, one fused Poisson update).  Default workload: the 2048 x 2048
+droplet case (radius 320, W = 5) in FP32, state resident in HBM.
+
+Prints one JSON line with the throughput (MLUPS), the HBM roofline of the
+sweep kernel measured live with HIP events, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (all 5 LB eqs/cell) at 2048² vs HBM roofline; sweep solves/hr; p99 latency"
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "sweep_hbm_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_04920_amd", "csrc", f)
+                  for f in ("lbm_ehd_device.hpp", "lbm_ehd_kernels.hpp", "lbm_ehd.hip")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter runs,
+    or None if they were taken on another version of the kernel."""
+    try:
+        with open(PMC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    ent = rec.get("workloads", {}).get(workload)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def cpu_baseline(params, drop, steps: int):
+    """The CPU oracle (plain FP64 C, OpenMP) on the same grid, few steps."""
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = oracle.Oracle(params)
+    o.init_droplet(drop["xc"], drop["yc"], drop["radius"], drop["noise"], drop["seed"])
+    o.step(1)                       # first touch of the state
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    cells = params["nx"] * params["ny"]
+    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": "%dx%d droplet case, %d steps after 1 warm-up step, FP64, %.1f s"
+                      % (params["nx"], params["ny"], steps, dt)}
+
+
+def copy_calibration(gib: float, reps: int, width: int):
+    """A plain device-to-device copy of known size with the library's copy
+    kernel (same buffer instructions as the sweep): its bandwidth is the
+    attainable HBM rate, and its FETCH_SIZE / WRITE_SIZE counters calibrate
+    the counter runs of the sweep."""
+    import torch
+
+    from paper_2501_04920_amd import lbm_ehd
+
+    n = int(gib * (1 << 30)) // 16 * 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+
+    def run():
+        lbm_ehd.lbm_ehd_stream_copy(a.data_ptr(), b.data_ptr(), 4 * n, st.cuda_stream, width)
+
+    for _ in range(3):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        run()
+    e1.record(st)
+    torch.cuda.synchronize()
+    assert bool((b == 1).all())
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * 4 * n
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "read_bytes": 4 * n,
+                      "write_bytes": 4 * n, "width": width, "ms": round(ms, 5),
+                      "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
+
+
+def summarize_pmc(paths, workload: str):
+    """Turn four rocprofv3 --pmc CSVs (sweep FETCH_SIZE, sweep WRITE_SIZE, copy
+    FETCH_SIZE, copy WRITE_SIZE; KiB per dispatch) into HBM bytes per sweep
+    launch, each counter scaled by what it reads for the copy kernel of known
+    size, and record them in the traffic file with the kernel source hash."""
+    import csv
+
+    def mean(path, kname, counter):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if kname in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        if not vals:
+            raise SystemExit("no %s rows for %s in %s" % (counter, kname, path))
+        return sum(vals) / len(vals) * 1024.0
+
+    sf, sw, cf, cw = paths
+    copy_read = copy_write = float(1 << 30)   # --copy-gib 1
+    kf = copy_read / mean(cf, "k_copy<4>", "FETCH_SIZE")
+    kw = copy_write / mean(cw, "k_copy<4>", "WRITE_SIZE")
+    fetch = mean(sf, "k_sweep", "FETCH_SIZE") * kf
+    write = mean(sw, "k_sweep", "WRITE_SIZE") * kw
+    try:
+        rec = json.load(open(PMC_FILE))
+    except (OSError, ValueError):
+        rec = {}
+    if rec.get("kernel_hash") != kernel_hash():
+        rec = {"kernel_hash": kernel_hash(), "workloads": {}}
+    rec["workloads"][workload] = {
+        "fetch_bytes": round(fetch), "write_bytes": round(write),
+        "bytes_per_launch": round(fetch + write),
+        "fetch_scale": round(kf, 4), "write_scale": round(kw, 4)}
+    with open(PMC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec["workloads"][workload]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
+    ap.add_argument("--n", type=int, default=2048, help="grid n x n (radius n / 6.4)")
+    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run the copy-kernel calibration of this size")
+    ap.add_argument("--copy-width", type=int, default=4, choices=[4, 16])
+    ap.add_argument("--summarize-pmc", nargs=4, metavar="CSV",
+                    help="sweep FETCH, sweep WRITE, copy FETCH, copy WRITE counter files")
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, "droplet-%d-%s" % (args.n, args.precision))
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_gib > 0:
+        copy_calibration(args.copy_gib, max(args.steps, 1), args.copy_width)
+        return
+
+    import torch
+
+    from paper_2501_04920_amd import lbm_ehd, workloads
+
+    n = args.n
+    if n == 2048:
+        cfg = workloads.config3()
+    else:
+        cfg = workloads.scaled(n, W=5.0)
+    params, drop = cfg["params"], cfg["droplet"]
+    workload = "droplet-%d-%s" % (n, args.precision)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sim = lbm_ehd.Simulation(dict(params, precision=args.precision), device=dev)
+    sim.init_droplet(drop["xc"], drop["yc"], drop["radius"], drop["noise"], drop["seed"])
+    stream = sim.stream
+    sim.step(args.warmup)
+    sim.synchronize()
+    torch.cuda.synchronize()
+
+    # per-launch duration of the sweep kernel: one launch per step, events on
+    # the stream the library launches on
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        sim.step(1)
+        b.record(stream)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+
+    cells = params["nx"] * params["ny"]
+    mlups = cells * args.steps / wall / 1e6
+    bpl = lbm_ehd.lbm_ehd_bytes_per_lup(args.precision)
+    achieved = bpl * cells / (kern_ms * 1e-3) / 1e9
+    diag = sim.diagnostics()
+    traffic = measured_traffic(workload)
+    line = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32", "bf16": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": workload, "nx": params["nx"], "ny": params["ny"],
+                   "radius": drop["radius"], "W": params["W"], "storage": args.precision,
+                   "poisson_sweeps_per_step": 1 + params["poisson_iters"],
+                   "bytes_per_lup": bpl},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_sweep",
+                     "kernel_ms": round(kern_ms, 5)},
+        "check": {"sum_phi": diag["sum_phi"], "nonfinite": diag["nonfinite"]},
+    }
+    sim.close()
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(params, drop, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,263 @@
+/*
+ * lbm_ehd.h -- C ABI of the MI355X (gfx950) implementation of the
+ * phase-field multiple-relaxation-time lattice Boltzmann method for two-phase
+ * electrohydrodynamic flow driven by the Onsager-Wien effect
+ * (Zheng, Wang, Xiong, Huang, Luo, arXiv 2501.04920, Sec. 4).
+ *
+ * One time step advances five coupled lattice Boltzmann equations on a 2-D
+ * grid (lattice units, dx = dt = 1):
+ *   f  (D2Q9)  incompressible Navier-Stokes, Eq. (51)-(57)
+ *   h  (D2Q9)  conservative Allen-Cahn phase field, Eq. (27)-(33)
+ *   p  (D2Q5)  cations, Eq. (34)-(43)
+ *   n  (D2Q5)  anions, Eq. (35)-(43)
+ *   g  (D2Q5)  electric potential, Eq. (44)-(49)
+ * coupled through the isotropic finite differences of Eq. (59), the
+ * phase-interpolated properties of Eq. (61), the field-enhanced dissociation
+ * and recombination source of Eq. (5)-(6) and the surface-tension and
+ * electric forces of Eq. (12)-(14).
+ *
+ * Geometry: x is periodic; the anode (psi = dpsi) lies half a lattice spacing
+ * below row 0 and the cathode (psi = 0) half a spacing above row ny-1
+ * (boundary conditions of Eq. (64) and Sec. 5.1).
+ *
+ * Conventions for every function:
+ *   - the return value is LBM_OK (0) or a negative LBM_E* code; on error
+ *     lbm_ehd_last_error() returns a message for the calling thread;
+ *   - host pointers are caller-owned and only read/written during the call;
+ *   - device pointers are hipMalloc'd (or PyTorch-allocated) memory on the
+ *     device the handle was created on;
+ *   - functions that enqueue GPU work do so on the handle's stream and return
+ *     without waiting, unless they are documented to synchronise.
+ * A handle is not thread-safe; distinct handles may be used concurrently.
+ */
+#ifndef LBM_EHD_H
+#define LBM_EHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef LBM_API
+#define LBM_API __attribute__((visibility("default")))
+#endif
+
+typedef int32_t lbm_status;
+#define LBM_OK 0
+#define LBM_EINVAL (-1)     /* invalid argument or parameter set */
+#define LBM_ENOMEM (-2)     /* device or host allocation failed */
+#define LBM_EDEVICE (-3)    /* a HIP call failed */
+#define LBM_ENONFINITE (-4) /* the state contains NaN or Inf */
+#define LBM_ESTATE (-5)     /* call out of order (e.g. step before init) */
+#define LBM_ERANGE (-6)     /* caller buffer too small */
+
+/* Storage precision of the populations (arithmetic is FP64 for LBM_FP64 and
+ * FP32 otherwise). */
+#define LBM_FP64 0
+#define LBM_FP32 1
+#define LBM_FP16_STORE 2 /* binary16 deviations from a reference state */
+#define LBM_BF16_STORE 3 /* bfloat16 deviations from a reference state */
+#define LBM_FP32_DEV 4   /* FP32 deviations from a reference state, FP32 arithmetic */
+#define LBM_FP32_F64 5   /* FP32 deviations from a reference state, FP64 arithmetic */
+
+/* Boundary conditions in y. */
+#define LBM_ELECTRODES 0 /* Eq. (64a): anode/cathode with ion conditions of Sec. 5.1 */
+#define LBM_INSULATING 1 /* electrodes for psi, f, h; ions bounce back (no ion flux) */
+#define LBM_PERIODIC 2   /* periodic in y as well (no walls) */
+
+/* Field selection bits for lbm_ehd_get_fields(). */
+#define LBM_FIELD_PHI (1u << 0)   /* order parameter, Eq. (33) */
+#define LBM_FIELD_PSI (1u << 1)   /* potential, Eq. (49) */
+#define LBM_FIELD_CP (1u << 2)    /* cation concentration c+, Eq. (42) */
+#define LBM_FIELD_CM (1u << 3)    /* anion concentration c-, Eq. (42) */
+#define LBM_FIELD_RHOE (1u << 4)  /* free charge density, Eq. (8) */
+#define LBM_FIELD_UX (1u << 5)    /* velocity, Eq. (56) */
+#define LBM_FIELD_UY (1u << 6)
+#define LBM_FIELD_P (1u << 7)     /* hydrodynamic pressure, Eq. (57) */
+#define LBM_FIELD_EX (1u << 8)    /* electric field E = -grad psi, Eq. (9), (59) */
+#define LBM_FIELD_EY (1u << 9)
+#define LBM_FIELD_ALL 0x3FFu
+
+/*
+ * Simulation parameters in lattice units.  Properties of the two phases are
+ * given for the outer ("v") phase plus the ratio liquid/vapour of Eq. (60);
+ * every property is interpolated linearly in phi (Eq. 61).
+ */
+typedef struct {
+  int32_t nx, ny;          /* grid; nx >= 2, ny >= 2 */
+  int32_t precision;       /* LBM_FP64, LBM_FP32, LBM_FP16_STORE, LBM_BF16_STORE,
+                              LBM_FP32_DEV, LBM_FP32_F64 */
+  int32_t walls;           /* LBM_ELECTRODES, LBM_INSULATING, LBM_PERIODIC */
+  int32_t reaction;        /* 1: R of Eq. (5)-(6); 0: R = 0 (leaky-dielectric limit, Sec. 5.2) */
+  int32_t poisson_form;    /* 1: source (rho_e + grad eps . grad psi)/eps, whose steady
+                              state is div(eps grad psi) = -rho_e (Eq. 7);
+                              0: rho_e/eps as printed in Eq. (44) */
+  int32_t poisson_norm;    /* 1: source weights w_i/(1 - w_0) so that the steady state
+                              solves Eq. (7); 0: weights w_i as printed in Eq. (44) */
+  int32_t flow;            /* 1: solve Eq. (51); 0: u = 0 and f is left as it is */
+  int32_t ion_force;       /* 1: keep L_i of Eq. (39); 0: drop it */
+  int32_t poisson_iters;   /* extra g-only sweeps before every step (0 = one fused
+                              g update per step) */
+  int32_t mask_f, mask_h, mask_p, mask_n, mask_g; /* bit k set: MRT row k relaxes with
+                              1/tau (Eq. 30, 37, 47, 55); other rows relax with s_free */
+  int32_t reserved;        /* must be 0 */
+  double rho_v, rho_r;     /* density, outer phase; ratio (Eq. 60) */
+  double eta_v, eta_r;     /* dynamic viscosity; tau_f = 1/2 + eta/(rho c_s^2), Eq. (55) */
+  double M_phi;            /* phase-field mobility; tau_h = 1/2 + M_phi/c_s^2, Eq. (30) */
+  double W;                /* interface width, Eq. (2) */
+  double zeta;             /* surface tension; beta = 12 zeta/W, kappa = 3 zeta W/2 (Eq. 13) */
+  double theta;            /* artificial diffusion of the Poisson LBE; tau_g = 1/2 + theta/c_s^2 */
+  double dpsi;             /* anode potential psi_0 (cathode psi_1 = 0) */
+  double eps_v, eps_r;     /* permittivity; ratio */
+  double mu_v, mu_r;       /* cation mobility, outer phase; ratio */
+  double m_ratio;          /* m = mu_- / mu_+ (Eq. 23) */
+  double v_th;             /* k_B T_r / e_0: D = v_th mu (Sec. 2.2); tau = 1/2 + D/c_s^2 (Eq. 37) */
+  double c0;               /* zero-field concentration (Eq. 5) */
+  double q;                /* elementary charge e_0: rho_e = q (c+ - c-), delta = q (mu+ + mu-)/eps */
+  double gamma_v;          /* Onsager constant of Eq. (6) in the outer phase; gamma ~ 1/eps */
+  double force_x, force_y; /* external body-force density added to F (tests) */
+  double s_free;           /* rate of the MRT rows not in the masks (1.0 in Sec. 6) */
+} lbm_ehd_params;
+
+/*
+ * Dimensionless description of a droplet case (Eq. 15, 23, 24, 60), mapped
+ * to lattice parameters by lbm_ehd_params_from_groups().
+ */
+typedef struct {
+  int32_t n;               /* grid n x n; the electrode gap d is n lattice spacings */
+  int32_t precision;
+  double radius;           /* initial droplet radius, lattice units */
+  double W;                /* interface width, lattice units (Cn = W/d) */
+  double Ca_E;             /* electric capillary number eps dpsi^2 r / (zeta d^2) */
+  double W0;               /* conduction number e0 c0 d^2 / (eps dpsi) */
+  double beta;             /* sqrt(O W0), Eq. (24) */
+  double eps_r, mu_r, rho_r, eta_r, m_ratio;
+  double sigma_r;          /* conductivity ratio; only with reaction = 0 (leaky model),
+                              where it sets mu_r (sigma ~ mu at uniform c0); 0 = unused */
+  int32_t reaction;        /* as in lbm_ehd_params */
+  int32_t reserved;
+  /* lattice choices (0 selects the default in brackets) */
+  double U;                /* ionic drift speed mu_bar dpsi / d [0.01] */
+  double alpha;            /* diffusion number D / (mu_bar dpsi) [0.01] */
+  double zeta;             /* [1e-3] */
+  double M_phi;            /* [0.1] */
+  double eta_v;            /* [0.1] */
+  double eps_v;            /* [1.0] */
+} lbm_ehd_groups;
+
+/*
+ * Caller-supplied device memory and stream.  pop[0] and pop[1] each hold
+ * pop_bytes (>= the size lbm_ehd_required_bytes() returns) and aux holds
+ * aux_bytes; the library ping-pongs between pop[0] and pop[1].  The memory
+ * stays owned by the caller and must outlive the handle.  stream is a
+ * hipStream_t (NULL: the null stream).
+ */
+typedef struct {
+  void *stream;
+  void *pop[2];
+  size_t pop_bytes;
+  void *aux;
+  size_t aux_bytes;
+} lbm_ehd_device;
+
+typedef struct {
+  int64_t step;            /* time steps taken since the last init */
+  double sum_phi;          /* FP64 sum of phi over the grid (Eq. 33) */
+  double sum_rhoe;         /* FP64 sum of rho_e (Eq. 8) */
+  double sum_p, sum_n;     /* FP64 sums of sum_i p_i and sum_i n_i */
+  int64_t nonfinite;       /* number of cells whose moments are NaN or Inf */
+  double D, L, H;          /* deformation factor of Eq. (63) and its lengths; the
+                              length along the field (y) through the phi-weighted
+                              centroid and across it, from the phi = 1/2 crossings
+                              (NaN when no droplet is found) */
+} lbm_ehd_diag;
+
+typedef struct lbm_ehd lbm_ehd; /* opaque handle */
+
+/* Fill *out with the defaults: FP32, electrodes, reaction on, the Eq. (7)
+ * Poisson form, rates as in Sec. 6 (free rows 1.0), theta = 0.3 (Sec. 4.2). */
+LBM_API lbm_status lbm_ehd_params_default(lbm_ehd_params *out);
+
+/* Map dimensionless groups to lattice parameters:
+ *   dpsi = n sqrt(Ca_E zeta/(eps_v R)), mu_bar = U n/dpsi, D = alpha mu_bar dpsi,
+ *   q = W0 eps_v dpsi/(c0 n^2) with c0 = 1, gamma_v = (beta^2/W0) n/dpsi.
+ * LBM_EINVAL on a non-positive group or an unreachable relaxation time. */
+LBM_API lbm_status lbm_ehd_params_from_groups(const lbm_ehd_groups *g, lbm_ehd_params *out);
+
+/* Bytes needed for each population buffer and for the aux buffer. */
+LBM_API lbm_status lbm_ehd_required_bytes(const lbm_ehd_params *p, size_t *pop_bytes,
+                                  size_t *aux_bytes);
+
+/* Create a simulation on the current HIP device.  dev may be NULL, in which
+ * case the library allocates (and later frees) the buffers itself and uses
+ * the null stream.  LBM_EINVAL: any tau <= 1/2, a non-finite coefficient,
+ * nx or ny < 2, unknown precision or walls. */
+LBM_API lbm_status lbm_ehd_create(const lbm_ehd_params *p, const lbm_ehd_device *dev, lbm_ehd **out);
+
+/* Initial droplet: phi = 1/2 (1 + tanh(2 (R - r)/W)) around (xc, yc), fluid at
+ * rest with p = 0, ions at c0 (1 + noise xi) with xi in [-1, 1) from SplitMix64
+ * outputs 2k+1 (cations) and 2k+2 (anions) of cell k = y nx + x, psi linear
+ * between the electrodes, every population at its equilibrium.  Resets the
+ * step counter.  Enqueues work. */
+LBM_API lbm_status lbm_ehd_init_droplet(lbm_ehd *h, double xc, double yc, double radius,
+                                double noise, uint64_t seed);
+
+/* Initial state from host fields [ny][nx] (FP64): equilibrium populations for
+ * phi, c+, c-, psi and velocity (ux, uy may be NULL: at rest), p = 0,
+ * (phi u)(t-1) = phi u.  Synchronises. */
+LBM_API lbm_status lbm_ehd_init_fields(lbm_ehd *h, const double *phi, const double *cp,
+                               const double *cm, const double *psi, const double *ux,
+                               const double *uy);
+
+/* `iters` g-only sweeps of Eq. (44) with phi and rho_e held fixed (Poisson
+ * pre-solve).  Enqueues work. */
+LBM_API lbm_status lbm_ehd_presolve(lbm_ehd *h, int32_t iters);
+
+/* One time step (poisson_iters extra g sweeps, then the fused sweep of all
+ * five equations).  Enqueues work. */
+LBM_API lbm_status lbm_ehd_step(lbm_ehd *h);
+
+/* nsteps time steps.  Enqueues work. */
+LBM_API lbm_status lbm_ehd_run(lbm_ehd *h, int64_t nsteps);
+
+/* Macroscopic fields at the current time, FP64, layout [field][ny][nx] for
+ * the selected bits of `mask` in increasing bit order.  n_doubles is the
+ * capacity of `out`; LBM_ERANGE if it is too small.  Synchronises. */
+LBM_API lbm_status lbm_ehd_get_fields(lbm_ehd *h, uint32_t mask, double *out, size_t n_doubles);
+
+/* FP64 invariants (sums in a fixed order, independent of launch shape), the
+ * non-finite count and the deformation factor.  Synchronises.  Returns
+ * LBM_ENONFINITE (after filling *out) if any cell is not finite. */
+LBM_API lbm_status lbm_ehd_diagnostics(lbm_ehd *h, lbm_ehd_diag *out);
+
+/* Current step count. */
+LBM_API int64_t lbm_ehd_time(const lbm_ehd *h);
+
+/* Wait for all work of the handle.  LBM_EDEVICE if a kernel failed. */
+LBM_API lbm_status lbm_ehd_synchronize(lbm_ehd *h);
+
+/* Release the handle and what the library allocated.  NULL is allowed. */
+LBM_API lbm_status lbm_ehd_destroy(lbm_ehd *h);
+
+/* Message of the last error on the calling thread ("" if none). */
+LBM_API const char *lbm_ehd_last_error(void);
+
+/* Algorithmic HBM bytes one lattice update moves in the fused sweep:
+ * 2 x 33 populations x storage width + (phi u) read and write. */
+LBM_API double lbm_ehd_bytes_per_lup(int32_t precision);
+
+/* Measurement helper, not part of the method: copy `bytes` (a multiple of
+ * 16) from device buffer src to dst on `stream` with the same raw buffer
+ * instructions the sweep uses, `width` = 4 (one dword per lane) or 16 bytes
+ * per lane.  Its bandwidth is the attainable HBM rate and its hardware
+ * counters calibrate the sweep's.  LBM_EINVAL on a bad size or width. */
+LBM_API lbm_status lbm_ehd_stream_copy(const void *src, void *dst, size_t bytes, void *stream,
+                                       int32_t width);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_EHD_H */

@@ -1,0 +1,671 @@
+// lbm_ehd.hip -- host runtime and C ABI of the five-equation phase-field
+// EHD lattice Boltzmann library (declarations and documentation in
+// include/lbm_ehd.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_ehd.h"
+#include "lbm_ehd_kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+size_t elem_size(int prec) {
+  switch (prec) {
+    case LBM_FP64: return 8;
+    case LBM_FP32: return 4;
+    case LBM_FP32_DEV:
+    case LBM_FP32_F64: return 4;
+    case LBM_FP16_STORE:
+    case LBM_BF16_STORE: return 2;
+    default: return 0;
+  }
+}
+size_t arith_size(int prec) { return (prec == LBM_FP64 || prec == LBM_FP32_F64) ? 8 : 4; }
+
+int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+
+bool finite_all(std::initializer_list<double> v) {
+  for (double d : v)
+    if (!std::isfinite(d)) return false;
+  return true;
+}
+
+}  // namespace
+
+struct lbm_ehd {
+  lbm_ehd_params P;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* pop[2] = {nullptr, nullptr};
+  size_t pop_bytes = 0;
+  void* aux = nullptr;
+  size_t aux_bytes = 0;
+  bool own = false;
+  int cur = 0;          // buffer holding the current state
+  int64_t step = 0;
+  bool ready = false;   // initial state written
+  int pitch = 0;
+  long long plane = 0;
+  // scratch owned by the library
+  void* mom = nullptr;      // phi, psi, rho_e planes (arithmetic type), [3][ny][nx]
+  void* gtmp = nullptr;     // g planes for the extra Poisson sweeps, [5][ny+2][pitch]
+  double* fld = nullptr;    // [10][ny][nx]
+  double* part = nullptr;   // [ny][NSUM]
+  double* red = nullptr;    // [NSUM]
+  double* line = nullptr;   // [2 ny + 2 nx]
+  double* upl = nullptr;    // uploaded initial fields [6][ny][nx]
+  int tile_rows = 16;
+  int band_major = 1;
+};
+
+namespace {
+
+template <class R>
+KP<R> make_kp(const lbm_ehd* h) {
+  const lbm_ehd_params& p = h->P;
+  KP<R> k;
+  std::memset(&k, 0, sizeof k);
+  k.nx = p.nx;
+  k.ny = p.ny;
+  k.pitch = h->pitch;
+  k.walls = p.walls;
+  k.plane = (uint32_t)h->plane;
+  k.pop_bytes = (uint32_t)(NPOP * h->plane * (long long)elem_size(p.precision));
+  k.g_bytes = (uint32_t)(5 * h->plane * (long long)elem_size(p.precision));
+  k.reaction = p.reaction;
+  k.poisson_form = p.poisson_form;
+  k.flow = p.flow;
+  k.ion_force = p.ion_force;
+  k.mask_f = p.mask_f;
+  k.mask_h = p.mask_h;
+  k.mask_p = p.mask_p;
+  k.mask_n = p.mask_n;
+  k.mask_g = p.mask_g;
+  k.rho_v = (R)p.rho_v;
+  k.drho = (R)(p.rho_v * p.rho_r - p.rho_v);
+  k.eta_v = (R)p.eta_v;
+  k.deta = (R)(p.eta_v * p.eta_r - p.eta_v);
+  k.eps_v = (R)p.eps_v;
+  k.deps = (R)(p.eps_v * p.eps_r - p.eps_v);
+  k.mu_v = (R)p.mu_v;
+  k.dmu = (R)(p.mu_v * p.mu_r - p.mu_v);
+  k.m_ratio = (R)p.m_ratio;
+  k.three_vth = (R)(3.0 * p.v_th);
+  k.c0sq = (R)(p.c0 * p.c0);
+  k.q = (R)p.q;
+  k.gve = (R)(p.gamma_v * p.eps_v);
+  k.beta4 = (R)(48.0 * p.zeta / p.W);
+  k.kappa = (R)(1.5 * p.zeta * p.W);
+  k.W = (R)p.W;
+  k.fourW = (R)(4.0 / p.W);
+  k.s_free = (R)p.s_free;
+  k.inv_tau_h = (R)(1.0 / (0.5 + 3.0 * p.M_phi));
+  k.inv_tau_g = (R)(1.0 / (0.5 + 3.0 * p.theta));
+  k.theta_src = (R)(p.poisson_norm ? p.theta * 1.5 : p.theta);  // 1/(1 - wbar_0) = 3/2
+  k.dpsi = (R)p.dpsi;
+  k.force_x = (R)p.force_x;
+  k.force_y = (R)p.force_y;
+  k.ref_p = (R)p.c0;
+  k.ref_n = (R)p.c0;
+  return k;
+}
+
+// Launch helpers, one instantiation per storage form.
+template <class S, class R, bool DEV>
+struct Form {
+  static S* buf(lbm_ehd* h, int i) { return static_cast<S*>(h->pop[i]); }
+  static R* jp(lbm_ehd* h) { return static_cast<R*>(h->aux); }
+
+  static lbm_status sweep(lbm_ehd* h, const S* srcg) {
+    const KP<R> kp = make_kp<R>(h);
+    const int nstrips = (h->P.nx + TILE_W - 1) / TILE_W;
+    const int tr = h->tile_rows;
+    const int nbands = (h->P.ny + tr - 1) / tr;
+    const int nb = nstrips * nbands;
+    const int chunk = (nb % 8 == 0) ? nb / 8 : 0;
+    const S* src = buf(h, h->cur);
+    if (!srcg) srcg = src + (long long)QG * h->plane;
+    hipLaunchKernelGGL((k_sweep<S, R, DEV>), dim3(nb), dim3(TILE_W), 0, h->stream, src, srcg,
+                       buf(h, 1 - h->cur), jp(h), kp, tr, nstrips, nbands, chunk,
+                       h->band_major);
+    HIP_TRY(hipGetLastError());
+    h->cur = 1 - h->cur;
+    return LBM_OK;
+  }
+
+  static dim3 grid2(const lbm_ehd* h) { return dim3((h->P.nx + 63) / 64, h->P.ny); }
+
+  static lbm_status moments(lbm_ehd* h, const S* srcg) {
+    const KP<R> kp = make_kp<R>(h);
+    const S* src = buf(h, h->cur);
+    if (!srcg) srcg = src + (long long)QG * h->plane;
+    hipLaunchKernelGGL((k_moments<S, R, DEV>), grid2(h), dim3(64), 0, h->stream, src, srcg,
+                       static_cast<R*>(h->mom), kp);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+  }
+
+  // `iters` g-only sweeps.  The g planes ping-pong between the state buffer
+  // and the scratch set; returns (in *gsrc) where the latest g lives.
+  static lbm_status poisson(lbm_ehd* h, int iters, const S** gsrc) {
+    const KP<R> kp = make_kp<R>(h);
+    S* gA = buf(h, h->cur) + (long long)QG * h->plane;
+    S* gB = static_cast<S*>(h->gtmp);
+    S* from = gA;
+    for (int it = 0; it < iters; ++it) {
+      lbm_status st = moments(h, from);
+      if (st) return st;
+      S* to = from == gA ? gB : gA;
+      hipLaunchKernelGGL((k_poisson<S, R, DEV>), grid2(h), dim3(64), 0, h->stream, from, to,
+                         static_cast<const R*>(h->mom), kp);
+      HIP_TRY(hipGetLastError());
+      from = to;
+    }
+    *gsrc = from;
+    return LBM_OK;
+  }
+
+  // Bring the latest g back into the state buffer (after a pre-solve).
+  static lbm_status settle_g(lbm_ehd* h, const S* gsrc) {
+    S* gA = buf(h, h->cur) + (long long)QG * h->plane;
+    if (gsrc != gA)
+      HIP_TRY(hipMemcpyAsync(gA, gsrc, 5 * h->plane * sizeof(S), hipMemcpyDeviceToDevice,
+                             h->stream));
+    return LBM_OK;
+  }
+
+  static lbm_status step(lbm_ehd* h) {
+    const S* g = nullptr;
+    if (h->P.poisson_iters > 0) {
+      lbm_status st = poisson(h, h->P.poisson_iters, &g);
+      if (st) return st;
+    }
+    return sweep(h, g);
+  }
+
+  static lbm_status presolve(lbm_ehd* h, int iters) {
+    const S* g = nullptr;
+    lbm_status st = poisson(h, iters, &g);
+    if (st) return st;
+    return settle_g(h, g);
+  }
+
+  static lbm_status init(lbm_ehd* h, const InitSpec& sp) {
+    const KP<R> kp = make_kp<R>(h);
+    h->cur = 0;
+    hipLaunchKernelGGL((k_init<S, R, DEV>), grid2(h), dim3(64), 0, h->stream, buf(h, 0), jp(h),
+                       kp, sp);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+  }
+
+  static lbm_status fields(lbm_ehd* h) {
+    lbm_status st = moments(h, nullptr);
+    if (st) return st;
+    const KP<R> kp = make_kp<R>(h);
+    const S* src = buf(h, h->cur);
+    hipLaunchKernelGGL((k_fields<S, R, DEV>), grid2(h), dim3(64), 0, h->stream, src,
+                       src + (long long)QG * h->plane, static_cast<const R*>(h->mom), h->fld,
+                       kp);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+  }
+
+  static lbm_status sums(lbm_ehd* h) {
+    const KP<R> kp = make_kp<R>(h);
+    const S* src = buf(h, h->cur);
+    hipLaunchKernelGGL((k_row_sums<S, R, DEV>), dim3(h->P.ny), dim3(256), 0, h->stream, src,
+                       src + (long long)QG * h->plane, h->part, kp);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, h->part, h->P.ny, h->red);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+  }
+};
+
+template <class F>
+lbm_status dispatch(lbm_ehd* h, F&& fn) {
+  switch (h->P.precision) {
+    case LBM_FP64: return fn(Form<double, double, false>{});
+    case LBM_FP32: return fn(Form<float, float, false>{});
+    case LBM_FP32_DEV: return fn(Form<float, float, true>{});
+    case LBM_FP32_F64: return fn(Form<float, double, true>{});
+    case LBM_FP16_STORE: return fn(Form<__half, float, true>{});
+    case LBM_BF16_STORE: return fn(Form<__hip_bfloat16, float, true>{});
+  }
+  return fail(LBM_EINVAL, "unknown precision");
+}
+
+lbm_status validate(const lbm_ehd_params* p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->nx < 2 || p->ny < 2) return fail(LBM_EINVAL, "nx and ny must be >= 2");
+  if ((long long)p->nx * p->ny > (1LL << 31)) return fail(LBM_EINVAL, "grid too large");
+  if (!elem_size(p->precision)) return fail(LBM_EINVAL, "unknown precision");
+  // kernels address a population buffer with 32-bit byte offsets
+  if ((double)NPOP * (p->ny + 2) * pitch_of(p->nx) * elem_size(p->precision) >= 4294967296.0)
+    return fail(LBM_EINVAL, "grid too large: a population buffer must stay below 4 GiB");
+  if (p->walls < 0 || p->walls > 2) return fail(LBM_EINVAL, "unknown walls");
+  if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+  if (p->poisson_iters < 0) return fail(LBM_EINVAL, "poisson_iters < 0");
+  if (!finite_all({p->rho_v, p->rho_r, p->eta_v, p->eta_r, p->M_phi, p->W, p->zeta, p->theta,
+                   p->dpsi, p->eps_v, p->eps_r, p->mu_v, p->mu_r, p->m_ratio, p->v_th, p->c0,
+                   p->q, p->gamma_v, p->force_x, p->force_y, p->s_free}))
+    return fail(LBM_EINVAL, "non-finite coefficient");
+  if (p->rho_v <= 0 || p->rho_r <= 0 || p->eps_v <= 0 || p->eps_r <= 0 || p->W <= 0)
+    return fail(LBM_EINVAL, "density, permittivity and W must be positive");
+  if (p->s_free <= 0 || p->s_free >= 2) return fail(LBM_EINVAL, "s_free must lie in (0, 2)");
+  // every relaxation time > 1/2 for phi in [0, 1] (the properties are linear)
+  for (double phi : {0.0, 1.0}) {
+    const double rho = p->rho_v + phi * (p->rho_v * p->rho_r - p->rho_v);
+    const double eta = p->eta_v + phi * (p->eta_v * p->eta_r - p->eta_v);
+    const double mu = p->mu_v + phi * (p->mu_v * p->mu_r - p->mu_v);
+    if (p->flow && !(eta / rho > 0)) return fail(LBM_EINVAL, "tau_f <= 1/2");
+    if (!(p->v_th * mu > 0) || !(p->v_th * mu * p->m_ratio > 0))
+      return fail(LBM_EINVAL, "tau_+ or tau_- <= 1/2 (v_th mu must be > 0)");
+    if (!(p->eps_v + phi * (p->eps_v * p->eps_r - p->eps_v) > 0))
+      return fail(LBM_EINVAL, "permittivity <= 0");
+  }
+  if (!(p->M_phi > 0)) return fail(LBM_EINVAL, "tau_h <= 1/2 (M_phi must be > 0)");
+  if (!(p->theta > 0)) return fail(LBM_EINVAL, "tau_g <= 1/2 (theta must be > 0)");
+  return LBM_OK;
+}
+
+void free_scratch(lbm_ehd* h) {
+  (void)hipFree(h->mom);
+  (void)hipFree(h->gtmp);
+  (void)hipFree(h->fld);
+  (void)hipFree(h->part);
+  (void)hipFree(h->red);
+  (void)hipFree(h->line);
+  (void)hipFree(h->upl);
+  if (h->own) {
+    (void)hipFree(h->pop[0]);
+    (void)hipFree(h->pop[1]);
+    (void)hipFree(h->aux);
+  }
+}
+
+// Length between the two phi = 1/2 crossings of a profile, walking out from
+// index `start` (linear interpolation between the bracketing nodes).
+bool span(const double* v, int n, double start, double* len) {
+  int i0 = (int)std::floor(start);
+  i0 = std::min(std::max(i0, 0), n - 1);
+  if (!(v[i0] >= 0.5)) return false;
+  double hi = NAN, lo = NAN;
+  for (int i = i0; i < n - 1; ++i)
+    if (v[i] >= 0.5 && v[i + 1] < 0.5) {
+      hi = i + (v[i] - 0.5) / (v[i] - v[i + 1]);
+      break;
+    }
+  for (int i = i0; i > 0; --i)
+    if (v[i] >= 0.5 && v[i - 1] < 0.5) {
+      lo = i - (v[i] - 0.5) / (v[i] - v[i - 1]);
+      break;
+    }
+  if (std::isnan(hi) || std::isnan(lo)) return false;
+  *len = hi - lo;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_ehd_params_default(lbm_ehd_params* o) {
+  if (!o) return fail(LBM_EINVAL, "out is NULL");
+  std::memset(o, 0, sizeof *o);
+  o->nx = o->ny = 128;
+  o->precision = LBM_FP32;
+  o->walls = LBM_ELECTRODES;
+  o->reaction = 1;
+  o->poisson_form = 1;
+  o->poisson_norm = 1;
+  o->flow = 1;
+  o->ion_force = 1;
+  o->mask_f = (1 << 3) | (1 << 4) | (1 << 5);
+  o->mask_h = o->mask_p = o->mask_n = o->mask_g = (1 << 1) | (1 << 2);
+  o->rho_v = 1.0;
+  o->rho_r = 1.0;
+  o->eta_v = 0.1;
+  o->eta_r = 1.0;
+  o->M_phi = 0.1;
+  o->W = 4.0;
+  o->zeta = 1e-3;
+  o->theta = 0.3;
+  o->eps_v = 1.0;
+  o->eps_r = 1.0;
+  o->mu_v = 1.0;
+  o->mu_r = 1.0;
+  o->m_ratio = 1.0;
+  o->v_th = 0.01;
+  o->c0 = 1.0;
+  o->s_free = 1.0;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_params_from_groups(const lbm_ehd_groups* g, lbm_ehd_params* o) {
+  if (!g || !o) return fail(LBM_EINVAL, "NULL argument");
+  lbm_ehd_params_default(o);
+  const double U = g->U > 0 ? g->U : 0.01, alpha = g->alpha > 0 ? g->alpha : 0.01;
+  const double zeta = g->zeta > 0 ? g->zeta : 1e-3, M_phi = g->M_phi > 0 ? g->M_phi : 0.1;
+  const double eta_v = g->eta_v > 0 ? g->eta_v : 0.1, eps_v = g->eps_v > 0 ? g->eps_v : 1.0;
+  const double n = g->n;
+  if (g->n < 8 || !(g->radius > 0) || !(g->W > 0) || !(g->Ca_E > 0) || !(g->eps_r > 0) ||
+      !(g->rho_r > 0) || !(g->eta_r > 0) || !(g->m_ratio > 0))
+    return fail(LBM_EINVAL, "groups: n >= 8 and positive radius, W, Ca_E, ratios required");
+  if (2 * g->radius + 2 * g->W >= n) return fail(LBM_EINVAL, "droplet does not fit the gap");
+  if (g->reaction && (!(g->W0 > 0) || !(g->beta > 0)))
+    return fail(LBM_EINVAL, "W0 and beta must be positive with the reaction on");
+  if (g->sigma_r > 0 && g->reaction)
+    return fail(LBM_EINVAL, "sigma_r applies to the leaky model only (reaction = 0)");
+  o->nx = o->ny = g->n;
+  o->precision = g->precision;
+  o->reaction = g->reaction;
+  o->W = g->W;
+  o->zeta = zeta;
+  o->M_phi = M_phi;
+  o->eta_v = eta_v;
+  o->eta_r = g->eta_r;
+  o->rho_r = g->rho_r;
+  o->eps_v = eps_v;
+  o->eps_r = g->eps_r;
+  o->m_ratio = g->m_ratio;
+  o->mu_r = g->sigma_r > 0 ? g->sigma_r : g->mu_r;
+  if (!(o->mu_r > 0)) return fail(LBM_EINVAL, "mu_r must be positive");
+  o->dpsi = n * std::sqrt(g->Ca_E * zeta / (eps_v * g->radius));
+  const double mu_bar = U * n / o->dpsi;
+  o->mu_v = mu_bar / std::sqrt(g->m_ratio);
+  o->v_th = alpha * o->dpsi;
+  o->c0 = 1.0;
+  o->q = g->W0 > 0 ? g->W0 * eps_v * o->dpsi / (n * n) : 0.0;
+  o->gamma_v = g->reaction ? (g->beta * g->beta / g->W0) * n / o->dpsi : 0.0;
+  return validate(o);
+}
+
+lbm_status lbm_ehd_required_bytes(const lbm_ehd_params* p, size_t* pop_bytes,
+                                  size_t* aux_bytes) {
+  lbm_status st = validate(p);
+  if (st) return st;
+  const size_t pitch = pitch_of(p->nx);
+  if (pop_bytes) *pop_bytes = (size_t)NPOP * (p->ny + 2) * pitch * elem_size(p->precision);
+  if (aux_bytes) *aux_bytes = 2 * (size_t)p->ny * pitch * arith_size(p->precision);
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_create(const lbm_ehd_params* p, const lbm_ehd_device* dev, lbm_ehd** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm_status st = validate(p);
+  if (st) return st;
+  size_t pb = 0, ab = 0;
+  lbm_ehd_required_bytes(p, &pb, &ab);
+  lbm_ehd* h = new (std::nothrow) lbm_ehd;
+  if (!h) return fail(LBM_ENOMEM, "host allocation failed");
+  h->P = *p;
+  h->pitch = pitch_of(p->nx);
+  h->plane = (long long)(p->ny + 2) * h->pitch;
+  const char* tr = std::getenv("LBM_EHD_TILE_ROWS");
+  const int nstrips = (p->nx + TILE_W - 1) / TILE_W;
+  // Bands as tall as possible (the h/g rows above and below a band are read
+  // twice) while keeping >= 2048 single-wave workgroups (8 per CU) in flight;
+  // measured on MI355X at 2048^2: 32 rows 16.5 GLUPS, 16 rows 15.2, 64 rows 12.0.
+  int rows = (int)std::max<long long>(1, (long long)nstrips * p->ny / 2048);
+  h->tile_rows = std::min(32, std::max(2, rows));
+  if (tr && std::atoi(tr) > 0) h->tile_rows = std::atoi(tr);
+  const char* bm = std::getenv("LBM_EHD_BAND_MAJOR");
+  if (bm) h->band_major = std::atoi(bm) != 0;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(LBM_EDEVICE, "no HIP device");
+  }
+  auto cleanup = [&](lbm_status code, const std::string& msg) {
+    free_scratch(h);
+    delete h;
+    return fail(code, msg);
+  };
+  if (dev) {
+    if (!dev->pop[0] || !dev->pop[1] || !dev->aux || dev->pop[0] == dev->pop[1])
+      return cleanup(LBM_EINVAL, "device buffers missing or aliased");
+    if (dev->pop_bytes < pb || dev->aux_bytes < ab)
+      return cleanup(LBM_ERANGE, "device buffers too small (need " + std::to_string(pb) +
+                                     " and " + std::to_string(ab) + " bytes)");
+    h->pop[0] = dev->pop[0];
+    h->pop[1] = dev->pop[1];
+    h->aux = dev->aux;
+    h->stream = static_cast<hipStream_t>(dev->stream);
+    h->own = false;
+  } else {
+    h->own = true;
+    if (hipMalloc(&h->pop[0], pb) != hipSuccess || hipMalloc(&h->pop[1], pb) != hipSuccess ||
+        hipMalloc(&h->aux, ab) != hipSuccess)
+      return cleanup(LBM_ENOMEM, "device allocation of the state failed");
+  }
+  h->pop_bytes = pb;
+  h->aux_bytes = ab;
+  const size_t nc = (size_t)p->nx * p->ny;
+  const size_t ar = arith_size(p->precision);
+  if (hipMalloc(&h->mom, 3 * nc * ar) != hipSuccess ||
+      hipMalloc(&h->gtmp, 5 * (size_t)h->plane * elem_size(p->precision)) != hipSuccess ||
+      hipMalloc(&h->fld, 10 * nc * sizeof(double)) != hipSuccess ||
+      hipMalloc(&h->part, (size_t)p->ny * NSUM * sizeof(double)) != hipSuccess ||
+      hipMalloc(&h->red, NSUM * sizeof(double)) != hipSuccess ||
+      hipMalloc(&h->line, (2 * (size_t)p->ny + 2 * (size_t)p->nx) * sizeof(double)) !=
+          hipSuccess)
+    return cleanup(LBM_ENOMEM, "device allocation of scratch failed");
+  *out = h;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_init_droplet(lbm_ehd* h, double xc, double yc, double radius, double noise,
+                                uint64_t seed) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!finite_all({xc, yc, radius, noise})) return fail(LBM_EINVAL, "non-finite argument");
+  if (noise < 0 || noise >= 1) return fail(LBM_EINVAL, "noise must lie in [0, 1)");
+  if (h->P.walls != LBM_PERIODIC && radius > 0 &&
+      (yc - radius < -0.5 || yc + radius > h->P.ny - 0.5))
+    return fail(LBM_EINVAL, "droplet crosses an electrode");
+  InitSpec sp;
+  std::memset(&sp, 0, sizeof sp);
+  sp.xc = xc;
+  sp.yc = yc;
+  sp.radius = radius;
+  sp.noise = noise;
+  sp.seed = seed;
+  lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::init(h, sp); });
+  if (st) return st;
+  h->step = 0;
+  h->ready = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_init_fields(lbm_ehd* h, const double* phi, const double* cp,
+                               const double* cm, const double* psi, const double* ux,
+                               const double* uy) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!phi || !cp || !cm || !psi) return fail(LBM_EINVAL, "phi, cp, cm and psi are required");
+  const size_t nc = (size_t)h->P.nx * h->P.ny;
+  if (!h->upl) HIP_TRY(hipMalloc(&h->upl, 6 * nc * sizeof(double)));
+  const double* srcs[6] = {phi, cp, cm, psi, ux, uy};
+  for (int i = 0; i < 6; ++i)
+    if (srcs[i])
+      HIP_TRY(hipMemcpyAsync(h->upl + i * nc, srcs[i], nc * sizeof(double),
+                             hipMemcpyHostToDevice, h->stream));
+  InitSpec sp;
+  std::memset(&sp, 0, sizeof sp);
+  sp.phi = h->upl;
+  sp.cp = h->upl + nc;
+  sp.cm = h->upl + 2 * nc;
+  sp.psi = h->upl + 3 * nc;
+  sp.ux = ux ? h->upl + 4 * nc : nullptr;
+  sp.uy = uy ? h->upl + 5 * nc : nullptr;
+  lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::init(h, sp); });
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->step = 0;
+  h->ready = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_presolve(lbm_ehd* h, int32_t iters) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h->ready) return fail(LBM_ESTATE, "presolve before init");
+  if (iters < 0) return fail(LBM_EINVAL, "iters < 0");
+  if (iters == 0) return LBM_OK;
+  return dispatch(h, [&](auto F) { return decltype(F)::presolve(h, iters); });
+}
+
+lbm_status lbm_ehd_step(lbm_ehd* h) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h->ready) return fail(LBM_ESTATE, "step before init");
+  lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::step(h); });
+  if (st) return st;
+  h->step += 1;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_run(lbm_ehd* h, int64_t nsteps) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  for (int64_t i = 0; i < nsteps; ++i) {
+    lbm_status st = lbm_ehd_step(h);
+    if (st) return st;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_get_fields(lbm_ehd* h, uint32_t mask, double* out, size_t n_doubles) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h->ready) return fail(LBM_ESTATE, "get_fields before init");
+  if (mask & ~LBM_FIELD_ALL) return fail(LBM_EINVAL, "unknown field bits");
+  const size_t nc = (size_t)h->P.nx * h->P.ny;
+  size_t nsel = 0;
+  for (int b = 0; b < 10; ++b) nsel += (mask >> b) & 1;
+  if (n_doubles < nsel * nc) return fail(LBM_ERANGE, "output buffer too small");
+  if (nsel && !out) return fail(LBM_EINVAL, "out is NULL");
+  lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::fields(h); });
+  if (st) return st;
+  size_t k = 0;
+  for (int b = 0; b < 10; ++b)
+    if ((mask >> b) & 1) {
+      HIP_TRY(hipMemcpyAsync(out + k * nc, h->fld + b * nc, nc * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+      ++k;
+    }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_diagnostics(lbm_ehd* h, lbm_ehd_diag* out) {
+  if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+  if (!h->ready) return fail(LBM_ESTATE, "diagnostics before init");
+  lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::sums(h); });
+  if (st) return st;
+  double r[NSUM];
+  HIP_TRY(hipMemcpyAsync(r, h->red, sizeof r, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  out->step = h->step;
+  out->sum_phi = r[0];
+  out->sum_rhoe = r[1];
+  out->sum_p = r[2];
+  out->sum_n = r[3];
+  out->nonfinite = (int64_t)r[6];
+  out->D = out->L = out->H = NAN;
+  if (out->nonfinite) return fail(LBM_ENONFINITE, "state contains NaN or Inf");
+  if (r[0] > 0) {
+    // deformation: phi on the lines through the centroid
+    const int nx = h->P.nx, ny = h->P.ny;
+    const double xb = r[4] / r[0], yb = r[5] / r[0];
+    st = dispatch(h, [&](auto F) { return decltype(F)::fields(h); });
+    if (st) return st;
+    const int j = (int)std::floor(xb), i = (int)std::floor(yb);
+    const int j1 = (j + 1) % nx, i1 = std::min(i + 1, ny - 1);
+    std::vector<double> c0(ny), c1(ny), r0(nx), r1(nx);
+    HIP_TRY(hipMemcpy2DAsync(c0.data(), sizeof(double), h->fld + j, nx * sizeof(double),
+                             sizeof(double), ny, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpy2DAsync(c1.data(), sizeof(double), h->fld + j1, nx * sizeof(double),
+                             sizeof(double), ny, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(r0.data(), h->fld + (size_t)i * nx, nx * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(r1.data(), h->fld + (size_t)i1 * nx, nx * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double tx = xb - j, ty = yb - i;
+    std::vector<double> col(ny), row(nx);
+    for (int y = 0; y < ny; ++y) col[y] = (1 - tx) * c0[y] + tx * c1[y];
+    for (int x = 0; x < nx; ++x) row[x] = (1 - ty) * r0[x] + ty * r1[x];
+    double L, H;
+    if (span(col.data(), ny, yb, &L) && span(row.data(), nx, xb, &H)) {
+      out->L = L;
+      out->H = H;
+      out->D = (L - H) / (L + H);
+    }
+  }
+  return LBM_OK;
+}
+
+int64_t lbm_ehd_time(const lbm_ehd* h) { return h ? h->step : -1; }
+
+lbm_status lbm_ehd_synchronize(lbm_ehd* h) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_destroy(lbm_ehd* h) {
+  if (!h) return LBM_OK;
+  (void)hipStreamSynchronize(h->stream);
+  free_scratch(h);
+  delete h;
+  return LBM_OK;
+}
+
+const char* lbm_ehd_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_ehd_stream_copy(const void* src, void* dst, size_t bytes, void* stream,
+                               int32_t width) {
+  if (!src || !dst || bytes == 0 || bytes % 16 || bytes >= 4294967296ull)
+    return fail(LBM_EINVAL, "copy size must be a positive multiple of 16 below 4 GiB");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int blocks = 256 * 16;
+  if (width == 4)
+    hipLaunchKernelGGL(k_copy<4>, dim3(blocks), dim3(256), 0, st, src, dst, (uint32_t)bytes);
+  else if (width == 16)
+    hipLaunchKernelGGL(k_copy<16>, dim3(blocks), dim3(256), 0, st, src, dst, (uint32_t)bytes);
+  else
+    return fail(LBM_EINVAL, "width must be 4 or 16");
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+double lbm_ehd_bytes_per_lup(int32_t precision) {
+  const size_t s = elem_size(precision);
+  if (!s) return 0.0;
+  return 2.0 * NPOP * s + 2.0 * 2.0 * arith_size(precision);
+}
+
+}  // extern "C"

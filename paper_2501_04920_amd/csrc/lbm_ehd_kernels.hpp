@@ -1,0 +1,619 @@
+// lbm_ehd_kernels.hpp -- kernels of the five-equation sweep and its helpers.
+//
+// k_sweep is the hot path: one pass over the grid advances f, h, p, n and g
+// by one time step (pull streaming fused with the collisions).  Each
+// workgroup is one wavefront that owns a 64-column strip of a band of rows and
+// walks down the band.  phi and psi, needed at the eight neighbours for the
+// isotropic stencils (Eq. 59), are the moments of the *pulled* h and g of
+// those neighbours, so the wave computes them one row ahead into a small LDS
+// ring (5 rows x 66 columns, the two halo columns by lanes 0 and 1) and keeps
+// the pulled h and g of that row in registers for the row's own update.  Every
+// population is read once and written once per step; only h and g of the two
+// halo columns and of the row above a band are read twice (from L2).
+#pragma once
+
+#include "lbm_ehd_device.hpp"
+
+namespace lbm {
+
+// Offsets of the pull sources of node (xc, yy): the population arriving along
+// c_i comes from (xc - c_ix, yy - c_iy).
+struct Cols {
+  int c, m, p;  // xc, xc - 1, xc + 1 (periodic in x)
+};
+
+__device__ inline Cols cols_of(int xc, int nx) {
+  Cols k;
+  k.c = xc;
+  k.m = xc == 0 ? nx - 1 : xc - 1;
+  k.p = xc == nx - 1 ? 0 : xc + 1;
+  return k;
+}
+
+template <class S, class R, bool DEV>
+__device__ inline void pull9(const PopView<S, R, DEV>& P, int q0, Cols k, int yy, uint32_t pitch,
+                             R x[9]) {
+  const uint32_t r0 = (uint32_t)(yy + 1) * pitch, rm = r0 - pitch, rp = r0 + pitch;
+  x[0] = P.at(q0 + 0, r0 + k.c, yy);
+  x[1] = P.at(q0 + 1, r0 + k.m, yy);
+  x[2] = P.at(q0 + 2, rm + k.c, yy - 1);
+  x[3] = P.at(q0 + 3, r0 + k.p, yy);
+  x[4] = P.at(q0 + 4, rp + k.c, yy + 1);
+  x[5] = P.at(q0 + 5, rm + k.m, yy - 1);
+  x[6] = P.at(q0 + 6, rm + k.p, yy - 1);
+  x[7] = P.at(q0 + 7, rp + k.p, yy + 1);
+  x[8] = P.at(q0 + 8, rp + k.m, yy + 1);
+}
+
+// Directions 1..4 of a D2Q5 set (the rest population is pulled separately).
+template <class S, class R, bool DEV>
+__device__ inline void pull4(const PopView<S, R, DEV>& P, int q0, Cols k, int yy, uint32_t pitch,
+                             R x[4]) {
+  const uint32_t r0 = (uint32_t)(yy + 1) * pitch, rm = r0 - pitch, rp = r0 + pitch;
+  x[0] = P.at(q0 + 1, r0 + k.m, yy);
+  x[1] = P.at(q0 + 2, rm + k.c, yy - 1);
+  x[2] = P.at(q0 + 3, r0 + k.p, yy);
+  x[3] = P.at(q0 + 4, rp + k.c, yy + 1);
+}
+
+template <class R>
+__device__ inline R sum9(const R h[9]) {
+  return h[0] + h[1] + h[2] + h[3] + h[4] + h[5] + h[6] + h[7] + h[8];
+}
+template <class R>
+__device__ inline R psi_of(const R g4[4]) {  // Eq. (49): 1/(1 - 1/3) = 3/2
+  return R(1.5) * (g4[0] + g4[1] + g4[2] + g4[3]);
+}
+
+// Neighbourhood of a node from three rows (down, centre, up), each given as
+// columns (x-1, x, x+1), in velocity order.
+template <class R>
+__device__ inline void nine(const R d[3], const R c[3], const R u[3], R o[9]) {
+  o[0] = c[1];
+  o[1] = c[2];
+  o[2] = u[1];
+  o[3] = c[0];
+  o[4] = d[1];
+  o[5] = u[2];
+  o[6] = u[0];
+  o[7] = d[0];
+  o[8] = d[2];
+}
+
+// Wall ghosts of the stencils: phi mirrored, psi odd about the wall value.
+template <class R>
+__device__ inline void ghost_row(const R phc[3], const R psc[3], R psi_w, R phg[3], R psg[3]) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    phg[j] = phc[j];
+    psg[j] = R(2) * psi_w - psc[j];
+  }
+}
+
+// Ghost-row writes of a node on a wall row (or on an edge row of a
+// y-periodic box).  At a wall, the population that comes back along c_i to
+// node x is pulled at step t+1 from ghost column x - c_ix; in a periodic box
+// the ghost row receives the populations leaving the opposite edge.
+template <class S, class R, bool DEV>
+struct Ghosts {
+  const PopView<S, R, DEV>& D;
+  const KP<R>& kp;
+  int y;
+  Cols k;
+  __device__ inline void put(int q, uint32_t off, int yrow, R v) const { D.put(q, off, yrow, v); }
+  __device__ inline uint32_t top() const { return (uint32_t)(kp.ny + 1) * kp.pitch; }
+  // D2Q9 set starting at plane q0 (f or h): bounce-back at walls
+  __device__ inline void set9(int q0, const R x[9]) const {
+    if (kp.walls == WALL_PERIODIC) {
+      if (y == kp.ny - 1) { put(q0 + 2, k.c, -1, x[2]); put(q0 + 5, k.c, -1, x[5]); put(q0 + 6, k.c, -1, x[6]); }
+      if (y == 0) {
+        put(q0 + 4, top() + k.c, kp.ny, x[4]); put(q0 + 7, top() + k.c, kp.ny, x[7]);
+        put(q0 + 8, top() + k.c, kp.ny, x[8]);
+      }
+      return;
+    }
+    if (y == 0) { put(q0 + 2, k.c, -1, x[4]); put(q0 + 5, k.m, -1, x[7]); put(q0 + 6, k.p, -1, x[8]); }
+    if (y == kp.ny - 1) {
+      put(q0 + 4, top() + k.c, kp.ny, x[2]); put(q0 + 7, top() + k.p, kp.ny, x[5]);
+      put(q0 + 8, top() + k.m, kp.ny, x[6]);
+    }
+  }
+  // D2Q5 set: reflected value at the bottom and top walls given by the caller
+  __device__ inline void set5(int q0, const R x[5], R bottom, R topv) const {
+    if (kp.walls == WALL_PERIODIC) {
+      if (y == kp.ny - 1) put(q0 + 2, k.c, -1, x[2]);
+      if (y == 0) put(q0 + 4, top() + k.c, kp.ny, x[4]);
+      return;
+    }
+    if (y == 0) put(q0 + 2, k.c, -1, bottom);
+    if (y == kp.ny - 1) put(q0 + 4, top() + k.c, kp.ny, topv);
+  }
+};
+
+// Per-node update once the pulled populations and the phi/psi neighbourhood
+// are known: macroscopic quantities, Eq. (58), then the five collisions, each
+// stored as soon as it is done.  h and g (directions 1-4) of the node are
+// fetched through `hg` right before their collisions; they were pulled one row
+// earlier and parked in LDS.
+template <class S, class R, bool DEV, class HG>
+__device__ inline void update_node(const PopView<S, R, DEV>& D, R* __restrict__ jprev,
+                                   const KP<R>& kp,
+                                   int x, int y, Cols k, const R phi9[9], const R psi9[9],
+                                   R f[9], R p[5], R n[5], R g0, const HG& hg) {
+  const R P = p[0] + p[1] + p[2] + p[3] + p[4];
+  const R Q = n[0] + n[1] + n[2] + n[3] + n[4];
+  Macro<R> m;
+  macro(phi9, psi9, P, Q, f, kp, m);
+
+  const uint32_t o = (uint32_t)(y + 1) * kp.pitch + x;
+  const bool edge = y == 0 || y == kp.ny - 1;
+  const Ghosts<S, R, DEV> G{D, kp, y, k};
+  const bool ins = kp.walls == WALL_INSULATING;
+  const R third = R(1) / R(3);
+
+  {  // g: Eq. (44)-(47); psi = dpsi at the anode, 0 at the cathode
+    R g[5];
+    g[0] = g0;
+    hg.g4(g + 1);
+    collide_g(g, m.psi, poisson_source(m.rhoe, m.eps, m.geps, m.gpsi, kp), kp);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) D.put(QG + i, o, y, g[i]);
+    if (edge) G.set5(QG, g, -g[4] + third * kp.dpsi, -g[2]);
+  }
+
+  collide_ion(p, m.cp, m.mup, m.itau_p, kp.mask_p, R(-1), m, kp);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) D.put(QP + i, o, y, p[i]);
+  // anode: c+ = 0; cathode: d c+/dn = 0 (wall value = node value)
+  if (edge) G.set5(QP, p, ins ? p[4] : -p[4], ins ? p[2] : -p[2] + third * m.cp);
+
+  collide_ion(n, m.cm, m.mum, m.itau_n, kp.mask_n, R(1), m, kp);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) D.put(QN + i, o, y, n[i]);
+  // anode: d c-/dn = 0; cathode: c- = 0
+  if (edge) G.set5(QN, n, ins ? n[4] : -n[4] + third * m.cm, ins ? n[2] : -n[2]);
+
+  {  // h: Eq. (27)-(32), with d(phi u)/dt of Eq. (58)
+    const uint32_t jo = (uint32_t)y * kp.pitch + x;
+    const uint32_t jpl = (uint32_t)kp.ny * kp.pitch;
+    const R Jx = m.phi * m.u[0], Jy = m.phi * m.u[1];
+    const R dJ[2] = {Jx - *elem(jprev, jo), Jy - *elem(jprev, jpl + jo)};
+    *elem(jprev, jo) = Jx;
+    *elem(jprev, jpl + jo) = Jy;
+    R h[9];
+    hg.h9(h);
+    collide_h(h, m, dJ, kp);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) D.put(QH + i, o, y, h[i]);
+    if (edge) G.set9(QH, h);
+  }
+
+  collide_f(f, m, kp);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) D.put(QF + i, o, y, f[i]);
+  if (edge) G.set9(QF, f);
+}
+
+// h and directions 1-4 of g of one node held in registers.
+template <class R>
+struct HGRegs {
+  const R* h;
+  const R* g;
+  __device__ inline void h9(R o[9]) const {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) o[i] = h[i];
+  }
+  __device__ inline void g4(R o[4]) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = g[i];
+  }
+};
+
+// ... or parked in LDS, one column per lane: [13][64].
+template <class R>
+struct HGLds {
+  const R (*s)[TILE_W];
+  int lane;
+  __device__ inline void h9(R o[9]) const {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) o[i] = s[i][lane];
+  }
+  __device__ inline void g4(R o[4]) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = s[9 + i][lane];
+  }
+};
+
+// The fused sweep.  grid = nstrips * nbands workgroups of 64 lanes.
+template <class S, class R, bool DEV>
+__global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
+                                              const S* __restrict__ srcg,
+                                              S* __restrict__ dst, R* __restrict__ jprev,
+                                              const KP<R> kp, int tile_rows, int nstrips,
+                                              int nbands, int xcd_chunk, int band_major) {
+  __shared__ R s_phi[RING][TILE_W + 2];
+  __shared__ R s_psi[RING][TILE_W + 2];
+  __shared__ R s_pull[2][13][TILE_W];  // pulled h and g1-4 of a row, by row parity
+
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous run of tiles (whole column strips) so that the halo rows and
+  // columns that neighbouring tiles share stay in one L2.
+  // Within a chunk, tiles go band by band across all strips, so that the
+  // workgroups running together on an XCD hold neighbouring strips of the same
+  // rows and the cache lines they share (pull shifts, halo columns) are
+  // fetched from HBM once.
+  int t = blockIdx.x;
+  if (xcd_chunk > 0) t = (t & 7) * xcd_chunk + (t >> 3);
+  int strip, band;
+  if (band_major) {
+    band = t / nstrips;
+    strip = t - band * nstrips;
+  } else {
+    strip = t / nbands;
+    band = t - strip * nbands;
+  }
+  const int nx = kp.nx, ny = kp.ny;
+  const uint32_t pitch = kp.pitch;
+  const int x0 = strip * TILE_W, y0 = band * tile_rows;
+  const int w = min(TILE_W, nx - x0);
+  const int lane = threadIdx.x;
+  const bool valid = lane < w;
+  const int x = x0 + (valid ? lane : 0);
+  const Cols k = cols_of(x, nx);
+  const int yend = min(y0 + tile_rows, ny);
+  const bool periodic = kp.walls == WALL_PERIODIC;
+  const PopView<S, R, DEV> Ph{make_rsrc(src, kp.pop_bytes), 0, &kp};
+  const PopView<S, R, DEV> Pg{make_rsrc(srcg, kp.g_bytes), QG, &kp};
+  const PopView<S, R, DEV> D{make_rsrc(dst, kp.pop_bytes), 0, &kp};
+
+  // halo column handled by lanes 0 (left) and 1 (right)
+  const int xh = lane == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + w == nx ? 0 : x0 + w);
+  const Cols kh = cols_of(xh, nx);
+  const int kcol = lane == 0 ? 0 : w + 1;
+
+  auto slot = [&](int yy) { return (yy - y0 + 1) % RING; };
+  // phi, psi of row yy into the ring; the lane's own pulls are parked in LDS
+  auto ring_row = [&](int yy) {
+    const int ys = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+    const int sl = slot(yy);
+    if (lane < 2) {
+      R hh[9], gg[4];
+      pull9(Ph, QH, kh, ys, pitch, hh);
+      pull4(Pg, 0, kh, ys, pitch, gg);
+      s_phi[sl][kcol] = sum9(hh);
+      s_psi[sl][kcol] = psi_of(gg);
+    }
+    if (valid) {
+      R h[9], g4[4];
+      pull9(Ph, QH, k, ys, pitch, h);
+      pull4(Pg, 0, k, ys, pitch, g4);
+      s_phi[sl][lane + 1] = sum9(h);
+      s_psi[sl][lane + 1] = psi_of(g4);
+      const int b = (yy - y0 + 2) & 1;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s_pull[b][i][lane] = h[i];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s_pull[b][9 + i][lane] = g4[i];
+    }
+  };
+
+  if (y0 > 0 || periodic) ring_row(y0 - 1);
+  ring_row(y0);
+
+  for (int y = y0; y < yend; ++y) {
+    const bool up = y + 1 < ny || periodic;
+    const bool down = y > 0 || periodic;
+    if (up) ring_row(y + 1);
+    __syncthreads();
+    if (valid) {
+      const int c = lane + 1, sc = slot(y);
+      R phC[3] = {s_phi[sc][c - 1], s_phi[sc][c], s_phi[sc][c + 1]};
+      R psC[3] = {s_psi[sc][c - 1], s_psi[sc][c], s_psi[sc][c + 1]};
+      R phU[3], psU[3], phD[3], psD[3];
+      if (up) {
+        const int su = slot(y + 1);
+        phU[0] = s_phi[su][c - 1]; phU[1] = s_phi[su][c]; phU[2] = s_phi[su][c + 1];
+        psU[0] = s_psi[su][c - 1]; psU[1] = s_psi[su][c]; psU[2] = s_psi[su][c + 1];
+      } else {
+        ghost_row(phC, psC, R(0), phU, psU);
+      }
+      if (down) {
+        const int sd = slot(y - 1);
+        phD[0] = s_phi[sd][c - 1]; phD[1] = s_phi[sd][c]; phD[2] = s_phi[sd][c + 1];
+        psD[0] = s_psi[sd][c - 1]; psD[1] = s_psi[sd][c]; psD[2] = s_psi[sd][c + 1];
+      } else {
+        ghost_row(phC, psC, kp.dpsi, phD, psD);
+      }
+      R phi9[9], psi9[9];
+      nine(phD, phC, phU, phi9);
+      nine(psD, psC, psU, psi9);
+
+      R f[9], p[5], n[5], t4[4];
+      pull9(Ph, QF, k, y, pitch, f);
+      const uint32_t r0 = (uint32_t)(y + 1) * pitch;
+      p[0] = Ph.at(QP, r0 + x, y);
+      n[0] = Ph.at(QN, r0 + x, y);
+      const R g0 = Pg.at(0, r0 + x, y);
+      pull4(Ph, QP, k, y, pitch, t4);
+      p[1] = t4[0]; p[2] = t4[1]; p[3] = t4[2]; p[4] = t4[3];
+      pull4(Ph, QN, k, y, pitch, t4);
+      n[1] = t4[0]; n[2] = t4[1]; n[3] = t4[2]; n[4] = t4[3];
+      const HGLds<R> hg{s_pull[(y - y0 + 2) & 1], lane};
+      update_node<S, R, DEV>(D, jprev, kp, x, y, k, phi9, psi9, f, p, n, g0, hg);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Helpers outside the hot loop.
+// ---------------------------------------------------------------------------
+
+// phi, psi and rho_e = e0 (sum p - sum n) of every node into compact planes.
+template <class S, class R, bool DEV>
+__global__ void k_moments(const S* __restrict__ src, const S* __restrict__ srcg,
+                          R* __restrict__ mom, const KP<R> kp) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= kp.nx) return;
+  const PopView<S, R, DEV> Ph{make_rsrc(src, kp.pop_bytes), 0, &kp};
+  const PopView<S, R, DEV> Pg{make_rsrc(srcg, kp.g_bytes), QG, &kp};
+  const Cols k = cols_of(x, kp.nx);
+  R h[9], g4[4], t4[4];
+  pull9(Ph, QH, k, y, kp.pitch, h);
+  pull4(Pg, 0, k, y, kp.pitch, g4);
+  const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
+  pull4(Ph, QP, k, y, kp.pitch, t4);
+  const R P = Ph.at(QP, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  pull4(Ph, QN, k, y, kp.pitch, t4);
+  const R Q = Ph.at(QN, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
+  mom[c] = sum9(h);
+  mom[np + c] = psi_of(g4);
+  mom[2 * np + c] = kp.q * (P - Q);
+}
+
+// phi / psi neighbourhood of (x, y) from the compact moment planes.
+template <class R>
+__device__ inline void hood(const R* __restrict__ mom, const KP<R>& kp, int x, int y,
+                            R phi9[9], R psi9[9]) {
+  const long long np = (long long)kp.nx * kp.ny;
+  const Cols k = cols_of(x, kp.nx);
+  const int cols[3] = {k.m, k.c, k.p};
+  R ph[3][3], ps[3][3];  // [row: down, centre, up][col]
+  const bool periodic = kp.walls == WALL_PERIODIC;
+  for (int r = 0; r < 3; ++r) {
+    int yy = y + r - 1;
+    if (yy < 0 || yy >= kp.ny) {
+      if (!periodic) continue;
+      yy = (yy + kp.ny) % kp.ny;
+    }
+    for (int j = 0; j < 3; ++j) {
+      ph[r][j] = mom[(long long)yy * kp.nx + cols[j]];
+      ps[r][j] = mom[np + (long long)yy * kp.nx + cols[j]];
+    }
+  }
+  if (!periodic) {
+    if (y == 0) ghost_row(ph[1], ps[1], kp.dpsi, ph[0], ps[0]);
+    if (y == kp.ny - 1) ghost_row(ph[1], ps[1], R(0), ph[2], ps[2]);
+  }
+  nine(ph[0], ph[1], ph[2], phi9);
+  nine(ps[0], ps[1], ps[2], psi9);
+}
+
+// Macroscopic fields (FP64 output, [10][ny][nx]).
+template <class S, class R, bool DEV>
+__global__ void k_fields(const S* __restrict__ src, const S* __restrict__ srcg,
+                         const R* __restrict__ mom, double* __restrict__ out, const KP<R> kp) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= kp.nx) return;
+  const PopView<S, R, DEV> Ph{make_rsrc(src, kp.pop_bytes), 0, &kp};
+  const Cols k = cols_of(x, kp.nx);
+  R phi9[9], psi9[9], f[9], t4[4];
+  hood(mom, kp, x, y, phi9, psi9);
+  pull9(Ph, QF, k, y, kp.pitch, f);
+  const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
+  pull4(Ph, QP, k, y, kp.pitch, t4);
+  const R P = Ph.at(QP, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  pull4(Ph, QN, k, y, kp.pitch, t4);
+  const R Q = Ph.at(QN, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  Macro<R> m;
+  macro(phi9, psi9, P, Q, f, kp, m);
+  const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
+  out[0 * np + c] = m.phi;
+  out[1 * np + c] = m.psi;
+  out[2 * np + c] = m.cp;
+  out[3 * np + c] = m.cm;
+  out[4 * np + c] = m.rhoe;
+  out[5 * np + c] = m.u[0];
+  out[6 * np + c] = m.u[1];
+  out[7 * np + c] = m.p;
+  out[8 * np + c] = m.E[0];
+  out[9 * np + c] = m.E[1];
+}
+
+// One g-only sweep (phi and rho_e held fixed): reads g from srcg, writes dstg.
+template <class S, class R, bool DEV>
+__global__ void k_poisson(const S* __restrict__ srcg, S* __restrict__ dstg,
+                          const R* __restrict__ mom, const KP<R> kp) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= kp.nx) return;
+  const PopView<S, R, DEV> Pg{make_rsrc(srcg, kp.g_bytes), QG, &kp};
+  const Cols k = cols_of(x, kp.nx);
+  R phi9[9], psi9[9], g4[4];
+  hood(mom, kp, x, y, phi9, psi9);
+  const long long np = (long long)kp.nx * kp.ny;
+  const long long c = (long long)y * kp.nx + x;
+  // psi of the node itself comes from its own pulled g (the plane holds the
+  // same value)
+  pull4(Pg, 0, k, y, kp.pitch, g4);
+  const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
+  R g[5] = {Pg.at(0, r0 + x, y), g4[0], g4[1], g4[2], g4[3]};
+  const R phi = phi9[0];
+  const R eps = phi * kp.deps + kp.eps_v;
+  R gphi[2], gpsi[2];
+  grad_lap<R>(phi9, gphi, nullptr);
+  grad_lap<R>(psi9, gpsi, nullptr);
+  const R geps[2] = {kp.deps * gphi[0], kp.deps * gphi[1]};
+  collide_g(g, psi9[0], poisson_source(mom[2 * np + c], eps, geps, gpsi, kp), kp);
+  const uint32_t o = (uint32_t)(y + 1) * kp.pitch + x;
+  // dstg points at the g0 plane (planes relative to the g set)
+  const PopView<S, R, DEV> DG{make_rsrc(dstg, kp.g_bytes), QG, &kp};
+  auto W = [&](int q, uint32_t off, int yrow, R v) { DG.put(q - QG, off, yrow, v); };
+  for (int i = 0; i < 5; ++i) W(QG + i, o, y, g[i]);
+  const uint32_t top = (uint32_t)(kp.ny + 1) * kp.pitch;
+  if (kp.walls == WALL_PERIODIC) {
+    if (y == kp.ny - 1) W(QG + 2, k.c, -1, g[2]);
+    if (y == 0) W(QG + 4, top + k.c, kp.ny, g[4]);
+  } else {
+    if (y == 0) W(QG + 2, k.c, -1, -g[4] + kp.dpsi / R(3));
+    if (y == kp.ny - 1) W(QG + 4, top + k.c, kp.ny, -g[2]);
+  }
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output number n (n >= 1) of the
+// generator started at `seed`.
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + n * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ inline double unit_noise(uint64_t seed, uint64_t n) {
+  return 2.0 * ((double)(splitmix64(seed, n) >> 11) * 0x1.0p-53) - 1.0;
+}
+
+struct InitSpec {
+  // droplet
+  double xc, yc, radius, noise;
+  uint64_t seed;
+  // or host-provided fields (device copies, [ny][nx]); ux/uy may be null
+  const double *phi, *cp, *cm, *psi, *ux, *uy;
+};
+
+// Equilibrium initial state.  The population arriving at node (x, y) along
+// c_i at the first step is the equilibrium there, so it is written where
+// that node pulls it from: row y - c_iy, column x - c_ix.
+template <class S, class R, bool DEV>
+__global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, const KP<R> kp,
+                       const InitSpec sp) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= kp.nx) return;
+  const long long c = (long long)y * kp.nx + x;
+  double phi, cp, cm, psi, ux = 0.0, uy = 0.0;
+  if (sp.phi) {
+    phi = sp.phi[c];
+    cp = sp.cp[c];
+    cm = sp.cm[c];
+    psi = sp.psi[c];
+    if (sp.ux) ux = sp.ux[c];
+    if (sp.uy) uy = sp.uy[c];
+  } else {
+    const double dx = x - sp.xc, dy = y - sp.yc;
+    const double r = sqrt(dx * dx + dy * dy);
+    phi = 0.5 * (1.0 + tanh(2.0 * (sp.radius - r) / (double)kp.W));
+    const double c0 = sqrt((double)kp.c0sq);
+    cp = c0 * (1.0 + sp.noise * unit_noise(sp.seed, 2 * (uint64_t)c + 1));
+    cm = c0 * (1.0 + sp.noise * unit_noise(sp.seed, 2 * (uint64_t)c + 2));
+    psi = kp.walls == WALL_PERIODIC ? 0.0 : (double)kp.dpsi * (kp.ny - 0.5 - y) / kp.ny;
+  }
+  const double rho = phi * (double)kp.drho + (double)kp.rho_v;
+  const double uu = ux * ux + uy * uy;
+  const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const double w9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  const double w5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+  const PopView<S, R, DEV> D{make_rsrc(dst, kp.pop_bytes), 0, &kp};
+  auto put = [&](int q, int i, double v) {
+    int xs = x - cx[i];
+    xs = xs < 0 ? xs + kp.nx : (xs >= kp.nx ? xs - kp.nx : xs);
+    const int ys = y - cy[i];
+    D.put(q, (uint32_t)(ys + 1) * kp.pitch + xs, ys, (R)v);
+  };
+  for (int i = 0; i < 9; ++i) {
+    const double cu = cx[i] * ux + cy[i] * uy;
+    // f: pressure-based equilibrium with p = 0
+    put(QF + i, i, rho * w9[i] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    put(QH + i, i, w9[i] * phi * (1.0 + 3.0 * cu));
+  }
+  for (int i = 0; i < 5; ++i) {
+    const double cu = cx[i] * ux + cy[i] * uy;
+    put(QP + i, i, w5[i] * cp * (1.0 + 3.0 * cu));
+    put(QN + i, i, w5[i] * cm * (1.0 + 3.0 * cu));
+    put(QG + i, i, i == 0 ? -2.0 / 3.0 * psi : psi / 6.0);
+  }
+  const long long jo = (long long)y * kp.pitch + x;
+  jprev[jo] = (R)(phi * ux);
+  jprev[(long long)kp.ny * kp.pitch + jo] = (R)(phi * uy);
+}
+
+// FP64 sums of one row: [phi, rho_e, sum p, sum n, phi x, phi y, nonfinite].
+// One workgroup per row, fixed-shape tree reduction: the result depends on
+// nx and ny only.
+constexpr int NSUM = 7;
+template <class S, class R, bool DEV>
+__global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
+                                                  const S* __restrict__ srcg,
+                                                  double* __restrict__ part, const KP<R> kp) {
+  __shared__ double sh[NSUM][256];
+  const int y = blockIdx.x, t = threadIdx.x;
+  const PopView<S, R, DEV> Ph{make_rsrc(src, kp.pop_bytes), 0, &kp};
+  const PopView<S, R, DEV> Pg{make_rsrc(srcg, kp.g_bytes), QG, &kp};
+  double acc[NSUM] = {0, 0, 0, 0, 0, 0, 0};
+  for (int x = t; x < kp.nx; x += 256) {
+    const Cols k = cols_of(x, kp.nx);
+    R h[9], t4[4], g4[4];
+    pull9(Ph, QH, k, y, kp.pitch, h);
+    const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
+    pull4(Ph, QP, k, y, kp.pitch, t4);
+    const double P = (double)Ph.at(QP, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+    pull4(Ph, QN, k, y, kp.pitch, t4);
+    const double Q = (double)Ph.at(QN, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+    pull4(Pg, 0, k, y, kp.pitch, g4);
+    const double phi = (double)sum9(h);
+    const double psi = (double)psi_of(g4);
+    acc[0] += phi;
+    acc[1] += (double)kp.q * (P - Q);
+    acc[2] += P;
+    acc[3] += Q;
+    acc[4] += phi * x;
+    acc[5] += phi * y;
+    if (!(isfinite(phi) && isfinite(P) && isfinite(Q) && isfinite(psi))) acc[6] += 1.0;
+  }
+  for (int j = 0; j < NSUM; ++j) sh[j][t] = acc[j];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s)
+      for (int j = 0; j < NSUM; ++j) sh[j][t] += sh[j][t + s];
+    __syncthreads();
+  }
+  if (t < NSUM) part[(long long)y * NSUM + t] = sh[t][0];
+}
+
+__global__ void k_sum_rows(const double* __restrict__ part, int ny, double* __restrict__ out) {
+  if (threadIdx.x < NSUM) {
+    double a = 0.0;
+    for (int y = 0; y < ny; ++y) a += part[(long long)y * NSUM + threadIdx.x];
+    out[threadIdx.x] = a;
+  }
+}
+
+// Plain copy through buffer descriptors (measurement helper).  Each lane
+// moves W bytes per iteration; the grid strides over the buffer.
+template <int W>
+__global__ __launch_bounds__(256) void k_copy(const void* __restrict__ src,
+                                              void* __restrict__ dst, uint32_t bytes) {
+  const Rsrc rs = make_rsrc(src, bytes), rd = make_rsrc(dst, bytes);
+  const uint32_t stride = gridDim.x * blockDim.x * W;
+  for (uint32_t o = (blockIdx.x * blockDim.x + threadIdx.x) * W; o < bytes; o += stride) {
+    if (W == 4) {
+      const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(v, rd, o, 0, LBM_STORE_POLICY);
+    } else {
+      typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(v, rd, o, 0, LBM_STORE_POLICY);
+    }
+  }
+}
+
+}  // namespace lbm
