@@ -53,14 +53,14 @@ typedef int32_t lbm_status;
 #define LBM_ESTATE (-5)     /* call out of order (e.g. step before init) */
 #define LBM_ERANGE (-6)     /* caller buffer too small */
 
-/* Storage precision of the populations (arithmetic is FP64 for LBM_FP64 and
- * FP32 otherwise). */
-#define LBM_FP64 0
-#define LBM_FP32 1
-#define LBM_FP16_STORE 2 /* binary16 deviations from a reference state */
-#define LBM_BF16_STORE 3 /* bfloat16 deviations from a reference state */
-#define LBM_FP32_DEV 4   /* FP32 deviations from a reference state, FP32 arithmetic */
-#define LBM_FP32_F64 5   /* FP32 deviations from a reference state, FP64 arithmetic */
+/* Storage and arithmetic precision.  Populations are always stored as
+ * deviations from a fixed reference state (h: w_i/2, p and n: wbar_i c0, g:
+ * the equilibrium of the uncharged linear potential, f: 0). */
+#define LBM_FP64 0       /* FP64 storage, FP64 arithmetic */
+#define LBM_FP32 1       /* FP32 storage, FP32 arithmetic */
+#define LBM_FP16_STORE 2 /* binary16 storage, FP32 arithmetic */
+#define LBM_BF16_STORE 3 /* bfloat16 storage, FP32 arithmetic */
+#define LBM_FP32_F64 5   /* FP32 storage, FP64 arithmetic */
 
 /* Boundary conditions in y. */
 #define LBM_ELECTRODES 0 /* Eq. (64a): anode/cathode with ion conditions of Sec. 5.1 */
@@ -88,7 +88,7 @@ typedef int32_t lbm_status;
 typedef struct {
   int32_t nx, ny;          /* grid; nx >= 2, ny >= 2 */
   int32_t precision;       /* LBM_FP64, LBM_FP32, LBM_FP16_STORE, LBM_BF16_STORE,
-                              LBM_FP32_DEV, LBM_FP32_F64 */
+                              LBM_FP32_F64 */
   int32_t walls;           /* LBM_ELECTRODES, LBM_INSULATING, LBM_PERIODIC */
   int32_t reaction;        /* 1: R of Eq. (5)-(6); 0: R = 0 (leaky-dielectric limit, Sec. 5.2) */
   int32_t poisson_form;    /* 1: source (rho_e + grad eps . grad psi)/eps, whose steady

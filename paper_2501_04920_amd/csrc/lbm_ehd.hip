@@ -37,7 +37,6 @@ size_t elem_size(int prec) {
   switch (prec) {
     case LBM_FP64: return 8;
     case LBM_FP32: return 4;
-    case LBM_FP32_DEV:
     case LBM_FP32_F64: return 4;
     case LBM_FP16_STORE:
     case LBM_BF16_STORE: return 2;
@@ -45,6 +44,8 @@ size_t elem_size(int prec) {
   }
 }
 size_t arith_size(int prec) { return (prec == LBM_FP64 || prec == LBM_FP32_F64) ? 8 : 4; }
+// width of the rest population of h (see RestOf)
+size_t rest_size(int prec) { return elem_size(prec) == 2 ? 4 : 8; }
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
@@ -94,6 +95,7 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.pitch = h->pitch;
   k.walls = p.walls;
   k.plane = (uint32_t)h->plane;
+  k.cells = (uint32_t)((long long)p.ny * h->pitch);
   k.pop_bytes = (uint32_t)(NPOP * h->plane * (long long)elem_size(p.precision));
   k.g_bytes = (uint32_t)(5 * h->plane * (long long)elem_size(p.precision));
   k.reaction = p.reaction;
@@ -115,6 +117,7 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.dmu = (R)(p.mu_v * p.mu_r - p.mu_v);
   k.m_ratio = (R)p.m_ratio;
   k.three_vth = (R)(3.0 * p.v_th);
+  k.c0 = (R)p.c0;
   k.c0sq = (R)(p.c0 * p.c0);
   k.q = (R)p.q;
   k.gve = (R)(p.gamma_v * p.eps_v);
@@ -127,18 +130,41 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.inv_tau_g = (R)(1.0 / (0.5 + 3.0 * p.theta));
   k.theta_src = (R)(p.poisson_norm ? p.theta * 1.5 : p.theta);  // 1/(1 - wbar_0) = 3/2
   k.dpsi = (R)p.dpsi;
+  const bool per = p.walls == LBM_PERIODIC;
+  k.psi_slope = per ? (R)0 : (R)(-p.dpsi / p.ny);
+  k.dr_g = per ? (R)0 : (R)(p.dpsi / p.ny / 6.0);
   k.force_x = (R)p.force_x;
   k.force_y = (R)p.force_y;
-  k.ref_p = (R)p.c0;
-  k.ref_n = (R)p.c0;
+  // binary16: keep the deviations of each set well inside the normal range
+  // (largest magnitudes: f ~ 1, h ~ 1/4, ions ~ c0, g ~ dpsi)
+  for (int i = 0; i < 5; ++i) k.sc[i] = k.isc[i] = (R)1;
+  if (p.precision == LBM_FP16_STORE) {
+    auto pow2_below = [](double v) { return std::ldexp(1.0, (int)std::floor(std::log2(v))); };
+    const double c0 = std::max(std::fabs(p.c0), 1e-6);
+    const double sets[5] = {4096.0, 1.0, pow2_below(4096.0 / c0), pow2_below(4096.0 / c0),
+                            pow2_below(4096.0 / std::max(std::fabs(p.dpsi), 1e-3))};
+    for (int i = 0; i < 5; ++i) {
+      k.sc[i] = (R)sets[i];
+      k.isc[i] = (R)(1.0 / sets[i]);
+    }
+  }
   return k;
 }
 
 // Launch helpers, one instantiation per storage form.
-template <class S, class R, bool DEV>
+template <class S, class R>
 struct Form {
+  typedef typename RestOf<S>::type T0;
   static S* buf(lbm_ehd* h, int i) { return static_cast<S*>(h->pop[i]); }
   static R* jp(lbm_ehd* h) { return static_cast<R*>(h->aux); }
+  // rest population of h, two planes after the two (phi u) planes; like
+  // the populations it ping-pongs between time levels (neighbouring
+  // workgroups read it for their phi halo)
+  static T0* h0(lbm_ehd* h, int i) {
+    return reinterpret_cast<T0*>(static_cast<char*>(h->aux) +
+                                 2 * (size_t)h->P.ny * h->pitch * sizeof(R)) +
+           (size_t)i * h->P.ny * h->pitch;
+  }
 
   static lbm_status sweep(lbm_ehd* h, const S* srcg) {
     const KP<R> kp = make_kp<R>(h);
@@ -149,8 +175,9 @@ struct Form {
     const int chunk = (nb % 8 == 0) ? nb / 8 : 0;
     const S* src = buf(h, h->cur);
     if (!srcg) srcg = src + (long long)QG * h->plane;
-    hipLaunchKernelGGL((k_sweep<S, R, DEV>), dim3(nb), dim3(TILE_W), 0, h->stream, src, srcg,
-                       buf(h, 1 - h->cur), jp(h), kp, tr, nstrips, nbands, chunk,
+    hipLaunchKernelGGL((k_sweep<S, R, T0>), dim3(nb), dim3(TILE_W), 0, h->stream, src, srcg,
+                       buf(h, 1 - h->cur), jp(h), h0(h, h->cur), h0(h, 1 - h->cur), kp, tr,
+                       nstrips, nbands, chunk,
                        h->band_major);
     HIP_TRY(hipGetLastError());
     h->cur = 1 - h->cur;
@@ -163,8 +190,8 @@ struct Form {
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
     if (!srcg) srcg = src + (long long)QG * h->plane;
-    hipLaunchKernelGGL((k_moments<S, R, DEV>), grid2(h), dim3(64), 0, h->stream, src, srcg,
-                       static_cast<R*>(h->mom), kp);
+    hipLaunchKernelGGL((k_moments<S, R, T0>), grid2(h), dim3(64), 0, h->stream, src, srcg,
+                       h0(h, h->cur), static_cast<R*>(h->mom), kp);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -180,7 +207,7 @@ struct Form {
       lbm_status st = moments(h, from);
       if (st) return st;
       S* to = from == gA ? gB : gA;
-      hipLaunchKernelGGL((k_poisson<S, R, DEV>), grid2(h), dim3(64), 0, h->stream, from, to,
+      hipLaunchKernelGGL((k_poisson<S, R>), grid2(h), dim3(64), 0, h->stream, from, to,
                          static_cast<const R*>(h->mom), kp);
       HIP_TRY(hipGetLastError());
       from = to;
@@ -217,8 +244,8 @@ struct Form {
   static lbm_status init(lbm_ehd* h, const InitSpec& sp) {
     const KP<R> kp = make_kp<R>(h);
     h->cur = 0;
-    hipLaunchKernelGGL((k_init<S, R, DEV>), grid2(h), dim3(64), 0, h->stream, buf(h, 0), jp(h),
-                       kp, sp);
+    hipLaunchKernelGGL((k_init<S, R, T0>), grid2(h), dim3(64), 0, h->stream, buf(h, 0), jp(h),
+                       h0(h, 0), kp, sp);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -228,9 +255,8 @@ struct Form {
     if (st) return st;
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
-    hipLaunchKernelGGL((k_fields<S, R, DEV>), grid2(h), dim3(64), 0, h->stream, src,
-                       src + (long long)QG * h->plane, static_cast<const R*>(h->mom), h->fld,
-                       kp);
+    hipLaunchKernelGGL((k_fields<S, R>), grid2(h), dim3(64), 0, h->stream, src,
+                       static_cast<const R*>(h->mom), h->fld, kp);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -238,8 +264,8 @@ struct Form {
   static lbm_status sums(lbm_ehd* h) {
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
-    hipLaunchKernelGGL((k_row_sums<S, R, DEV>), dim3(h->P.ny), dim3(256), 0, h->stream, src,
-                       src + (long long)QG * h->plane, h->part, kp);
+    hipLaunchKernelGGL((k_row_sums<S, R, T0>), dim3(h->P.ny), dim3(256), 0, h->stream, src,
+                       src + (long long)QG * h->plane, h0(h, h->cur), h->part, kp);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, h->part, h->P.ny, h->red);
     HIP_TRY(hipGetLastError());
@@ -250,12 +276,11 @@ struct Form {
 template <class F>
 lbm_status dispatch(lbm_ehd* h, F&& fn) {
   switch (h->P.precision) {
-    case LBM_FP64: return fn(Form<double, double, false>{});
-    case LBM_FP32: return fn(Form<float, float, false>{});
-    case LBM_FP32_DEV: return fn(Form<float, float, true>{});
-    case LBM_FP32_F64: return fn(Form<float, double, true>{});
-    case LBM_FP16_STORE: return fn(Form<__half, float, true>{});
-    case LBM_BF16_STORE: return fn(Form<__hip_bfloat16, float, true>{});
+    case LBM_FP64: return fn(Form<double, double>{});
+    case LBM_FP32: return fn(Form<float, float>{});
+    case LBM_FP32_F64: return fn(Form<float, double>{});
+    case LBM_FP16_STORE: return fn(Form<__half, float>{});
+    case LBM_BF16_STORE: return fn(Form<__hip_bfloat16, float>{});
   }
   return fail(LBM_EINVAL, "unknown precision");
 }
@@ -307,6 +332,14 @@ void free_scratch(lbm_ehd* h) {
     (void)hipFree(h->pop[1]);
     (void)hipFree(h->aux);
   }
+}
+
+void fill_init_params(const lbm_ehd* h, InitSpec* sp) {
+  sp->W = h->P.W;
+  sp->c0 = h->P.c0;
+  sp->dpsi = h->P.dpsi;
+  sp->rho_v = h->P.rho_v;
+  sp->drho = h->P.rho_v * h->P.rho_r - h->P.rho_v;
 }
 
 // Length between the two phi = 1/2 crossings of a profile, walking out from
@@ -412,7 +445,9 @@ lbm_status lbm_ehd_required_bytes(const lbm_ehd_params* p, size_t* pop_bytes,
   if (st) return st;
   const size_t pitch = pitch_of(p->nx);
   if (pop_bytes) *pop_bytes = (size_t)NPOP * (p->ny + 2) * pitch * elem_size(p->precision);
-  if (aux_bytes) *aux_bytes = 2 * (size_t)p->ny * pitch * arith_size(p->precision);
+  if (aux_bytes)
+    *aux_bytes =
+        (size_t)p->ny * pitch * (2 * arith_size(p->precision) + 2 * rest_size(p->precision));
   return LBM_OK;
 }
 
@@ -495,6 +530,7 @@ lbm_status lbm_ehd_init_droplet(lbm_ehd* h, double xc, double yc, double radius,
   sp.radius = radius;
   sp.noise = noise;
   sp.seed = seed;
+  fill_init_params(h, &sp);
   lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::init(h, sp); });
   if (st) return st;
   h->step = 0;
@@ -522,6 +558,7 @@ lbm_status lbm_ehd_init_fields(lbm_ehd* h, const double* phi, const double* cp,
   sp.psi = h->upl + 3 * nc;
   sp.ux = ux ? h->upl + 4 * nc : nullptr;
   sp.uy = uy ? h->upl + 5 * nc : nullptr;
+  fill_init_params(h, &sp);
   lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::init(h, sp); });
   if (st) return st;
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -665,7 +702,9 @@ lbm_status lbm_ehd_stream_copy(const void* src, void* dst, size_t bytes, void* s
 double lbm_ehd_bytes_per_lup(int32_t precision) {
   const size_t s = elem_size(precision);
   if (!s) return 0.0;
-  return 2.0 * NPOP * s + 2.0 * 2.0 * arith_size(precision);
+  // 32 moving or pulled planes, the rest population of h and (phi u)(t-1),
+  // each read once and written once
+  return 2.0 * (NPOP - 1) * s + 2.0 * rest_size(precision) + 2.0 * 2.0 * arith_size(precision);
 }
 
 }  // extern "C"

@@ -1,17 +1,28 @@
-// lbm_ehd_device.hpp -- device code of the fused five-equation sweep.
+// lbm_ehd_device.hpp -- device arithmetic of the five-equation sweep.
 //
 // Method: Zheng, Wang, Xiong, Huang, Luo, "Phase-field lattice Boltzmann
 // method for two-phase electrohydrodynamic flows induced by Onsager-Wien
 // effect", arXiv 2501.04920, Sec. 4.
 //
-// Memory layout (structure of arrays, one plane per population):
-//   plane q of buffer B holds, at row r = y + 1 and column x, the
+// Memory layout (structure of arrays, one plane per population; the rest
+// population of h lives in the aux buffer, see RestOf):
+//   plane q of a buffer holds, at row r = y + 1 and column x, the
 //   post-collision population q of node (x, y) from the previous step, so
 //   that the population arriving at (x, y) along c_q is read ("pulled") at
 //   row y - c_qy + 1, column (x - c_qx) mod nx.  Rows 0 and ny + 1 are ghost
 //   rows: at a wall they hold the reflected populations written by the wall
 //   node itself, in a y-periodic box the populations leaving the opposite
 //   edge.  33 planes: f 0-8, h 9-17, p 18-22, n 23-27, g 28-32.
+//
+// Deviation form: every plane stores x_q - ref_q with a fixed reference
+//   f: 0;  h: w_q / 2;  p, n: wbar_q c0;
+//   g: the equilibrium of the uncharged linear potential of the stored row,
+//      psi_lin(y) = dpsi (ny - 1/2 - y) / ny (0 in a y-periodic box).
+// All arithmetic works on deviations: phi' = phi - 1/2, P' = sum p - c0,
+// Q' = sum n - c0, psi' = psi - psi_lin.  The charge density q (P' - Q') and
+// the reaction (solved for R directly) never subtract two numbers near c0,
+// which keeps FP32 and 16-bit storage accurate.  Every step is the same
+// arithmetic as the paper's up to rounding.
 //
 // Velocity order (both lattices share the first five): 0 rest, 1 +x, 2 +y,
 // 3 -x, 4 -y, 5 (+x,+y), 6 (-x,+y), 7 (-x,-y), 8 (+x,-y)  (Eq. 25-26).
@@ -40,21 +51,28 @@ constexpr int RING = 5;     // rows of phi/psi kept in LDS
 template <class R>
 struct KP {
   int nx, ny, pitch, walls;
-  uint32_t plane;   // elements per population plane, (ny + 2) * pitch
+  uint32_t plane;               // elements per population plane, (ny + 2) * pitch
+  uint32_t cells;               // elements per aux plane, ny * pitch
   uint32_t pop_bytes, g_bytes;  // sizes of a population buffer and of a g set
   int reaction, poisson_form, flow, ion_force;
   int mask_f, mask_h, mask_p, mask_n, mask_g;
   R rho_v, drho, eta_v, deta, eps_v, deps, mu_v, dmu, m_ratio;
   R three_vth;       // 3 k_B T / e0, so that 1/tau = 1/(1/2 + 3 v_th mu)
-  R c0sq, q, gve;    // c0^2, e0, gamma_v * eps_v
+  R c0, c0sq, q, gve;  // c0, c0^2, e0, gamma_v * eps_v
   R beta4, kappa;    // 4 beta = 48 zeta / W, kappa = 3 zeta W / 2 (Eq. 13)
   R W, fourW;        // interface width and 4 / W (Eq. 2)
   R s_free, inv_tau_h, inv_tau_g;
   R theta_src;       // theta times the source normalisation
-  R dpsi, force_x, force_y;
-  // reference states of the 16-bit storage forms (zero otherwise)
-  R ref_p, ref_n;    // concentration whose rest equilibrium is subtracted
+  R dpsi, psi_slope; // anode potential; d psi_lin / dy (0 in a periodic box)
+  R dr_g;            // (psi_lin(y - 1) - psi_lin(y)) / 6: reference shift of g2, g4
+  R force_x, force_y;
+  R sc[5], isc[5];   // binary16 storage: power-of-two scale of each set (f h p n g)
 };
+
+// Population set of plane q: 0 f, 1 h, 2 p, 3 n, 4 g.
+__host__ __device__ constexpr int set_of(int q) {
+  return q < QH ? 0 : (q < QP ? 1 : (q < QN ? 2 : (q < QG ? 3 : 4)));
+}
 
 // ---------------------------------------------------------------------------
 // Buffer access.  Population planes are read and written with raw buffer
@@ -65,11 +83,6 @@ struct KP {
 // ---------------------------------------------------------------------------
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 
-// cache policy of population stores (gfx940+ encoding: bit 1 = nt)
-#ifndef LBM_STORE_POLICY
-#define LBM_STORE_POLICY 0
-#endif
-
 __device__ inline Rsrc make_rsrc(const void* base, uint32_t bytes) {
   // raw buffer (stride 0), range in bytes; word 3 as used for gfx9 raw buffers
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
@@ -77,8 +90,6 @@ __device__ inline Rsrc make_rsrc(const void* base, uint32_t bytes) {
 }
 
 // Storage codecs: load/store one element at byte offsets (voff, soff).
-// FP64/FP32 store the populations as they are; the 16-bit forms store
-// x - ref, ref a fixed reference state per plane.
 template <class S, class R>
 struct Codec;
 
@@ -90,7 +101,7 @@ struct Codec<double, double> {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, double x) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, LBM_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, 0);
   }
 };
 template <>
@@ -99,7 +110,7 @@ struct Codec<float, float> {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, v, s, LBM_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, v, s, 0);
   }
 };
 template <>
@@ -108,7 +119,7 @@ struct Codec<float, double> {
     return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, double x) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)x), r, v, s, LBM_STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)x), r, v, s, 0);
   }
 };
 template <>
@@ -119,7 +130,7 @@ struct Codec<__half, float> {
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(x)),
-                                          r, v, s, LBM_STORE_POLICY);
+                                          r, v, s, 0);
   }
 };
 template <>
@@ -130,30 +141,84 @@ struct Codec<__hip_bfloat16, float> {
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
     __builtin_amdgcn_raw_buffer_store_b16(
-        __builtin_bit_cast(unsigned short, __float2bfloat16(x)), r, v, s, LBM_STORE_POLICY);
+        __builtin_bit_cast(unsigned short, __float2bfloat16(x)), r, v, s, 0);
   }
 };
 
-// Reference of plane q for the 16-bit storage forms: the rest equilibrium of
-// a uniform state.  f: 0; h: w_q / 2; p, n: wbar_q c_ref; g: the populations of
-// the uncharged linear potential of row y.
-template <class R>
-__device__ inline R plane_ref(int q, int y, const KP<R>& kp) {
-  const R w9[9] = {R(4) / R(9), R(1) / R(9), R(1) / R(9), R(1) / R(9), R(1) / R(9),
-                   R(1) / R(36), R(1) / R(36), R(1) / R(36), R(1) / R(36)};
-  if (q < QH) return R(0);
-  if (q < QP) return R(0.5) * w9[q - QH];
-  const int k = q < QN ? q - QP : (q < QG ? q - QN : q - QG);
-  const R wb = k == 0 ? R(1) / R(3) : R(1) / R(6);
-  if (q < QN) return wb * kp.ref_p;
-  if (q < QG) return wb * kp.ref_n;
-  if (kp.walls == WALL_PERIODIC) return R(0);
-  // linear potential between psi(-1/2) = dpsi and psi(ny - 1/2) = 0; the
-  // population of plane q stored at row y is the post-collision value of node
-  // y, i.e. the equilibrium of the linear potential there
-  const R psi = kp.dpsi * (R(kp.ny) - R(0.5) - R(y)) / R(kp.ny);
-  return k == 0 ? -R(2) / R(3) * psi : psi / R(6);
+// The value x takes once converted to the storage type.
+template <class S, class R>
+__device__ inline R stored_as(R x);
+template <>
+__device__ inline double stored_as<double, double>(double x) { return x; }
+template <>
+__device__ inline float stored_as<float, float>(float x) { return x; }
+template <>
+__device__ inline double stored_as<float, double>(double x) { return (double)(float)x; }
+template <>
+__device__ inline float stored_as<__half, float>(float x) {
+  return __half2float(__float2half_rn(x));
 }
+template <>
+__device__ inline float stored_as<__hip_bfloat16, float>(float x) {
+  return __bfloat162float(__float2bfloat16(x));
+}
+
+// Type of the rest population of h, kept next to (phi u)(t-1) and wider than
+// the other populations: it absorbs the rounding of the eight moving h
+// populations of its node, so that every collision conserves phi to FP64
+// rounding (FP32 storage) or FP32 rounding (16-bit storage).
+template <class S>
+struct RestOf {
+  typedef double type;
+};
+template <>
+struct RestOf<__half> {
+  typedef float type;
+};
+template <>
+struct RestOf<__hip_bfloat16> {
+  typedef float type;
+};
+
+// binary16 has a narrow exponent range: its deviations are stored scaled by a
+// power of two per set (exact) so that small values stay normal numbers.
+template <class S>
+struct Scaled {
+  static constexpr bool value = false;
+};
+template <>
+struct Scaled<__half> {
+  static constexpr bool value = true;
+};
+
+// A population buffer (or the g set of one) seen through a buffer
+// descriptor: element `off` of plane q (planes counted from the view's base;
+// `qoff` is the population index of that base, for the set scale).
+template <class S, class R>
+struct PopView {
+  Rsrc rs;
+  const KP<R>* kp;
+  int qoff;
+  __device__ inline R at(int q, uint32_t off) const {
+    R v = Codec<S, R>::ld(rs, off * (uint32_t)sizeof(S),
+                          (uint32_t)q * kp->plane * (uint32_t)sizeof(S));
+    if (Scaled<S>::value) v *= kp->isc[set_of(q + qoff)];
+    return v;
+  }
+  __device__ inline void put(int q, uint32_t off, R v) const {
+    if (Scaled<S>::value) v *= kp->sc[set_of(q + qoff)];
+    Codec<S, R>::st(rs, off * (uint32_t)sizeof(S), (uint32_t)q * kp->plane * (uint32_t)sizeof(S),
+                    v);
+  }
+  // the value v takes once stored in plane q
+  __device__ inline R stored(int q, R v) const {
+    if (Scaled<S>::value) {
+      const int k = set_of(q + qoff);
+      return stored_as<S, R>(v * kp->sc[k]) * kp->isc[k];
+    }
+    return stored_as<S, R>(v);
+  }
+};
 
 // Element `e` of a plain array, addressed as uniform base + 32-bit byte
 // offset (scalar-base + vector-offset form).
@@ -161,31 +226,21 @@ template <class T>
 __device__ inline T* elem(T* base, uint32_t e) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + e * (uint32_t)sizeof(T));
 }
-template <class T>
-__device__ inline const T* elem(const T* base, uint32_t e) {
-  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + e * (uint32_t)sizeof(T));
-}
 
-// A population buffer (or the g set of one) seen through a buffer
-// descriptor.  Element `off` of plane q (counted from the first plane of the
-// view, population index q + qoff) lies at lattice row `yrow`.
-template <class S, class R, bool DEV>
-struct PopView {
-  Rsrc rs;
-  int qoff;
-  const KP<R>* kp;
-  __device__ inline R at(int q, uint32_t off, int yrow) const {
-    R v = Codec<S, R>::ld(rs, off * (uint32_t)sizeof(S),
-                          (uint32_t)q * kp->plane * (uint32_t)sizeof(S));
-    if (DEV) v += plane_ref<R>(q + qoff, yrow, *kp);
-    return v;
-  }
-  __device__ inline void put(int q, uint32_t off, int yrow, R v) const {
-    if (DEV) v -= plane_ref<R>(q + qoff, yrow, *kp);
-    Codec<S, R>::st(rs, off * (uint32_t)sizeof(S), (uint32_t)q * kp->plane * (uint32_t)sizeof(S),
-                    v);
-  }
-};
+// Reference of population q stored at lattice row y (the deviation form
+// above), used where absolute values enter or leave: initialisation and
+// field output.
+__device__ inline double plane_ref(int q, int y, int ny, int walls, double c0, double dpsi) {
+  const double w9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  if (q < QH) return 0.0;
+  if (q < QP) return 0.5 * w9[q - QH];
+  const int k = q < QN ? q - QP : (q < QG ? q - QN : q - QG);
+  const double wb = k == 0 ? 1.0 / 3 : 1.0 / 6;
+  if (q < QG) return wb * c0;
+  const double psi = walls == WALL_PERIODIC ? 0.0 : dpsi * (ny - 0.5 - y) / ny;
+  return k == 0 ? -2.0 / 3 * psi : psi / 6;
+}
 
 // ---------------------------------------------------------------------------
 // Moment transforms: Eq. (28) and its inverse, Eq. (46) and its inverse.
@@ -245,15 +300,15 @@ __device__ inline R rate(int mask, int k, R inv_tau, R s_free) {
 
 // ---------------------------------------------------------------------------
 // Macroscopic quantities of one node (Sec. 4: Eq. 5-9, 12-14, 33, 41-43, 49,
-// 56-57, 59, 61).  chi9 arrays hold the node (index 0) and its eight
-// neighbours x + c_i in the velocity order above.
+// 56-57, 59, 61).  phi9 / psi9 hold phi' and psi' of the node (index 0) and
+// of its eight neighbours x + c_i, in the velocity order above.
 // ---------------------------------------------------------------------------
 template <class R>
 struct Macro {
-  R phi, psi, rho, eps, mup, mum;
+  R phi, phid, psid, rho, eps, mup, mum;  // phi, phi', psi'
   R itau_f, itau_p, itau_n;
   R gphi[2], lphi, gpsi[2], E[2];
-  R cp, cm, Rr, rhoe;
+  R cpd, cmd, cp, cm, Rr, rhoe;           // c+', c-', c+, c-, R, rho_e
   R F[2], grho[2], geps[2];
   R u[2], p;
 };
@@ -268,21 +323,26 @@ __device__ inline void grad_lap(const R c[9], R g[2], R* lap) {
            R(1) / R(6) * (c[5] + c[6] + c[7] + c[8] - R(4) * c[0]);
 }
 
-// Cation root of Eq. (42) in a cancellation-free form (same root).
+// Eq. (41)-(43) solved for the reaction rate itself.  With c+ = P + R/2 and
+// c- = Q + R/2 (Eq. 41), R = delta (c0^2 F - c+ c-) (Eq. 5) is the root of
+//   (delta/4) R^2 + (1 + delta (P + Q)/2) R - delta (c0^2 F - P Q) = 0
+// that gives c+ >= 0, the same root as Eq. (42).  c0^2 F - P Q is formed from
+// deviations: c0^2 (F - 1) - c0 (P' + Q') - P' Q'.
 template <class R>
-__device__ inline void ion_roots(R cbp, R cbm, R lam0, R* cp, R* cm) {
-  const R b = R(1) - lam0 * (cbp - cbm);
-  const R root = sqrt(b * b + R(4) * lam0 * cbp);
-  *cp = b >= R(0) ? R(2) * cbp / (b + root) : (root - b) / (R(2) * lam0);
-  *cm = *cp - cbp + cbm;
+__device__ inline R reaction_rate(R delta, R c0, R c0sq, R Fm1, R Pd, R Qd) {
+  const R Cn = c0sq * Fm1 - c0 * (Pd + Qd) - Pd * Qd;
+  const R B = R(1) + R(0.5) * delta * (R(2) * c0 + Pd + Qd);
+  const R AC = R(0.25) * delta * delta * Cn;  // (delta/4) (delta Cn)
+  return R(2) * delta * Cn / (B + sqrt(B * B + R(4) * AC));
 }
 
 template <class R>
-__device__ inline void macro(const R phi9[9], const R psi9[9], R P, R Q, const R f[9],
+__device__ inline void macro(const R phi9[9], const R psi9[9], R Pd, R Qd, const R f[9],
                              const KP<R>& kp, Macro<R>& m) {
-  const R phi = phi9[0];
+  m.phid = phi9[0];
+  const R phi = R(0.5) + phi9[0];
   m.phi = phi;
-  m.psi = psi9[0];
+  m.psid = psi9[0];
   // Eq. (61)
   m.rho = phi * kp.drho + kp.rho_v;
   const R eta = phi * kp.deta + kp.eta_v;
@@ -293,9 +353,10 @@ __device__ inline void macro(const R phi9[9], const R psi9[9], R P, R Q, const R
   m.itau_f = R(1) / (R(0.5) + R(3) * eta / m.rho);
   m.itau_p = R(1) / (R(0.5) + kp.three_vth * m.mup);
   m.itau_n = R(1) / (R(0.5) + kp.three_vth * m.mum);
-  // Eq. (59), (9)
+  // Eq. (59), (9); the linear part of psi contributes its exact gradient
   grad_lap(phi9, m.gphi, &m.lphi);
   grad_lap<R>(psi9, m.gpsi, nullptr);
+  m.gpsi[1] += kp.psi_slope;
   m.E[0] = -m.gpsi[0];
   m.E[1] = -m.gpsi[1];
   // Eq. (5), (6), (41)-(43), (8)
@@ -303,20 +364,19 @@ __device__ inline void macro(const R phi9[9], const R psi9[9], R P, R Q, const R
   if (kp.reaction) {
     const R delta = kp.q * (m.mup + m.mum) / m.eps;
     const R gamma = kp.gve / m.eps;
-    const R Fo = R(1) + R(2) * gamma * sqrt(E2);
-    const R lam0 = R(0.5) * delta;
-    const R gen = lam0 * kp.c0sq * Fo;
-    const R cbp = P + gen, cbm = Q + gen;
-    ion_roots(cbp, cbm, lam0, &m.cp, &m.cm);
-    m.Rr = delta * (kp.c0sq * Fo - m.cp * m.cm);
+    m.Rr = reaction_rate(delta, kp.c0, kp.c0sq, R(2) * gamma * sqrt(E2), Pd, Qd);
+    m.cpd = Pd + R(0.5) * m.Rr;
+    m.cmd = Qd + R(0.5) * m.Rr;
   } else {
-    m.cp = P;
-    m.cm = Q;
     m.Rr = R(0);
+    m.cpd = Pd;
+    m.cmd = Qd;
   }
-  m.rhoe = kp.q * (m.cp - m.cm);
-  // Eq. (12)-(14)
-  const R mu_phi = kp.beta4 * phi * (phi - R(1)) * (phi - R(0.5)) - kp.kappa * m.lphi;
+  m.cp = kp.c0 + m.cpd;
+  m.cm = kp.c0 + m.cmd;
+  m.rhoe = kp.q * (Pd - Qd);  // c+ - c- = P - Q
+  // Eq. (12)-(14); phi - 1/2 = phi'
+  const R mu_phi = kp.beta4 * phi * (phi - R(1)) * phi9[0] - kp.kappa * m.lphi;
   m.grho[0] = kp.drho * m.gphi[0];
   m.grho[1] = kp.drho * m.gphi[1];
   m.geps[0] = kp.deps * m.gphi[0];
@@ -341,10 +401,11 @@ __device__ inline void macro(const R phi9[9], const R psi9[9], R P, R Q, const R
 }
 
 // ---------------------------------------------------------------------------
-// Collisions (moment space).  Each writes post-collision populations.
+// Collisions (moment space, on deviations).  Each writes post-collision
+// deviations.
 // ---------------------------------------------------------------------------
 
-// f: Eq. (51)-(55).
+// f: Eq. (51)-(55) (reference 0).
 template <class R>
 __device__ inline void collide_f(R f[9], const Macro<R>& m, const KP<R>& kp) {
   if (!kp.flow) return;
@@ -381,12 +442,12 @@ __device__ inline void collide_f(R f[9], const Macro<R>& m, const KP<R>& kp) {
   inv9(mo, f);
 }
 
-// h: Eq. (27)-(32).  dJ = d(phi u)/dt by Eq. (58).
+// h: Eq. (27)-(32) on deviations from w_i / 2.  dJ = d(phi u)/dt by Eq. (58).
 template <class R>
 __device__ inline void collide_h(R h[9], const Macro<R>& m, const R dJ[2], const KP<R>& kp) {
   R mo[9];
   fwd9(h, mo);
-  const R phi = m.phi, ux = m.u[0], uy = m.u[1];
+  const R phi = m.phi, phid = m.phid, ux = m.u[0], uy = m.u[1];
   const R third = R(1) / R(3), ninth = R(1) / R(9);
   const R gn = sqrt(m.gphi[0] * m.gphi[0] + m.gphi[1] * m.gphi[1]);
   R nx = R(0), ny = R(0);
@@ -397,15 +458,15 @@ __device__ inline void collide_h(R h[9], const Macro<R>& m, const R dJ[2], const
   const R lam = kp.fourW * phi * (R(1) - phi);
   const R Ax = R(3) * dJ[0] + lam * nx, Ay = R(3) * dJ[1] + lam * ny;
   R eq[9], fo[9];
-  eq[0] = phi;
+  eq[0] = phid;
   eq[1] = phi * ux;
   eq[2] = phi * uy;
-  eq[3] = third * phi;
-  eq[4] = third * phi;
+  eq[3] = third * phid;
+  eq[4] = third * phid;
   eq[5] = R(0);
   eq[6] = third * phi * ux;
   eq[7] = third * phi * uy;
-  eq[8] = ninth * phi;
+  eq[8] = ninth * phid;
   fo[0] = R(0);
   fo[1] = third * Ax;
   fo[2] = third * Ay;
@@ -423,10 +484,10 @@ __device__ inline void collide_h(R h[9], const Macro<R>& m, const R dJ[2], const
   inv9(mo, h);
 }
 
-// p and n: Eq. (34)-(40) on D2Q5.  sign = -1 for cations (- S G),
-// +1 for anions (+ S Gbar).
+// p and n: Eq. (34)-(40) on D2Q5, deviations from wbar_i c0.  cd is c - c0,
+// c the concentration; sign = -1 for cations (- S G), +1 for anions (+ S Gbar).
 template <class R>
-__device__ inline void collide_ion(R x[5], R c, R mu, R itau, int mask, R sign,
+__device__ inline void collide_ion(R x[5], R cd, R c, R mu, R itau, int mask, R sign,
                                    const Macro<R>& m, const KP<R>& kp) {
   R mo[5];
   fwd5(x, mo);
@@ -434,7 +495,7 @@ __device__ inline void collide_ion(R x[5], R c, R mu, R itau, int mask, R sign,
   const R Lx = kp.ion_force ? c * m.F[0] : R(0);
   const R Ly = kp.ion_force ? c * m.F[1] : R(0);
   const R Gx = mu * c * m.gpsi[0], Gy = mu * c * m.gpsi[1];
-  const R eq[5] = {c, c * m.u[0], c * m.u[1], third * c, third * c};
+  const R eq[5] = {cd, c * m.u[0], c * m.u[1], third * cd, third * cd};
   const R so[5] = {m.Rr, Lx, Ly, third * m.Rr, third * m.Rr};
   const R dr[5] = {R(0), Gx, Gy, R(0), R(0)};
 #pragma unroll
@@ -454,13 +515,17 @@ __device__ inline R poisson_source(R rhoe, R eps, const R geps[2], const R gpsi[
   return s / eps;
 }
 
-// g: Eq. (44)-(47).
+// g: Eq. (44)-(47) on deviations from the linear-potential equilibrium of the
+// node's own row.  Entering, g[2] and g[4] were stored relative to the rows
+// below and above; their references differ from the node's by +-dr_g.
 template <class R>
-__device__ inline void collide_g(R g[5], R psi, R Spsi, const KP<R>& kp) {
+__device__ inline void collide_g(R g[5], R psid, R Spsi, const KP<R>& kp) {
+  g[2] += kp.dr_g;
+  g[4] -= kp.dr_g;
   R mo[5];
   fwd5(g, mo);
   const R third = R(1) / R(3);
-  const R eq[5] = {R(0), R(0), R(0), third * psi, third * psi};
+  const R eq[5] = {R(0), R(0), R(0), third * psid, third * psid};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const R s = rate(kp.mask_g, k, kp.inv_tau_g, kp.s_free);

@@ -6,8 +6,8 @@
 // walks down the band.  phi and psi, needed at the eight neighbours for the
 // isotropic stencils (Eq. 59), are the moments of the *pulled* h and g of
 // those neighbours, so the wave computes them one row ahead into a small LDS
-// ring (5 rows x 66 columns, the two halo columns by lanes 0 and 1) and keeps
-// the pulled h and g of that row in registers for the row's own update.  Every
+// ring (5 rows x 66 columns, the two halo columns by lanes 0 and 1) and parks
+// the pulled h and g of that row in LDS for the row's own update.  Every
 // population is read once and written once per step; only h and g of the two
 // halo columns and of the row above a band are read twice (from L2).
 #pragma once
@@ -15,6 +15,11 @@
 #include "lbm_ehd_device.hpp"
 
 namespace lbm {
+
+template <class T>
+__device__ inline const T* elem(const T* base, uint32_t e) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + e * (uint32_t)sizeof(T));
+}
 
 // Offsets of the pull sources of node (xc, yy): the population arriving along
 // c_i comes from (xc - c_ix, yy - c_iy).
@@ -30,38 +35,57 @@ __device__ inline Cols cols_of(int xc, int nx) {
   return k;
 }
 
-template <class S, class R, bool DEV>
-__device__ inline void pull9(const PopView<S, R, DEV>& P, int q0, Cols k, int yy, uint32_t pitch,
+template <class S, class R>
+__device__ inline void pull9(const PopView<S, R>& P, int q0, Cols k, int yy, uint32_t pitch,
                              R x[9]) {
   const uint32_t r0 = (uint32_t)(yy + 1) * pitch, rm = r0 - pitch, rp = r0 + pitch;
-  x[0] = P.at(q0 + 0, r0 + k.c, yy);
-  x[1] = P.at(q0 + 1, r0 + k.m, yy);
-  x[2] = P.at(q0 + 2, rm + k.c, yy - 1);
-  x[3] = P.at(q0 + 3, r0 + k.p, yy);
-  x[4] = P.at(q0 + 4, rp + k.c, yy + 1);
-  x[5] = P.at(q0 + 5, rm + k.m, yy - 1);
-  x[6] = P.at(q0 + 6, rm + k.p, yy - 1);
-  x[7] = P.at(q0 + 7, rp + k.p, yy + 1);
-  x[8] = P.at(q0 + 8, rp + k.m, yy + 1);
+  x[0] = P.at(q0 + 0, r0 + k.c);
+  x[1] = P.at(q0 + 1, r0 + k.m);
+  x[2] = P.at(q0 + 2, rm + k.c);
+  x[3] = P.at(q0 + 3, r0 + k.p);
+  x[4] = P.at(q0 + 4, rp + k.c);
+  x[5] = P.at(q0 + 5, rm + k.m);
+  x[6] = P.at(q0 + 6, rm + k.p);
+  x[7] = P.at(q0 + 7, rp + k.p);
+  x[8] = P.at(q0 + 8, rp + k.m);
 }
 
 // Directions 1..4 of a D2Q5 set (the rest population is pulled separately).
-template <class S, class R, bool DEV>
-__device__ inline void pull4(const PopView<S, R, DEV>& P, int q0, Cols k, int yy, uint32_t pitch,
+template <class S, class R>
+__device__ inline void pull4(const PopView<S, R>& P, int q0, Cols k, int yy, uint32_t pitch,
                              R x[4]) {
   const uint32_t r0 = (uint32_t)(yy + 1) * pitch, rm = r0 - pitch, rp = r0 + pitch;
-  x[0] = P.at(q0 + 1, r0 + k.m, yy);
-  x[1] = P.at(q0 + 2, rm + k.c, yy - 1);
-  x[2] = P.at(q0 + 3, r0 + k.p, yy);
-  x[3] = P.at(q0 + 4, rp + k.c, yy + 1);
+  x[0] = P.at(q0 + 1, r0 + k.m);
+  x[1] = P.at(q0 + 2, rm + k.c);
+  x[2] = P.at(q0 + 3, r0 + k.p);
+  x[3] = P.at(q0 + 4, rp + k.c);
+}
+
+// The h set of node (xc, yy): h0 from the rest plane (in place), h1..h8
+// pulled.
+template <class S, class R, class T0>
+__device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x, Cols k,
+                              int yy, uint32_t pitch, R x[9]) {
+  const uint32_t r0 = (uint32_t)(yy + 1) * pitch, rm = r0 - pitch, rp = r0 + pitch;
+  x[0] = (R)*elem(h0x, (uint32_t)yy * pitch + k.c);
+  x[1] = P.at(QH + 1, r0 + k.m);
+  x[2] = P.at(QH + 2, rm + k.c);
+  x[3] = P.at(QH + 3, r0 + k.p);
+  x[4] = P.at(QH + 4, rp + k.c);
+  x[5] = P.at(QH + 5, rm + k.m);
+  x[6] = P.at(QH + 6, rm + k.p);
+  x[7] = P.at(QH + 7, rp + k.p);
+  x[8] = P.at(QH + 8, rp + k.m);
 }
 
 template <class R>
 __device__ inline R sum9(const R h[9]) {
   return h[0] + h[1] + h[2] + h[3] + h[4] + h[5] + h[6] + h[7] + h[8];
 }
+// psi' of Eq. (49): 1/(1 - 1/3) = 3/2 times the deviations of g1..g4 (their
+// references add up to psi_lin of the node's row)
 template <class R>
-__device__ inline R psi_of(const R g4[4]) {  // Eq. (49): 1/(1 - 1/3) = 3/2
+__device__ inline R psi_of(const R g4[4]) {
   return R(1.5) * (g4[0] + g4[1] + g4[2] + g4[3]);
 }
 
@@ -81,73 +105,81 @@ __device__ inline void nine(const R d[3], const R c[3], const R u[3], R o[9]) {
 }
 
 // Wall ghosts of the stencils: phi mirrored, psi odd about the wall value.
+// In deviation form the wall value of psi' is 0 at both electrodes.
 template <class R>
-__device__ inline void ghost_row(const R phc[3], const R psc[3], R psi_w, R phg[3], R psg[3]) {
+__device__ inline void ghost_row(const R phc[3], const R psc[3], R phg[3], R psg[3]) {
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     phg[j] = phc[j];
-    psg[j] = R(2) * psi_w - psc[j];
+    psg[j] = -psc[j];
   }
 }
 
 // Ghost-row writes of a node on a wall row (or on an edge row of a
 // y-periodic box).  At a wall, the population that comes back along c_i to
 // node x is pulled at step t+1 from ghost column x - c_ix; in a periodic box
-// the ghost row receives the populations leaving the opposite edge.
-template <class S, class R, bool DEV>
+// the ghost row receives the populations leaving the opposite edge.  Values
+// are deviations (the wall rules below are written for them).
+template <class S, class R>
 struct Ghosts {
-  const PopView<S, R, DEV>& D;
+  const PopView<S, R>& D;
   const KP<R>& kp;
   int y;
   Cols k;
-  __device__ inline void put(int q, uint32_t off, int yrow, R v) const { D.put(q, off, yrow, v); }
   __device__ inline uint32_t top() const { return (uint32_t)(kp.ny + 1) * kp.pitch; }
   // D2Q9 set starting at plane q0 (f or h): bounce-back at walls
   __device__ inline void set9(int q0, const R x[9]) const {
     if (kp.walls == WALL_PERIODIC) {
-      if (y == kp.ny - 1) { put(q0 + 2, k.c, -1, x[2]); put(q0 + 5, k.c, -1, x[5]); put(q0 + 6, k.c, -1, x[6]); }
+      if (y == kp.ny - 1) { D.put(q0 + 2, k.c, x[2]); D.put(q0 + 5, k.c, x[5]); D.put(q0 + 6, k.c, x[6]); }
       if (y == 0) {
-        put(q0 + 4, top() + k.c, kp.ny, x[4]); put(q0 + 7, top() + k.c, kp.ny, x[7]);
-        put(q0 + 8, top() + k.c, kp.ny, x[8]);
+        D.put(q0 + 4, top() + k.c, x[4]); D.put(q0 + 7, top() + k.c, x[7]);
+        D.put(q0 + 8, top() + k.c, x[8]);
       }
       return;
     }
-    if (y == 0) { put(q0 + 2, k.c, -1, x[4]); put(q0 + 5, k.m, -1, x[7]); put(q0 + 6, k.p, -1, x[8]); }
+    if (y == 0) { D.put(q0 + 2, k.c, x[4]); D.put(q0 + 5, k.m, x[7]); D.put(q0 + 6, k.p, x[8]); }
     if (y == kp.ny - 1) {
-      put(q0 + 4, top() + k.c, kp.ny, x[2]); put(q0 + 7, top() + k.p, kp.ny, x[5]);
-      put(q0 + 8, top() + k.m, kp.ny, x[6]);
+      D.put(q0 + 4, top() + k.c, x[2]); D.put(q0 + 7, top() + k.p, x[5]);
+      D.put(q0 + 8, top() + k.m, x[6]);
     }
   }
   // D2Q5 set: reflected value at the bottom and top walls given by the caller
   __device__ inline void set5(int q0, const R x[5], R bottom, R topv) const {
     if (kp.walls == WALL_PERIODIC) {
-      if (y == kp.ny - 1) put(q0 + 2, k.c, -1, x[2]);
-      if (y == 0) put(q0 + 4, top() + k.c, kp.ny, x[4]);
+      if (y == kp.ny - 1) D.put(q0 + 2, k.c, x[2]);
+      if (y == 0) D.put(q0 + 4, top() + k.c, x[4]);
       return;
     }
-    if (y == 0) put(q0 + 2, k.c, -1, bottom);
-    if (y == kp.ny - 1) put(q0 + 4, top() + k.c, kp.ny, topv);
+    if (y == 0) D.put(q0 + 2, k.c, bottom);
+    if (y == kp.ny - 1) D.put(q0 + 4, top() + k.c, topv);
   }
 };
 
-// Per-node update once the pulled populations and the phi/psi neighbourhood
-// are known: macroscopic quantities, Eq. (58), then the five collisions, each
-// stored as soon as it is done.  h and g (directions 1-4) of the node are
-// fetched through `hg` right before their collisions; they were pulled one row
-// earlier and parked in LDS.
-template <class S, class R, bool DEV, class HG>
-__device__ inline void update_node(const PopView<S, R, DEV>& D, R* __restrict__ jprev,
-                                   const KP<R>& kp,
-                                   int x, int y, Cols k, const R phi9[9], const R psi9[9],
-                                   R f[9], R p[5], R n[5], R g0, const HG& hg) {
-  const R P = p[0] + p[1] + p[2] + p[3] + p[4];
-  const R Q = n[0] + n[1] + n[2] + n[3] + n[4];
+// Per-node update once the pulled populations and the phi'/psi'
+// neighbourhood are known: macroscopic quantities, then the five collisions,
+// each stored as soon as it is done.  h and g (directions 1-4) of the node
+// are fetched through `hg` right before their collisions; they were pulled one
+// row earlier and parked in LDS.
+//
+// Wall rules in deviation form: bounce-back keeps the deviation; the
+// anti-bounce-back of an ion with wall concentration c_w stores
+// -x*_opp + 2 wbar (c_w - c0), i.e. -x*_opp - c0/3 for c_w = 0 and
+// -x*_opp + c'/3 for c_w = c(node); for g the linear potential meets the
+// electrode potentials exactly, so the rule is -x*_opp.
+template <class S, class R, class T0, class HG>
+__device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev,
+                                   const T0* __restrict__ h0src, T0* __restrict__ h0dst,
+                                   const KP<R>& kp, int x, int y, Cols k, const R phi9[9],
+                                   const R psi9[9], R f[9], R p[5], R n[5], R g0,
+                                   const HG& hg) {
+  const R Pd = p[0] + p[1] + p[2] + p[3] + p[4];
+  const R Qd = n[0] + n[1] + n[2] + n[3] + n[4];
   Macro<R> m;
-  macro(phi9, psi9, P, Q, f, kp, m);
+  macro(phi9, psi9, Pd, Qd, f, kp, m);
 
   const uint32_t o = (uint32_t)(y + 1) * kp.pitch + x;
   const bool edge = y == 0 || y == kp.ny - 1;
-  const Ghosts<S, R, DEV> G{D, kp, y, k};
+  const Ghosts<S, R> G{D, kp, y, k};
   const bool ins = kp.walls == WALL_INSULATING;
   const R third = R(1) / R(3);
 
@@ -155,61 +187,57 @@ __device__ inline void update_node(const PopView<S, R, DEV>& D, R* __restrict__ 
     R g[5];
     g[0] = g0;
     hg.g4(g + 1);
-    collide_g(g, m.psi, poisson_source(m.rhoe, m.eps, m.geps, m.gpsi, kp), kp);
+    collide_g(g, m.psid, poisson_source(m.rhoe, m.eps, m.geps, m.gpsi, kp), kp);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) D.put(QG + i, o, y, g[i]);
-    if (edge) G.set5(QG, g, -g[4] + third * kp.dpsi, -g[2]);
+    for (int i = 0; i < 5; ++i) D.put(QG + i, o, g[i]);
+    if (edge) G.set5(QG, g, -g[4], -g[2]);
   }
 
-  collide_ion(p, m.cp, m.mup, m.itau_p, kp.mask_p, R(-1), m, kp);
+  collide_ion(p, m.cpd, m.cp, m.mup, m.itau_p, kp.mask_p, R(-1), m, kp);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) D.put(QP + i, o, y, p[i]);
+  for (int i = 0; i < 5; ++i) D.put(QP + i, o, p[i]);
   // anode: c+ = 0; cathode: d c+/dn = 0 (wall value = node value)
-  if (edge) G.set5(QP, p, ins ? p[4] : -p[4], ins ? p[2] : -p[2] + third * m.cp);
+  if (edge) G.set5(QP, p, ins ? p[4] : -p[4] - third * kp.c0, ins ? p[2] : -p[2] + third * m.cpd);
 
-  collide_ion(n, m.cm, m.mum, m.itau_n, kp.mask_n, R(1), m, kp);
+  collide_ion(n, m.cmd, m.cm, m.mum, m.itau_n, kp.mask_n, R(1), m, kp);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) D.put(QN + i, o, y, n[i]);
+  for (int i = 0; i < 5; ++i) D.put(QN + i, o, n[i]);
   // anode: d c-/dn = 0; cathode: c- = 0
-  if (edge) G.set5(QN, n, ins ? n[4] : -n[4] + third * m.cm, ins ? n[2] : -n[2]);
+  if (edge) G.set5(QN, n, ins ? n[4] : -n[4] + third * m.cmd, ins ? n[2] : -n[2] - third * kp.c0);
 
   {  // h: Eq. (27)-(32), with d(phi u)/dt of Eq. (58)
     const uint32_t jo = (uint32_t)y * kp.pitch + x;
-    const uint32_t jpl = (uint32_t)kp.ny * kp.pitch;
+    const uint32_t jpl = kp.cells;
     const R Jx = m.phi * m.u[0], Jy = m.phi * m.u[1];
     const R dJ[2] = {Jx - *elem(jprev, jo), Jy - *elem(jprev, jpl + jo)};
     *elem(jprev, jo) = Jx;
     *elem(jprev, jpl + jo) = Jy;
+    const T0 h0in = *elem(h0src, jo);
     R h[9];
     hg.h9(h);
+    h[0] = (R)h0in;
+    double mass = (double)h0in;  // exact sum of the node's incoming h
+#pragma unroll
+    for (int i = 1; i < 9; ++i) mass += (double)h[i];
     collide_h(h, m, dJ, kp);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) D.put(QH + i, o, y, h[i]);
+    for (int i = 1; i < 9; ++i) {
+      h[i] = D.stored(QH + i, h[i]);
+      D.put(QH + i, o, h[i]);
+      mass -= (double)h[i];
+    }
+    // the rest population takes what the eight stored ones leave of the mass
+    *elem(h0dst, jo) = (T0)mass;
     if (edge) G.set9(QH, h);
   }
 
   collide_f(f, m, kp);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) D.put(QF + i, o, y, f[i]);
+  for (int i = 0; i < 9; ++i) D.put(QF + i, o, f[i]);
   if (edge) G.set9(QF, f);
 }
 
-// h and directions 1-4 of g of one node held in registers.
-template <class R>
-struct HGRegs {
-  const R* h;
-  const R* g;
-  __device__ inline void h9(R o[9]) const {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) o[i] = h[i];
-  }
-  __device__ inline void g4(R o[4]) const {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = g[i];
-  }
-};
-
-// ... or parked in LDS, one column per lane: [13][64].
+// h and directions 1-4 of g of one node parked in LDS, one column per lane.
 template <class R>
 struct HGLds {
   const R (*s)[TILE_W];
@@ -225,23 +253,23 @@ struct HGLds {
 };
 
 // The fused sweep.  grid = nstrips * nbands workgroups of 64 lanes.
-template <class S, class R, bool DEV>
+template <class S, class R, class T0>
 __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
                                               const S* __restrict__ srcg,
                                               S* __restrict__ dst, R* __restrict__ jprev,
-                                              const KP<R> kp, int tile_rows, int nstrips,
-                                              int nbands, int xcd_chunk, int band_major) {
+                                              const T0* __restrict__ h0x,
+                                              T0* __restrict__ h0dst, const KP<R> kp,
+                                              int tile_rows, int nstrips, int nbands,
+                                              int xcd_chunk, int band_major) {
   __shared__ R s_phi[RING][TILE_W + 2];
   __shared__ R s_psi[RING][TILE_W + 2];
   __shared__ R s_pull[2][13][TILE_W];  // pulled h and g1-4 of a row, by row parity
 
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous run of tiles (whole column strips) so that the halo rows and
-  // columns that neighbouring tiles share stay in one L2.
-  // Within a chunk, tiles go band by band across all strips, so that the
-  // workgroups running together on an XCD hold neighbouring strips of the same
-  // rows and the cache lines they share (pull shifts, halo columns) are
-  // fetched from HBM once.
+  // contiguous run of tiles.  Within a run, tiles go band by band across all
+  // strips, so that the workgroups running together on an XCD hold
+  // neighbouring strips of the same rows and the cache lines they share (pull
+  // shifts, halo columns) are fetched from HBM once.
   int t = blockIdx.x;
   if (xcd_chunk > 0) t = (t & 7) * xcd_chunk + (t >> 3);
   int strip, band;
@@ -262,9 +290,9 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
   const Cols k = cols_of(x, nx);
   const int yend = min(y0 + tile_rows, ny);
   const bool periodic = kp.walls == WALL_PERIODIC;
-  const PopView<S, R, DEV> Ph{make_rsrc(src, kp.pop_bytes), 0, &kp};
-  const PopView<S, R, DEV> Pg{make_rsrc(srcg, kp.g_bytes), QG, &kp};
-  const PopView<S, R, DEV> D{make_rsrc(dst, kp.pop_bytes), 0, &kp};
+  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
+  const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
+  const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp, 0};
 
   // halo column handled by lanes 0 (left) and 1 (right)
   const int xh = lane == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + w == nx ? 0 : x0 + w);
@@ -272,20 +300,20 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
   const int kcol = lane == 0 ? 0 : w + 1;
 
   auto slot = [&](int yy) { return (yy - y0 + 1) % RING; };
-  // phi, psi of row yy into the ring; the lane's own pulls are parked in LDS
+  // phi', psi' of row yy into the ring; the lane's own pulls are parked in LDS
   auto ring_row = [&](int yy) {
     const int ys = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
     const int sl = slot(yy);
     if (lane < 2) {
       R hh[9], gg[4];
-      pull9(Ph, QH, kh, ys, pitch, hh);
+      pull_h(Ph, h0x, kh, ys, pitch, hh);
       pull4(Pg, 0, kh, ys, pitch, gg);
       s_phi[sl][kcol] = sum9(hh);
       s_psi[sl][kcol] = psi_of(gg);
     }
     if (valid) {
       R h[9], g4[4];
-      pull9(Ph, QH, k, ys, pitch, h);
+      pull_h(Ph, h0x, k, ys, pitch, h);
       pull4(Pg, 0, k, ys, pitch, g4);
       s_phi[sl][lane + 1] = sum9(h);
       s_psi[sl][lane + 1] = psi_of(g4);
@@ -315,14 +343,14 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
         phU[0] = s_phi[su][c - 1]; phU[1] = s_phi[su][c]; phU[2] = s_phi[su][c + 1];
         psU[0] = s_psi[su][c - 1]; psU[1] = s_psi[su][c]; psU[2] = s_psi[su][c + 1];
       } else {
-        ghost_row(phC, psC, R(0), phU, psU);
+        ghost_row(phC, psC, phU, psU);
       }
       if (down) {
         const int sd = slot(y - 1);
         phD[0] = s_phi[sd][c - 1]; phD[1] = s_phi[sd][c]; phD[2] = s_phi[sd][c + 1];
         psD[0] = s_psi[sd][c - 1]; psD[1] = s_psi[sd][c]; psD[2] = s_psi[sd][c + 1];
       } else {
-        ghost_row(phC, psC, kp.dpsi, phD, psD);
+        ghost_row(phC, psC, phD, psD);
       }
       R phi9[9], psi9[9];
       nine(phD, phC, phU, phi9);
@@ -331,15 +359,15 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
       R f[9], p[5], n[5], t4[4];
       pull9(Ph, QF, k, y, pitch, f);
       const uint32_t r0 = (uint32_t)(y + 1) * pitch;
-      p[0] = Ph.at(QP, r0 + x, y);
-      n[0] = Ph.at(QN, r0 + x, y);
-      const R g0 = Pg.at(0, r0 + x, y);
+      p[0] = Ph.at(QP, r0 + x);
+      n[0] = Ph.at(QN, r0 + x);
+      const R g0 = Pg.at(0, r0 + x);
       pull4(Ph, QP, k, y, pitch, t4);
       p[1] = t4[0]; p[2] = t4[1]; p[3] = t4[2]; p[4] = t4[3];
       pull4(Ph, QN, k, y, pitch, t4);
       n[1] = t4[0]; n[2] = t4[1]; n[3] = t4[2]; n[4] = t4[3];
       const HGLds<R> hg{s_pull[(y - y0 + 2) & 1], lane};
-      update_node<S, R, DEV>(D, jprev, kp, x, y, k, phi9, psi9, f, p, n, g0, hg);
+      update_node<S, R, T0>(D, jprev, h0x, h0dst, kp, x, y, k, phi9, psi9, f, p, n, g0, hg);
     }
   }
 }
@@ -348,30 +376,30 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
 // Helpers outside the hot loop.
 // ---------------------------------------------------------------------------
 
-// phi, psi and rho_e = e0 (sum p - sum n) of every node into compact planes.
-template <class S, class R, bool DEV>
+// phi', psi' and rho_e = e0 (P' - Q') of every node into compact planes.
+template <class S, class R, class T0>
 __global__ void k_moments(const S* __restrict__ src, const S* __restrict__ srcg,
-                          R* __restrict__ mom, const KP<R> kp) {
+                          const T0* __restrict__ h0x, R* __restrict__ mom, const KP<R> kp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
-  const PopView<S, R, DEV> Ph{make_rsrc(src, kp.pop_bytes), 0, &kp};
-  const PopView<S, R, DEV> Pg{make_rsrc(srcg, kp.g_bytes), QG, &kp};
+  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
+  const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
   const Cols k = cols_of(x, kp.nx);
   R h[9], g4[4], t4[4];
-  pull9(Ph, QH, k, y, kp.pitch, h);
+  pull_h(Ph, h0x, k, y, kp.pitch, h);
   pull4(Pg, 0, k, y, kp.pitch, g4);
   const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
   pull4(Ph, QP, k, y, kp.pitch, t4);
-  const R P = Ph.at(QP, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Pd = Ph.at(QP, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
   pull4(Ph, QN, k, y, kp.pitch, t4);
-  const R Q = Ph.at(QN, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Qd = Ph.at(QN, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
   const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
   mom[c] = sum9(h);
   mom[np + c] = psi_of(g4);
-  mom[2 * np + c] = kp.q * (P - Q);
+  mom[2 * np + c] = kp.q * (Pd - Qd);
 }
 
-// phi / psi neighbourhood of (x, y) from the compact moment planes.
+// phi' / psi' neighbourhood of (x, y) from the compact moment planes.
 template <class R>
 __device__ inline void hood(const R* __restrict__ mom, const KP<R>& kp, int x, int y,
                             R phi9[9], R psi9[9]) {
@@ -392,36 +420,38 @@ __device__ inline void hood(const R* __restrict__ mom, const KP<R>& kp, int x, i
     }
   }
   if (!periodic) {
-    if (y == 0) ghost_row(ph[1], ps[1], kp.dpsi, ph[0], ps[0]);
-    if (y == kp.ny - 1) ghost_row(ph[1], ps[1], R(0), ph[2], ps[2]);
+    if (y == 0) ghost_row(ph[1], ps[1], ph[0], ps[0]);
+    if (y == kp.ny - 1) ghost_row(ph[1], ps[1], ph[2], ps[2]);
   }
   nine(ph[0], ph[1], ph[2], phi9);
   nine(ps[0], ps[1], ps[2], psi9);
 }
 
-// Macroscopic fields (FP64 output, [10][ny][nx]).
-template <class S, class R, bool DEV>
-__global__ void k_fields(const S* __restrict__ src, const S* __restrict__ srcg,
-                         const R* __restrict__ mom, double* __restrict__ out, const KP<R> kp) {
+// Macroscopic fields (FP64 output, [10][ny][nx]), absolute values.
+template <class S, class R>
+__global__ void k_fields(const S* __restrict__ src, const R* __restrict__ mom,
+                         double* __restrict__ out, const KP<R> kp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
-  const PopView<S, R, DEV> Ph{make_rsrc(src, kp.pop_bytes), 0, &kp};
+  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
   const Cols k = cols_of(x, kp.nx);
   R phi9[9], psi9[9], f[9], t4[4];
   hood(mom, kp, x, y, phi9, psi9);
   pull9(Ph, QF, k, y, kp.pitch, f);
   const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
   pull4(Ph, QP, k, y, kp.pitch, t4);
-  const R P = Ph.at(QP, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Pd = Ph.at(QP, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
   pull4(Ph, QN, k, y, kp.pitch, t4);
-  const R Q = Ph.at(QN, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Qd = Ph.at(QN, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
   Macro<R> m;
-  macro(phi9, psi9, P, Q, f, kp, m);
+  macro(phi9, psi9, Pd, Qd, f, kp, m);
   const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
-  out[0 * np + c] = m.phi;
-  out[1 * np + c] = m.psi;
-  out[2 * np + c] = m.cp;
-  out[3 * np + c] = m.cm;
+  const double psi_lin =
+      kp.walls == WALL_PERIODIC ? 0.0 : (double)kp.dpsi * (kp.ny - 0.5 - y) / kp.ny;
+  out[0 * np + c] = 0.5 + (double)m.phid;
+  out[1 * np + c] = psi_lin + (double)m.psid;
+  out[2 * np + c] = (double)kp.c0 + (double)m.cpd;
+  out[3 * np + c] = (double)kp.c0 + (double)m.cmd;
   out[4 * np + c] = m.rhoe;
   out[5 * np + c] = m.u[0];
   out[6 * np + c] = m.u[1];
@@ -431,41 +461,37 @@ __global__ void k_fields(const S* __restrict__ src, const S* __restrict__ srcg,
 }
 
 // One g-only sweep (phi and rho_e held fixed): reads g from srcg, writes dstg.
-template <class S, class R, bool DEV>
+template <class S, class R>
 __global__ void k_poisson(const S* __restrict__ srcg, S* __restrict__ dstg,
                           const R* __restrict__ mom, const KP<R> kp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
-  const PopView<S, R, DEV> Pg{make_rsrc(srcg, kp.g_bytes), QG, &kp};
+  const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
+  const PopView<S, R> DG{make_rsrc(dstg, kp.g_bytes), &kp, QG};
   const Cols k = cols_of(x, kp.nx);
   R phi9[9], psi9[9], g4[4];
   hood(mom, kp, x, y, phi9, psi9);
   const long long np = (long long)kp.nx * kp.ny;
   const long long c = (long long)y * kp.nx + x;
-  // psi of the node itself comes from its own pulled g (the plane holds the
-  // same value)
   pull4(Pg, 0, k, y, kp.pitch, g4);
   const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
-  R g[5] = {Pg.at(0, r0 + x, y), g4[0], g4[1], g4[2], g4[3]};
-  const R phi = phi9[0];
-  const R eps = phi * kp.deps + kp.eps_v;
+  R g[5] = {Pg.at(0, r0 + x), g4[0], g4[1], g4[2], g4[3]};
+  const R eps = (R(0.5) + phi9[0]) * kp.deps + kp.eps_v;
   R gphi[2], gpsi[2];
   grad_lap<R>(phi9, gphi, nullptr);
   grad_lap<R>(psi9, gpsi, nullptr);
+  gpsi[1] += kp.psi_slope;
   const R geps[2] = {kp.deps * gphi[0], kp.deps * gphi[1]};
   collide_g(g, psi9[0], poisson_source(mom[2 * np + c], eps, geps, gpsi, kp), kp);
   const uint32_t o = (uint32_t)(y + 1) * kp.pitch + x;
-  // dstg points at the g0 plane (planes relative to the g set)
-  const PopView<S, R, DEV> DG{make_rsrc(dstg, kp.g_bytes), QG, &kp};
-  auto W = [&](int q, uint32_t off, int yrow, R v) { DG.put(q - QG, off, yrow, v); };
-  for (int i = 0; i < 5; ++i) W(QG + i, o, y, g[i]);
+  for (int i = 0; i < 5; ++i) DG.put(i, o, g[i]);
   const uint32_t top = (uint32_t)(kp.ny + 1) * kp.pitch;
   if (kp.walls == WALL_PERIODIC) {
-    if (y == kp.ny - 1) W(QG + 2, k.c, -1, g[2]);
-    if (y == 0) W(QG + 4, top + k.c, kp.ny, g[4]);
+    if (y == kp.ny - 1) DG.put(2, k.c, g[2]);
+    if (y == 0) DG.put(4, top + k.c, g[4]);
   } else {
-    if (y == 0) W(QG + 2, k.c, -1, -g[4] + kp.dpsi / R(3));
-    if (y == kp.ny - 1) W(QG + 4, top + k.c, kp.ny, -g[2]);
+    if (y == 0) DG.put(2, k.c, -g[4]);
+    if (y == kp.ny - 1) DG.put(4, top + k.c, -g[2]);
   }
 }
 
@@ -487,14 +513,17 @@ struct InitSpec {
   uint64_t seed;
   // or host-provided fields (device copies, [ny][nx]); ux/uy may be null
   const double *phi, *cp, *cm, *psi, *ux, *uy;
+  // absolute parameters (FP64)
+  double W, c0, dpsi, rho_v, drho;
 };
 
 // Equilibrium initial state.  The population arriving at node (x, y) along
 // c_i at the first step is the equilibrium there, so it is written where
-// that node pulls it from: row y - c_iy, column x - c_ix.
-template <class S, class R, bool DEV>
-__global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, const KP<R> kp,
-                       const InitSpec sp) {
+// that node pulls it from: row y - c_iy, column x - c_ix, as a deviation from
+// the reference of that row.
+template <class S, class R, class T0>
+__global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restrict__ h0x,
+                       const KP<R> kp, const InitSpec sp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
   const long long c = (long long)y * kp.nx + x;
@@ -509,75 +538,89 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, const KP<R> k
   } else {
     const double dx = x - sp.xc, dy = y - sp.yc;
     const double r = sqrt(dx * dx + dy * dy);
-    phi = 0.5 * (1.0 + tanh(2.0 * (sp.radius - r) / (double)kp.W));
-    const double c0 = sqrt((double)kp.c0sq);
-    cp = c0 * (1.0 + sp.noise * unit_noise(sp.seed, 2 * (uint64_t)c + 1));
-    cm = c0 * (1.0 + sp.noise * unit_noise(sp.seed, 2 * (uint64_t)c + 2));
-    psi = kp.walls == WALL_PERIODIC ? 0.0 : (double)kp.dpsi * (kp.ny - 0.5 - y) / kp.ny;
+    phi = 0.5 * (1.0 + tanh(2.0 * (sp.radius - r) / sp.W));
+    cp = sp.c0 * (1.0 + sp.noise * unit_noise(sp.seed, 2 * (uint64_t)c + 1));
+    cm = sp.c0 * (1.0 + sp.noise * unit_noise(sp.seed, 2 * (uint64_t)c + 2));
+    psi = kp.walls == WALL_PERIODIC ? 0.0 : sp.dpsi * (kp.ny - 0.5 - y) / kp.ny;
   }
-  const double rho = phi * (double)kp.drho + (double)kp.rho_v;
+  const double rho = phi * sp.drho + sp.rho_v;
   const double uu = ux * ux + uy * uy;
   const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   const double w9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const double w5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
-  const PopView<S, R, DEV> D{make_rsrc(dst, kp.pop_bytes), 0, &kp};
+  const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp, 0};
   auto put = [&](int q, int i, double v) {
     int xs = x - cx[i];
     xs = xs < 0 ? xs + kp.nx : (xs >= kp.nx ? xs - kp.nx : xs);
     const int ys = y - cy[i];
-    D.put(q, (uint32_t)(ys + 1) * kp.pitch + xs, ys, (R)v);
+    const double ref = plane_ref(q, ys, kp.ny, kp.walls, sp.c0, sp.dpsi);
+    D.put(q, (uint32_t)(ys + 1) * kp.pitch + xs, (R)(v - ref));
   };
+  // h: the rest population (which does not move) takes phi minus what the
+  // eight stored moving populations hold, so that phi is exact from the start
+  double hrest = phi - 0.5;
   for (int i = 0; i < 9; ++i) {
     const double cu = cx[i] * ux + cy[i] * uy;
     // f: pressure-based equilibrium with p = 0
     put(QF + i, i, rho * w9[i] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-    put(QH + i, i, w9[i] * phi * (1.0 + 3.0 * cu));
+    if (i > 0) {
+      const double dev = w9[i] * phi * (1.0 + 3.0 * cu) - 0.5 * w9[i];
+      const R st = D.stored(QH + i, (R)dev);
+      put(QH + i, i, (double)st + 0.5 * w9[i]);
+      hrest -= (double)st;
+    }
   }
+  *elem(h0x, (uint32_t)y * kp.pitch + x) = (T0)hrest;
   for (int i = 0; i < 5; ++i) {
     const double cu = cx[i] * ux + cy[i] * uy;
     put(QP + i, i, w5[i] * cp * (1.0 + 3.0 * cu));
     put(QN + i, i, w5[i] * cm * (1.0 + 3.0 * cu));
     put(QG + i, i, i == 0 ? -2.0 / 3.0 * psi : psi / 6.0);
   }
-  const long long jo = (long long)y * kp.pitch + x;
-  jprev[jo] = (R)(phi * ux);
-  jprev[(long long)kp.ny * kp.pitch + jo] = (R)(phi * uy);
+  const uint32_t jo = (uint32_t)y * kp.pitch + x;
+  *elem(jprev, jo) = (R)(phi * ux);
+  *elem(jprev, kp.cells + jo) = (R)(phi * uy);
 }
 
 // FP64 sums of one row: [phi, rho_e, sum p, sum n, phi x, phi y, nonfinite].
 // One workgroup per row, fixed-shape tree reduction: the result depends on
 // nx and ny only.
 constexpr int NSUM = 7;
-template <class S, class R, bool DEV>
+template <class S, class R, class T0>
 __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
                                                   const S* __restrict__ srcg,
+                                                  const T0* __restrict__ h0x,
                                                   double* __restrict__ part, const KP<R> kp) {
   __shared__ double sh[NSUM][256];
   const int y = blockIdx.x, t = threadIdx.x;
-  const PopView<S, R, DEV> Ph{make_rsrc(src, kp.pop_bytes), 0, &kp};
-  const PopView<S, R, DEV> Pg{make_rsrc(srcg, kp.g_bytes), QG, &kp};
+  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
+  const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
   double acc[NSUM] = {0, 0, 0, 0, 0, 0, 0};
+  const double c0 = (double)kp.c0;
   for (int x = t; x < kp.nx; x += 256) {
     const Cols k = cols_of(x, kp.nx);
     R h[9], t4[4], g4[4];
     pull9(Ph, QH, k, y, kp.pitch, h);
     const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
+    const double h0 = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
     pull4(Ph, QP, k, y, kp.pitch, t4);
-    const double P = (double)Ph.at(QP, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+    const double Pd = (double)Ph.at(QP, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
     pull4(Ph, QN, k, y, kp.pitch, t4);
-    const double Q = (double)Ph.at(QN, r0 + x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+    const double Qd = (double)Ph.at(QN, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
     pull4(Pg, 0, k, y, kp.pitch, g4);
-    const double phi = (double)sum9(h);
-    const double psi = (double)psi_of(g4);
+    double phid = h0;
+    for (int i = 1; i < 9; ++i) phid += (double)h[i];
+    const double phi = 0.5 + phid;
+    const double psid = (double)psi_of(g4);
     acc[0] += phi;
-    acc[1] += (double)kp.q * (P - Q);
-    acc[2] += P;
-    acc[3] += Q;
+    acc[1] += (double)kp.q * (Pd - Qd);
+    acc[2] += c0 + Pd;
+    acc[3] += c0 + Qd;
     acc[4] += phi * x;
     acc[5] += phi * y;
-    if (!(isfinite(phi) && isfinite(P) && isfinite(Q) && isfinite(psi))) acc[6] += 1.0;
+    if (!(isfinite(phid) && isfinite(Pd) && isfinite(Qd) && isfinite(psid))) acc[6] += 1.0;
   }
   for (int j = 0; j < NSUM; ++j) sh[j][t] = acc[j];
   __syncthreads();
@@ -607,11 +650,11 @@ __global__ __launch_bounds__(256) void k_copy(const void* __restrict__ src,
   for (uint32_t o = (blockIdx.x * blockDim.x + threadIdx.x) * W; o < bytes; o += stride) {
     if (W == 4) {
       const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(rs, o, 0, 0);
-      __builtin_amdgcn_raw_buffer_store_b32(v, rd, o, 0, LBM_STORE_POLICY);
+      __builtin_amdgcn_raw_buffer_store_b32(v, rd, o, 0, 0);
     } else {
       typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
       const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0);
-      __builtin_amdgcn_raw_buffer_store_b128(v, rd, o, 0, LBM_STORE_POLICY);
+      __builtin_amdgcn_raw_buffer_store_b128(v, rd, o, 0, 0);
     }
   }
 }

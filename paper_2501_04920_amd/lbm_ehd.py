@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("LBM_EHD_LIB", os.path.join(HERE, "liblbm_ehd.so"))
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE, LBM_ERANGE = (
     0, -1, -2, -3, -4, -5, -6)
-PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fp32dev": 4, "fp32f64": 5}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fp32f64": 5}
 WALLS = {"electrodes": 0, "insulating": 1, "periodic": 2}
 FIELDS = ("phi", "psi", "cp", "cm", "rhoe", "ux", "uy", "p", "Ex", "Ey")
 FIELD_BITS = {name: 1 << i for i, name in enumerate(FIELDS)}

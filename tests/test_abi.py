@@ -37,10 +37,12 @@ def test_defaults_and_bytes():
     assert (p.nx, p.ny, p.precision, p.walls) == (128, 128, 1, 0)
     assert p.mask_f == 0b111000 and p.mask_h == 0b110 and p.theta == 0.3
     pop, aux = lbm_ehd.lbm_ehd_required_bytes(p)
-    assert pop == 33 * 130 * 128 * 4 and aux == 2 * 128 * 128 * 4
-    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp32") == 280.0
-    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 148.0
-    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp64") == 560.0
+    # (phi u)(t-1) in FP32 and two time levels of the rest population of h in FP64
+    assert pop == 33 * 130 * 128 * 4 and aux == 128 * 128 * (2 * 4 + 2 * 8)
+    # 32 moving planes + rest of h + (phi u), each read and written once
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp32") == 2 * 32 * 4 + 2 * 8 + 2 * 8
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 2 * 32 * 2 + 2 * 4 + 2 * 8
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp64") == 2 * 32 * 8 + 2 * 8 + 2 * 16
 
 
 @pytest.mark.parametrize("bad", [dict(nx=1), dict(v_th=0.0), dict(eta_v=0.0), dict(M_phi=0.0),
