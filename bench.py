@@ -142,7 +142,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16", "bf16"])
+    ap.add_argument("--precision", default="fp32",
+                    choices=["fp64", "fp32", "fp32f64", "fp16", "bf16"])
     ap.add_argument("--n", type=int, default=2048, help="grid n x n (radius n / 6.4)")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
@@ -211,7 +212,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f32", "bf16": "f32"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32f64": "f64", "fp16": "f32",
+                  "bf16": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": workload, "nx": params["nx"], "ny": params["ny"],
                    "radius": drop["radius"], "W": params["W"], "storage": args.precision,

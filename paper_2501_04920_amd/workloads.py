@@ -76,6 +76,13 @@ def config3():
                 droplet=droplet(2048, 320.0), presolve=0, steps=50000)
 
 
+def scaled_restriction():
+    """The 2048^2 case restricted to 512^2 (radius 80, W = 5, same groups):
+    the grid on which the 16-bit storage forms are compared with the oracle."""
+    return dict(name="droplet-512-w5", params=lattice_params(512, 80.0, W=5.0),
+                droplet=droplet(512, 80.0), presolve=0, steps=20000)
+
+
 def scaled(n: int, *, W=4.0, **groups):
     """The droplet case at grid n with radius n / 6.4 (as in the 128^2 case)."""
     r = n / 6.4

@@ -1,0 +1,68 @@
+"""Write the stored oracle references for the long FP32 comparisons.
+
+Runs only the CPU oracle (``oracle/``) on the 512 x 512 droplet cases (radius
+80, W = 4; eps_r in {0.5, 2} x mu_r in {0.5, 2} x Ca_E in {0.25, 1}) for
+20 000 steps, and the 512 x 512, W = 5 restriction of the 2048 x 2048 case,
+and stores per case:
+  - the deformation factor D (Eq. 63) every 500 steps,
+  - the L2 norms of rho_e and |u| every 500 steps,
+  - phi, psi, c+, c-, rho_e, u_x, u_y, p on every 8th row and column at the end.
+Usage: python tests/golden/make_oracle_refs.py [case-name ...]
+Each case takes ~15 min on 8 cores.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2501_04920_amd import workloads  # noqa: E402
+
+EVERY = 500
+SUB = 8
+SAVED = ("phi", "psi", "cp", "cm", "rhoe", "ux", "uy", "p")
+
+
+def cases():
+    out = {c["name"]: c for c in workloads.config2_points()}
+    r = workloads.scaled_restriction()
+    out[r["name"]] = r
+    return out
+
+
+def run(case):
+    p, d = case["params"], case["droplet"]
+    o = oracle.Oracle(p)
+    o.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"], presolve=case["presolve"])
+    steps = case["steps"]
+    t, D, rn, un = [], [], [], []
+    t0 = time.time()
+    for k in range(0, steps + 1, EVERY):
+        if k:
+            o.step(EVERY)
+        f = o.fields()
+        t.append(k)
+        D.append(oracle.deformation(f["phi"])[0])
+        rn.append(float(np.linalg.norm(f["rhoe"])))
+        un.append(float(np.sqrt((f["ux"] ** 2 + f["uy"] ** 2).sum())))
+        print("%s step %d D %.6e (%.0f s)" % (case["name"], k, D[-1], time.time() - t0),
+              flush=True)
+    f = o.fields()
+    np.savez_compressed(os.path.join(HERE, case["name"] + ".npz"),
+                        t=np.array(t), D=np.array(D), rhoe_l2=np.array(rn),
+                        u_l2=np.array(un), sub=SUB,
+                        **{k: f[k][::SUB, ::SUB] for k in SAVED})
+
+
+if __name__ == "__main__":
+    todo = cases()
+    names = sys.argv[1:] or sorted(todo)
+    for n in names:
+        run(todo[n])
