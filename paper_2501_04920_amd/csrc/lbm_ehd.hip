@@ -70,10 +70,8 @@ struct lbm_ehd {
   int64_t step = 0;
   bool ready = false;   // initial state written
   int pitch = 0;
-  long long plane = 0;
   // scratch owned by the library
   void* mom = nullptr;      // phi, psi, rho_e planes (arithmetic type), [3][ny][nx]
-  void* gtmp = nullptr;     // g planes for the extra Poisson sweeps, [5][ny+2][pitch]
   double* fld = nullptr;    // [10][ny][nx]
   double* part = nullptr;   // [ny][NSUM]
   double* red = nullptr;    // [NSUM]
@@ -94,10 +92,10 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.ny = p.ny;
   k.pitch = h->pitch;
   k.walls = p.walls;
-  k.plane = (uint32_t)h->plane;
+  k.rstride = (uint32_t)(NPOP * h->pitch);
   k.cells = (uint32_t)((long long)p.ny * h->pitch);
-  k.pop_bytes = (uint32_t)(NPOP * h->plane * (long long)elem_size(p.precision));
-  k.g_bytes = (uint32_t)(5 * h->plane * (long long)elem_size(p.precision));
+  k.pop_bytes = (uint32_t)h->pop_bytes;
+  k.g_bytes = (uint32_t)(h->pop_bytes - (size_t)QG * h->pitch * elem_size(p.precision));
   k.reaction = p.reaction;
   k.poisson_form = p.poisson_form;
   k.flow = p.flow;
@@ -174,7 +172,7 @@ struct Form {
     const int nb = nstrips * nbands;
     const int chunk = (nb % 8 == 0) ? nb / 8 : 0;
     const S* src = buf(h, h->cur);
-    if (!srcg) srcg = src + (long long)QG * h->plane;
+    if (!srcg) srcg = gset(h, h->cur);
     hipLaunchKernelGGL((k_sweep<S, R, T0>), dim3(nb), dim3(TILE_W), 0, h->stream, src, srcg,
                        buf(h, 1 - h->cur), jp(h), h0(h, h->cur), h0(h, 1 - h->cur), kp, tr,
                        nstrips, nbands, chunk,
@@ -189,19 +187,23 @@ struct Form {
   static lbm_status moments(lbm_ehd* h, const S* srcg) {
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
-    if (!srcg) srcg = src + (long long)QG * h->plane;
+    if (!srcg) srcg = gset(h, h->cur);
     hipLaunchKernelGGL((k_moments<S, R, T0>), grid2(h), dim3(64), 0, h->stream, src, srcg,
                        h0(h, h->cur), static_cast<R*>(h->mom), kp);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
 
-  // `iters` g-only sweeps.  The g planes ping-pong between the state buffer
-  // and the scratch set; returns (in *gsrc) where the latest g lives.
+  // The g set of buffer i: population QG of row 0 (rows keep their stride).
+  static S* gset(lbm_ehd* h, int i) { return buf(h, i) + (size_t)QG * h->pitch; }
+
+  // `iters` g-only sweeps.  The g set ping-pongs between the state buffer and
+  // the g lines of the other buffer, which the next sweep overwrites anyway;
+  // returns (in *gsrc) where the latest g lives.
   static lbm_status poisson(lbm_ehd* h, int iters, const S** gsrc) {
     const KP<R> kp = make_kp<R>(h);
-    S* gA = buf(h, h->cur) + (long long)QG * h->plane;
-    S* gB = static_cast<S*>(h->gtmp);
+    S* gA = gset(h, h->cur);
+    S* gB = gset(h, 1 - h->cur);
     S* from = gA;
     for (int it = 0; it < iters; ++it) {
       lbm_status st = moments(h, from);
@@ -216,22 +218,27 @@ struct Form {
     return LBM_OK;
   }
 
-  // Bring the latest g back into the state buffer (after a pre-solve).
+  // Bring the latest g back into the state buffer: the five g lines of
+  // every row.
   static lbm_status settle_g(lbm_ehd* h, const S* gsrc) {
-    S* gA = buf(h, h->cur) + (long long)QG * h->plane;
-    if (gsrc != gA)
-      HIP_TRY(hipMemcpyAsync(gA, gsrc, 5 * h->plane * sizeof(S), hipMemcpyDeviceToDevice,
-                             h->stream));
+    S* gA = gset(h, h->cur);
+    if (gsrc != gA) {
+      const size_t row = (size_t)NPOP * h->pitch * sizeof(S);
+      HIP_TRY(hipMemcpy2DAsync(gA, row, gsrc, row, 5 * (size_t)h->pitch * sizeof(S),
+                               (size_t)h->P.ny + 2, hipMemcpyDeviceToDevice, h->stream));
+    }
     return LBM_OK;
   }
 
   static lbm_status step(lbm_ehd* h) {
-    const S* g = nullptr;
     if (h->P.poisson_iters > 0) {
+      const S* g = nullptr;
       lbm_status st = poisson(h, h->P.poisson_iters, &g);
       if (st) return st;
+      st = settle_g(h, g);
+      if (st) return st;
     }
-    return sweep(h, g);
+    return sweep(h, nullptr);
   }
 
   static lbm_status presolve(lbm_ehd* h, int iters) {
@@ -265,7 +272,7 @@ struct Form {
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
     hipLaunchKernelGGL((k_row_sums<S, R, T0>), dim3(h->P.ny), dim3(256), 0, h->stream, src,
-                       src + (long long)QG * h->plane, h0(h, h->cur), h->part, kp);
+                       gset(h, h->cur), h0(h, h->cur), h->part, kp);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, h->part, h->P.ny, h->red);
     HIP_TRY(hipGetLastError());
@@ -321,7 +328,6 @@ lbm_status validate(const lbm_ehd_params* p) {
 
 void free_scratch(lbm_ehd* h) {
   (void)hipFree(h->mom);
-  (void)hipFree(h->gtmp);
   (void)hipFree(h->fld);
   (void)hipFree(h->part);
   (void)hipFree(h->red);
@@ -462,7 +468,6 @@ lbm_status lbm_ehd_create(const lbm_ehd_params* p, const lbm_ehd_device* dev, lb
   if (!h) return fail(LBM_ENOMEM, "host allocation failed");
   h->P = *p;
   h->pitch = pitch_of(p->nx);
-  h->plane = (long long)(p->ny + 2) * h->pitch;
   const char* tr = std::getenv("LBM_EHD_TILE_ROWS");
   const int nstrips = (p->nx + TILE_W - 1) / TILE_W;
   // Bands as tall as possible (the h/g rows above and below a band are read
@@ -504,7 +509,6 @@ lbm_status lbm_ehd_create(const lbm_ehd_params* p, const lbm_ehd_device* dev, lb
   const size_t nc = (size_t)p->nx * p->ny;
   const size_t ar = arith_size(p->precision);
   if (hipMalloc(&h->mom, 3 * nc * ar) != hipSuccess ||
-      hipMalloc(&h->gtmp, 5 * (size_t)h->plane * elem_size(p->precision)) != hipSuccess ||
       hipMalloc(&h->fld, 10 * nc * sizeof(double)) != hipSuccess ||
       hipMalloc(&h->part, (size_t)p->ny * NSUM * sizeof(double)) != hipSuccess ||
       hipMalloc(&h->red, NSUM * sizeof(double)) != hipSuccess ||

@@ -36,9 +36,8 @@ __device__ inline Cols cols_of(int xc, int nx) {
 }
 
 template <class S, class R>
-__device__ inline void pull9(const PopView<S, R>& P, int q0, Cols k, int yy, uint32_t pitch,
-                             R x[9]) {
-  const uint32_t r0 = (uint32_t)(yy + 1) * pitch, rm = r0 - pitch, rp = r0 + pitch;
+__device__ inline void pull9(const PopView<S, R>& P, int q0, Cols k, int yy, R x[9]) {
+  const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
   x[0] = P.at(q0 + 0, r0 + k.c);
   x[1] = P.at(q0 + 1, r0 + k.m);
   x[2] = P.at(q0 + 2, rm + k.c);
@@ -52,9 +51,8 @@ __device__ inline void pull9(const PopView<S, R>& P, int q0, Cols k, int yy, uin
 
 // Directions 1..4 of a D2Q5 set (the rest population is pulled separately).
 template <class S, class R>
-__device__ inline void pull4(const PopView<S, R>& P, int q0, Cols k, int yy, uint32_t pitch,
-                             R x[4]) {
-  const uint32_t r0 = (uint32_t)(yy + 1) * pitch, rm = r0 - pitch, rp = r0 + pitch;
+__device__ inline void pull4(const PopView<S, R>& P, int q0, Cols k, int yy, R x[4]) {
+  const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
   x[0] = P.at(q0 + 1, r0 + k.m);
   x[1] = P.at(q0 + 2, rm + k.c);
   x[2] = P.at(q0 + 3, r0 + k.p);
@@ -65,9 +63,9 @@ __device__ inline void pull4(const PopView<S, R>& P, int q0, Cols k, int yy, uin
 // pulled.
 template <class S, class R, class T0>
 __device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x, Cols k,
-                              int yy, uint32_t pitch, R x[9]) {
-  const uint32_t r0 = (uint32_t)(yy + 1) * pitch, rm = r0 - pitch, rp = r0 + pitch;
-  x[0] = (R)*elem(h0x, (uint32_t)yy * pitch + k.c);
+                              int yy, R x[9]) {
+  const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
+  x[0] = (R)*elem(h0x, (uint32_t)yy * P.kp->pitch + k.c);
   x[1] = P.at(QH + 1, r0 + k.m);
   x[2] = P.at(QH + 2, rm + k.c);
   x[3] = P.at(QH + 3, r0 + k.p);
@@ -126,7 +124,7 @@ struct Ghosts {
   const KP<R>& kp;
   int y;
   Cols k;
-  __device__ inline uint32_t top() const { return (uint32_t)(kp.ny + 1) * kp.pitch; }
+  __device__ inline uint32_t top() const { return D.row(kp.ny + 1); }
   // D2Q9 set starting at plane q0 (f or h): bounce-back at walls
   __device__ inline void set9(int q0, const R x[9]) const {
     if (kp.walls == WALL_PERIODIC) {
@@ -177,7 +175,7 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   Macro<R> m;
   macro(phi9, psi9, Pd, Qd, f, kp, m);
 
-  const uint32_t o = (uint32_t)(y + 1) * kp.pitch + x;
+  const uint32_t o = D.row(y + 1) + x;
   const bool edge = y == 0 || y == kp.ny - 1;
   const Ghosts<S, R> G{D, kp, y, k};
   const bool ins = kp.walls == WALL_INSULATING;
@@ -187,7 +185,7 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     R g[5];
     g[0] = g0;
     hg.g4(g + 1);
-    collide_g(g, m.psid, poisson_source(m.rhoe, m.eps, m.geps, m.gpsi, kp), kp);
+    collide_g(g, m.psid, poisson_source(m.rhoe, m.ieps, m.geps, m.gpsi, kp), kp);
 #pragma unroll
     for (int i = 0; i < 5; ++i) D.put(QG + i, o, g[i]);
     if (edge) G.set5(QG, g, -g[4], -g[2]);
@@ -281,7 +279,6 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
     band = t - strip * nbands;
   }
   const int nx = kp.nx, ny = kp.ny;
-  const uint32_t pitch = kp.pitch;
   const int x0 = strip * TILE_W, y0 = band * tile_rows;
   const int w = min(TILE_W, nx - x0);
   const int lane = threadIdx.x;
@@ -306,15 +303,15 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
     const int sl = slot(yy);
     if (lane < 2) {
       R hh[9], gg[4];
-      pull_h(Ph, h0x, kh, ys, pitch, hh);
-      pull4(Pg, 0, kh, ys, pitch, gg);
+      pull_h(Ph, h0x, kh, ys, hh);
+      pull4(Pg, 0, kh, ys, gg);
       s_phi[sl][kcol] = sum9(hh);
       s_psi[sl][kcol] = psi_of(gg);
     }
     if (valid) {
       R h[9], g4[4];
-      pull_h(Ph, h0x, k, ys, pitch, h);
-      pull4(Pg, 0, k, ys, pitch, g4);
+      pull_h(Ph, h0x, k, ys, h);
+      pull4(Pg, 0, k, ys, g4);
       s_phi[sl][lane + 1] = sum9(h);
       s_psi[sl][lane + 1] = psi_of(g4);
       const int b = (yy - y0 + 2) & 1;
@@ -331,6 +328,19 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
   for (int y = y0; y < yend; ++y) {
     const bool up = y + 1 < ny || periodic;
     const bool down = y > 0 || periodic;
+    // The row's own f, p, n and g0 are requested before the ring row, so that
+    // both sets of loads are in flight together (one memory round trip per
+    // row instead of two).  Lanes past the grid edge read column x0.
+    R f[9], p[5], n[5], t4[4];
+    pull9(Ph, QF, k, y, f);
+    const uint32_t r0 = Ph.row(y + 1);
+    p[0] = Ph.at(QP, r0 + x);
+    n[0] = Ph.at(QN, r0 + x);
+    const R g0 = Pg.at(0, r0 + x);
+    pull4(Ph, QP, k, y, t4);
+    p[1] = t4[0]; p[2] = t4[1]; p[3] = t4[2]; p[4] = t4[3];
+    pull4(Ph, QN, k, y, t4);
+    n[1] = t4[0]; n[2] = t4[1]; n[3] = t4[2]; n[4] = t4[3];
     if (up) ring_row(y + 1);
     __syncthreads();
     if (valid) {
@@ -356,16 +366,6 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
       nine(phD, phC, phU, phi9);
       nine(psD, psC, psU, psi9);
 
-      R f[9], p[5], n[5], t4[4];
-      pull9(Ph, QF, k, y, pitch, f);
-      const uint32_t r0 = (uint32_t)(y + 1) * pitch;
-      p[0] = Ph.at(QP, r0 + x);
-      n[0] = Ph.at(QN, r0 + x);
-      const R g0 = Pg.at(0, r0 + x);
-      pull4(Ph, QP, k, y, pitch, t4);
-      p[1] = t4[0]; p[2] = t4[1]; p[3] = t4[2]; p[4] = t4[3];
-      pull4(Ph, QN, k, y, pitch, t4);
-      n[1] = t4[0]; n[2] = t4[1]; n[3] = t4[2]; n[4] = t4[3];
       const HGLds<R> hg{s_pull[(y - y0 + 2) & 1], lane};
       update_node<S, R, T0>(D, jprev, h0x, h0dst, kp, x, y, k, phi9, psi9, f, p, n, g0, hg);
     }
@@ -386,12 +386,12 @@ __global__ void k_moments(const S* __restrict__ src, const S* __restrict__ srcg,
   const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
   const Cols k = cols_of(x, kp.nx);
   R h[9], g4[4], t4[4];
-  pull_h(Ph, h0x, k, y, kp.pitch, h);
-  pull4(Pg, 0, k, y, kp.pitch, g4);
-  const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
-  pull4(Ph, QP, k, y, kp.pitch, t4);
+  pull_h(Ph, h0x, k, y, h);
+  pull4(Pg, 0, k, y, g4);
+  const uint32_t r0 = Ph.row(y + 1);
+  pull4(Ph, QP, k, y, t4);
   const R Pd = Ph.at(QP, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
-  pull4(Ph, QN, k, y, kp.pitch, t4);
+  pull4(Ph, QN, k, y, t4);
   const R Qd = Ph.at(QN, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
   const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
   mom[c] = sum9(h);
@@ -437,11 +437,11 @@ __global__ void k_fields(const S* __restrict__ src, const R* __restrict__ mom,
   const Cols k = cols_of(x, kp.nx);
   R phi9[9], psi9[9], f[9], t4[4];
   hood(mom, kp, x, y, phi9, psi9);
-  pull9(Ph, QF, k, y, kp.pitch, f);
-  const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
-  pull4(Ph, QP, k, y, kp.pitch, t4);
+  pull9(Ph, QF, k, y, f);
+  const uint32_t r0 = Ph.row(y + 1);
+  pull4(Ph, QP, k, y, t4);
   const R Pd = Ph.at(QP, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
-  pull4(Ph, QN, k, y, kp.pitch, t4);
+  pull4(Ph, QN, k, y, t4);
   const R Qd = Ph.at(QN, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
   Macro<R> m;
   macro(phi9, psi9, Pd, Qd, f, kp, m);
@@ -473,8 +473,8 @@ __global__ void k_poisson(const S* __restrict__ srcg, S* __restrict__ dstg,
   hood(mom, kp, x, y, phi9, psi9);
   const long long np = (long long)kp.nx * kp.ny;
   const long long c = (long long)y * kp.nx + x;
-  pull4(Pg, 0, k, y, kp.pitch, g4);
-  const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
+  pull4(Pg, 0, k, y, g4);
+  const uint32_t r0 = Pg.row(y + 1);
   R g[5] = {Pg.at(0, r0 + x), g4[0], g4[1], g4[2], g4[3]};
   const R eps = (R(0.5) + phi9[0]) * kp.deps + kp.eps_v;
   R gphi[2], gpsi[2];
@@ -482,10 +482,10 @@ __global__ void k_poisson(const S* __restrict__ srcg, S* __restrict__ dstg,
   grad_lap<R>(psi9, gpsi, nullptr);
   gpsi[1] += kp.psi_slope;
   const R geps[2] = {kp.deps * gphi[0], kp.deps * gphi[1]};
-  collide_g(g, psi9[0], poisson_source(mom[2 * np + c], eps, geps, gpsi, kp), kp);
-  const uint32_t o = (uint32_t)(y + 1) * kp.pitch + x;
+  collide_g(g, psi9[0], poisson_source(mom[2 * np + c], recip(eps), geps, gpsi, kp), kp);
+  const uint32_t o = DG.row(y + 1) + x;
   for (int i = 0; i < 5; ++i) DG.put(i, o, g[i]);
-  const uint32_t top = (uint32_t)(kp.ny + 1) * kp.pitch;
+  const uint32_t top = DG.row(kp.ny + 1);
   if (kp.walls == WALL_PERIODIC) {
     if (y == kp.ny - 1) DG.put(2, k.c, g[2]);
     if (y == 0) DG.put(4, top + k.c, g[4]);
@@ -556,7 +556,7 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
     xs = xs < 0 ? xs + kp.nx : (xs >= kp.nx ? xs - kp.nx : xs);
     const int ys = y - cy[i];
     const double ref = plane_ref(q, ys, kp.ny, kp.walls, sp.c0, sp.dpsi);
-    D.put(q, (uint32_t)(ys + 1) * kp.pitch + xs, (R)(v - ref));
+    D.put(q, D.row(ys + 1) + xs, (R)(v - ref));
   };
   // h: the rest population (which does not move) takes phi minus what the
   // eight stored moving populations hold, so that phi is exact from the start
@@ -602,14 +602,14 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
   for (int x = t; x < kp.nx; x += 256) {
     const Cols k = cols_of(x, kp.nx);
     R h[9], t4[4], g4[4];
-    pull9(Ph, QH, k, y, kp.pitch, h);
-    const uint32_t r0 = (uint32_t)(y + 1) * kp.pitch;
+    pull9(Ph, QH, k, y, h);
+    const uint32_t r0 = Ph.row(y + 1);
     const double h0 = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
-    pull4(Ph, QP, k, y, kp.pitch, t4);
+    pull4(Ph, QP, k, y, t4);
     const double Pd = (double)Ph.at(QP, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
-    pull4(Ph, QN, k, y, kp.pitch, t4);
+    pull4(Ph, QN, k, y, t4);
     const double Qd = (double)Ph.at(QN, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
-    pull4(Pg, 0, k, y, kp.pitch, g4);
+    pull4(Pg, 0, k, y, g4);
     double phid = h0;
     for (int i = 1; i < 9; ++i) phid += (double)h[i];
     const double phi = 0.5 + phid;
