@@ -145,7 +145,11 @@ def main():
     ap.add_argument("--precision", default="fp32",
                     choices=["fp64", "fp32", "fp32f64", "fp16", "bf16"])
     ap.add_argument("--n", type=int, default=2048, help="grid n x n (radius n / 6.4)")
-    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=64)
+    ap.add_argument("--waves", type=int, default=0,
+                    help="wavefronts per sweep workgroup (1, 2, 4, 8; 0 = library default)")
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="rows per sweep band (0 = library default)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run the copy-kernel calibration of this size")
@@ -181,6 +185,10 @@ def main():
     torch.cuda.set_device(dev)
     sim = lbm_ehd.Simulation(dict(params, precision=args.precision), device=dev)
     sim.init_droplet(drop["xc"], drop["yc"], drop["radius"], drop["noise"], drop["seed"])
+    if args.waves or args.tile_rows:
+        w0, r0 = sim.launch
+        sim.set_launch(args.waves or w0, args.tile_rows or r0)
+    waves, tile_rows = sim.launch
     stream = sim.stream
     sim.step(args.warmup)
     sim.synchronize()
@@ -218,7 +226,7 @@ def main():
         "config": {"workload": workload, "nx": params["nx"], "ny": params["ny"],
                    "radius": drop["radius"], "W": params["W"], "storage": args.precision,
                    "poisson_sweeps_per_step": 1 + params["poisson_iters"],
-                   "bytes_per_lup": bpl},
+                   "bytes_per_lup": bpl, "waves": waves, "tile_rows": tile_rows},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_sweep",

@@ -235,6 +235,15 @@ LBM_API lbm_status lbm_ehd_diagnostics(lbm_ehd *h, lbm_ehd_diag *out);
 /* Current step count. */
 LBM_API int64_t lbm_ehd_time(const lbm_ehd *h);
 
+/* Launch shape of the fused sweep: `waves` wavefronts per workgroup (1, 2 or
+ * or 8; a workgroup owns a strip of 64 * waves columns and walks down a band of
+ * `tile_rows` rows, tile_rows >= 1, clamped to ny).  Results do not depend on
+ * the shape (every node runs the same arithmetic), only the speed does.
+ * lbm_ehd_create picks a default from the grid size; the shape applies from
+ * the next step.  LBM_EINVAL on other values. */
+LBM_API lbm_status lbm_ehd_set_launch(lbm_ehd *h, int32_t waves, int32_t tile_rows);
+LBM_API lbm_status lbm_ehd_get_launch(const lbm_ehd *h, int32_t *waves, int32_t *tile_rows);
+
 /* Wait for all work of the handle.  LBM_EDEVICE if a kernel failed. */
 LBM_API lbm_status lbm_ehd_synchronize(lbm_ehd *h);
 
@@ -244,8 +253,10 @@ LBM_API lbm_status lbm_ehd_destroy(lbm_ehd *h);
 /* Message of the last error on the calling thread ("" if none). */
 LBM_API const char *lbm_ehd_last_error(void);
 
-/* Algorithmic HBM bytes one lattice update moves in the fused sweep:
- * 2 x 33 populations x storage width + (phi u) read and write. */
+/* Algorithmic HBM bytes one lattice update moves in the fused sweep: the 32
+ * moving populations in the storage type, the rest population of h in its
+ * wider type and (phi u)(t-1) in the arithmetic type, each read and written
+ * once. */
 LBM_API double lbm_ehd_bytes_per_lup(int32_t precision);
 
 /* Measurement helper, not part of the method: copy `bytes` (a multiple of

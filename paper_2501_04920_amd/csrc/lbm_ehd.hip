@@ -78,6 +78,7 @@ struct lbm_ehd {
   double* line = nullptr;   // [2 ny + 2 nx]
   double* upl = nullptr;    // uploaded initial fields [6][ny][nx]
   int tile_rows = 16;
+  int waves = 1;        // wavefronts per sweep workgroup (strip of 64 * waves columns)
   int band_major = 1;
 };
 
@@ -164,19 +165,27 @@ struct Form {
            (size_t)i * h->P.ny * h->pitch;
   }
 
-  static lbm_status sweep(lbm_ehd* h, const S* srcg) {
-    const KP<R> kp = make_kp<R>(h);
-    const int nstrips = (h->P.nx + TILE_W - 1) / TILE_W;
+  template <int NW>
+  static void launch_sweep(lbm_ehd* h, const S* srcg, const KP<R>& kp) {
+    const int nstrips = (h->P.nx + 64 * NW - 1) / (64 * NW);
     const int tr = h->tile_rows;
     const int nbands = (h->P.ny + tr - 1) / tr;
     const int nb = nstrips * nbands;
     const int chunk = (nb % 8 == 0) ? nb / 8 : 0;
-    const S* src = buf(h, h->cur);
+    hipLaunchKernelGGL((k_sweep<S, R, T0, NW>), dim3(nb), dim3(64 * NW), 0, h->stream,
+                       buf(h, h->cur), srcg, buf(h, 1 - h->cur), jp(h), h0(h, h->cur),
+                       h0(h, 1 - h->cur), kp, tr, nstrips, nbands, chunk, h->band_major);
+  }
+
+  static lbm_status sweep(lbm_ehd* h, const S* srcg) {
+    const KP<R> kp = make_kp<R>(h);
     if (!srcg) srcg = gset(h, h->cur);
-    hipLaunchKernelGGL((k_sweep<S, R, T0>), dim3(nb), dim3(TILE_W), 0, h->stream, src, srcg,
-                       buf(h, 1 - h->cur), jp(h), h0(h, h->cur), h0(h, 1 - h->cur), kp, tr,
-                       nstrips, nbands, chunk,
-                       h->band_major);
+    switch (h->waves) {
+      case 8: launch_sweep<8>(h, srcg, kp); break;
+      case 4: launch_sweep<4>(h, srcg, kp); break;
+      case 2: launch_sweep<2>(h, srcg, kp); break;
+      default: launch_sweep<1>(h, srcg, kp); break;
+    }
     HIP_TRY(hipGetLastError());
     h->cur = 1 - h->cur;
     return LBM_OK;
@@ -340,6 +349,21 @@ void free_scratch(lbm_ehd* h) {
   }
 }
 
+// Default launch shape of the sweep for a grid: strips of 256 columns (four
+// waves in step) where the grid is that wide, and the tallest band (the h/g
+// rows above and below a band are read twice) that still puts about 4096
+// wavefronts in flight, four per SIMD.  Measured on MI355X at 2048^2 in FP32
+// (GLUPS): 1 wave 15.8-16.0, 2 waves 16.3-16.8, 4 waves 17.1-17.5, 8 waves
+// 16.6-17.6, bands of 4-32 rows within 2 % of each other; bands of 64 rows
+// leave too few workgroups (12.9-13.8).
+void default_launch(const lbm_ehd_params* p, int* waves, int* tile_rows) {
+  *waves = p->nx >= 256 ? 4 : (p->nx >= 128 ? 2 : 1);
+  const long long strips = (p->nx + 64 * *waves - 1) / (64 * *waves);
+  int rows = 32;
+  while (rows > 2 && strips * *waves * ((p->ny + rows - 1) / rows) < 4096) rows /= 2;
+  *tile_rows = std::min(rows, p->ny);
+}
+
 void fill_init_params(const lbm_ehd* h, InitSpec* sp) {
   sp->W = h->P.W;
   sp->c0 = h->P.c0;
@@ -468,16 +492,7 @@ lbm_status lbm_ehd_create(const lbm_ehd_params* p, const lbm_ehd_device* dev, lb
   if (!h) return fail(LBM_ENOMEM, "host allocation failed");
   h->P = *p;
   h->pitch = pitch_of(p->nx);
-  const char* tr = std::getenv("LBM_EHD_TILE_ROWS");
-  const int nstrips = (p->nx + TILE_W - 1) / TILE_W;
-  // Bands as tall as possible (the h/g rows above and below a band are read
-  // twice) while keeping >= 2048 single-wave workgroups (8 per CU) in flight;
-  // measured on MI355X at 2048^2: 32 rows 16.5 GLUPS, 16 rows 15.2, 64 rows 12.0.
-  int rows = (int)std::max<long long>(1, (long long)nstrips * p->ny / 2048);
-  h->tile_rows = std::min(32, std::max(2, rows));
-  if (tr && std::atoi(tr) > 0) h->tile_rows = std::atoi(tr);
-  const char* bm = std::getenv("LBM_EHD_BAND_MAJOR");
-  if (bm) h->band_major = std::atoi(bm) != 0;
+  default_launch(p, &h->waves, &h->tile_rows);
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return fail(LBM_EDEVICE, "no HIP device");
@@ -669,6 +684,23 @@ lbm_status lbm_ehd_diagnostics(lbm_ehd* h, lbm_ehd_diag* out) {
 }
 
 int64_t lbm_ehd_time(const lbm_ehd* h) { return h ? h->step : -1; }
+
+lbm_status lbm_ehd_set_launch(lbm_ehd* h, int32_t waves, int32_t tile_rows) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (waves != 1 && waves != 2 && waves != 4 && waves != 8)
+    return fail(LBM_EINVAL, "waves must be 1, 2, 4 or 8");
+  if (tile_rows < 1) return fail(LBM_EINVAL, "tile_rows must be >= 1");
+  h->waves = waves;
+  h->tile_rows = std::min<int32_t>(tile_rows, h->P.ny);
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_get_launch(const lbm_ehd* h, int32_t* waves, int32_t* tile_rows) {
+  if (!h || !waves || !tile_rows) return fail(LBM_EINVAL, "NULL argument");
+  *waves = h->waves;
+  *tile_rows = h->tile_rows;
+  return LBM_OK;
+}
 
 lbm_status lbm_ehd_synchronize(lbm_ehd* h) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");

@@ -2,14 +2,18 @@
 //
 // k_sweep is the hot path: one pass over the grid advances f, h, p, n and g
 // by one time step (pull streaming fused with the collisions).  Each
-// workgroup is one wavefront that owns a 64-column strip of a band of rows and
-// walks down the band.  phi and psi, needed at the eight neighbours for the
-// isotropic stencils (Eq. 59), are the moments of the *pulled* h and g of
-// those neighbours, so the wave computes them one row ahead into a small LDS
-// ring (5 rows x 66 columns, the two halo columns by lanes 0 and 1) and parks
-// the pulled h and g of that row in LDS for the row's own update.  Every
-// population is read once and written once per step; only h and g of the two
-// halo columns and of the row above a band are read twice (from L2).
+// workgroup of NW wavefronts owns a strip of 64 NW columns of a band of rows
+// and walks down the band, one row per barrier, so that its waves read each
+// row's lines together (the pull shifts and strip edges then fall in lines
+// the workgroup is already fetching; measured on MI355X, four waves in step
+// draw ~15 % more bandwidth than independent single-wave strips).  phi and
+// psi, needed at the eight neighbours for the isotropic stencils (Eq. 59),
+// are the moments of the *pulled* h and g of those neighbours, so the
+// workgroup computes them one row ahead into a small LDS ring (5 rows x
+// 64 NW + 2 columns, the two halo columns by threads 0 and 1) and each thread
+// parks the pulled h and g of its node in LDS for the row's own update.
+// Every population is read once and written once per step; only h and g of
+// the two halo columns and of the rows above a band are read twice.
 #pragma once
 
 #include "lbm_ehd_device.hpp"
@@ -235,10 +239,10 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   if (edge) G.set9(QF, f);
 }
 
-// h and directions 1-4 of g of one node parked in LDS, one column per lane.
-template <class R>
+// h and directions 1-4 of g of one node parked in LDS, one column per thread.
+template <class R, int TW>
 struct HGLds {
-  const R (*s)[TILE_W];
+  const R (*s)[TW];
   int lane;
   __device__ inline void h9(R o[9]) const {
 #pragma unroll
@@ -250,18 +254,19 @@ struct HGLds {
   }
 };
 
-// The fused sweep.  grid = nstrips * nbands workgroups of 64 lanes.
-template <class S, class R, class T0>
-__global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
+// The fused sweep.  grid = nstrips * nbands workgroups of 64 NW threads.
+template <class S, class R, class T0, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep(const S* __restrict__ src,
                                               const S* __restrict__ srcg,
                                               S* __restrict__ dst, R* __restrict__ jprev,
                                               const T0* __restrict__ h0x,
                                               T0* __restrict__ h0dst, const KP<R> kp,
                                               int tile_rows, int nstrips, int nbands,
                                               int xcd_chunk, int band_major) {
-  __shared__ R s_phi[RING][TILE_W + 2];
-  __shared__ R s_psi[RING][TILE_W + 2];
-  __shared__ R s_pull[2][13][TILE_W];  // pulled h and g1-4 of a row, by row parity
+  constexpr int TW = 64 * NW;
+  __shared__ R s_phi[RING][TW + 2];
+  __shared__ R s_psi[RING][TW + 2];
+  __shared__ R s_pull[2][13][TW];  // pulled h and g1-4 of a row, by row parity
 
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
   // contiguous run of tiles.  Within a run, tiles go band by band across all
@@ -279,8 +284,8 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
     band = t - strip * nbands;
   }
   const int nx = kp.nx, ny = kp.ny;
-  const int x0 = strip * TILE_W, y0 = band * tile_rows;
-  const int w = min(TILE_W, nx - x0);
+  const int x0 = strip * TW, y0 = band * tile_rows;
+  const int w = min(TW, nx - x0);
   const int lane = threadIdx.x;
   const bool valid = lane < w;
   const int x = x0 + (valid ? lane : 0);
@@ -366,7 +371,7 @@ __global__ __launch_bounds__(64) void k_sweep(const S* __restrict__ src,
       nine(phD, phC, phU, phi9);
       nine(psD, psC, psU, psi9);
 
-      const HGLds<R> hg{s_pull[(y - y0 + 2) & 1], lane};
+      const HGLds<R, TW> hg{s_pull[(y - y0 + 2) & 1], lane};
       update_node<S, R, T0>(D, jprev, h0x, h0dst, kp, x, y, k, phi9, psi9, f, p, n, g0, hg);
     }
   }

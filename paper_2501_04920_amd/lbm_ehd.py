@@ -113,6 +113,8 @@ def lib() -> ctypes.CDLL:
             "lbm_ehd_diagnostics": [vp, P(lbm_ehd_diag)],
             "lbm_ehd_synchronize": [vp],
             "lbm_ehd_destroy": [vp],
+            "lbm_ehd_set_launch": [vp, ctypes.c_int32, ctypes.c_int32],
+            "lbm_ehd_get_launch": [vp, P(ctypes.c_int32), P(ctypes.c_int32)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -222,6 +224,16 @@ def lbm_ehd_destroy(h):
     _check(lib().lbm_ehd_destroy(h))
 
 
+def lbm_ehd_set_launch(h, waves: int, tile_rows: int):
+    _check(lib().lbm_ehd_set_launch(h, waves, tile_rows))
+
+
+def lbm_ehd_get_launch(h):
+    w, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lbm_ehd_get_launch(h, ctypes.byref(w), ctypes.byref(r)))
+    return w.value, r.value
+
+
 def lbm_ehd_stream_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream_ptr: int, width=4):
     _check(lib().lbm_ehd_stream_copy(src_ptr, dst_ptr, nbytes, stream_ptr, width))
 
@@ -326,3 +338,11 @@ class Simulation:
 
     def synchronize(self):
         lbm_ehd_synchronize(self.handle)
+
+    def set_launch(self, waves: int, tile_rows: int):
+        lbm_ehd_set_launch(self.handle, waves, tile_rows)
+        return self
+
+    @property
+    def launch(self):
+        return lbm_ehd_get_launch(self.handle)

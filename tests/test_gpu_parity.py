@@ -167,6 +167,42 @@ def test_bitwise_repeatable_fp32():
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_launch_shape_does_not_change_results(precision):
+    """Every node runs the same arithmetic whatever the strip width (waves
+    per workgroup) and band height: results are bitwise equal.  300 x 70
+    leaves a ragged last strip for every width and a short last band."""
+    p = workloads.lattice_params(70, 12.0)
+    p["nx"] = 300
+    d = dict(xc=149.5, yc=34.5, radius=12.0, noise=1e-3, seed=3)
+    ref = None
+    for waves, rows in ((1, 1), (1, 7), (2, 16), (4, 3), (4, 32), (8, 5), (8, 70)):
+        sim = lbm_ehd.Simulation(dict(p, precision=precision), device="cuda:0")
+        sim.set_launch(waves, rows)
+        assert sim.launch == (waves, rows)
+        sim.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"], presolve=4)
+        sim.step(60)
+        f = sim.fields()
+        sim.close()
+        if ref is None:
+            ref = f
+            continue
+        for k in ALL10:
+            assert np.array_equal(f[k], ref[k]), (waves, rows, k)
+
+
+def test_set_launch_rejects_bad_shapes():
+    sim = lbm_ehd.Simulation(dict(workloads.lattice_params(32, 5.0), precision="fp32"),
+                             device="cuda:0")
+    for waves, rows in ((3, 8), (16, 8), (0, 8), (4, 0), (1, -2)):
+        with pytest.raises(lbm_ehd.LbmError) as e:
+            sim.set_launch(waves, rows)
+        assert e.value.code == lbm_ehd.LBM_EINVAL
+    sim.set_launch(2, 1000)           # clamped to ny
+    assert sim.launch == (2, 32)
+    sim.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "bf16"])
 def test_sum_phi_conserved(precision):
     cfg = workloads.config1()
