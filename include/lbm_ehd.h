@@ -119,6 +119,12 @@ typedef struct {
   double gamma_v;          /* Onsager constant of Eq. (6) in the outer phase; gamma ~ 1/eps */
   double force_x, force_y; /* external body-force density added to F (tests) */
   double s_free;           /* rate of the MRT rows not in the masks (1.0 in Sec. 6) */
+  double n_eps;            /* the unit normal grad(phi)/|grad(phi)| of Eq. (1), (32) is
+                              evaluated as grad(phi)/sqrt(|grad(phi)|^2 + n_eps^2)
+                              (default 1e-4): the bare form is undefined where
+                              grad(phi) = 0 and lambda is not small (a droplet's centre),
+                              and there it turns rounding into O(1e-5) changes of phi.
+                              0: bare form, taken as 0 where |grad(phi)| < 1e-12 */
 } lbm_ehd_params;
 
 /*

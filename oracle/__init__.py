@@ -57,7 +57,7 @@ class OracleParams(ctypes.Structure):
         ("m_ratio", ctypes.c_double), ("v_th", ctypes.c_double),
         ("c0", ctypes.c_double), ("q", ctypes.c_double), ("gamma_v", ctypes.c_double),
         ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
-        ("s_free", ctypes.c_double),
+        ("s_free", ctypes.c_double), ("n_eps", ctypes.c_double),
     ]
 
 
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
         L.orc_fforce.argtypes = [ctypes.c_double] * 6 + [dp]
         L.orc_heq.argtypes = [ctypes.c_double] * 3 + [dp]
         L.orc_hforce.argtypes = [ctypes.c_double] * 6 + [dp]
+        L.orc_unit_normal.argtypes = [ctypes.c_double] * 3 + [dp]
         L.orc_ioneq.argtypes = [ctypes.c_double] * 3 + [dp]
         L.orc_ionsrc.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, dp]
         L.orc_iondrift.argtypes = [ctypes.c_double] * 4 + [dp]
@@ -244,6 +245,10 @@ def fforce(ux, uy, grx, gry, Fx, Fy):
 
 def heq(phi, ux, uy):
     return _vec(lib().orc_heq, 9, phi, ux, uy)
+
+
+def unit_normal(gx, gy, n_eps):
+    return _vec(lib().orc_unit_normal, 2, gx, gy, n_eps)
 
 
 def hforce(dJx, dJy, nx, ny, phi, W):

@@ -53,7 +53,14 @@
  *     anti-bounces back with the concentration of the wall node itself;
  *   - stencil ghosts: phi mirrored across the wall, psi odd about the wall
  *     value; grad(rho) and grad(eps) follow from grad(phi) by Eq. (61);
- *   - the unit normal grad(phi)/|grad(phi)| is taken as 0 where
+ *   - the unit normal grad(phi)/|grad(phi)| of Eq. (1) and (32) is undefined
+ *     where grad(phi) = 0, which happens where lambda of Eq. (2) is not
+ *     small (the centre of a droplet, phi < 1 there); next to such a point
+ *     its direction follows the rounding of grad(phi), and the step turns
+ *     a 1e-15 change of one population into a 1e-5 change of phi within
+ *     1000 steps.  It is evaluated as grad(phi)/sqrt(|grad(phi)|^2 + n_eps^2)
+ *     (default n_eps = 1e-4 in lattice units, far below the interface's
+ *     |grad(phi)| ~ 1/W); n_eps = 0 selects the bare form, taken as 0 where
  *     |grad(phi)| < 1e-12;
  *   - d(phi u)/dt at the first step uses (phi u)(t-1) = 0.
  */
@@ -132,6 +139,7 @@ typedef struct {
   double gamma_v;        /* Onsager constant of Eq. (6) in the outer phase */
   double force_x, force_y; /* external body-force density (tests) */
   double s_free;         /* rate of the free MRT rows */
+  double n_eps;          /* regularisation of the unit normal (0: bare form) */
 } orc_params;
 
 typedef struct {
@@ -283,6 +291,24 @@ static void heq(double phi, const double *u, double *out) {
 }
 
 /* Eq. (32): dJ = d(phi u)/dt, nhat = grad(phi)/|grad(phi)|. */
+/* The unit normal grad(phi)/|grad(phi)| of Eq. (1) and (32), regularised
+ * as grad(phi)/sqrt(|grad(phi)|^2 + n_eps^2); n_eps = 0: the bare form,
+ * taken as 0 where |grad(phi)| < 1e-12. */
+static void unit_normal(const double g[2], double n_eps, double n[2]) {
+  double g2 = g[0] * g[0] + g[1] * g[1];
+  if (n_eps > 0.0) {
+    double d = sqrt(g2 + n_eps * n_eps);
+    n[0] = g[0] / d;
+    n[1] = g[1] / d;
+  } else if (sqrt(g2) >= 1e-12) {
+    double d = sqrt(g2);
+    n[0] = g[0] / d;
+    n[1] = g[1] / d;
+  } else {
+    n[0] = n[1] = 0.0;
+  }
+}
+
 static void hforce(const double *dJ, const double *nhat, double phi, double W, double *out) {
   double lam = 4.0 * phi * (1.0 - phi) / W; /* Eq. (2) */
   for (int i = 0; i < 9; ++i) {
@@ -503,12 +529,8 @@ static void collide_at(orc_state *s, int x, int y, mrt_memo *mm) {
   }
 
   /* h, Eq. (27) with Eq. (29)-(32). */
-  double gn = sqrt(m.gphi[0] * m.gphi[0] + m.gphi[1] * m.gphi[1]);
-  double nhat[2] = {0.0, 0.0};
-  if (gn >= 1e-12) {
-    nhat[0] = m.gphi[0] / gn;
-    nhat[1] = m.gphi[1] / gn;
-  }
+  double nhat[2];
+  unit_normal(m.gphi, P->n_eps, nhat);
   for (int i = 0; i < 9; ++i) x9[i] = s->pop[(OF_H + i) * nc + c];
   rates(9, P->mask_h, m.tau_h, P->s_free, sv);
   mrt_cached(mm, 1, 9, M9, s->M9i, sv, &A9, &B9);
@@ -707,6 +729,7 @@ ORC_API void orc_params_default(orc_params *p) {
   p->q = 0.0;
   p->gamma_v = 0.0;
   p->s_free = 1.0;
+  p->n_eps = 1e-4;
 }
 
 ORC_API orc_state *orc_create(const orc_params *p) {
@@ -942,6 +965,10 @@ ORC_API void orc_iondrift(double mu, double c, double gx, double gy, double *out
   iondrift(mu, c, g, out);
 }
 ORC_API void orc_geq(double psi, double *out) { geq(psi, out); }
+ORC_API void orc_unit_normal(double gx, double gy, double n_eps, double *out) {
+  double g[2] = {gx, gy};
+  unit_normal(g, n_eps, out);
+}
 ORC_API void orc_ion_solve(double cbp, double cbm, double lam0, double *cp_cm) {
   ion_solve(cbp, cbm, lam0, &cp_cm[0], &cp_cm[1]);
 }

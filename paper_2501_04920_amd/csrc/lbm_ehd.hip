@@ -125,6 +125,7 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.W = (R)p.W;
   k.fourW = (R)(4.0 / p.W);
   k.s_free = (R)p.s_free;
+  k.n_eps2 = (R)(p.n_eps * p.n_eps);
   k.inv_tau_h = (R)(1.0 / (0.5 + 3.0 * p.M_phi));
   k.inv_tau_g = (R)(1.0 / (0.5 + 3.0 * p.theta));
   k.theta_src = (R)(p.poisson_norm ? p.theta * 1.5 : p.theta);  // 1/(1 - wbar_0) = 3/2
@@ -314,11 +315,12 @@ lbm_status validate(const lbm_ehd_params* p) {
   if (p->poisson_iters < 0) return fail(LBM_EINVAL, "poisson_iters < 0");
   if (!finite_all({p->rho_v, p->rho_r, p->eta_v, p->eta_r, p->M_phi, p->W, p->zeta, p->theta,
                    p->dpsi, p->eps_v, p->eps_r, p->mu_v, p->mu_r, p->m_ratio, p->v_th, p->c0,
-                   p->q, p->gamma_v, p->force_x, p->force_y, p->s_free}))
+                   p->q, p->gamma_v, p->force_x, p->force_y, p->s_free, p->n_eps}))
     return fail(LBM_EINVAL, "non-finite coefficient");
   if (p->rho_v <= 0 || p->rho_r <= 0 || p->eps_v <= 0 || p->eps_r <= 0 || p->W <= 0)
     return fail(LBM_EINVAL, "density, permittivity and W must be positive");
   if (p->s_free <= 0 || p->s_free >= 2) return fail(LBM_EINVAL, "s_free must lie in (0, 2)");
+  if (p->n_eps < 0) return fail(LBM_EINVAL, "n_eps must be >= 0");
   // every relaxation time > 1/2 for phi in [0, 1] (the properties are linear)
   for (double phi : {0.0, 1.0}) {
     const double rho = p->rho_v + phi * (p->rho_v * p->rho_r - p->rho_v);
@@ -427,6 +429,7 @@ lbm_status lbm_ehd_params_default(lbm_ehd_params* o) {
   o->v_th = 0.01;
   o->c0 = 1.0;
   o->s_free = 1.0;
+  o->n_eps = 1e-4;
   return LBM_OK;
 }
 

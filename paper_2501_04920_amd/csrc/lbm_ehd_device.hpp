@@ -67,6 +67,7 @@ struct KP {
   R beta4, kappa;    // 4 beta = 48 zeta / W, kappa = 3 zeta W / 2 (Eq. 13)
   R W, fourW;        // interface width and 4 / W (Eq. 2)
   R s_free, inv_tau_h, inv_tau_g;
+  R n_eps2;          // square of the unit normal's regularisation (0: bare form)
   R theta_src;       // theta times the source normalisation
   R dpsi, psi_slope; // anode potential; d psi_lin / dy (0 in a periodic box)
   R dr_g;            // (psi_lin(y - 1) - psi_lin(y)) / 6: reference shift of g2, g4
@@ -466,10 +467,11 @@ __device__ inline void collide_h(R h[9], const Macro<R>& m, const R dJ[2], const
   fwd9(h, mo);
   const R phi = m.phi, phid = m.phid, ux = m.u[0], uy = m.u[1];
   const R third = R(1) / R(3), ninth = R(1) / R(9);
-  const R gn = sqrt(m.gphi[0] * m.gphi[0] + m.gphi[1] * m.gphi[1]);
+  // unit normal grad(phi)/|grad(phi)|, regularised where grad(phi) -> 0
+  const R g2 = m.gphi[0] * m.gphi[0] + m.gphi[1] * m.gphi[1];
   R nx = R(0), ny = R(0);
-  if (gn >= R(1e-12)) {
-    const R ign = recip(gn);
+  if (kp.n_eps2 > R(0) || g2 >= R(1e-24)) {
+    const R ign = recip(sqrt(g2 + kp.n_eps2));
     nx = m.gphi[0] * ign;
     ny = m.gphi[1] * ign;
   }

@@ -48,7 +48,7 @@ class lbm_ehd_params(ctypes.Structure):
         ("m_ratio", ctypes.c_double), ("v_th", ctypes.c_double),
         ("c0", ctypes.c_double), ("q", ctypes.c_double), ("gamma_v", ctypes.c_double),
         ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
-        ("s_free", ctypes.c_double),
+        ("s_free", ctypes.c_double), ("n_eps", ctypes.c_double),
     ]
 
 

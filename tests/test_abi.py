@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     # int32 block then doubles, no padding surprises
-    assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 16 * 4 + 21 * 8
+    assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 16 * 4 + 22 * 8
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_diag) == 9 * 8
 
 
@@ -47,7 +47,7 @@ def test_defaults_and_bytes():
 
 @pytest.mark.parametrize("bad", [dict(nx=1), dict(v_th=0.0), dict(eta_v=0.0), dict(M_phi=0.0),
                                  dict(theta=-0.1), dict(precision=7), dict(walls=5),
-                                 dict(W=float("nan")), dict(s_free=2.0), dict(reserved=1),
+                                 dict(W=float("nan")), dict(s_free=2.0), dict(reserved=1), dict(n_eps=-1.0),
                                  dict(nx=20000, ny=20000)])
 def test_invalid_parameters_rejected(bad):
     p = lbm_ehd.make_params(**bad)

@@ -36,11 +36,9 @@ def test_config1_droplet_fp64():
     assert max(errs.values()) <= 1e-10
 
 
-# FP32 storage rounds the f populations, which carry the pressure (about ten
-# times the momentum here), so the velocity random-walks at the 1e-7-per-step
-# level; every other field stays within 2e-5 of the FP64 oracle after 2000
-# steps.  With FP64 arithmetic on FP32 storage the velocity is within 2e-5 too.
-FP32_BARS = {"fp32": dict(ux=5e-5, uy=5e-5), "fp32f64": {}}
+# Every field within 2e-5 of the FP64 oracle after 2000 steps, in FP32
+# storage with FP32 or FP64 arithmetic (measured: <= 6e-6 and <= 1.1e-7).
+FP32_BARS = {"fp32": {}, "fp32f64": {}}
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp32f64"])
@@ -100,7 +98,12 @@ def test_small_and_odd_shapes_fp64(shape):
     y = np.arange(ny)[:, None] * np.ones((1, nx))
     x = np.ones((ny, 1)) * np.arange(nx)[None, :]
     rng = np.random.default_rng(nx * 1000 + ny)
-    phi = 0.5 * (1 + np.tanh(np.sin(2 * np.pi * x / nx) * 2 + np.cos(2 * np.pi * y / ny)))
+    # no grid-symmetric extremum of phi: where grad(phi) vanishes by symmetry
+    # while lambda of Eq. (2) is large, the regularised normal passes rounding
+    # on with a gain of up to lambda / n_eps, which two correct FP64
+    # implementations do not share
+    phi = 0.5 * (1 + np.tanh(np.sin(2 * np.pi * (x + 0.3) / nx) * 2
+                             + np.cos(2 * np.pi * (y + 0.3) / ny)))
     cp = 1 + 0.01 * rng.uniform(-1, 1, (ny, nx))
     cm = 1 + 0.01 * rng.uniform(-1, 1, (ny, nx))
     psi = p["dpsi"] * (ny - 0.5 - y) / ny

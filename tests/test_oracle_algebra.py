@@ -225,3 +225,28 @@ def test_deformation_of_analytic_ellipse(orc, a, b):
     D, L, H = orc.deformation(phi)
     assert abs(L - 2 * a) < 0.1 and abs(H - 2 * b) < 0.1
     assert abs(D - (a - b) / (a + b)) < 1e-3
+
+
+def test_unit_normal_reading(orc):
+    """grad(phi)/|grad(phi)| of Eq. (1), (32): where the gradient is well
+    above the regularisation it is the unit vector along grad(phi) to second
+    order in n_eps/|g|; it never exceeds unit length, points along grad(phi)
+    and goes to 0 continuously with the gradient; the bare form (n_eps = 0)
+    is the unit vector itself, and 0 below 1e-12."""
+    rng = np.random.default_rng(7)
+    eps = 1e-4
+    for _ in range(50):
+        g = rng.normal(size=2) * 10.0 ** rng.uniform(-8, 0)
+        gn = np.linalg.norm(g)
+        n = orc.unit_normal(*g, eps)
+        assert np.linalg.norm(n) < 1.0
+        assert abs(n[0] * g[1] - n[1] * g[0]) <= 1e-15 * gn   # parallel to g
+        assert n @ g > 0
+        if gn > 100 * eps:
+            assert np.linalg.norm(n - g / gn) <= (eps / gn) ** 2
+        if gn < 1e-2 * eps:
+            assert np.linalg.norm(n) <= gn / eps                 # continuous at 0
+        bare = orc.unit_normal(*g, 0.0)
+        assert abs(np.linalg.norm(bare) - 1.0) < 1e-15
+    assert np.array_equal(orc.unit_normal(0.0, 0.0, eps), [0.0, 0.0])
+    assert np.array_equal(orc.unit_normal(3e-13, 4e-13, 0.0), [0.0, 0.0])

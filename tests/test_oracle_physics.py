@@ -253,3 +253,27 @@ def test_mirror_symmetry_without_noise(orc):
         scale = abs(a).max()
         assert scale > 0
         assert abs(a - sign * a[:, ::-1]).max() <= 1e-11 * scale, k
+
+
+@pytest.mark.parametrize("n_eps, grows", [(1e-4, False), (0.0, True)])
+def test_droplet_case_is_well_conditioned(orc, n_eps, grows):
+    """A change of 1e-15 (relative) in one h population at the droplet centre
+    must stay at rounding level after 1000 steps of the 128^2 droplet case.
+    With the bare unit normal (n_eps = 0) it does not: at the centre
+    grad(phi) -> 0 while lambda of Eq. (2) stays ~1e-5, so the direction of
+    the normal follows rounding and the change grows by ten orders."""
+    cfg = workloads.config1()
+    p, d = dict(cfg["params"], n_eps=n_eps), cfg["droplet"]
+    a, b = orc.Oracle(p), orc.Oracle(p)
+    for o in (a, b):
+        o.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"])
+    pop, jp = b.get_state()
+    pop[9 + 1, 64, 64] *= 1.0 + 1e-15
+    b.set_state(pop, jp)
+    a.step(1000)
+    b.step(1000)
+    dphi = np.abs(a.fields()["phi"] - b.fields()["phi"]).max()
+    if grows:
+        assert dphi > 1e-9
+    else:
+        assert dphi < 1e-12
