@@ -250,6 +250,62 @@ LBM_API int64_t lbm_ehd_time(const lbm_ehd *h);
 LBM_API lbm_status lbm_ehd_set_launch(lbm_ehd *h, int32_t waves, int32_t tile_rows);
 LBM_API lbm_status lbm_ehd_get_launch(const lbm_ehd *h, int32_t *waves, int32_t *tile_rows);
 
+/*
+ * Batched sweeps.  Several initialised simulations of any grid sizes, with
+ * the same storage precision and poisson_iters = 0, are advanced together:
+ * each step is ONE kernel launch over the tiles of all members (each tile
+ * runs the single-simulation tile code on its own member), and whole blocks
+ * of steps are captured once in a HIP graph and replayed.  Every member's
+ * arithmetic is the same as when it steps alone, so its results are bitwise
+ * those of lbm_ehd_run.
+ *
+ * The batch keeps pointers to its members: they must outlive it (or be
+ * removed first).  While in a batch, members are stepped on the batch's
+ * stream and must not be stepped on their own; their step counters and
+ * current buffers are kept up to date, so lbm_ehd_get_fields and
+ * lbm_ehd_diagnostics work on them after lbm_ehd_batch_synchronize.
+ */
+typedef struct lbm_ehd_batch lbm_ehd_batch;
+
+/* Group `n` members (n >= 0; NULL list allowed for n = 0) on `stream`, which
+ * must not be the legacy default stream (graphs cannot be captured there);
+ * NULL: the batch creates its own blocking stream of default priority,
+ * ordered with the default stream and destroyed with the batch.  LBM_EINVAL on mixed precisions, members with
+ * poisson_iters != 0, duplicates or members on another device; LBM_ESTATE if
+ * a member is not initialised. */
+LBM_API lbm_status lbm_ehd_batch_create(lbm_ehd *const *sims, int32_t n, void *stream,
+                                        lbm_ehd_batch **out);
+/* Add a member (same checks as create; the member's own stream is
+ * synchronised first) or remove one (the batch stream is synchronised, so
+ * the removed member's state is complete).  Takes effect at the next run. */
+LBM_API lbm_status lbm_ehd_batch_add(lbm_ehd_batch *b, lbm_ehd *h);
+LBM_API lbm_status lbm_ehd_batch_remove(lbm_ehd_batch *b, lbm_ehd *h);
+/* Number of members, -1 for NULL. */
+LBM_API int32_t lbm_ehd_batch_size(const lbm_ehd_batch *b);
+/* Launch shape of the batched sweep (as lbm_ehd_set_launch; one shape for
+ * all members; bands are clamped to each member's ny). */
+LBM_API lbm_status lbm_ehd_batch_set_launch(lbm_ehd_batch *b, int32_t waves, int32_t tile_rows);
+LBM_API lbm_status lbm_ehd_batch_get_launch(const lbm_ehd_batch *b, int32_t *waves,
+                                            int32_t *tile_rows);
+/* Steps per captured graph block (even, default 16; 0: no graphs). */
+LBM_API lbm_status lbm_ehd_batch_set_graph_steps(lbm_ehd_batch *b, int32_t steps);
+/* Advance every member by `nsteps` (whole blocks by graph replay, the rest
+ * by direct launches).  Asynchronous on the batch stream. */
+LBM_API lbm_status lbm_ehd_batch_run(lbm_ehd_batch *b, int64_t nsteps);
+/* Choose the launch shape: time `steps_per_trial` (even, >= 2) steps of the
+ * batch for each candidate (waves 1, 2, 4, 8 not much wider than the widest
+ * member x bands of 2, 4, 8, 16, 32 rows) with HIP events and keep the
+ * fastest.  The trial steps are real steps of every member (results do not
+ * depend on the shape); their count is returned in *steps_taken.  Blocks
+ * until the trials are done. */
+LBM_API lbm_status lbm_ehd_batch_autotune(lbm_ehd_batch *b, int32_t steps_per_trial,
+                                          int32_t *waves, int32_t *tile_rows,
+                                          int64_t *steps_taken);
+/* Wait for the batch's work.  LBM_EDEVICE if a kernel failed. */
+LBM_API lbm_status lbm_ehd_batch_synchronize(lbm_ehd_batch *b);
+/* Release the batch (not its members).  NULL is allowed. */
+LBM_API lbm_status lbm_ehd_batch_destroy(lbm_ehd_batch *b);
+
 /* Wait for all work of the handle.  LBM_EDEVICE if a kernel failed. */
 LBM_API lbm_status lbm_ehd_synchronize(lbm_ehd *h);
 

@@ -79,10 +79,38 @@ struct lbm_ehd {
   double* upl = nullptr;    // uploaded initial fields [6][ny][nx]
   int tile_rows = 16;
   int waves = 1;        // wavefronts per sweep workgroup (strip of 64 * waves columns)
-  int band_major = 1;
+  // The sweep runs as a batch of one (the same kernel as lbm_ehd_batch_run,
+  // so a simulation gives bitwise the same results alone and in a batch):
+  // its descriptor, written with cur = desc_cur, and its tile list.
+  void* d_desc = nullptr;
+  BatchTile* d_tiles = nullptr;
+  int ntiles = 0;
+  int desc_cur = 0;
 };
 
 namespace {
+
+// Tile list of a set of simulations: larger ones first, each band by band
+// across its strips of 64 * waves columns, padded with empty tiles to a
+// multiple of 8 (the sweep gives each XCD one contiguous run of tiles).
+std::vector<BatchTile> tile_list(const std::vector<const lbm_ehd*>& sims, int waves,
+                                 int tile_rows) {
+  std::vector<int> order(sims.size());
+  for (size_t i = 0; i < sims.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return (long long)sims[a]->P.nx * sims[a]->P.ny > (long long)sims[c]->P.nx * sims[c]->P.ny;
+  });
+  const int tw = 64 * waves;
+  std::vector<BatchTile> tl;
+  for (int i : order) {
+    const lbm_ehd_params& P = sims[i]->P;
+    const int tr = std::min(tile_rows, P.ny);
+    for (int y0 = 0; y0 < P.ny; y0 += tr)
+      for (int x0 = 0; x0 < P.nx; x0 += tw) tl.push_back({i, x0, y0, std::min(y0 + tr, P.ny)});
+  }
+  while (tl.empty() || tl.size() % 8) tl.push_back({-1, 0, 0, 0});
+  return tl;
+}
 
 template <class R>
 KP<R> make_kp(const lbm_ehd* h) {
@@ -166,28 +194,65 @@ struct Form {
            (size_t)i * h->P.ny * h->pitch;
   }
 
-  template <int NW>
-  static void launch_sweep(lbm_ehd* h, const S* srcg, const KP<R>& kp) {
-    const int nstrips = (h->P.nx + 64 * NW - 1) / (64 * NW);
-    const int tr = h->tile_rows;
-    const int nbands = (h->P.ny + tr - 1) / tr;
-    const int nb = nstrips * nbands;
-    const int chunk = (nb % 8 == 0) ? nb / 8 : 0;
-    hipLaunchKernelGGL((k_sweep<S, R, T0, NW>), dim3(nb), dim3(64 * NW), 0, h->stream,
-                       buf(h, h->cur), srcg, buf(h, 1 - h->cur), jp(h), h0(h, h->cur),
-                       h0(h, 1 - h->cur), kp, tr, nstrips, nbands, chunk, h->band_major);
+  typedef SimDesc<S, R, T0> Desc;
+
+  // Descriptor of a simulation for the tile kernel.
+  static Desc desc(lbm_ehd* h) {
+    Desc d;
+    std::memset(&d, 0, sizeof d);
+    d.kp = make_kp<R>(h);
+    d.pop[0] = buf(h, 0);
+    d.pop[1] = buf(h, 1);
+    d.jprev = jp(h);
+    d.h0[0] = h0(h, 0);
+    d.h0[1] = h0(h, 1);
+    d.cur = h->cur;
+    return d;
   }
 
-  static lbm_status sweep(lbm_ehd* h, const S* srcg) {
-    const KP<R> kp = make_kp<R>(h);
-    if (!srcg) srcg = gset(h, h->cur);
-    switch (h->waves) {
-      case 8: launch_sweep<8>(h, srcg, kp); break;
-      case 4: launch_sweep<4>(h, srcg, kp); break;
-      case 2: launch_sweep<2>(h, srcg, kp); break;
-      default: launch_sweep<1>(h, srcg, kp); break;
+  // Upload the simulation's descriptor and tile list (at creation and when
+  // the launch shape changes; never inside a step).
+  static lbm_status prepare_sweep(lbm_ehd* h) {
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const Desc d = desc(h);
+    const std::vector<BatchTile> tl = tile_list({h}, h->waves, h->tile_rows);
+    (void)hipFree(h->d_tiles);
+    h->d_tiles = nullptr;
+    if (!h->d_desc) HIP_TRY(hipMalloc(&h->d_desc, sizeof(Desc)));
+    HIP_TRY(hipMalloc(&h->d_tiles, tl.size() * sizeof(BatchTile)));
+    HIP_TRY(hipMemcpy(h->d_desc, &d, sizeof d, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->d_tiles, tl.data(), tl.size() * sizeof(BatchTile),
+                      hipMemcpyHostToDevice));
+    h->ntiles = (int)tl.size();
+    h->desc_cur = h->cur;
+    return LBM_OK;
+  }
+
+  template <int NW>
+  static void launch_nw(const void* descs, const BatchTile* tiles, int ntiles, int flip,
+                        hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep_batch<S, R, T0, NW>), dim3(ntiles), dim3(64 * NW), 0, st,
+                       static_cast<const Desc*>(descs), tiles, ntiles / 8, flip);
+  }
+
+  // One fused sweep over the tiles `tiles` (a multiple of 8) of the members
+  // described by `descs`; `flip` = 1 swaps every member's buffers.
+  static lbm_status launch_tiles(int waves, const void* descs, const BatchTile* tiles,
+                                 int ntiles, int flip, hipStream_t st) {
+    switch (waves) {
+      case 8: launch_nw<8>(descs, tiles, ntiles, flip, st); break;
+      case 4: launch_nw<4>(descs, tiles, ntiles, flip, st); break;
+      case 2: launch_nw<2>(descs, tiles, ntiles, flip, st); break;
+      default: launch_nw<1>(descs, tiles, ntiles, flip, st); break;
     }
     HIP_TRY(hipGetLastError());
+    return LBM_OK;
+  }
+
+  static lbm_status sweep(lbm_ehd* h) {
+    lbm_status st = launch_tiles(h->waves, h->d_desc, h->d_tiles, h->ntiles,
+                                 h->cur ^ h->desc_cur, h->stream);
+    if (st) return st;
     h->cur = 1 - h->cur;
     return LBM_OK;
   }
@@ -248,7 +313,7 @@ struct Form {
       st = settle_g(h, g);
       if (st) return st;
     }
-    return sweep(h, nullptr);
+    return sweep(h);
   }
 
   static lbm_status presolve(lbm_ehd* h, int iters) {
@@ -289,6 +354,94 @@ struct Form {
     return LBM_OK;
   }
 };
+
+// ---------------------------------------------------------------------------
+// Batched sweeps: several simulations advanced by one launch per step over the
+// tiles of all members (k_sweep_batch).
+// ---------------------------------------------------------------------------
+}  // namespace
+
+struct lbm_ehd_batch {
+  std::vector<lbm_ehd*> sims;
+  int precision = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;        // created by the library (graphs need a stream other
+                                  // than the legacy default one)
+  int waves = 2, tile_rows = 8;
+  int graph_steps = 16;           // steps per captured block (even)
+  // device copies of the member descriptors and of the tile list
+  void* d_desc = nullptr;
+  size_t desc_cap = 0;            // bytes
+  void* h_desc = nullptr;         // pinned staging of the descriptors
+  BatchTile* d_tiles = nullptr;
+  size_t tiles_cap = 0;           // tiles
+  BatchTile* h_tiles = nullptr;   // pinned staging of the tile list
+  int ntiles = 0;                 // padded to a multiple of 8
+  bool dirty = true;              // descriptors / tiles / graph must be rebuilt
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+template <class S, class R>
+struct BatchForm {
+  typedef Form<S, R> F;
+  typedef typename F::Desc Desc;
+
+  // Descriptors and tile list of the current members and launch shape.
+  static lbm_status rebuild(lbm_ehd_batch* b) {
+    HIP_TRY(hipStreamSynchronize(b->stream));  // staging buffers may still be in use
+    const size_t n = b->sims.size();
+    const size_t dbytes = std::max<size_t>(1, n) * sizeof(Desc);
+    if (dbytes > b->desc_cap) {
+      (void)hipFree(b->d_desc);
+      (void)hipHostFree(b->h_desc);
+      b->d_desc = b->h_desc = nullptr;
+      b->desc_cap = 0;
+      HIP_TRY(hipMalloc(&b->d_desc, dbytes));
+      HIP_TRY(hipHostMalloc(&b->h_desc, dbytes, hipHostMallocDefault));
+      b->desc_cap = dbytes;
+    }
+    Desc* hd = static_cast<Desc*>(b->h_desc);
+    for (size_t i = 0; i < n; ++i) hd[i] = F::desc(b->sims[i]);
+    const std::vector<BatchTile> tl =
+        tile_list(std::vector<const lbm_ehd*>(b->sims.begin(), b->sims.end()), b->waves,
+                  b->tile_rows);
+    if (tl.size() > b->tiles_cap) {
+      (void)hipFree(b->d_tiles);
+      (void)hipHostFree(b->h_tiles);
+      b->d_tiles = b->h_tiles = nullptr;
+      b->tiles_cap = 0;
+      HIP_TRY(hipMalloc(&b->d_tiles, tl.size() * sizeof(BatchTile)));
+      HIP_TRY(hipHostMalloc(&b->h_tiles, tl.size() * sizeof(BatchTile), hipHostMallocDefault));
+      b->tiles_cap = tl.size();
+    }
+    std::copy(tl.begin(), tl.end(), b->h_tiles);
+    b->ntiles = (int)tl.size();
+    HIP_TRY(hipMemcpyAsync(b->d_desc, b->h_desc, n * sizeof(Desc), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_tiles, b->h_tiles, tl.size() * sizeof(BatchTile),
+                           hipMemcpyHostToDevice, b->stream));
+    return LBM_OK;
+  }
+
+  static lbm_status launch(lbm_ehd_batch* b, int flip) {
+    return F::launch_tiles(b->waves, b->d_desc, b->d_tiles, b->ntiles, flip, b->stream);
+  }
+};
+
+template <class F>
+lbm_status dispatch_prec(int precision, F&& fn) {
+  switch (precision) {
+    case LBM_FP64: return fn(BatchForm<double, double>{});
+    case LBM_FP32: return fn(BatchForm<float, float>{});
+    case LBM_FP32_F64: return fn(BatchForm<float, double>{});
+    case LBM_FP16_STORE: return fn(BatchForm<__half, float>{});
+    case LBM_BF16_STORE: return fn(BatchForm<__hip_bfloat16, float>{});
+  }
+  return fail(LBM_EINVAL, "unknown precision");
+}
 
 template <class F>
 lbm_status dispatch(lbm_ehd* h, F&& fn) {
@@ -338,6 +491,8 @@ lbm_status validate(const lbm_ehd_params* p) {
 }
 
 void free_scratch(lbm_ehd* h) {
+  (void)hipFree(h->d_desc);
+  (void)hipFree(h->d_tiles);
   (void)hipFree(h->mom);
   (void)hipFree(h->fld);
   (void)hipFree(h->part);
@@ -353,16 +508,16 @@ void free_scratch(lbm_ehd* h) {
 
 // Default launch shape of the sweep for a grid: strips of 256 columns (four
 // waves in step) where the grid is that wide, and the tallest band (the h/g
-// rows above and below a band are read twice) that still puts about 4096
-// wavefronts in flight, four per SIMD.  Measured on MI355X at 2048^2 in FP32
-// (GLUPS): 1 wave 15.8-16.0, 2 waves 16.3-16.8, 4 waves 17.1-17.5, 8 waves
-// 16.6-17.6, bands of 4-32 rows within 2 % of each other; bands of 64 rows
-// leave too few workgroups (12.9-13.8).
+// rows above and below a band are read twice) that still puts about 8192
+// wavefronts in flight.  Measured on MI355X at 2048^2 (GLUPS, bands of 4 /
+// 8 / 16 rows): FP32 17.2 / 17.0 / 16.7, FP16 27.1 / 27.9 / 27.9, FP64 9.5 /
+// 9.4 / 9.4 with four waves; one wave 15.8-16.0 in FP32, two 16.3-16.8,
+// eight 16.6-17.6; bands of 64 rows leave too few workgroups (12.9-13.8).
 void default_launch(const lbm_ehd_params* p, int* waves, int* tile_rows) {
   *waves = p->nx >= 256 ? 4 : (p->nx >= 128 ? 2 : 1);
   const long long strips = (p->nx + 64 * *waves - 1) / (64 * *waves);
   int rows = 32;
-  while (rows > 2 && strips * *waves * ((p->ny + rows - 1) / rows) < 4096) rows /= 2;
+  while (rows > 2 && strips * *waves * ((p->ny + rows - 1) / rows) < 8192) rows /= 2;
   *tile_rows = std::min(rows, p->ny);
 }
 
@@ -533,6 +688,11 @@ lbm_status lbm_ehd_create(const lbm_ehd_params* p, const lbm_ehd_device* dev, lb
       hipMalloc(&h->line, (2 * (size_t)p->ny + 2 * (size_t)p->nx) * sizeof(double)) !=
           hipSuccess)
     return cleanup(LBM_ENOMEM, "device allocation of scratch failed");
+  st = dispatch(h, [&](auto F) { return decltype(F)::prepare_sweep(h); });
+  if (st) {
+    const std::string msg = g_err;
+    return cleanup(st, msg);
+  }
   *out = h;
   return LBM_OK;
 }
@@ -695,7 +855,7 @@ lbm_status lbm_ehd_set_launch(lbm_ehd* h, int32_t waves, int32_t tile_rows) {
   if (tile_rows < 1) return fail(LBM_EINVAL, "tile_rows must be >= 1");
   h->waves = waves;
   h->tile_rows = std::min<int32_t>(tile_rows, h->P.ny);
-  return LBM_OK;
+  return dispatch(h, [&](auto F) { return decltype(F)::prepare_sweep(h); });
 }
 
 lbm_status lbm_ehd_get_launch(const lbm_ehd* h, int32_t* waves, int32_t* tile_rows) {
@@ -735,6 +895,247 @@ lbm_status lbm_ehd_stream_copy(const void* src, void* dst, size_t bytes, void* s
   else
     return fail(LBM_EINVAL, "width must be 4 or 16");
   HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched sweeps.
+// ---------------------------------------------------------------------------
+namespace {
+
+void batch_drop_graph(lbm_ehd_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+lbm_status batch_prepare(lbm_ehd_batch* b) {
+  if (!b->dirty) return LBM_OK;
+  batch_drop_graph(b);
+  lbm_status st = dispatch_prec(b->precision, [&](auto F) { return decltype(F)::rebuild(b); });
+  if (st) return st;
+  b->dirty = false;
+  return LBM_OK;
+}
+
+lbm_status batch_check_member(const lbm_ehd_batch* b, const lbm_ehd* h) {
+  if (!h) return fail(LBM_EINVAL, "NULL member");
+  if (!h->ready) return fail(LBM_ESTATE, "batch member not initialised");
+  if (h->P.precision != b->precision) return fail(LBM_EINVAL, "batch members differ in precision");
+  if (h->P.poisson_iters != 0) return fail(LBM_EINVAL, "batch members need poisson_iters = 0");
+  if (std::find(b->sims.begin(), b->sims.end(), h) != b->sims.end())
+    return fail(LBM_EINVAL, "simulation is already a batch member");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != h->device)
+    return fail(LBM_EINVAL, "batch members must live on the current device");
+  return LBM_OK;
+}
+
+// `n` steps launched directly (no graph); members' state moves n times.
+lbm_status batch_direct(lbm_ehd_batch* b, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) {
+    lbm_status st =
+        dispatch_prec(b->precision, [&](auto F) { return decltype(F)::launch(b, (int)(i & 1)); });
+    if (st) return st;
+  }
+  if (n & 1) {  // every member's current buffer changed: record it
+    for (lbm_ehd* h : b->sims) h->cur = 1 - h->cur;
+    b->dirty = true;
+  }
+  for (lbm_ehd* h : b->sims) h->step += n;
+  return LBM_OK;
+}
+
+}  // namespace
+
+lbm_status lbm_ehd_batch_create(lbm_ehd* const* sims, int32_t n, void* stream,
+                                lbm_ehd_batch** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || (n > 0 && !sims)) return fail(LBM_EINVAL, "bad member list");
+  lbm_ehd_batch* b = new (std::nothrow) lbm_ehd_batch;
+  if (!b) return fail(LBM_ENOMEM, "host allocation failed");
+  b->precision = n > 0 && sims[0] ? sims[0]->P.precision : -1;
+  if (stream) {
+    b->stream = static_cast<hipStream_t>(stream);
+  } else {
+    // a blocking stream of default priority: ordered with the legacy default
+    // stream that members may use
+    if (hipStreamCreate(&b->stream) != hipSuccess) {
+      delete b;
+      return fail(LBM_EDEVICE, "hipStreamCreate failed");
+    }
+    b->own_stream = true;
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    lbm_status st = batch_check_member(b, sims[i]);
+    if (st) {
+      const std::string msg = g_err;
+      lbm_ehd_batch_destroy(b);
+      return fail(st, msg);
+    }
+    b->sims.push_back(sims[i]);
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_batch_add(lbm_ehd_batch* b, lbm_ehd* h) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (b->sims.empty() && h) b->precision = h->P.precision;
+  lbm_status st = batch_check_member(b, h);
+  if (st) return st;
+  // the member's own pending work must be done before the batch stream uses it
+  if (h->stream != b->stream) HIP_TRY(hipStreamSynchronize(h->stream));
+  b->sims.push_back(h);
+  b->dirty = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_batch_remove(lbm_ehd_batch* b, lbm_ehd* h) {
+  if (!b || !h) return fail(LBM_EINVAL, "NULL argument");
+  auto it = std::find(b->sims.begin(), b->sims.end(), h);
+  if (it == b->sims.end()) return fail(LBM_EINVAL, "not a member of the batch");
+  // the member's state must be complete before it is used on its own stream
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->sims.erase(it);
+  b->dirty = true;
+  return LBM_OK;
+}
+
+int32_t lbm_ehd_batch_size(const lbm_ehd_batch* b) { return b ? (int32_t)b->sims.size() : -1; }
+
+lbm_status lbm_ehd_batch_set_launch(lbm_ehd_batch* b, int32_t waves, int32_t tile_rows) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (waves != 1 && waves != 2 && waves != 4 && waves != 8)
+    return fail(LBM_EINVAL, "waves must be 1, 2, 4 or 8");
+  if (tile_rows < 1) return fail(LBM_EINVAL, "tile_rows must be >= 1");
+  if (waves != b->waves || tile_rows != b->tile_rows) b->dirty = true;
+  b->waves = waves;
+  b->tile_rows = tile_rows;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_batch_get_launch(const lbm_ehd_batch* b, int32_t* waves, int32_t* tile_rows) {
+  if (!b || !waves || !tile_rows) return fail(LBM_EINVAL, "NULL argument");
+  *waves = b->waves;
+  *tile_rows = b->tile_rows;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_batch_set_graph_steps(lbm_ehd_batch* b, int32_t steps) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (steps < 0 || (steps & 1)) return fail(LBM_EINVAL, "graph steps must be even and >= 0");
+  if (steps != b->graph_steps) batch_drop_graph(b);
+  b->graph_steps = steps;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_batch_run(lbm_ehd_batch* b, int64_t nsteps) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  if (b->sims.empty() || nsteps == 0) return LBM_OK;
+  lbm_status st = batch_prepare(b);
+  if (st) return st;
+  const int G = b->graph_steps;
+  int64_t blocks = G > 0 ? nsteps / G : 0;
+  if (blocks > 0 && !b->exec) {
+    // capture one block of G steps (flip 0, 1, 0, ...): an even number of
+    // steps leaves every member's state in the buffer it started in, so the
+    // block can be replayed as it is
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    lbm_status cst = LBM_OK;
+    for (int i = 0; i < G && !cst; ++i)
+      cst = dispatch_prec(b->precision, [&](auto F) { return decltype(F)::launch(b, i & 1); });
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (cst) {
+      if (g) (void)hipGraphDestroy(g);
+      return cst;
+    }
+    HIP_TRY(e);
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  for (int64_t k = 0; k < blocks; ++k) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  for (lbm_ehd* h : b->sims) h->step += blocks * G;
+  return batch_direct(b, nsteps - blocks * G);
+}
+
+lbm_status lbm_ehd_batch_autotune(lbm_ehd_batch* b, int32_t steps_per_trial, int32_t* waves,
+                                  int32_t* tile_rows, int64_t* steps_taken) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (steps_per_trial < 2 || (steps_per_trial & 1))
+    return fail(LBM_EINVAL, "steps_per_trial must be even and >= 2");
+  int64_t taken = 0;
+  if (b->sims.empty()) {
+    if (steps_taken) *steps_taken = 0;
+    return LBM_OK;
+  }
+  int maxn = 0;
+  for (lbm_ehd* h : b->sims) maxn = std::max(maxn, h->P.nx);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bw = b->waves, br = b->tile_rows;
+  lbm_status st = LBM_OK;
+  for (int w : {1, 2, 4, 8}) {
+    if (w > 1 && 64 * w > 2 * maxn) continue;  // strips mostly empty
+    for (int r : {2, 4, 8, 16, 32}) {
+      st = lbm_ehd_batch_set_launch(b, w, r);
+      if (!st) st = batch_prepare(b);
+      if (!st) st = batch_direct(b, 2);  // warm-up at this shape
+      if (!st) st = batch_prepare(b);
+      if (st) break;
+      (void)hipEventRecord(e0, b->stream);
+      st = batch_direct(b, steps_per_trial);
+      (void)hipEventRecord(e1, b->stream);
+      if (st) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st = fail(LBM_EDEVICE, "autotune: kernel failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      taken += steps_per_trial + 2;
+      if (ms < best) {
+        best = ms;
+        bw = w;
+        br = r;
+      }
+    }
+    if (st) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  st = lbm_ehd_batch_set_launch(b, bw, br);
+  if (st) return st;
+  if (waves) *waves = bw;
+  if (tile_rows) *tile_rows = br;
+  if (steps_taken) *steps_taken = taken;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_batch_synchronize(lbm_ehd_batch* b) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (b->stream) HIP_TRY(hipStreamSynchronize(b->stream));
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_batch_destroy(lbm_ehd_batch* b) {
+  if (!b) return LBM_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  (void)hipFree(b->d_desc);
+  (void)hipFree(b->d_tiles);
+  (void)hipHostFree(b->h_desc);
+  (void)hipHostFree(b->h_tiles);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
   return LBM_OK;
 }
 

@@ -254,43 +254,29 @@ struct HGLds {
   }
 };
 
-// The fused sweep.  grid = nstrips * nbands workgroups of 64 NW threads.
-template <class S, class R, class T0, int NW>
-__global__ __launch_bounds__(64 * NW) void k_sweep(const S* __restrict__ src,
-                                              const S* __restrict__ srcg,
-                                              S* __restrict__ dst, R* __restrict__ jprev,
-                                              const T0* __restrict__ h0x,
-                                              T0* __restrict__ h0dst, const KP<R> kp,
-                                              int tile_rows, int nstrips, int nbands,
-                                              int xcd_chunk, int band_major) {
-  constexpr int TW = 64 * NW;
-  __shared__ R s_phi[RING][TW + 2];
-  __shared__ R s_psi[RING][TW + 2];
-  __shared__ R s_pull[2][13][TW];  // pulled h and g1-4 of a row, by row parity
+// LDS of one sweep workgroup: the phi'/psi' ring and the parked h, g1-4.
+template <class R, int TW>
+struct SweepLds {
+  R phi[RING][TW + 2];
+  R psi[RING][TW + 2];
+  R pull[2][13][TW];  // pulled h and g1-4 of a row, by row parity
+};
 
-  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous run of tiles.  Within a run, tiles go band by band across all
-  // strips, so that the workgroups running together on an XCD hold
-  // neighbouring strips of the same rows and the cache lines they share (pull
-  // shifts, halo columns) are fetched from HBM once.
-  int t = blockIdx.x;
-  if (xcd_chunk > 0) t = (t & 7) * xcd_chunk + (t >> 3);
-  int strip, band;
-  if (band_major) {
-    band = t / nstrips;
-    strip = t - band * nstrips;
-  } else {
-    strip = t / nbands;
-    band = t - strip * nbands;
-  }
+// One tile of the fused sweep: columns [x0, x0 + 64 NW) of rows [y0, yend)
+// of one simulation, walked down row by row by the whole workgroup.
+template <class S, class R, class T0, int NW>
+__device__ inline void sweep_tile(SweepLds<R, 64 * NW>& L, const S* __restrict__ src,
+                                  const S* __restrict__ srcg, S* __restrict__ dst,
+                                  R* __restrict__ jprev, const T0* __restrict__ h0x,
+                                  T0* __restrict__ h0dst, const KP<R>& kp, int x0, int y0,
+                                  int yend) {
+  constexpr int TW = 64 * NW;
   const int nx = kp.nx, ny = kp.ny;
-  const int x0 = strip * TW, y0 = band * tile_rows;
   const int w = min(TW, nx - x0);
   const int lane = threadIdx.x;
   const bool valid = lane < w;
   const int x = x0 + (valid ? lane : 0);
   const Cols k = cols_of(x, nx);
-  const int yend = min(y0 + tile_rows, ny);
   const bool periodic = kp.walls == WALL_PERIODIC;
   const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
   const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
@@ -302,7 +288,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const S* __restrict__ src,
   const int kcol = lane == 0 ? 0 : w + 1;
 
   auto slot = [&](int yy) { return (yy - y0 + 1) % RING; };
-  // phi', psi' of row yy into the ring; the lane's own pulls are parked in LDS
+  // phi', psi' of row yy into the ring; each thread's own pulls are parked in LDS
   auto ring_row = [&](int yy) {
     const int ys = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
     const int sl = slot(yy);
@@ -310,20 +296,20 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const S* __restrict__ src,
       R hh[9], gg[4];
       pull_h(Ph, h0x, kh, ys, hh);
       pull4(Pg, 0, kh, ys, gg);
-      s_phi[sl][kcol] = sum9(hh);
-      s_psi[sl][kcol] = psi_of(gg);
+      L.phi[sl][kcol] = sum9(hh);
+      L.psi[sl][kcol] = psi_of(gg);
     }
     if (valid) {
       R h[9], g4[4];
       pull_h(Ph, h0x, k, ys, h);
       pull4(Pg, 0, k, ys, g4);
-      s_phi[sl][lane + 1] = sum9(h);
-      s_psi[sl][lane + 1] = psi_of(g4);
+      L.phi[sl][lane + 1] = sum9(h);
+      L.psi[sl][lane + 1] = psi_of(g4);
       const int b = (yy - y0 + 2) & 1;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) s_pull[b][i][lane] = h[i];
+      for (int i = 0; i < 9; ++i) L.pull[b][i][lane] = h[i];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) s_pull[b][9 + i][lane] = g4[i];
+      for (int i = 0; i < 4; ++i) L.pull[b][9 + i][lane] = g4[i];
     }
   };
 
@@ -350,20 +336,20 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const S* __restrict__ src,
     __syncthreads();
     if (valid) {
       const int c = lane + 1, sc = slot(y);
-      R phC[3] = {s_phi[sc][c - 1], s_phi[sc][c], s_phi[sc][c + 1]};
-      R psC[3] = {s_psi[sc][c - 1], s_psi[sc][c], s_psi[sc][c + 1]};
+      R phC[3] = {L.phi[sc][c - 1], L.phi[sc][c], L.phi[sc][c + 1]};
+      R psC[3] = {L.psi[sc][c - 1], L.psi[sc][c], L.psi[sc][c + 1]};
       R phU[3], psU[3], phD[3], psD[3];
       if (up) {
         const int su = slot(y + 1);
-        phU[0] = s_phi[su][c - 1]; phU[1] = s_phi[su][c]; phU[2] = s_phi[su][c + 1];
-        psU[0] = s_psi[su][c - 1]; psU[1] = s_psi[su][c]; psU[2] = s_psi[su][c + 1];
+        phU[0] = L.phi[su][c - 1]; phU[1] = L.phi[su][c]; phU[2] = L.phi[su][c + 1];
+        psU[0] = L.psi[su][c - 1]; psU[1] = L.psi[su][c]; psU[2] = L.psi[su][c + 1];
       } else {
         ghost_row(phC, psC, phU, psU);
       }
       if (down) {
         const int sd = slot(y - 1);
-        phD[0] = s_phi[sd][c - 1]; phD[1] = s_phi[sd][c]; phD[2] = s_phi[sd][c + 1];
-        psD[0] = s_psi[sd][c - 1]; psD[1] = s_psi[sd][c]; psD[2] = s_psi[sd][c + 1];
+        phD[0] = L.phi[sd][c - 1]; phD[1] = L.phi[sd][c]; phD[2] = L.phi[sd][c + 1];
+        psD[0] = L.psi[sd][c - 1]; psD[1] = L.psi[sd][c]; psD[2] = L.psi[sd][c + 1];
       } else {
         ghost_row(phC, psC, phD, psD);
       }
@@ -371,10 +357,58 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const S* __restrict__ src,
       nine(phD, phC, phU, phi9);
       nine(psD, psC, psU, psi9);
 
-      const HGLds<R, TW> hg{s_pull[(y - y0 + 2) & 1], lane};
+      const HGLds<R, TW> hg{L.pull[(y - y0 + 2) & 1], lane};
       update_node<S, R, T0>(D, jprev, h0x, h0dst, kp, x, y, k, phi9, psi9, f, p, n, g0, hg);
     }
   }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; the remap gives each
+// XCD a contiguous run of tiles (`xcd_chunk` = tiles / 8, 0: no remap).
+__device__ inline int xcd_tile(int xcd_chunk) {
+  const int t = blockIdx.x;
+  return xcd_chunk > 0 ? (t & 7) * xcd_chunk + (t >> 3) : t;
+}
+
+// One member of a batch of simulations swept by a single launch: its
+// parameters, its two population buffers, (phi u)(t-1) and the two time
+// levels of the rest population of h.  `cur` is the buffer holding its
+// current state.
+template <class S, class R, class T0>
+struct SimDesc {
+  KP<R> kp;
+  S* pop[2];
+  R* jprev;
+  T0* h0[2];
+  int cur;
+};
+
+// A tile of a batched sweep: simulation index (-1: padding), first column,
+// first row and end row.
+struct BatchTile {
+  int sim, x0, y0, yend;
+};
+
+// The fused sweep: one workgroup per tile of the list, each running the tile
+// code on its own simulation.  A single simulation is a list of one member;
+// a batch of simulations of any sizes is swept by one launch.  Tiles of a
+// member go band by band across all its strips, and the remap gives each XCD
+// a contiguous run of them, so that the workgroups running together on an
+// XCD hold neighbouring strips of the same rows and the cache lines they
+// share are fetched from HBM once.  `flip` = 1 swaps every member's buffers
+// (odd steps of a captured block).
+template <class S, class R, class T0, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep_batch(const SimDesc<S, R, T0>* __restrict__ sims,
+                                                         const BatchTile* __restrict__ tiles,
+                                                         int xcd_chunk, int flip) {
+  __shared__ SweepLds<R, 64 * NW> L;
+  const BatchTile tl = tiles[xcd_tile(xcd_chunk)];
+  if (tl.sim < 0) return;
+  const SimDesc<S, R, T0>& sd = sims[tl.sim];
+  const int a = (sd.cur + flip) & 1;
+  const S* src = sd.pop[a];
+  sweep_tile<S, R, T0, NW>(L, src, src + (size_t)QG * sd.kp.pitch, sd.pop[1 - a], sd.jprev,
+                           sd.h0[a], sd.h0[1 - a], sd.kp, tl.x0, tl.y0, tl.yend);
 }
 
 // ---------------------------------------------------------------------------

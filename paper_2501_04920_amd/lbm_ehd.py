@@ -115,11 +115,24 @@ def lib() -> ctypes.CDLL:
             "lbm_ehd_destroy": [vp],
             "lbm_ehd_set_launch": [vp, ctypes.c_int32, ctypes.c_int32],
             "lbm_ehd_get_launch": [vp, P(ctypes.c_int32), P(ctypes.c_int32)],
+            "lbm_ehd_batch_create": [P(vp), ctypes.c_int32, vp, P(vp)],
+            "lbm_ehd_batch_add": [vp, vp],
+            "lbm_ehd_batch_remove": [vp, vp],
+            "lbm_ehd_batch_set_launch": [vp, ctypes.c_int32, ctypes.c_int32],
+            "lbm_ehd_batch_get_launch": [vp, P(ctypes.c_int32), P(ctypes.c_int32)],
+            "lbm_ehd_batch_set_graph_steps": [vp, ctypes.c_int32],
+            "lbm_ehd_batch_run": [vp, ctypes.c_int64],
+            "lbm_ehd_batch_autotune": [vp, ctypes.c_int32, P(ctypes.c_int32),
+                                       P(ctypes.c_int32), P(ctypes.c_int64)],
+            "lbm_ehd_batch_synchronize": [vp],
+            "lbm_ehd_batch_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int32
+        L.lbm_ehd_batch_size.argtypes = [vp]
+        L.lbm_ehd_batch_size.restype = ctypes.c_int32
         L.lbm_ehd_time.argtypes = [vp]
         L.lbm_ehd_time.restype = ctypes.c_int64
         L.lbm_ehd_last_error.argtypes = []
@@ -234,6 +247,58 @@ def lbm_ehd_get_launch(h):
     return w.value, r.value
 
 
+def lbm_ehd_batch_create(handles, stream_ptr=None) -> ctypes.c_void_p:
+    arr = (ctypes.c_void_p * max(1, len(handles)))(*handles)
+    out = ctypes.c_void_p()
+    _check(lib().lbm_ehd_batch_create(arr, len(handles), stream_ptr, ctypes.byref(out)))
+    return out
+
+
+def lbm_ehd_batch_add(b, h):
+    _check(lib().lbm_ehd_batch_add(b, h))
+
+
+def lbm_ehd_batch_remove(b, h):
+    _check(lib().lbm_ehd_batch_remove(b, h))
+
+
+def lbm_ehd_batch_size(b) -> int:
+    return int(lib().lbm_ehd_batch_size(b))
+
+
+def lbm_ehd_batch_set_launch(b, waves: int, tile_rows: int):
+    _check(lib().lbm_ehd_batch_set_launch(b, waves, tile_rows))
+
+
+def lbm_ehd_batch_get_launch(b):
+    w, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lbm_ehd_batch_get_launch(b, ctypes.byref(w), ctypes.byref(r)))
+    return w.value, r.value
+
+
+def lbm_ehd_batch_set_graph_steps(b, steps: int):
+    _check(lib().lbm_ehd_batch_set_graph_steps(b, steps))
+
+
+def lbm_ehd_batch_run(b, nsteps: int):
+    _check(lib().lbm_ehd_batch_run(b, nsteps))
+
+
+def lbm_ehd_batch_autotune(b, steps_per_trial: int):
+    w, r, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().lbm_ehd_batch_autotune(b, steps_per_trial, ctypes.byref(w), ctypes.byref(r),
+                                        ctypes.byref(n)))
+    return w.value, r.value, n.value
+
+
+def lbm_ehd_batch_synchronize(b):
+    _check(lib().lbm_ehd_batch_synchronize(b))
+
+
+def lbm_ehd_batch_destroy(b):
+    _check(lib().lbm_ehd_batch_destroy(b))
+
+
 def lbm_ehd_stream_copy(src_ptr: int, dst_ptr: int, nbytes: int, stream_ptr: int, width=4):
     _check(lib().lbm_ehd_stream_copy(src_ptr, dst_ptr, nbytes, stream_ptr, width))
 
@@ -346,3 +411,61 @@ class Simulation:
     @property
     def launch(self):
         return lbm_ehd_get_launch(self.handle)
+
+
+class Batch:
+    """Simulations advanced together by one launch per step (see
+    lbm_ehd_batch_create).  Members are Simulation objects on one device; the
+    batch runs on the first member's stream unless another is given."""
+
+    def __init__(self, sims=(), stream=None):
+        self.members = list(sims)
+        sp = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        self.handle = lbm_ehd_batch_create([m.handle for m in self.members], sp)
+
+    def add(self, sim):
+        lbm_ehd_batch_add(self.handle, sim.handle)
+        self.members.append(sim)
+        return self
+
+    def remove(self, sim):
+        lbm_ehd_batch_remove(self.handle, sim.handle)
+        self.members.remove(sim)
+        return self
+
+    def __len__(self):
+        return lbm_ehd_batch_size(self.handle)
+
+    def set_launch(self, waves: int, tile_rows: int):
+        lbm_ehd_batch_set_launch(self.handle, waves, tile_rows)
+        return self
+
+    @property
+    def launch(self):
+        return lbm_ehd_batch_get_launch(self.handle)
+
+    def set_graph_steps(self, steps: int):
+        lbm_ehd_batch_set_graph_steps(self.handle, steps)
+        return self
+
+    def run(self, nsteps: int):
+        lbm_ehd_batch_run(self.handle, nsteps)
+        return self
+
+    def autotune(self, steps_per_trial: int = 10):
+        """Returns (waves, tile_rows, steps taken by the trials)."""
+        return lbm_ehd_batch_autotune(self.handle, steps_per_trial)
+
+    def synchronize(self):
+        lbm_ehd_batch_synchronize(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lbm_ehd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,123 @@
+"""Batched sweeps: members of a batch, advanced by one launch per step over
+all their tiles (graph-captured blocks), give bitwise the results they give
+when stepped alone, whatever the launch shape, the block structure or the
+membership changes on the way; and a member agrees with the CPU oracle.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_common import rel_l2, run_oracle  # noqa: E402
+
+from paper_2501_04920_amd import lbm_ehd, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+ALL10 = ("phi", "psi", "cp", "cm", "rhoe", "ux", "uy", "p", "Ex", "Ey")
+
+# uneven grids and parameters: (nx, ny, radius, eps_r, mu_r, Ca_E)
+MEMBERS = [(64, 64, 10.0, 2.0, 1.0, 0.5), (100, 70, 12.0, 0.5, 2.0, 0.25),
+           (128, 96, 15.0, 4.0, 0.25, 1.0), (200, 150, 24.0, 0.25, 4.0, 0.5),
+           (37, 41, 6.0, 1.0, 1.0, 0.5)]
+
+
+def _member(i, precision):
+    nx, ny, r, er, mr, ca = MEMBERS[i]
+    p = workloads.lattice_params(ny, r, nx=nx, eps_r=er, mu_r=mr, Ca_E=ca)
+    sim = lbm_ehd.Simulation(dict(p, precision=precision), device="cuda:0")
+    sim.init_droplet((nx - 1) / 2 + 0.3, (ny - 1) / 2 - 0.2, r, 1e-3, 11 + i, presolve=6)
+    return sim, p
+
+
+def _alone(i, precision, steps):
+    sim, p = _member(i, precision)
+    sim.step(steps)
+    f = sim.fields()
+    sim.close()
+    return f
+
+
+def _same(a, b, tag):
+    for k in ALL10:
+        assert np.array_equal(a[k], b[k]), (tag, k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "bf16"])
+def test_batch_equals_members_alone(precision):
+    sims = [_member(i, precision)[0] for i in range(len(MEMBERS))]
+    b = lbm_ehd.Batch(sims)
+    assert len(b) == len(MEMBERS)
+    b.set_launch(2, 8).set_graph_steps(8)
+    b.run(37)          # 4 graph blocks of 8 and 5 direct steps (odd: buffers swap)
+    b.run(3)
+    b.synchronize()
+    for i, s in enumerate(sims):
+        assert s.time == 40
+        _same(s.fields(), _alone(i, precision, 40), "member %d" % i)
+    b.close()
+
+
+def test_autotune_and_membership_changes():
+    """Trial steps are real steps; members added and removed between runs
+    keep results equal to running alone."""
+    sims = [_member(i, "fp32")[0] for i in range(3)]
+    b = lbm_ehd.Batch(sims[:2])
+    waves, rows, taken = b.autotune(4)
+    assert waves in (1, 2, 4, 8) and rows in (2, 4, 8, 16, 32) and taken > 0
+    assert b.launch == (waves, rows)
+    b.run(10)
+    b.add(sims[2])                 # joins at its own time 0
+    b.run(7)
+    b.remove(sims[0])
+    b.run(6)
+    b.synchronize()
+    want = [taken + 17, taken + 23, 13]
+    for i, s in enumerate(sims):
+        assert s.time == want[i]
+        _same(s.fields(), _alone(i, "fp32", want[i]), "member %d" % i)
+    b.close()
+
+
+def test_batched_member_matches_oracle_fp64():
+    sims = [_member(i, "fp64")[0] for i in (4, 1)]
+    b = lbm_ehd.Batch(sims).set_launch(1, 4)
+    b.run(120)
+    b.synchronize()
+    nx, ny, r, er, mr, ca = MEMBERS[1]
+    _, p = _member(1, "fp64")
+    d = dict(xc=(nx - 1) / 2 + 0.3, yc=(ny - 1) / 2 - 0.2, radius=r, noise=1e-3, seed=12)
+    o = run_oracle(p, droplet=d, presolve=6, steps=120)
+    errs = rel_l2(sims[1].fields(), o.fields(), p, ALL10)
+    assert max(errs.values()) <= 1e-10, errs
+    b.close()
+
+
+def test_batch_rejects_bad_members():
+    a, _ = _member(0, "fp32")
+    c, _ = _member(1, "fp16")
+    with pytest.raises(lbm_ehd.LbmError) as e:
+        lbm_ehd.Batch([a, c])
+    assert e.value.code == lbm_ehd.LBM_EINVAL
+    with pytest.raises(lbm_ehd.LbmError):
+        lbm_ehd.Batch([a, a])
+    p = workloads.lattice_params(32, 5.0)
+    q = lbm_ehd.Simulation(dict(p, precision="fp32", poisson_iters=1), device="cuda:0")
+    q.init_droplet(15.5, 15.5, 5.0)
+    with pytest.raises(lbm_ehd.LbmError):
+        lbm_ehd.Batch([a, q])
+    u = lbm_ehd.Simulation(dict(p, precision="fp32"), device="cuda:0")
+    with pytest.raises(lbm_ehd.LbmError) as e:
+        lbm_ehd.Batch([u])                     # not initialised
+    assert e.value.code == lbm_ehd.LBM_ESTATE
+    b = lbm_ehd.Batch([a])
+    for bad in ((3, 4), (2, 0)):
+        with pytest.raises(lbm_ehd.LbmError):
+            b.set_launch(*bad)
+    with pytest.raises(lbm_ehd.LbmError):
+        b.set_graph_steps(5)
+    with pytest.raises(lbm_ehd.LbmError):
+        b.remove(c)
+    b.close()
