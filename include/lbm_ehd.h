@@ -196,6 +196,13 @@ LBM_API lbm_status lbm_ehd_params_from_groups(const lbm_ehd_groups *g, lbm_ehd_p
 LBM_API lbm_status lbm_ehd_required_bytes(const lbm_ehd_params *p, size_t *pop_bytes,
                                   size_t *aux_bytes);
 
+/* Device bytes one simulation needs at most when the library allocates its
+ * state (dev = NULL): both population buffers, the aux buffer and the
+ * library's scratch (moment and field planes for readback, allocated on first
+ * use; sums; the sweep's tile list).  For admission control by HBM
+ * footprint.  LBM_EINVAL as lbm_ehd_required_bytes. */
+LBM_API lbm_status lbm_ehd_footprint_bytes(const lbm_ehd_params *p, size_t *bytes);
+
 /* Create a simulation on the current HIP device.  dev may be NULL, in which
  * case the library allocates (and later frees) the buffers itself and uses
  * the null stream.  LBM_EINVAL: any tau <= 1/2, a non-finite coefficient,
@@ -305,6 +312,62 @@ LBM_API lbm_status lbm_ehd_batch_autotune(lbm_ehd_batch *b, int32_t steps_per_tr
 LBM_API lbm_status lbm_ehd_batch_synchronize(lbm_ehd_batch *b);
 /* Release the batch (not its members).  NULL is allowed. */
 LBM_API lbm_status lbm_ehd_batch_destroy(lbm_ehd_batch *b);
+
+/*
+ * Serving: a request server with continuous batching.  Each request is a
+ * droplet simulation (parameters, droplet, number of steps).  Requests wait
+ * in arrival order; at every scheduling round the server retires finished
+ * requests, admits waiting ones that fit the HBM budget (first fit in
+ * arrival order, by lbm_ehd_footprint_bytes), and advances all running
+ * requests by one block of steps as members of one batch (one sweep launch
+ * per step).  State stays resident on the device from admission to release.
+ * A request's results are bitwise those of the same simulation run alone.
+ * Single-threaded: call the server functions from one thread.  Errors of the
+ * server functions are described by lbm_ehd_server_last_error().
+ */
+typedef struct lbm_ehd_server lbm_ehd_server;
+
+enum { LBM_REQ_QUEUED = 0, LBM_REQ_RUNNING = 1, LBM_REQ_DONE = 2, LBM_REQ_FAILED = 3 };
+
+typedef struct {
+  int64_t id;
+  int32_t state;           /* LBM_REQ_* */
+  int32_t reserved;
+  int64_t steps_done, steps_total;
+  double t_submit, t_start, t_done; /* seconds since server creation; -1 if not yet */
+  size_t footprint;        /* device bytes counted against the budget */
+  lbm_ehd_diag diag;       /* at completion (D, sums) */
+} lbm_ehd_request_info;
+
+/* A server with `hbm_budget_bytes` of device memory for request state and
+ * blocks of at most `block_steps` steps (even, >= 2) between scheduling
+ * rounds.  Runs on its own stream on the current device. */
+LBM_API lbm_status lbm_ehd_server_create(size_t hbm_budget_bytes, int32_t block_steps,
+                                         lbm_ehd_server **out);
+/* Queue a request: parameters (poisson_iters = 0; one storage precision per
+ * server), droplet as lbm_ehd_init_droplet, `nsteps` steps.  The id is
+ * written to *id.  LBM_ERANGE if the request alone exceeds the budget. */
+LBM_API lbm_status lbm_ehd_server_submit(lbm_ehd_server *s, const lbm_ehd_params *p, double xc,
+                                         double yc, double radius, double noise, uint64_t seed,
+                                         int64_t nsteps, int64_t *id);
+/* One scheduling round: retire, admit, launch the next block (asynchronous;
+ * retiring waits for the blocks before it).  Writes the numbers of running
+ * and queued requests (either pointer may be NULL). */
+LBM_API lbm_status lbm_ehd_server_advance(lbm_ehd_server *s, int32_t *running, int32_t *queued);
+/* State, timestamps and (when done) diagnostics of a request. */
+LBM_API lbm_status lbm_ehd_server_info(lbm_ehd_server *s, int64_t id, lbm_ehd_request_info *out);
+/* Fields of a finished request, as lbm_ehd_get_fields.  LBM_ESTATE if not done. */
+LBM_API lbm_status lbm_ehd_server_fields(lbm_ehd_server *s, int64_t id, uint32_t mask,
+                                         double *out, size_t n_doubles);
+/* Forget a finished or failed request and free its device memory.
+ * LBM_ESTATE while it is queued or running. */
+LBM_API lbm_status lbm_ehd_server_release(lbm_ehd_server *s, int64_t id);
+/* Device bytes held by admitted, unreleased requests. */
+LBM_API size_t lbm_ehd_server_used_bytes(const lbm_ehd_server *s);
+/* Message of the last server error on the calling thread. */
+LBM_API const char *lbm_ehd_server_last_error(void);
+/* Wait for the server's work and free everything it holds.  NULL allowed. */
+LBM_API lbm_status lbm_ehd_server_destroy(lbm_ehd_server *s);
 
 /* Wait for all work of the handle.  LBM_EDEVICE if a kernel failed. */
 LBM_API lbm_status lbm_ehd_synchronize(lbm_ehd *h);

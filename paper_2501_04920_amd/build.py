@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "lbm_ehd.hip")
+SRC = [os.path.join(HERE, "csrc", "lbm_ehd.hip"), os.path.join(HERE, "csrc", "lbm_ehd_serve.cpp")]
 LIB = os.path.join(HERE, "liblbm_ehd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -22,7 +22,7 @@ FLAGS = [
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), "-o", tmp, SRC]
+           "-I", os.path.join(HERE, "csrc"), "-o", tmp, *SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

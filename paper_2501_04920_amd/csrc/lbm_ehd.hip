@@ -260,6 +260,9 @@ struct Form {
   static dim3 grid2(const lbm_ehd* h) { return dim3((h->P.nx + 63) / 64, h->P.ny); }
 
   static lbm_status moments(lbm_ehd* h, const S* srcg) {
+    // scratch allocated on first use: a simulation that only steps holds
+    // its state and nothing else
+    if (!h->mom) HIP_TRY(hipMalloc(&h->mom, 3 * (size_t)h->P.nx * h->P.ny * sizeof(R)));
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
     if (!srcg) srcg = gset(h, h->cur);
@@ -335,6 +338,7 @@ struct Form {
   static lbm_status fields(lbm_ehd* h) {
     lbm_status st = moments(h, nullptr);
     if (st) return st;
+    if (!h->fld) HIP_TRY(hipMalloc(&h->fld, 10 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
     hipLaunchKernelGGL((k_fields<S, R>), grid2(h), dim3(64), 0, h->stream, src,
@@ -639,6 +643,21 @@ lbm_status lbm_ehd_required_bytes(const lbm_ehd_params* p, size_t* pop_bytes,
   return LBM_OK;
 }
 
+lbm_status lbm_ehd_footprint_bytes(const lbm_ehd_params* p, size_t* bytes) {
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  size_t pb = 0, ab = 0;
+  lbm_status st = lbm_ehd_required_bytes(p, &pb, &ab);
+  if (st) return st;
+  const size_t nc = (size_t)p->nx * p->ny;
+  // state + moment and field scratch (allocated on first use) + sums, lines
+  // and the sweep's tile list at its largest (one wave, bands of one row)
+  *bytes = 2 * pb + ab + 3 * nc * arith_size(p->precision) + 10 * nc * sizeof(double) +
+           (size_t)p->ny * NSUM * sizeof(double) + NSUM * sizeof(double) +
+           (2 * (size_t)p->ny + 2 * (size_t)p->nx) * sizeof(double) +
+           ((size_t)p->ny * ((p->nx + 63) / 64) + 8) * sizeof(BatchTile) + 4096;
+  return LBM_OK;
+}
+
 lbm_status lbm_ehd_create(const lbm_ehd_params* p, const lbm_ehd_device* dev, lbm_ehd** out) {
   if (!out) return fail(LBM_EINVAL, "out is NULL");
   *out = nullptr;
@@ -679,11 +698,7 @@ lbm_status lbm_ehd_create(const lbm_ehd_params* p, const lbm_ehd_device* dev, lb
   }
   h->pop_bytes = pb;
   h->aux_bytes = ab;
-  const size_t nc = (size_t)p->nx * p->ny;
-  const size_t ar = arith_size(p->precision);
-  if (hipMalloc(&h->mom, 3 * nc * ar) != hipSuccess ||
-      hipMalloc(&h->fld, 10 * nc * sizeof(double)) != hipSuccess ||
-      hipMalloc(&h->part, (size_t)p->ny * NSUM * sizeof(double)) != hipSuccess ||
+  if (hipMalloc(&h->part, (size_t)p->ny * NSUM * sizeof(double)) != hipSuccess ||
       hipMalloc(&h->red, NSUM * sizeof(double)) != hipSuccess ||
       hipMalloc(&h->line, (2 * (size_t)p->ny + 2 * (size_t)p->nx) * sizeof(double)) !=
           hipSuccess)

@@ -83,6 +83,17 @@ class lbm_ehd_diag(ctypes.Structure):
     ]
 
 
+class lbm_ehd_request_info(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("state", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("steps_done", ctypes.c_int64), ("steps_total", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("footprint", ctypes.c_size_t),
+                ("diag", lbm_ehd_diag)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -94,6 +105,12 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("liblbm_ehd.so is not built (run __graft_entry__.build()); "
                                "there is no CPU fallback")
+        # torch ships its own HIP runtime and loads it into the global symbol
+        # scope.  Importing torch first makes the library's HIP calls bind to
+        # that same runtime: one runtime per process, so the buffers, streams
+        # and events torch hands over and the library's kernels share queues
+        # (with two runtimes, whichever initialises second finds no GPU).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER
         vp = ctypes.c_void_p
@@ -126,11 +143,25 @@ def lib() -> ctypes.CDLL:
                                        P(ctypes.c_int32), P(ctypes.c_int64)],
             "lbm_ehd_batch_synchronize": [vp],
             "lbm_ehd_batch_destroy": [vp],
+            "lbm_ehd_footprint_bytes": [P(lbm_ehd_params), P(ctypes.c_size_t)],
+            "lbm_ehd_server_create": [ctypes.c_size_t, ctypes.c_int32, P(vp)],
+            "lbm_ehd_server_submit": [vp, P(lbm_ehd_params), ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                      ctypes.c_int64, P(ctypes.c_int64)],
+            "lbm_ehd_server_advance": [vp, P(ctypes.c_int32), P(ctypes.c_int32)],
+            "lbm_ehd_server_info": [vp, ctypes.c_int64, P(lbm_ehd_request_info)],
+            "lbm_ehd_server_fields": [vp, ctypes.c_int64, ctypes.c_uint32, _dp, ctypes.c_size_t],
+            "lbm_ehd_server_release": [vp, ctypes.c_int64],
+            "lbm_ehd_server_destroy": [vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int32
+        L.lbm_ehd_server_used_bytes.argtypes = [vp]
+        L.lbm_ehd_server_used_bytes.restype = ctypes.c_size_t
+        L.lbm_ehd_server_last_error.argtypes = []
+        L.lbm_ehd_server_last_error.restype = ctypes.c_char_p
         L.lbm_ehd_batch_size.argtypes = [vp]
         L.lbm_ehd_batch_size.restype = ctypes.c_int32
         L.lbm_ehd_time.argtypes = [vp]
@@ -462,6 +493,74 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             lbm_ehd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lbm_ehd_footprint_bytes(p: lbm_ehd_params) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().lbm_ehd_footprint_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def _scheck(code: int):
+    if code != LBM_OK:
+        raise LbmError(code, lib().lbm_ehd_server_last_error().decode())
+
+
+class Server:
+    """Continuous-batching request server (see lbm_ehd_server_create)."""
+
+    def __init__(self, hbm_budget_bytes: int, block_steps: int = 256):
+        self.handle = ctypes.c_void_p()
+        _scheck(lib().lbm_ehd_server_create(int(hbm_budget_bytes), block_steps,
+                                            ctypes.byref(self.handle)))
+
+    def submit(self, params, xc, yc, radius, noise=0.0, seed=0, steps=0) -> int:
+        p = params if isinstance(params, lbm_ehd_params) else make_params(**params)
+        rid = ctypes.c_int64()
+        _scheck(lib().lbm_ehd_server_submit(self.handle, ctypes.byref(p), xc, yc, radius, noise,
+                                            seed, steps, ctypes.byref(rid)))
+        return rid.value
+
+    def advance(self):
+        """One scheduling round; returns (running, queued)."""
+        r, q = ctypes.c_int32(), ctypes.c_int32()
+        _scheck(lib().lbm_ehd_server_advance(self.handle, ctypes.byref(r), ctypes.byref(q)))
+        return r.value, q.value
+
+    def info(self, rid: int) -> dict:
+        i = lbm_ehd_request_info()
+        _scheck(lib().lbm_ehd_server_info(self.handle, rid, ctypes.byref(i)))
+        out = {f[0]: getattr(i, f[0]) for f in lbm_ehd_request_info._fields_ if f[0] != "diag"}
+        out["diag"] = {f[0]: getattr(i.diag, f[0]) for f in lbm_ehd_diag._fields_}
+        return out
+
+    def fields(self, rid: int, ny: int, nx: int, names=FIELDS) -> dict:
+        mask = 0
+        for n in names:
+            mask |= FIELD_BITS[n]
+        order = [n for n in FIELDS if mask & FIELD_BITS[n]]
+        out = np.empty((len(order), ny, nx))
+        _scheck(lib().lbm_ehd_server_fields(self.handle, rid, mask,
+                                            out.ctypes.data_as(_dp), out.size))
+        return {n: out[i] for i, n in enumerate(order)}
+
+    def release(self, rid: int):
+        _scheck(lib().lbm_ehd_server_release(self.handle, rid))
+
+    @property
+    def used_bytes(self) -> int:
+        return int(lib().lbm_ehd_server_used_bytes(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _scheck(lib().lbm_ehd_server_destroy(self.handle))
             self.handle = None
 
     def __del__(self):

@@ -30,6 +30,7 @@ def test_struct_sizes_match_header_layout():
     # int32 block then doubles, no padding surprises
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 16 * 4 + 22 * 8
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_diag) == 9 * 8
+    assert ctypes.sizeof(lbm_ehd.lbm_ehd_request_info) == 8 + 4 + 4 + 2 * 8 + 3 * 8 + 8 + 9 * 8
 
 
 def test_defaults_and_bytes():
@@ -90,3 +91,12 @@ def test_groups_rejects_sigma_with_reaction():
     g.reaction = 0
     p = lbm_ehd.lbm_ehd_params_from_groups(g)
     assert p.mu_r == 5.0 and p.reaction == 0
+
+
+def test_footprint_covers_state_and_scratch():
+    p = lbm_ehd.make_params(nx=300, ny=200, precision="fp16")
+    pop, aux = lbm_ehd.lbm_ehd_required_bytes(p)
+    fp = lbm_ehd.lbm_ehd_footprint_bytes(p)
+    # state, then FP32 moment planes and FP64 field planes for readback
+    assert fp >= 2 * pop + aux + 300 * 200 * (3 * 4 + 10 * 8)
+    assert fp < 2 * pop + aux + 300 * 200 * (3 * 4 + 10 * 8) + 1 << 20
