@@ -137,6 +137,161 @@ def summarize_pmc(paths, workload: str):
     print(json.dumps(rec["workloads"][workload]))
 
 
+def _alone_D(m, precision, steps):
+    """Deformation of one member run alone (its own launches) and the wall
+    time of that run."""
+    import torch
+
+    from paper_2501_04920_amd import lbm_ehd
+
+    p, d = m["params"], m["droplet"]
+    sim = lbm_ehd.Simulation(dict(p, precision=precision), device="cuda:0")
+    sim.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    dt = time.perf_counter() - t0
+    D = sim.diagnostics()["D"]
+    sim.close()
+    return D, dt
+
+
+def bench_batched(args):
+    """64 droplets of uneven sizes (128^2-1024^2) in one batch, FP16 storage,
+    autotuned launch shape, 10k steps each: sweep solves per hour.  Baseline:
+    the same 64 runs one after the other in plain FP32 (timed on a sample of
+    steps and scaled); error: D of sampled members against the member run
+    alone in plain FP32."""
+    import torch
+
+    from paper_2501_04920_amd import lbm_ehd, workloads
+
+    members = workloads.config4_members(count=args.members, steps=args.batch_steps)
+    steps = args.batch_steps
+    sims = []
+    for m in members:
+        p, d = m["params"], m["droplet"]
+        s = lbm_ehd.Simulation(dict(p, precision="fp16"), device="cuda:0")
+        s.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"])
+        sims.append(s)
+    torch.cuda.synchronize()
+    b = lbm_ehd.Batch(sims)
+    t0 = time.perf_counter()
+    waves, rows, taken = b.autotune(10)
+    b.run(steps - taken)
+    b.synchronize()
+    wall = time.perf_counter() - t0
+    cells = sum(m["params"]["nx"] * m["params"]["ny"] for m in members)
+    D_batch = [s.diagnostics()["D"] for s in sims]
+    b.close()
+    for s in sims:
+        s.close()
+    # baseline: each member alone in FP32, timed over a few steps, scaled
+    seq = 0.0
+    for m in members:
+        _, dt = _alone_D(m, "fp32", args.seq_steps)
+        seq += dt * steps / args.seq_steps
+    # error of the FP16 batch against FP32 alone, on every 8th member
+    errs = []
+    for k in range(0, len(members), 8):
+        D32, _ = _alone_D(members[k], "fp32", steps)
+        errs.append(abs(D_batch[k] - D32))
+    line = {
+        "metric": "sweep solves/hr", "value": round(len(members) * 3600.0 / wall, 1),
+        "unit": "solves/hr", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(wall / steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched-%d-droplets-128-1024" % len(members),
+                   "cells": cells, "storage": "fp16", "waves": waves, "tile_rows": rows,
+                   "autotune_steps": taken},
+        "aggregate_glups": round(cells * steps / wall / 1e9, 3),
+        "sequential_fp32_s": round(seq, 2), "speedup_vs_sequential_fp32": round(seq / wall, 2),
+        "D_err_vs_fp32_alone_max": max(errs), "D_err_members": list(range(0, len(members), 8)),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _serve_trace(trace, budget, block):
+    """Replay a trace in real time through the request server; returns
+    per-request (latency s, cells x steps) and the makespan."""
+    from paper_2501_04920_amd import lbm_ehd
+
+    srv = lbm_ehd.Server(budget, block_steps=block)
+    pending = sorted(trace, key=lambda r: r["arrival"])
+    ids = {}
+    done = {}
+    t0 = time.perf_counter()
+    k = 0
+    max_running = 0
+    while len(done) < len(trace):
+        now = time.perf_counter() - t0
+        while k < len(pending) and pending[k]["arrival"] <= now:
+            r = pending[k]
+            d = r["droplet"]
+            rid = srv.submit(dict(r["params"], precision="fp16"), d["xc"], d["yc"], d["radius"],
+                             d["noise"], d["seed"], r["steps"])
+            ids[rid] = r
+            k += 1
+        running, queued = srv.advance()
+        max_running = max(max_running, running)
+        for rid in list(ids):
+            inf = srv.info(rid)
+            if inf["state"] >= lbm_ehd.REQ_DONE:
+                r = ids.pop(rid)
+                done[r["name"]] = (inf["t_done"] - inf["t_submit"],
+                                   r["params"]["nx"] * r["params"]["ny"] * r["steps"],
+                                   inf["state"], inf["diag"]["D"])
+                srv.release(rid)
+        if running == 0 and queued == 0 and k < len(pending):
+            time.sleep(max(0.0, pending[k]["arrival"] - (time.perf_counter() - t0)))
+    makespan = time.perf_counter() - t0
+    srv.close()
+    return done, makespan, max_running
+
+
+def bench_serving(args):
+    """Poisson arrivals (20 per second, seeded) of droplet requests 64^2-2048^2
+    with 2k-50k steps, served with HBM-footprint admission and continuous
+    batching (FP16 storage): p50 / p99 completion latency and throughput; then
+    the same requests at a rate giving ~70 % load."""
+    import numpy as np
+
+    from paper_2501_04920_amd import lbm_ehd, workloads
+
+    trace = workloads.config5_trace(count=args.requests, rate=args.rate)
+    budget = int(args.budget_gib * (1 << 30))
+    done, span, maxrun = _serve_trace(trace, budget, args.block)
+    lat = np.array([v[0] for v in done.values()])
+    work = sum(v[1] for v in done.values())
+    glups = work / span / 1e9
+    failed = sum(1 for v in done.values() if v[2] != lbm_ehd.REQ_DONE)
+    # a sub-saturation trace: the same requests, arrival rate for ~70 % load
+    mean_work = work / len(trace)
+    rate_sub = 0.7 * glups * 1e9 / mean_work
+    sub = None
+    if args.sub:
+        trace2 = workloads.config5_trace(count=args.requests, rate=rate_sub)
+        done2, span2, _ = _serve_trace(trace2, budget, args.block)
+        lat2 = np.array([v[0] for v in done2.values()])
+        sub = {"rate_per_s": round(rate_sub, 3), "p50_s": round(float(np.percentile(lat2, 50)), 3),
+               "p99_s": round(float(np.percentile(lat2, 99)), 3),
+               "makespan_s": round(span2, 2)}
+    line = {
+        "metric": "p99 latency", "value": round(float(np.percentile(lat, 99)), 3), "unit": "s",
+        "n_gpus": 1, "steps": int(sum(r["steps"] for r in trace)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving-%d-requests-64-2048-rate%g" % (len(trace), args.rate),
+                   "storage": "fp16", "hbm_budget_gib": args.budget_gib, "block_steps": args.block},
+        "p50_s": round(float(np.percentile(lat, 50)), 3),
+        "throughput_req_per_s": round(len(trace) / span, 3), "aggregate_glups": round(glups, 3),
+        "makespan_s": round(span, 2), "max_running": maxrun, "failed": failed,
+        "sub_saturation": sub,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +311,16 @@ def main():
     ap.add_argument("--copy-width", type=int, default=4, choices=[4, 16])
     ap.add_argument("--summarize-pmc", nargs=4, metavar="CSV",
                     help="sweep FETCH, sweep WRITE, copy FETCH, copy WRITE counter files")
+    ap.add_argument("--form", default="single", choices=["single", "batched", "serving"],
+                    help="single simulation (default), batched sweep or request server")
+    ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=10000)
+    ap.add_argument("--seq-steps", type=int, default=100)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--sub", type=int, default=1, help="also run the ~70 %% load trace")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc, "droplet-%d-%s" % (args.n, args.precision))
@@ -167,6 +332,12 @@ def main():
 
     if args.copy_gib > 0:
         copy_calibration(args.copy_gib, max(args.steps, 1), args.copy_width)
+        return
+    if args.form == "batched":
+        bench_batched(args)
+        return
+    if args.form == "serving":
+        bench_serving(args)
         return
 
     import torch
@@ -229,7 +400,7 @@ def main():
                    "bytes_per_lup": bpl, "waves": waves, "tile_rows": tile_rows},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_sweep",
+                     "traffic": traffic, "kernel": "k_sweep_batch",
                      "kernel_ms": round(kern_ms, 5)},
         "check": {"sum_phi": diag["sum_phi"], "nonfinite": diag["nonfinite"]},
     }

@@ -88,3 +88,72 @@ def scaled(n: int, *, W=4.0, **groups):
     r = n / 6.4
     return dict(name="droplet-%d" % n, params=lattice_params(n, r, W=W, **groups),
                 droplet=droplet(n, r), presolve=0, steps=0)
+
+
+def _groups_at(d_mm: float, mult: float):
+    """Dimensionless groups at electrode gap d (mm) and applied voltage mult x
+    the base voltage: W0 ~ d^2 / dpsi and O ~ dpsi / d, anchored at the
+    paper's d = 2 mm values; beta = sqrt(O W0) (Eq. 24); Ca_E = 0.5 mult^2
+    (the base voltage gives the 0.5 of the 128^2 case)."""
+    W0 = W0_2MM * (d_mm / 2.0) ** 2 / mult
+    O = BETA_2MM ** 2 / W0_2MM * mult * (2.0 / d_mm)
+    return dict(W0=W0, beta=math.sqrt(O * W0), Ca_E=0.5 * mult * mult)
+
+
+def _latin_hypercube(rng, n: int, dims: int):
+    """n points in [0, 1)^dims, one in each of the n strata of every axis."""
+    import numpy as np
+
+    u = (rng.random((n, dims)) + np.arange(n)[:, None]) / n
+    for j in range(dims):
+        u[:, j] = u[rng.permutation(n), j]
+    return u
+
+
+def config4_members(count=64, seed=0, steps=10000):
+    """Batched sweep: `count` droplets on square grids N drawn log-uniformly
+    from 128 to 1024 (radius N / 6.4, W = 4), and a Latin hypercube in log
+    space over d in [0.5, 2] mm, dpsi in [0.5, 2] x base, eps_r and mu_r in
+    [0.25, 4]; FP16 storage."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(np.exp(rng.uniform(math.log(128), math.log(1024), count))).astype(int)
+    lhs = _latin_hypercube(rng, count, 4)
+    lo = np.log([0.5, 0.5, 0.25, 0.25])
+    hi = np.log([2.0, 2.0, 4.0, 4.0])
+    pts = np.exp(lo + lhs * (hi - lo))
+    out = []
+    for k in range(count):
+        n = int(sizes[k])
+        d_mm, mult, eps_r, mu_r = (float(v) for v in pts[k])
+        r = n / 6.4
+        g = _groups_at(d_mm, mult)
+        out.append(dict(name="batch-%02d-n%d" % (k, n), d_mm=d_mm, dpsi_mult=mult,
+                        params=lattice_params(n, r, eps_r=eps_r, mu_r=mu_r, **g),
+                        droplet=droplet(n, r, seed=k), steps=steps))
+    return out
+
+
+def config5_trace(count=256, rate=20.0, seed=0):
+    """Serving trace: Poisson arrivals at `rate` per second; grids N
+    log-uniform in [64, 2048] (radius N / 6.4, W = 4); eps_r, mu_r log-uniform
+    in [0.25, 4]; dpsi multiplier log-uniform in [0.5, 2] (d = 2 mm); step
+    budgets log-uniform integers in [2000, 50000]."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, count)
+    t = np.cumsum(gaps) - gaps[0]
+    lu = lambda a, b: float(np.exp(rng.uniform(math.log(a), math.log(b))))  # noqa: E731
+    out = []
+    for k in range(count):
+        n = int(round(lu(64, 2048)))
+        eps_r, mu_r, mult = lu(0.25, 4.0), lu(0.25, 4.0), lu(0.5, 2.0)
+        steps = int(round(lu(2000, 50000)))
+        r = n / 6.4
+        out.append(dict(name="req-%03d-n%d" % (k, n), arrival=float(t[k]), steps=steps,
+                        params=lattice_params(n, r, eps_r=eps_r, mu_r=mu_r,
+                                              **_groups_at(2.0, mult)),
+                        droplet=droplet(n, r, seed=1000 + k)))
+    return out
