@@ -112,6 +112,16 @@ std::vector<BatchTile> tile_list(const std::vector<const lbm_ehd*>& sims, int wa
   return tl;
 }
 
+// Offset of the +y / -y g references from psi_lin / 6: the steady
+// post-collision g of the uncharged potential carries (1/s_2 - 1) G / 6 in
+// the +y population and minus that in the -y one, with s_2 the rate of the
+// y first moment and G = dpsi / ny the applied field.
+double a_g_of(const lbm_ehd_params& p) {
+  if (p.walls == LBM_PERIODIC) return 0.0;
+  const double s2 = ((p.mask_g >> 2) & 1) ? 1.0 / (0.5 + 3.0 * p.theta) : p.s_free;
+  return (1.0 / s2 - 1.0) * p.dpsi / p.ny / 6.0;
+}
+
 template <class R>
 KP<R> make_kp(const lbm_ehd* h) {
   const lbm_ehd_params& p = h->P;
@@ -160,7 +170,7 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.dpsi = (R)p.dpsi;
   const bool per = p.walls == LBM_PERIODIC;
   k.psi_slope = per ? (R)0 : (R)(-p.dpsi / p.ny);
-  k.dr_g = per ? (R)0 : (R)(p.dpsi / p.ny / 6.0);
+  k.a_g = (R)a_g_of(p);
   k.force_x = (R)p.force_x;
   k.force_y = (R)p.force_y;
   // binary16: keep the deviations of each set well inside the normal range
@@ -201,6 +211,7 @@ struct Form {
     Desc d;
     std::memset(&d, 0, sizeof d);
     d.kp = make_kp<R>(h);
+    d.kpw = make_kp<T0>(h);
     d.pop[0] = buf(h, 0);
     d.pop[1] = buf(h, 1);
     d.jprev = jp(h);
@@ -259,18 +270,22 @@ struct Form {
 
   static dim3 grid2(const lbm_ehd* h) { return dim3((h->P.nx + 63) / 64, h->P.ny); }
 
-  static lbm_status moments(lbm_ehd* h, const S* srcg) {
-    // scratch allocated on first use: a simulation that only steps holds
-    // its state and nothing else
-    if (!h->mom) HIP_TRY(hipMalloc(&h->mom, 3 * (size_t)h->P.nx * h->P.ny * sizeof(R)));
-    const KP<R> kp = make_kp<R>(h);
+  // phi', psi', rho_e planes in type RF (R for the Poisson sweeps, the wide
+  // type T0 for readback).  Scratch is allocated on first use (room for
+  // FP64 planes): a simulation that only steps holds its state and nothing
+  // else.
+  template <class RF>
+  static lbm_status moments_as(lbm_ehd* h, const S* srcg) {
+    if (!h->mom) HIP_TRY(hipMalloc(&h->mom, 3 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
+    const KP<RF> kp = make_kp<RF>(h);
     const S* src = buf(h, h->cur);
     if (!srcg) srcg = gset(h, h->cur);
-    hipLaunchKernelGGL((k_moments<S, R, T0>), grid2(h), dim3(64), 0, h->stream, src, srcg,
-                       h0(h, h->cur), static_cast<R*>(h->mom), kp);
+    hipLaunchKernelGGL((k_moments<S, RF, T0>), grid2(h), dim3(64), 0, h->stream, src, srcg,
+                       h0(h, h->cur), static_cast<RF*>(h->mom), kp);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
+  static lbm_status moments(lbm_ehd* h, const S* srcg) { return moments_as<R>(h, srcg); }
 
   // The g set of buffer i: population QG of row 0 (rows keep their stride).
   static S* gset(lbm_ehd* h, int i) { return buf(h, i) + (size_t)QG * h->pitch; }
@@ -335,14 +350,17 @@ struct Form {
     return LBM_OK;
   }
 
+  // Readback in the wide type T0 (FP64 for FP32 and FP64 storage): the
+  // derived fields (u, p, E, ...) are formed from the stored state without
+  // adding FP32 rounding of their own.
   static lbm_status fields(lbm_ehd* h) {
-    lbm_status st = moments(h, nullptr);
+    lbm_status st = moments_as<T0>(h, nullptr);
     if (st) return st;
     if (!h->fld) HIP_TRY(hipMalloc(&h->fld, 10 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
-    const KP<R> kp = make_kp<R>(h);
+    const KP<T0> kp = make_kp<T0>(h);
     const S* src = buf(h, h->cur);
-    hipLaunchKernelGGL((k_fields<S, R>), grid2(h), dim3(64), 0, h->stream, src,
-                       static_cast<const R*>(h->mom), h->fld, kp);
+    hipLaunchKernelGGL((k_fields<S, T0>), grid2(h), dim3(64), 0, h->stream, src,
+                       static_cast<const T0*>(h->mom), h->fld, kp);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -531,6 +549,7 @@ void fill_init_params(const lbm_ehd* h, InitSpec* sp) {
   sp->dpsi = h->P.dpsi;
   sp->rho_v = h->P.rho_v;
   sp->drho = h->P.rho_v * h->P.rho_r - h->P.rho_v;
+  sp->a_g = a_g_of(h->P);
 }
 
 // Length between the two phi = 1/2 crossings of a profile, walking out from
@@ -651,7 +670,7 @@ lbm_status lbm_ehd_footprint_bytes(const lbm_ehd_params* p, size_t* bytes) {
   const size_t nc = (size_t)p->nx * p->ny;
   // state + moment and field scratch (allocated on first use) + sums, lines
   // and the sweep's tile list at its largest (one wave, bands of one row)
-  *bytes = 2 * pb + ab + 3 * nc * arith_size(p->precision) + 10 * nc * sizeof(double) +
+  *bytes = 2 * pb + ab + 3 * nc * sizeof(double) + 10 * nc * sizeof(double) +
            (size_t)p->ny * NSUM * sizeof(double) + NSUM * sizeof(double) +
            (2 * (size_t)p->ny + 2 * (size_t)p->nx) * sizeof(double) +
            ((size_t)p->ny * ((p->nx + 63) / 64) + 8) * sizeof(BatchTile) + 4096;

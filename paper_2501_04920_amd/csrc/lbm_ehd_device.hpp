@@ -21,13 +21,20 @@
 //
 // Deviation form: every plane stores x_q - ref_q with a fixed reference
 //   f: 0;  h: w_q / 2;  p, n: wbar_q c0;
-//   g: the equilibrium of the uncharged linear potential of the stored row,
-//      psi_lin(y) = dpsi (ny - 1/2 - y) / ny (0 in a y-periodic box).
+//   g: the exact steady post-collision populations of the uncharged
+//      potential between the electrodes, psi_lin(y) = dpsi (ny - 1/2 - y) / ny
+//      (0 in a y-periodic box): -2 psi_lin / 3, psi_lin / 6 (+x, -x),
+//      psi_lin / 6 +- a_g (+y, -y), a_g = (tau_g - 1) dpsi / (6 ny).  These
+//      are a fixed point of streaming, the g collision of Eq. (44)-(47)
+//      without source, and the anti-bounce-back at both electrodes, so the
+//      pulled deviations are the stored ones (no reference shift) and the g
+//      update is the same MRT collision applied to deviations alone.
 // All arithmetic works on deviations: phi' = phi - 1/2, P' = sum p - c0,
 // Q' = sum n - c0, psi' = psi - psi_lin.  The charge density q (P' - Q') and
 // the reaction (solved for R directly) never subtract two numbers near c0,
-// which keeps FP32 and 16-bit storage accurate.  Every step is the same
-// arithmetic as the paper's up to rounding.
+// and the Poisson update never carries the O(dpsi / ny) populations of the
+// applied field, which keeps FP32 and 16-bit arithmetic accurate.  Every step
+// is the same arithmetic as the paper's up to rounding.
 //
 // Velocity order (both lattices share the first five): 0 rest, 1 +x, 2 +y,
 // 3 -x, 4 -y, 5 (+x,+y), 6 (-x,+y), 7 (-x,-y), 8 (+x,-y)  (Eq. 25-26).
@@ -70,7 +77,7 @@ struct KP {
   R n_eps2;          // square of the unit normal's regularisation (0: bare form)
   R theta_src;       // theta times the source normalisation
   R dpsi, psi_slope; // anode potential; d psi_lin / dy (0 in a periodic box)
-  R dr_g;            // (psi_lin(y - 1) - psi_lin(y)) / 6: reference shift of g2, g4
+  R a_g;             // (tau_g - 1) dpsi / (6 ny): reference offset of g +-y
   R force_x, force_y;
   R sc[5], isc[5];   // binary16 storage: power-of-two scale of each set (f h p n g)
 };
@@ -241,7 +248,8 @@ __device__ inline T* elem(T* base, uint32_t e) {
 // Reference of population q stored at lattice row y (the deviation form
 // above), used where absolute values enter or leave: initialisation and
 // field output.
-__device__ inline double plane_ref(int q, int y, int ny, int walls, double c0, double dpsi) {
+__device__ inline double plane_ref(int q, int y, int ny, int walls, double c0, double dpsi,
+                                  double a_g) {
   const double w9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   if (q < QH) return 0.0;
@@ -250,7 +258,7 @@ __device__ inline double plane_ref(int q, int y, int ny, int walls, double c0, d
   const double wb = k == 0 ? 1.0 / 3 : 1.0 / 6;
   if (q < QG) return wb * c0;
   const double psi = walls == WALL_PERIODIC ? 0.0 : dpsi * (ny - 0.5 - y) / ny;
-  return k == 0 ? -2.0 / 3 * psi : psi / 6;
+  return k == 0 ? -2.0 / 3 * psi : psi / 6 + (k == 2 ? a_g : (k == 4 ? -a_g : 0.0));
 }
 
 // ---------------------------------------------------------------------------
@@ -353,11 +361,16 @@ __device__ inline R reaction_rate(R delta, R c0, R c0sq, R Fm1, R Pd, R Qd) {
   return R(2) * delta * Cn * recip(B + sqrt(B * B + R(4) * AC));
 }
 
-template <class R>
-__device__ inline void macro(const R phi9[9], const R psi9[9], R Pd, R Qd, const R f[9],
+// phi9 comes in the type RP of the phase ring (FP64 with FP32 storage): the
+// chemical potential of Eq. (13) is the small difference of a double-well
+// term and kappa lap(phi), each ~50 times larger near equilibrium, so phi',
+// its stencils and mu_phi are formed in RP and rounded to R afterwards.
+template <class R, class RP>
+__device__ inline void macro(const RP phi9[9], const R psi9[9], R Pd, R Qd, const R f[9],
                              const KP<R>& kp, Macro<R>& m) {
-  m.phid = phi9[0];
-  const R phi = R(0.5) + phi9[0];
+  m.phid = (R)phi9[0];
+  const RP phiw = RP(0.5) + phi9[0];
+  const R phi = (R)phiw;
   m.phi = phi;
   m.psid = psi9[0];
   // Eq. (61)
@@ -373,7 +386,11 @@ __device__ inline void macro(const R phi9[9], const R psi9[9], R Pd, R Qd, const
   m.itau_p = recip(R(0.5) + kp.three_vth * m.mup);
   m.itau_n = recip(R(0.5) + kp.three_vth * m.mum);
   // Eq. (59), (9); the linear part of psi contributes its exact gradient
-  grad_lap(phi9, m.gphi, &m.lphi);
+  RP gph[2], lph;
+  grad_lap<RP>(phi9, gph, &lph);
+  m.gphi[0] = (R)gph[0];
+  m.gphi[1] = (R)gph[1];
+  m.lphi = (R)lph;
   grad_lap<R>(psi9, m.gpsi, nullptr);
   m.gpsi[1] += kp.psi_slope;
   m.E[0] = -m.gpsi[0];
@@ -395,7 +412,8 @@ __device__ inline void macro(const R phi9[9], const R psi9[9], R Pd, R Qd, const
   m.cm = kp.c0 + m.cmd;
   m.rhoe = kp.q * (Pd - Qd);  // c+ - c- = P - Q
   // Eq. (12)-(14); phi - 1/2 = phi'
-  const R mu_phi = kp.beta4 * phi * (phi - R(1)) * phi9[0] - kp.kappa * m.lphi;
+  const R mu_phi =
+      (R)((RP)kp.beta4 * phiw * (phiw - RP(1)) * phi9[0] - (RP)kp.kappa * lph);
   m.grho[0] = kp.drho * m.gphi[0];
   m.grho[1] = kp.drho * m.gphi[1];
   m.geps[0] = kp.deps * m.gphi[0];
@@ -461,19 +479,20 @@ __device__ inline void collide_f(R f[9], const Macro<R>& m, const KP<R>& kp) {
 }
 
 // h: Eq. (27)-(32) on deviations from w_i / 2.  dJ = d(phi u)/dt by Eq. (58).
-template <class R>
-__device__ inline void collide_h(R h[9], const Macro<R>& m, const R dJ[2], const KP<R>& kp) {
+template <class R, class M>
+__device__ inline void collide_h(R h[9], const Macro<M>& m, const R dJ[2], const KP<R>& kp) {
   R mo[9];
   fwd9(h, mo);
-  const R phi = m.phi, phid = m.phid, ux = m.u[0], uy = m.u[1];
+  const R phi = (R)m.phi, phid = (R)m.phid, ux = (R)m.u[0], uy = (R)m.u[1];
+  const R gx = (R)m.gphi[0], gy = (R)m.gphi[1];
   const R third = R(1) / R(3), ninth = R(1) / R(9);
   // unit normal grad(phi)/|grad(phi)|, regularised where grad(phi) -> 0
-  const R g2 = m.gphi[0] * m.gphi[0] + m.gphi[1] * m.gphi[1];
+  const R g2 = gx * gx + gy * gy;
   R nx = R(0), ny = R(0);
   if (kp.n_eps2 > R(0) || g2 >= R(1e-24)) {
     const R ign = recip(sqrt(g2 + kp.n_eps2));
-    nx = m.gphi[0] * ign;
-    ny = m.gphi[1] * ign;
+    nx = gx * ign;
+    ny = gy * ign;
   }
   const R lam = kp.fourW * phi * (R(1) - phi);
   const R Ax = R(3) * dJ[0] + lam * nx, Ay = R(3) * dJ[1] + lam * ny;
@@ -504,58 +523,65 @@ __device__ inline void collide_h(R h[9], const Macro<R>& m, const R dJ[2], const
   inv9(mo, h);
 }
 
-// p and n: Eq. (34)-(40) on D2Q5, deviations from wbar_i c0.  cd is c - c0,
-// c the concentration; sign = -1 for cations (- S G), +1 for anions (+ S Gbar).
-template <class R>
-__device__ inline void collide_ion(R x[5], R cd, R c, R mu, R itau, int mask, R sign,
+// p and n: Eq. (34)-(40) on D2Q5, deviations from wbar_i c0.  cd is c - c0;
+// sign = -1 for cations (- S G), +1 for anions (+ S Gbar).  W is the working
+// type (FP64 with FP32 storage: the drift flux mu c grad(psi) is ~10 times
+// the deviations that carry the charge, and its FP32 rounding would random-
+// walk rho_e); c = c0 + cd is formed in W.
+template <class W, class R>
+__device__ inline void collide_ion(W x[5], W cd, R mu, R itau, int mask, W sign,
                                    const Macro<R>& m, const KP<R>& kp) {
-  R mo[5];
+  W mo[5];
   fwd5(x, mo);
-  const R third = R(1) / R(3);
-  const R Lx = kp.ion_force ? c * m.F[0] : R(0);
-  const R Ly = kp.ion_force ? c * m.F[1] : R(0);
-  const R Gx = mu * c * m.gpsi[0], Gy = mu * c * m.gpsi[1];
-  const R eq[5] = {cd, c * m.u[0], c * m.u[1], third * cd, third * cd};
-  const R so[5] = {m.Rr, Lx, Ly, third * m.Rr, third * m.Rr};
-  const R dr[5] = {R(0), Gx, Gy, R(0), R(0)};
+  const W third = W(1) / W(3);
+  const W c = (W)kp.c0 + cd;
+  const W Lx = kp.ion_force ? c * (W)m.F[0] : W(0);
+  const W Ly = kp.ion_force ? c * (W)m.F[1] : W(0);
+  const W Gx = (W)mu * c * (W)m.gpsi[0], Gy = (W)mu * c * (W)m.gpsi[1];
+  const W Rr = (W)m.Rr;
+  const W eq[5] = {cd, c * (W)m.u[0], c * (W)m.u[1], third * cd, third * cd};
+  const W so[5] = {Rr, Lx, Ly, third * Rr, third * Rr};
+  const W dr[5] = {W(0), Gx, Gy, W(0), W(0)};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const R s = rate(mask, k, itau, kp.s_free);
-    mo[k] = mo[k] - s * (mo[k] - eq[k]) + (R(1) - R(0.5) * s) * so[k] + sign * s * dr[k];
+    const W s = (W)rate(mask, k, itau, kp.s_free);
+    mo[k] = mo[k] - s * (mo[k] - eq[k]) + (W(1) - W(0.5) * s) * so[k] + sign * s * dr[k];
   }
   inv5(mo, x);
 }
 
-// Poisson source S_psi of Eq. (44) (or its variable-eps form).
-template <class R>
-__device__ inline R poisson_source(R rhoe, R ieps, const R geps[2], const R gpsi[2],
+// Poisson source S_psi of Eq. (44) (or its variable-eps form), in W.
+template <class W, class R>
+__device__ inline W poisson_source(R rhoe, R eps, const R geps[2], const R gpsi[2],
                                    const KP<R>& kp) {
-  R s = rhoe;
-  if (kp.poisson_form) s += geps[0] * gpsi[0] + geps[1] * gpsi[1];
-  return s * ieps;
+  W s = (W)rhoe;
+  if (kp.poisson_form) s += (W)geps[0] * (W)gpsi[0] + (W)geps[1] * (W)gpsi[1];
+  return s / (W)eps;
 }
 
-// g: Eq. (44)-(47) on deviations from the linear-potential equilibrium of the
-// node's own row.  Entering, g[2] and g[4] were stored relative to the rows
-// below and above; their references differ from the node's by +-dr_g.
-template <class R>
-__device__ inline void collide_g(R g[5], R psid, R Spsi, const KP<R>& kp) {
-  g[2] += kp.dr_g;
-  g[4] -= kp.dr_g;
-  R mo[5];
+// g: Eq. (44)-(47) on deviations from the uncharged steady state (see the
+// deviation form above): the collision is affine in g and psi, and the
+// reference is its fixed point, so the deviations obey the same collision
+// with the equilibrium of psi' and the source.
+// W is the working type: FP64 with FP32 storage, because the Poisson LBE is
+// an iterative solve whose rounding noise is amplified by the condition
+// number of the Laplacian (~ny^2); in FP32 it limits psi' to ~1e-6.
+template <class W, class R>
+__device__ inline void collide_g(W g[5], W psid, W Spsi, const KP<R>& kp) {
+  W mo[5];
   fwd5(g, mo);
-  const R third = R(1) / R(3);
-  const R eq[5] = {R(0), R(0), R(0), third * psid, third * psid};
+  const W third = W(1) / W(3);
+  const W eq[5] = {W(0), W(0), W(0), third * psid, third * psid};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const R s = rate(kp.mask_g, k, kp.inv_tau_g, kp.s_free);
+    const W s = (W)rate(kp.mask_g, k, kp.inv_tau_g, kp.s_free);
     mo[k] = mo[k] - s * (mo[k] - eq[k]);
   }
   inv5(mo, g);
-  const R src = kp.theta_src * Spsi;
-  g[0] += src * (R(1) / R(3));
+  const W src = (W)kp.theta_src * Spsi;
+  g[0] += src * (W(1) / W(3));
 #pragma unroll
-  for (int k = 1; k < 5; ++k) g[k] += src * (R(1) / R(6));
+  for (int k = 1; k < 5; ++k) g[k] += src * (W(1) / W(6));
 }
 
 }  // namespace lbm

@@ -63,13 +63,15 @@ __device__ inline void pull4(const PopView<S, R>& P, int q0, Cols k, int yy, R x
   x[3] = P.at(q0 + 4, rp + k.c);
 }
 
-// The h set of node (xc, yy): h0 from the rest plane (in place), h1..h8
-// pulled.
+// The h set of node (xc, yy): h0 from the rest plane (in place; also
+// returned in its own wider type), h1..h8 pulled.
 template <class S, class R, class T0>
 __device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x, Cols k,
-                              int yy, R x[9]) {
+                              int yy, R x[9], T0* h0 = nullptr) {
   const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
-  x[0] = (R)*elem(h0x, (uint32_t)yy * P.kp->pitch + k.c);
+  const T0 r = *elem(h0x, (uint32_t)yy * P.kp->pitch + k.c);
+  if (h0) *h0 = r;
+  x[0] = (R)r;
   x[1] = P.at(QH + 1, r0 + k.m);
   x[2] = P.at(QH + 2, rm + k.c);
   x[3] = P.at(QH + 3, r0 + k.p);
@@ -83,6 +85,15 @@ __device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x
 template <class R>
 __device__ inline R sum9(const R h[9]) {
   return h[0] + h[1] + h[2] + h[3] + h[4] + h[5] + h[6] + h[7] + h[8];
+}
+// phi' of Eq. (33) in the ring type RP, from the wide rest population and the
+// eight pulled ones
+template <class RP, class R>
+__device__ inline RP phi_of(RP h0, const R h[9]) {
+  RP s = h0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) s += (RP)h[i];
+  return s;
 }
 // psi' of Eq. (49): 1/(1 - 1/3) = 3/2 times the deviations of g1..g4 (their
 // references add up to psi_lin of the node's row)
@@ -108,8 +119,8 @@ __device__ inline void nine(const R d[3], const R c[3], const R u[3], R o[9]) {
 
 // Wall ghosts of the stencils: phi mirrored, psi odd about the wall value.
 // In deviation form the wall value of psi' is 0 at both electrodes.
-template <class R>
-__device__ inline void ghost_row(const R phc[3], const R psc[3], R phg[3], R psg[3]) {
+template <class RP, class R>
+__device__ inline void ghost_row(const RP phc[3], const R psc[3], RP phg[3], R psg[3]) {
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     phg[j] = phc[j];
@@ -171,13 +182,30 @@ struct Ghosts {
 template <class S, class R, class T0, class HG>
 __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev,
                                    const T0* __restrict__ h0src, T0* __restrict__ h0dst,
-                                   const KP<R>& kp, int x, int y, Cols k, const R phi9[9],
-                                   const R psi9[9], R f[9], R p[5], R n[5], R g0,
-                                   const HG& hg) {
-  const R Pd = p[0] + p[1] + p[2] + p[3] + p[4];
-  const R Qd = n[0] + n[1] + n[2] + n[3] + n[4];
-  Macro<R> m;
-  macro(phi9, psi9, Pd, Qd, f, kp, m);
+                                   const KP<R>& kp, const KP<T0>& kpw, int x, int y, Cols k,
+                                   const T0 phi9[9], const R psi9[9], R f[9], R p[5], R n[5],
+                                   R g0, const HG& hg) {
+  // Working type W: the wide type (FP64 with FP32 storage) for the
+  // macroscopic quantities and the f, p, n and g collisions; the h collision
+  // runs in R.  In FP32 the pressure and the potential, which the method
+  // integrates over many steps with little damping, random-walk away at the
+  // 1e-5 level over 20k steps; in FP64 they stay at the storage's rounding.
+  typedef T0 W;
+  W fw[9], pw[5], nw[5], ps9[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    fw[i] = (W)f[i];
+    ps9[i] = (W)psi9[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    pw[i] = (W)p[i];
+    nw[i] = (W)n[i];
+  }
+  const W Pd = pw[0] + pw[1] + pw[2] + pw[3] + pw[4];
+  const W Qd = nw[0] + nw[1] + nw[2] + nw[3] + nw[4];
+  Macro<W> m;
+  macro(phi9, ps9, Pd, Qd, fw, kpw, m);
 
   const uint32_t o = D.row(y + 1) + x;
   const bool edge = y == 0 || y == kp.ny - 1;
@@ -185,32 +213,50 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   const bool ins = kp.walls == WALL_INSULATING;
   const R third = R(1) / R(3);
 
-  {  // g: Eq. (44)-(47); psi = dpsi at the anode, 0 at the cathode
-    R g[5];
-    g[0] = g0;
-    hg.g4(g + 1);
-    collide_g(g, m.psid, poisson_source(m.rhoe, m.ieps, m.geps, m.gpsi, kp), kp);
+  // f first: its nine wide populations are then free for the rest
+  collide_f(fw, m, kpw);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) D.put(QG + i, o, g[i]);
+  for (int i = 0; i < 9; ++i) {
+    f[i] = (R)fw[i];
+    D.put(QF + i, o, f[i]);
+  }
+  if (edge) G.set9(QF, f);
+
+  {  // g: Eq. (44)-(47); psi = dpsi at the anode, 0 at the cathode
+    R g4[4];
+    hg.g4(g4);
+    W gw[5] = {(W)g0, (W)g4[0], (W)g4[1], (W)g4[2], (W)g4[3]};
+    collide_g(gw, m.psid, poisson_source<W>(m.rhoe, m.eps, m.geps, m.gpsi, kpw), kpw);
+    R g[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      g[i] = (R)gw[i];
+      D.put(QG + i, o, g[i]);
+    }
     if (edge) G.set5(QG, g, -g[4], -g[2]);
   }
 
-  collide_ion(p, m.cpd, m.cp, m.mup, m.itau_p, kp.mask_p, R(-1), m, kp);
+  collide_ion(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
+  collide_ion(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
 #pragma unroll
-  for (int i = 0; i < 5; ++i) D.put(QP + i, o, p[i]);
+  for (int i = 0; i < 5; ++i) {
+    p[i] = (R)pw[i];
+    n[i] = (R)nw[i];
+    D.put(QP + i, o, p[i]);
+  }
+  const R cpd = (R)m.cpd, cmd = (R)m.cmd;
   // anode: c+ = 0; cathode: d c+/dn = 0 (wall value = node value)
-  if (edge) G.set5(QP, p, ins ? p[4] : -p[4] - third * kp.c0, ins ? p[2] : -p[2] + third * m.cpd);
+  if (edge) G.set5(QP, p, ins ? p[4] : -p[4] - third * kp.c0, ins ? p[2] : -p[2] + third * cpd);
 
-  collide_ion(n, m.cmd, m.cm, m.mum, m.itau_n, kp.mask_n, R(1), m, kp);
 #pragma unroll
   for (int i = 0; i < 5; ++i) D.put(QN + i, o, n[i]);
   // anode: d c-/dn = 0; cathode: c- = 0
-  if (edge) G.set5(QN, n, ins ? n[4] : -n[4] + third * m.cmd, ins ? n[2] : -n[2] - third * kp.c0);
+  if (edge) G.set5(QN, n, ins ? n[4] : -n[4] + third * cmd, ins ? n[2] : -n[2] - third * kp.c0);
 
   {  // h: Eq. (27)-(32), with d(phi u)/dt of Eq. (58)
     const uint32_t jo = (uint32_t)y * kp.pitch + x;
     const uint32_t jpl = kp.cells;
-    const R Jx = m.phi * m.u[0], Jy = m.phi * m.u[1];
+    const R Jx = (R)(m.phi * m.u[0]), Jy = (R)(m.phi * m.u[1]);
     const R dJ[2] = {Jx - *elem(jprev, jo), Jy - *elem(jprev, jpl + jo)};
     *elem(jprev, jo) = Jx;
     *elem(jprev, jpl + jo) = Jy;
@@ -233,43 +279,42 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     if (edge) G.set9(QH, h);
   }
 
-  collide_f(f, m, kp);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) D.put(QF + i, o, f[i]);
-  if (edge) G.set9(QF, f);
 }
 
-// h and directions 1-4 of g of one node parked in LDS, one column per thread.
+// h1-h8 and g1-g4 of one node parked in LDS, one column per thread (h0 is
+// read again from the rest plane in its wider type).
 template <class R, int TW>
 struct HGLds {
   const R (*s)[TW];
   int lane;
   __device__ inline void h9(R o[9]) const {
+    o[0] = R(0);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) o[i] = s[i][lane];
+    for (int i = 1; i < 9; ++i) o[i] = s[i - 1][lane];
   }
   __device__ inline void g4(R o[4]) const {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = s[9 + i][lane];
+    for (int i = 0; i < 4; ++i) o[i] = s[8 + i][lane];
   }
 };
 
-// LDS of one sweep workgroup: the phi'/psi' ring and the parked h, g1-4.
-template <class R, int TW>
+// LDS of one sweep workgroup: the phi' ring (in RP), the psi' ring and the
+// parked h1-h8, g1-g4.
+template <class R, class RP, int TW>
 struct SweepLds {
-  R phi[RING][TW + 2];
+  RP phi[RING][TW + 2];
   R psi[RING][TW + 2];
-  R pull[2][13][TW];  // pulled h and g1-4 of a row, by row parity
+  R pull[2][12][TW];  // pulled h1-8 and g1-4 of a row, by row parity
 };
 
 // One tile of the fused sweep: columns [x0, x0 + 64 NW) of rows [y0, yend)
 // of one simulation, walked down row by row by the whole workgroup.
 template <class S, class R, class T0, int NW>
-__device__ inline void sweep_tile(SweepLds<R, 64 * NW>& L, const S* __restrict__ src,
+__device__ inline void sweep_tile(SweepLds<R, T0, 64 * NW>& L, const S* __restrict__ src,
                                   const S* __restrict__ srcg, S* __restrict__ dst,
                                   R* __restrict__ jprev, const T0* __restrict__ h0x,
-                                  T0* __restrict__ h0dst, const KP<R>& kp, int x0, int y0,
-                                  int yend) {
+                                  T0* __restrict__ h0dst, const KP<R>& kp,
+                                  const KP<T0>& kpw, int x0, int y0, int yend) {
   constexpr int TW = 64 * NW;
   const int nx = kp.nx, ny = kp.ny;
   const int w = min(TW, nx - x0);
@@ -294,22 +339,24 @@ __device__ inline void sweep_tile(SweepLds<R, 64 * NW>& L, const S* __restrict__
     const int sl = slot(yy);
     if (lane < 2) {
       R hh[9], gg[4];
-      pull_h(Ph, h0x, kh, ys, hh);
+      T0 hh0;
+      pull_h(Ph, h0x, kh, ys, hh, &hh0);
       pull4(Pg, 0, kh, ys, gg);
-      L.phi[sl][kcol] = sum9(hh);
+      L.phi[sl][kcol] = phi_of<T0>(hh0, hh);
       L.psi[sl][kcol] = psi_of(gg);
     }
     if (valid) {
       R h[9], g4[4];
-      pull_h(Ph, h0x, k, ys, h);
+      T0 h0;
+      pull_h(Ph, h0x, k, ys, h, &h0);
       pull4(Pg, 0, k, ys, g4);
-      L.phi[sl][lane + 1] = sum9(h);
+      L.phi[sl][lane + 1] = phi_of<T0>(h0, h);
       L.psi[sl][lane + 1] = psi_of(g4);
       const int b = (yy - y0 + 2) & 1;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) L.pull[b][i][lane] = h[i];
+      for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = h[i];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) L.pull[b][9 + i][lane] = g4[i];
+      for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = g4[i];
     }
   };
 
@@ -336,9 +383,10 @@ __device__ inline void sweep_tile(SweepLds<R, 64 * NW>& L, const S* __restrict__
     __syncthreads();
     if (valid) {
       const int c = lane + 1, sc = slot(y);
-      R phC[3] = {L.phi[sc][c - 1], L.phi[sc][c], L.phi[sc][c + 1]};
+      T0 phC[3] = {L.phi[sc][c - 1], L.phi[sc][c], L.phi[sc][c + 1]};
       R psC[3] = {L.psi[sc][c - 1], L.psi[sc][c], L.psi[sc][c + 1]};
-      R phU[3], psU[3], phD[3], psD[3];
+      T0 phU[3], phD[3];
+      R psU[3], psD[3];
       if (up) {
         const int su = slot(y + 1);
         phU[0] = L.phi[su][c - 1]; phU[1] = L.phi[su][c]; phU[2] = L.phi[su][c + 1];
@@ -353,12 +401,13 @@ __device__ inline void sweep_tile(SweepLds<R, 64 * NW>& L, const S* __restrict__
       } else {
         ghost_row(phC, psC, phD, psD);
       }
-      R phi9[9], psi9[9];
+      T0 phi9[9];
+      R psi9[9];
       nine(phD, phC, phU, phi9);
       nine(psD, psC, psU, psi9);
 
       const HGLds<R, TW> hg{L.pull[(y - y0 + 2) & 1], lane};
-      update_node<S, R, T0>(D, jprev, h0x, h0dst, kp, x, y, k, phi9, psi9, f, p, n, g0, hg);
+      update_node<S, R, T0>(D, jprev, h0x, h0dst, kp, kpw, x, y, k, phi9, psi9, f, p, n, g0, hg);
     }
   }
 }
@@ -377,6 +426,7 @@ __device__ inline int xcd_tile(int xcd_chunk) {
 template <class S, class R, class T0>
 struct SimDesc {
   KP<R> kp;
+  KP<T0> kpw;  // the same constants in the wide working type
   S* pop[2];
   R* jprev;
   T0* h0[2];
@@ -397,18 +447,23 @@ struct BatchTile {
 // XCD hold neighbouring strips of the same rows and the cache lines they
 // share are fetched from HBM once.  `flip` = 1 swaps every member's buffers
 // (odd steps of a captured block).
+//
+// At least four waves per SIMD are asked of the register allocator: with the
+// FP64 working type of FP32 storage it otherwise settles on 144 VGPRs (three
+// waves); four waves with a few spilled registers are up to 18 % faster on
+// MI355X at 2048^2.
 template <class S, class R, class T0, int NW>
-__global__ __launch_bounds__(64 * NW) void k_sweep_batch(const SimDesc<S, R, T0>* __restrict__ sims,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_batch(const SimDesc<S, R, T0>* __restrict__ sims,
                                                          const BatchTile* __restrict__ tiles,
                                                          int xcd_chunk, int flip) {
-  __shared__ SweepLds<R, 64 * NW> L;
+  __shared__ SweepLds<R, T0, 64 * NW> L;
   const BatchTile tl = tiles[xcd_tile(xcd_chunk)];
   if (tl.sim < 0) return;
   const SimDesc<S, R, T0>& sd = sims[tl.sim];
   const int a = (sd.cur + flip) & 1;
   const S* src = sd.pop[a];
   sweep_tile<S, R, T0, NW>(L, src, src + (size_t)QG * sd.kp.pitch, sd.pop[1 - a], sd.jprev,
-                           sd.h0[a], sd.h0[1 - a], sd.kp, tl.x0, tl.y0, tl.yend);
+                           sd.h0[a], sd.h0[1 - a], sd.kp, sd.kpw, tl.x0, tl.y0, tl.yend);
 }
 
 // ---------------------------------------------------------------------------
@@ -521,7 +576,7 @@ __global__ void k_poisson(const S* __restrict__ srcg, S* __restrict__ dstg,
   grad_lap<R>(psi9, gpsi, nullptr);
   gpsi[1] += kp.psi_slope;
   const R geps[2] = {kp.deps * gphi[0], kp.deps * gphi[1]};
-  collide_g(g, psi9[0], poisson_source(mom[2 * np + c], recip(eps), geps, gpsi, kp), kp);
+  collide_g(g, psi9[0], poisson_source<R>(mom[2 * np + c], eps, geps, gpsi, kp), kp);
   const uint32_t o = DG.row(y + 1) + x;
   for (int i = 0; i < 5; ++i) DG.put(i, o, g[i]);
   const uint32_t top = DG.row(kp.ny + 1);
@@ -553,7 +608,7 @@ struct InitSpec {
   // or host-provided fields (device copies, [ny][nx]); ux/uy may be null
   const double *phi, *cp, *cm, *psi, *ux, *uy;
   // absolute parameters (FP64)
-  double W, c0, dpsi, rho_v, drho;
+  double W, c0, dpsi, rho_v, drho, a_g;
 };
 
 // Equilibrium initial state.  The population arriving at node (x, y) along
@@ -594,7 +649,7 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
     int xs = x - cx[i];
     xs = xs < 0 ? xs + kp.nx : (xs >= kp.nx ? xs - kp.nx : xs);
     const int ys = y - cy[i];
-    const double ref = plane_ref(q, ys, kp.ny, kp.walls, sp.c0, sp.dpsi);
+    const double ref = plane_ref(q, ys, kp.ny, kp.walls, sp.c0, sp.dpsi, sp.a_g);
     D.put(q, D.row(ys + 1) + xs, (R)(v - ref));
   };
   // h: the rest population (which does not move) takes phi minus what the

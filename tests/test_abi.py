@@ -97,6 +97,6 @@ def test_footprint_covers_state_and_scratch():
     p = lbm_ehd.make_params(nx=300, ny=200, precision="fp16")
     pop, aux = lbm_ehd.lbm_ehd_required_bytes(p)
     fp = lbm_ehd.lbm_ehd_footprint_bytes(p)
-    # state, then FP32 moment planes and FP64 field planes for readback
-    assert fp >= 2 * pop + aux + 300 * 200 * (3 * 4 + 10 * 8)
-    assert fp < 2 * pop + aux + 300 * 200 * (3 * 4 + 10 * 8) + 1 << 20
+    # state, then FP64 moment and field planes for readback
+    assert fp >= 2 * pop + aux + 300 * 200 * (3 * 8 + 10 * 8)
+    assert fp < 2 * pop + aux + 300 * 200 * (3 * 8 + 10 * 8) + (1 << 20)
