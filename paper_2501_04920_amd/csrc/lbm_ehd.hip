@@ -44,8 +44,11 @@ size_t elem_size(int prec) {
   }
 }
 size_t arith_size(int prec) { return (prec == LBM_FP64 || prec == LBM_FP32_F64) ? 8 : 4; }
-// width of the rest population of h (see RestOf)
-size_t rest_size(int prec) { return elem_size(prec) == 2 ? 4 : 8; }
+// width of the rest population of h (see RestOf): FP64 in every form
+size_t rest_size(int) { return 8; }
+// 16-bit storage also reads and writes the line of h0 in the population
+// buffers (the reference phase of the moving h, see LocalH)
+bool local_h(int prec) { return elem_size(prec) == 2; }
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
@@ -122,6 +125,24 @@ double a_g_of(const lbm_ehd_params& p) {
   return (1.0 / s2 - 1.0) * p.dpsi / p.ny / 6.0;
 }
 
+// Offsets of the ion lines stored in 16 bits: the uniform steady bulk of the
+// outer phase in the applied field G = dpsi / ny (0 in a y-periodic box) has
+// c_b = c0 sqrt(1 + 2 gamma_v G) (reaction on) and drifts at +mu_+ G
+// (cations) and -mu_- G (anions), i.e. populations wbar_q c_b (1 +- 3 c_qy
+// mu G), given as offsets from wbar_q c0.
+void ion_offsets(const lbm_ehd_params& p, double out[10]) {
+  const double G = p.walls == LBM_PERIODIC ? 0.0 : p.dpsi / p.ny;
+  const double cb = p.reaction ? p.c0 * std::sqrt(1.0 + 2.0 * p.gamma_v * G) : p.c0;
+  const double wb[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+  for (int s = 0; s < 2; ++s) {
+    const double drift = s == 0 ? p.mu_v * G : -p.mu_v * p.m_ratio * G;
+    for (int k = 0; k < 5; ++k) {
+      const double cy = k == 2 ? 1.0 : (k == 4 ? -1.0 : 0.0);
+      out[5 * s + k] = wb[k] * (cb * (1.0 + 3.0 * cy * drift) - p.c0);
+    }
+  }
+}
+
 template <class R>
 KP<R> make_kp(const lbm_ehd* h) {
   const lbm_ehd_params& p = h->P;
@@ -171,6 +192,9 @@ KP<R> make_kp(const lbm_ehd* h) {
   const bool per = p.walls == LBM_PERIODIC;
   k.psi_slope = per ? (R)0 : (R)(-p.dpsi / p.ny);
   k.a_g = (R)a_g_of(p);
+  double io[10];
+  ion_offsets(p, io);
+  for (int i = 0; i < 10; ++i) k.iofs[i] = (R)io[i];
   k.force_x = (R)p.force_x;
   k.force_y = (R)p.force_y;
   // binary16: keep the deviations of each set well inside the normal range
@@ -179,7 +203,9 @@ KP<R> make_kp(const lbm_ehd* h) {
   if (p.precision == LBM_FP16_STORE) {
     auto pow2_below = [](double v) { return std::ldexp(1.0, (int)std::floor(std::log2(v))); };
     const double c0 = std::max(std::fabs(p.c0), 1e-6);
-    const double sets[5] = {4096.0, 1.0, pow2_below(4096.0 / c0), pow2_below(4096.0 / c0),
+    // h: the deviations from the node-local references are ~1e-3 and the
+    // references themselves lie in [-1/2, 1/2]
+    const double sets[5] = {4096.0, 64.0, pow2_below(4096.0 / c0), pow2_below(4096.0 / c0),
                             pow2_below(4096.0 / std::max(std::fabs(p.dpsi), 1e-3))};
     for (int i = 0; i < 5; ++i) {
       k.sc[i] = (R)sets[i];
@@ -193,6 +219,7 @@ KP<R> make_kp(const lbm_ehd* h) {
 template <class S, class R>
 struct Form {
   typedef typename RestOf<S>::type T0;
+  typedef typename WorkOf<S>::type W;
   static S* buf(lbm_ehd* h, int i) { return static_cast<S*>(h->pop[i]); }
   static R* jp(lbm_ehd* h) { return static_cast<R*>(h->aux); }
   // rest population of h, two planes after the two (phi u) planes; like
@@ -211,7 +238,7 @@ struct Form {
     Desc d;
     std::memset(&d, 0, sizeof d);
     d.kp = make_kp<R>(h);
-    d.kpw = make_kp<T0>(h);
+    d.kpw = make_kp<W>(h);
     d.pop[0] = buf(h, 0);
     d.pop[1] = buf(h, 1);
     d.jprev = jp(h);
@@ -350,17 +377,17 @@ struct Form {
     return LBM_OK;
   }
 
-  // Readback in the wide type T0 (FP64 for FP32 and FP64 storage): the
+  // Readback in the working type W (FP64 for FP32 and FP64 storage): the
   // derived fields (u, p, E, ...) are formed from the stored state without
   // adding FP32 rounding of their own.
   static lbm_status fields(lbm_ehd* h) {
-    lbm_status st = moments_as<T0>(h, nullptr);
+    lbm_status st = moments_as<W>(h, nullptr);
     if (st) return st;
     if (!h->fld) HIP_TRY(hipMalloc(&h->fld, 10 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
-    const KP<T0> kp = make_kp<T0>(h);
+    const KP<W> kp = make_kp<W>(h);
     const S* src = buf(h, h->cur);
-    hipLaunchKernelGGL((k_fields<S, T0>), grid2(h), dim3(64), 0, h->stream, src,
-                       static_cast<const T0*>(h->mom), h->fld, kp);
+    hipLaunchKernelGGL((k_fields<S, W>), grid2(h), dim3(64), 0, h->stream, src,
+                       static_cast<const W*>(h->mom), h->fld, kp);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -1176,9 +1203,11 @@ lbm_status lbm_ehd_batch_destroy(lbm_ehd_batch* b) {
 double lbm_ehd_bytes_per_lup(int32_t precision) {
   const size_t s = elem_size(precision);
   if (!s) return 0.0;
-  // 32 moving or pulled planes, the rest population of h and (phi u)(t-1),
-  // each read once and written once
-  return 2.0 * (NPOP - 1) * s + 2.0 * rest_size(precision) + 2.0 * 2.0 * arith_size(precision);
+  // 32 moving or pulled planes (and the reference phase of h with 16-bit
+  // storage), the rest population of h and (phi u)(t-1), each read once and
+  // written once
+  return 2.0 * (NPOP - 1 + (local_h(precision) ? 1 : 0)) * s + 2.0 * rest_size(precision) +
+         2.0 * 2.0 * arith_size(precision);
 }
 
 }  // extern "C"

@@ -20,7 +20,15 @@
 //   apart, which the HBM serves measurably faster.
 //
 // Deviation form: every plane stores x_q - ref_q with a fixed reference
-//   f: 0;  h: w_q / 2;  p, n: wbar_q c0;
+//   f: 0;  h: w_q / 2;
+//   p, n: wbar_q c0.  With 16-bit storage the ion lines are stored relative
+//      to the uniform steady bulk instead: concentration c_b = c0 sqrt(1 +
+//      2 gamma_v G) (the Onsager-Wien equilibrium in the applied field
+//      G = dpsi / ny of the outer phase) drifting at mu_v G, wbar_q c_b
+//      (1 +- 3 c_qy mu_v G), so that neither the field-enhanced dissociation
+//      nor the ohmic flux of the bulk is carried by the 16-bit values (the
+//      collisions still work on deviations from wbar_q c0: loads add and
+//      stores subtract the per-line offset);
 //   g: the exact steady post-collision populations of the uncharged
 //      potential between the electrodes, psi_lin(y) = dpsi (ny - 1/2 - y) / ny
 //      (0 in a y-periodic box): -2 psi_lin / 3, psi_lin / 6 (+x, -x),
@@ -78,6 +86,7 @@ struct KP {
   R theta_src;       // theta times the source normalisation
   R dpsi, psi_slope; // anode potential; d psi_lin / dy (0 in a periodic box)
   R a_g;             // (tau_g - 1) dpsi / (6 ny): reference offset of g +-y
+  R iofs[10];        // 16-bit storage: offsets of the p and n lines (see above)
   R force_x, force_y;
   R sc[5], isc[5];   // binary16 storage: power-of-two scale of each set (f h p n g)
 };
@@ -180,20 +189,30 @@ __device__ inline float stored_as<__hip_bfloat16, float>(float x) {
   return __bfloat162float(__float2bfloat16(x));
 }
 
-// Type of the rest population of h, kept next to (phi u)(t-1) and wider than
-// the other populations: it absorbs the rounding of the eight moving h
+// Type of the rest population of h, kept next to (phi u)(t-1): FP64 in
+// every storage form.  It absorbs the rounding of the eight moving h
 // populations of its node, so that every collision conserves phi to FP64
-// rounding (FP32 storage) or FP32 rounding (16-bit storage).
+// rounding.  (In FP32 the per-step changes of slowly varying cells would
+// fall below half an ulp of the rest population and be lost, always in the
+// same direction.)
 template <class S>
 struct RestOf {
   typedef double type;
 };
+
+// Working type of the sweep for a storage type: the phase ring, the
+// macroscopic quantities, the f, p, n, g collisions and the readback.  FP64
+// with FP32 or FP64 storage, FP32 with 16-bit storage.
+template <class S>
+struct WorkOf {
+  typedef double type;
+};
 template <>
-struct RestOf<__half> {
+struct WorkOf<__half> {
   typedef float type;
 };
 template <>
-struct RestOf<__hip_bfloat16> {
+struct WorkOf<__hip_bfloat16> {
   typedef float type;
 };
 
@@ -208,6 +227,39 @@ struct Scaled<__half> {
   static constexpr bool value = true;
 };
 
+// 16-bit storage keeps the moving h populations relative to w_i times the
+// phase of the node they arrive at, phi'~ (phi' = phi - 1/2 of that node at
+// the step they were sent, rounded to the storage type and stored by the node
+// itself in the line of h0, which the population buffers do not otherwise
+// use).  The stored deviations are then the O(|u|) and non-equilibrium parts
+// only, about a hundred times smaller than phi itself, and 16-bit rounding
+// no longer shakes the interface.  Wider storage keeps the fixed reference.
+template <class S>
+struct LocalH {
+  static constexpr bool value = false;
+};
+template <>
+struct LocalH<__half> {
+  static constexpr bool value = true;
+};
+template <>
+struct LocalH<__hip_bfloat16> {
+  static constexpr bool value = true;
+};
+// lattice weights of Eq. (25), for the references above
+__device__ constexpr float W9F[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
+                                     1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+// the moving h population a node reconstructs from a stored deviation and
+// its reference phase.  The sender books exactly this value into the rest
+// population, so both sides must round alike: one fused multiply-add, never
+// left to the compiler's contraction (which differs between call sites).
+__device__ inline float h_from(float dev, int i, float phit) {
+  return __builtin_fmaf(W9F[i], phit, dev);
+}
+__device__ inline double h_from(double dev, int i, double phit) {
+  return __builtin_fma((double)W9F[i], phit, dev);
+}
+
 // A population buffer (or its g set) seen through a buffer descriptor:
 // population q (counted from the view's base; `qoff` is the population index
 // of that base, for the set scale) at element offset `off` = row(r) + x.
@@ -217,24 +269,32 @@ struct PopView {
   const KP<R>* kp;
   int qoff;
   __device__ inline uint32_t row(int r) const { return (uint32_t)r * kp->rstride; }
+  // offset of the ion lines with 16-bit storage (see the deviation form)
+  __device__ inline R ofs(int q) const {
+    const int a = q + qoff;
+    if (!LocalH<S>::value || a < QP || a >= QG) return R(0);
+    return kp->iofs[a - QP];
+  }
   __device__ inline R at(int q, uint32_t off) const {
     R v = Codec<S, R>::ld(rs, off * (uint32_t)sizeof(S),
                           (uint32_t)q * kp->pitch * (uint32_t)sizeof(S));
     if (Scaled<S>::value) v *= kp->isc[set_of(q + qoff)];
-    return v;
+    return v + ofs(q);
   }
   __device__ inline void put(int q, uint32_t off, R v) const {
+    v -= ofs(q);
     if (Scaled<S>::value) v *= kp->sc[set_of(q + qoff)];
     Codec<S, R>::st(rs, off * (uint32_t)sizeof(S), (uint32_t)q * kp->pitch * (uint32_t)sizeof(S),
                     v);
   }
-  // the value v takes once stored in plane q
+  // the value v takes once stored in plane q (and loaded back)
   __device__ inline R stored(int q, R v) const {
+    const R o = ofs(q);
     if (Scaled<S>::value) {
       const int k = set_of(q + qoff);
-      return stored_as<S, R>(v * kp->sc[k]) * kp->isc[k];
+      return stored_as<S, R>((v - o) * kp->sc[k]) * kp->isc[k] + o;
     }
-    return stored_as<S, R>(v);
+    return stored_as<S, R>(v - o) + o;
   }
 };
 
@@ -256,7 +316,7 @@ __device__ inline double plane_ref(int q, int y, int ny, int walls, double c0, d
   if (q < QP) return 0.5 * w9[q - QH];
   const int k = q < QN ? q - QP : (q < QG ? q - QN : q - QG);
   const double wb = k == 0 ? 1.0 / 3 : 1.0 / 6;
-  if (q < QG) return wb * c0;
+  if (q < QG) return wb * c0;  // the drift offsets are PopView's
   const double psi = walls == WALL_PERIODIC ? 0.0 : dpsi * (ny - 0.5 - y) / ny;
   return k == 0 ? -2.0 / 3 * psi : psi / 6 + (k == 2 ? a_g : (k == 4 ? -a_g : 0.0));
 }

@@ -80,6 +80,11 @@ __device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x
   x[6] = P.at(QH + 6, rm + k.p);
   x[7] = P.at(QH + 7, rp + k.p);
   x[8] = P.at(QH + 8, rp + k.m);
+  if (LocalH<S>::value) {
+    const R t = P.at(QH, r0 + k.c);  // the node's own reference phase
+#pragma unroll
+    for (int i = 1; i < 9; ++i) x[i] = h_from(x[i], i, t);
+  }
 }
 
 template <class R>
@@ -182,15 +187,16 @@ struct Ghosts {
 template <class S, class R, class T0, class HG>
 __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev,
                                    const T0* __restrict__ h0src, T0* __restrict__ h0dst,
-                                   const KP<R>& kp, const KP<T0>& kpw, int x, int y, Cols k,
-                                   const T0 phi9[9], const R psi9[9], R f[9], R p[5], R n[5],
-                                   R g0, const HG& hg) {
+                                   const KP<R>& kp, const KP<typename WorkOf<S>::type>& kpw, int x,
+                                   int y, Cols k, const typename WorkOf<S>::type phi9[9],
+                                   const R psi9[9], R f[9], R p[5], R n[5], R g0,
+                                   const HG& hg) {
   // Working type W: the wide type (FP64 with FP32 storage) for the
   // macroscopic quantities and the f, p, n and g collisions; the h collision
   // runs in R.  In FP32 the pressure and the potential, which the method
   // integrates over many steps with little damping, random-walk away at the
   // 1e-5 level over 20k steps; in FP64 they stay at the storage's rounding.
-  typedef T0 W;
+  typedef typename WorkOf<S>::type W;
   W fw[9], pw[5], nw[5], ps9[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -268,11 +274,26 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
 #pragma unroll
     for (int i = 1; i < 9; ++i) mass += (double)h[i];
     collide_h(h, m, dJ, kp);
+    // reference phase of each destination (16-bit storage; 0 otherwise):
+    // phi'~ of node x + c_i, or of the node itself for populations that a
+    // wall sends back to it
+    R t[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) t[i] = R(0);
+    if (LocalH<S>::value) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) t[i] = D.stored(QH, (R)phi9[i]);
+      if (kp.walls != WALL_PERIODIC) {
+        if (y == 0) t[4] = t[7] = t[8] = t[0];
+        if (y == kp.ny - 1) t[2] = t[5] = t[6] = t[0];
+      }
+      D.put(QH, o, t[0]);  // this node's reference for the next step
+    }
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-      h[i] = D.stored(QH + i, h[i]);
+      h[i] = D.stored(QH + i, h[i] - (R)W9F[i] * t[i]);
       D.put(QH + i, o, h[i]);
-      mass -= (double)h[i];
+      mass -= (double)h_from(h[i], i, t[i]);
     }
     // the rest population takes what the eight stored ones leave of the mass
     *elem(h0dst, jo) = (T0)mass;
@@ -310,11 +331,14 @@ struct SweepLds {
 // One tile of the fused sweep: columns [x0, x0 + 64 NW) of rows [y0, yend)
 // of one simulation, walked down row by row by the whole workgroup.
 template <class S, class R, class T0, int NW>
-__device__ inline void sweep_tile(SweepLds<R, T0, 64 * NW>& L, const S* __restrict__ src,
+__device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>& L,
+                                  const S* __restrict__ src,
                                   const S* __restrict__ srcg, S* __restrict__ dst,
                                   R* __restrict__ jprev, const T0* __restrict__ h0x,
                                   T0* __restrict__ h0dst, const KP<R>& kp,
-                                  const KP<T0>& kpw, int x0, int y0, int yend) {
+                                  const KP<typename WorkOf<S>::type>& kpw, int x0, int y0,
+                                  int yend) {
+  typedef typename WorkOf<S>::type W;
   constexpr int TW = 64 * NW;
   const int nx = kp.nx, ny = kp.ny;
   const int w = min(TW, nx - x0);
@@ -342,7 +366,7 @@ __device__ inline void sweep_tile(SweepLds<R, T0, 64 * NW>& L, const S* __restri
       T0 hh0;
       pull_h(Ph, h0x, kh, ys, hh, &hh0);
       pull4(Pg, 0, kh, ys, gg);
-      L.phi[sl][kcol] = phi_of<T0>(hh0, hh);
+      L.phi[sl][kcol] = phi_of<W>((W)hh0, hh);
       L.psi[sl][kcol] = psi_of(gg);
     }
     if (valid) {
@@ -350,7 +374,7 @@ __device__ inline void sweep_tile(SweepLds<R, T0, 64 * NW>& L, const S* __restri
       T0 h0;
       pull_h(Ph, h0x, k, ys, h, &h0);
       pull4(Pg, 0, k, ys, g4);
-      L.phi[sl][lane + 1] = phi_of<T0>(h0, h);
+      L.phi[sl][lane + 1] = phi_of<W>((W)h0, h);
       L.psi[sl][lane + 1] = psi_of(g4);
       const int b = (yy - y0 + 2) & 1;
 #pragma unroll
@@ -383,9 +407,9 @@ __device__ inline void sweep_tile(SweepLds<R, T0, 64 * NW>& L, const S* __restri
     __syncthreads();
     if (valid) {
       const int c = lane + 1, sc = slot(y);
-      T0 phC[3] = {L.phi[sc][c - 1], L.phi[sc][c], L.phi[sc][c + 1]};
+      W phC[3] = {L.phi[sc][c - 1], L.phi[sc][c], L.phi[sc][c + 1]};
       R psC[3] = {L.psi[sc][c - 1], L.psi[sc][c], L.psi[sc][c + 1]};
-      T0 phU[3], phD[3];
+      W phU[3], phD[3];
       R psU[3], psD[3];
       if (up) {
         const int su = slot(y + 1);
@@ -401,7 +425,7 @@ __device__ inline void sweep_tile(SweepLds<R, T0, 64 * NW>& L, const S* __restri
       } else {
         ghost_row(phC, psC, phD, psD);
       }
-      T0 phi9[9];
+      W phi9[9];
       R psi9[9];
       nine(phD, phC, phU, phi9);
       nine(psD, psC, psU, psi9);
@@ -426,7 +450,7 @@ __device__ inline int xcd_tile(int xcd_chunk) {
 template <class S, class R, class T0>
 struct SimDesc {
   KP<R> kp;
-  KP<T0> kpw;  // the same constants in the wide working type
+  KP<typename WorkOf<S>::type> kpw;  // the same constants in the working type
   S* pop[2];
   R* jprev;
   T0* h0[2];
@@ -448,15 +472,16 @@ struct BatchTile {
 // share are fetched from HBM once.  `flip` = 1 swaps every member's buffers
 // (odd steps of a captured block).
 //
-// At least four waves per SIMD are asked of the register allocator: with the
-// FP64 working type of FP32 storage it otherwise settles on 144 VGPRs (three
-// waves); four waves with a few spilled registers are up to 18 % faster on
-// MI355X at 2048^2.
+// At least four waves per SIMD are asked of the register allocator (two with
+// FP64 arithmetic): with the FP64 working type of FP32 storage it otherwise
+// settles on 144 VGPRs (three waves); four waves with a few spilled
+// registers are up to 18 % faster on MI355X at 2048^2.
 template <class S, class R, class T0, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_batch(const SimDesc<S, R, T0>* __restrict__ sims,
-                                                         const BatchTile* __restrict__ tiles,
-                                                         int xcd_chunk, int flip) {
-  __shared__ SweepLds<R, T0, 64 * NW> L;
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
+    const SimDesc<S, R, T0>* __restrict__ sims,
+    const BatchTile* __restrict__ tiles, int xcd_chunk, int flip) {
+  __shared__ SweepLds<R, typename WorkOf<S>::type, 64 * NW> L;
   const BatchTile tl = tiles[xcd_tile(xcd_chunk)];
   if (tl.sim < 0) return;
   const SimDesc<S, R, T0>& sd = sims[tl.sim];
@@ -655,15 +680,20 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
   // h: the rest population (which does not move) takes phi minus what the
   // eight stored moving populations hold, so that phi is exact from the start
   double hrest = phi - 0.5;
+  R tref = R(0);  // this node's reference phase (16-bit storage)
+  if (LocalH<S>::value) {
+    tref = D.stored(QH, (R)(phi - 0.5));
+    D.put(QH, D.row(y + 1) + x, tref);
+  }
   for (int i = 0; i < 9; ++i) {
     const double cu = cx[i] * ux + cy[i] * uy;
     // f: pressure-based equilibrium with p = 0
     put(QF + i, i, rho * w9[i] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
     if (i > 0) {
       const double dev = w9[i] * phi * (1.0 + 3.0 * cu) - 0.5 * w9[i];
-      const R st = D.stored(QH + i, (R)dev);
+      const R st = D.stored(QH + i, (R)(dev - (double)W9F[i] * (double)tref));
       put(QH + i, i, (double)st + 0.5 * w9[i]);
-      hrest -= (double)st;
+      hrest -= (double)h_from(st, i, tref);
     }
   }
   *elem(h0x, (uint32_t)y * kp.pitch + x) = (T0)hrest;
@@ -696,7 +726,7 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
   for (int x = t; x < kp.nx; x += 256) {
     const Cols k = cols_of(x, kp.nx);
     R h[9], t4[4], g4[4];
-    pull9(Ph, QH, k, y, h);
+    pull_h(Ph, h0x, k, y, h);
     const uint32_t r0 = Ph.row(y + 1);
     const double h0 = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
     pull4(Ph, QP, k, y, t4);

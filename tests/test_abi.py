@@ -42,7 +42,7 @@ def test_defaults_and_bytes():
     assert pop == 33 * 130 * 128 * 4 and aux == 128 * 128 * (2 * 4 + 2 * 8)
     # 32 moving planes + rest of h + (phi u), each read and written once
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp32") == 2 * 32 * 4 + 2 * 8 + 2 * 8
-    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 2 * 32 * 2 + 2 * 4 + 2 * 8
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 2 * 33 * 2 + 2 * 8 + 2 * 8
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp64") == 2 * 32 * 8 + 2 * 8 + 2 * 16
 
 

@@ -214,9 +214,9 @@ def test_sum_phi_conserved(precision):
     s0 = sim.diagnostics()["sum_phi"]
     sim.step(1000)
     s1 = sim.diagnostics()["sum_phi"]
-    # FP64 rest population: exact to FP64 rounding; FP32 rest (16-bit forms):
-    # to FP32 rounding of one value per cell and step
-    assert abs(s1 / s0 - 1) < (1e-12 if precision in ("fp64", "fp32") else 1e-7)
+    # the FP64 rest population absorbs the rounding of the stored moving h:
+    # exact to FP64 rounding in every storage form
+    assert abs(s1 / s0 - 1) < 1e-12
 
 
 def test_error_paths():
