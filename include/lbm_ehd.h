@@ -378,10 +378,13 @@ LBM_API lbm_status lbm_ehd_destroy(lbm_ehd *h);
 /* Message of the last error on the calling thread ("" if none). */
 LBM_API const char *lbm_ehd_last_error(void);
 
-/* Algorithmic HBM bytes one lattice update moves in the fused sweep: the 32
- * moving populations in the storage type, the rest population of h in its
- * wider type and (phi u)(t-1) in the arithmetic type, each read and written
- * once. */
+/* Algorithmic HBM bytes one lattice update moves in the fused sweep, each
+ * item read and written once: the 32 moving populations in the storage type
+ * (with 16-bit storage: 30, the rest populations of the two ions being kept
+ * in FP64, plus the line of the reference phase of h), the FP64 rest
+ * populations (h0; with 16-bit storage also p0 and n0) and (phi u)(t-1) in
+ * the arithmetic type.  FP64 560, FP32 288, FP32 storage with FP64
+ * arithmetic 304, FP16 and BF16 188. */
 LBM_API double lbm_ehd_bytes_per_lup(int32_t precision);
 
 /* Measurement helper, not part of the method: copy `bytes` (a multiple of

@@ -44,11 +44,12 @@ size_t elem_size(int prec) {
   }
 }
 size_t arith_size(int prec) { return (prec == LBM_FP64 || prec == LBM_FP32_F64) ? 8 : 4; }
-// width of the rest population of h (see RestOf): FP64 in every form
-size_t rest_size(int) { return 8; }
 // 16-bit storage also reads and writes the line of h0 in the population
 // buffers (the reference phase of the moving h, see LocalH)
 bool local_h(int prec) { return elem_size(prec) == 2; }
+// bytes per cell and time level of the FP64 rest populations (see RestOf and
+// IonRest): h0, and with 16-bit storage also p0 and n0
+size_t rest_bytes(int prec) { return 8 * (local_h(prec) ? 3 : 1); }
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
@@ -222,13 +223,14 @@ struct Form {
   typedef typename WorkOf<S>::type W;
   static S* buf(lbm_ehd* h, int i) { return static_cast<S*>(h->pop[i]); }
   static R* jp(lbm_ehd* h) { return static_cast<R*>(h->aux); }
-  // rest population of h, two planes after the two (phi u) planes; like
-  // the populations it ping-pongs between time levels (neighbouring
-  // workgroups read it for their phi halo)
+  // FP64 rest populations of time level i, after the two (phi u) planes:
+  // h0 (then p0, n0 with 16-bit storage), one plane each.  Like the
+  // populations they ping-pong between time levels (neighbouring workgroups
+  // read h0 for their phi halo).
   static T0* h0(lbm_ehd* h, int i) {
     return reinterpret_cast<T0*>(static_cast<char*>(h->aux) +
                                  2 * (size_t)h->P.ny * h->pitch * sizeof(R)) +
-           (size_t)i * h->P.ny * h->pitch;
+           (size_t)i * rest_planes<S>() * h->P.ny * h->pitch;
   }
 
   typedef SimDesc<S, R, T0> Desc;
@@ -386,8 +388,8 @@ struct Form {
     if (!h->fld) HIP_TRY(hipMalloc(&h->fld, 10 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
     const KP<W> kp = make_kp<W>(h);
     const S* src = buf(h, h->cur);
-    hipLaunchKernelGGL((k_fields<S, W>), grid2(h), dim3(64), 0, h->stream, src,
-                       static_cast<const W*>(h->mom), h->fld, kp);
+    hipLaunchKernelGGL((k_fields<S, W, T0>), grid2(h), dim3(64), 0, h->stream, src,
+                       h0(h, h->cur), static_cast<const W*>(h->mom), h->fld, kp);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -685,7 +687,7 @@ lbm_status lbm_ehd_required_bytes(const lbm_ehd_params* p, size_t* pop_bytes,
   if (pop_bytes) *pop_bytes = (size_t)NPOP * (p->ny + 2) * pitch * elem_size(p->precision);
   if (aux_bytes)
     *aux_bytes =
-        (size_t)p->ny * pitch * (2 * arith_size(p->precision) + 2 * rest_size(p->precision));
+        (size_t)p->ny * pitch * (2 * arith_size(p->precision) + 2 * rest_bytes(p->precision));
   return LBM_OK;
 }
 
@@ -1203,11 +1205,11 @@ lbm_status lbm_ehd_batch_destroy(lbm_ehd_batch* b) {
 double lbm_ehd_bytes_per_lup(int32_t precision) {
   const size_t s = elem_size(precision);
   if (!s) return 0.0;
-  // 32 moving or pulled planes (and the reference phase of h with 16-bit
-  // storage), the rest population of h and (phi u)(t-1), each read once and
-  // written once
-  return 2.0 * (NPOP - 1 + (local_h(precision) ? 1 : 0)) * s + 2.0 * rest_size(precision) +
-         2.0 * 2.0 * arith_size(precision);
+  // the moving populations (32; with 16-bit storage 30, plus the reference
+  // phase of h), the FP64 rest populations and (phi u)(t-1), each read once
+  // and written once
+  const double lines = local_h(precision) ? NPOP - 3 + 1 : NPOP - 1;
+  return 2.0 * lines * s + 2.0 * rest_bytes(precision) + 2.0 * 2.0 * arith_size(precision);
 }
 
 }  // extern "C"

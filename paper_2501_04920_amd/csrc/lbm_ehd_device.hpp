@@ -246,6 +246,22 @@ template <>
 struct LocalH<__hip_bfloat16> {
   static constexpr bool value = true;
 };
+// 16-bit storage also keeps the rest populations of the two ions in FP64
+// planes beside that of h, and like it they take what the node's four stored
+// moving populations leave: each collision then changes a node's ion content
+// by exactly the reaction term.  Rounded to 16 bits, the content of slowly
+// varying nodes would move by a fraction of an ulp per step, always in the
+// same direction, and the charge, which relaxes only over the dielectric
+// time, would integrate that drift.
+template <class S>
+struct IonRest {
+  static constexpr bool value = LocalH<S>::value;
+};
+// FP64 rest planes per time level: h0, then p0 and n0 where kept there
+template <class S>
+constexpr int rest_planes() {
+  return IonRest<S>::value ? 3 : 1;
+}
 // lattice weights of Eq. (25), for the references above
 __device__ constexpr float W9F[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
                                      1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};

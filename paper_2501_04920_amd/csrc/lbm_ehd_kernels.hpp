@@ -87,6 +87,17 @@ __device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x
   }
 }
 
+// Rest population (deviation) of the ion set starting at line q0 (QP or QN)
+// of node (x, y): from its FP64 plane (16-bit storage) or from line q0.
+template <class S, class R, class T0>
+__device__ inline double ion_rest(const PopView<S, R>& P, const T0* __restrict__ h0x, int q0,
+                                  int x, int y) {
+  if (IonRest<S>::value)
+    return (double)*elem(h0x, (uint32_t)(q0 == QP ? 1 : 2) * P.kp->cells +
+                                  (uint32_t)y * P.kp->pitch + x);
+  return (double)P.at(q0, P.row(y + 1) + x);
+}
+
 template <class R>
 __device__ inline R sum9(const R h[9]) {
   return h[0] + h[1] + h[2] + h[3] + h[4] + h[5] + h[6] + h[7] + h[8];
@@ -208,6 +219,20 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     pw[i] = (W)p[i];
     nw[i] = (W)n[i];
   }
+  const uint32_t jo = (uint32_t)y * kp.pitch + x;
+  // exact incoming ion content of the node (FP64 ion rest populations)
+  double Pin = 0.0, Qin = 0.0;
+  if (IonRest<S>::value) {
+    Pin = (double)*elem(h0src, kp.cells + jo);
+    Qin = (double)*elem(h0src, 2 * kp.cells + jo);
+    pw[0] = (W)Pin;
+    nw[0] = (W)Qin;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      Pin += (double)p[i];
+      Qin += (double)n[i];
+    }
+  }
   const W Pd = pw[0] + pw[1] + pw[2] + pw[3] + pw[4];
   const W Qd = nw[0] + nw[1] + nw[2] + nw[3] + nw[4];
   Macro<W> m;
@@ -248,19 +273,36 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   for (int i = 0; i < 5; ++i) {
     p[i] = (R)pw[i];
     n[i] = (R)nw[i];
-    D.put(QP + i, o, p[i]);
+  }
+  if (IonRest<S>::value) {
+    // the collision adds the reaction term to each ion's content (Eq. 41);
+    // the rest populations take what the stored moving ones leave of it
+    double Pout = Pin + (double)m.Rr, Qout = Qin + (double)m.Rr;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      D.put(QP + i, o, p[i]);
+      Pout -= (double)D.stored(QP + i, p[i]);
+    }
+    *elem(h0dst, kp.cells + jo) = (T0)Pout;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      D.put(QN + i, o, n[i]);
+      Qout -= (double)D.stored(QN + i, n[i]);
+    }
+    *elem(h0dst, 2 * kp.cells + jo) = (T0)Qout;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) D.put(QP + i, o, p[i]);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) D.put(QN + i, o, n[i]);
   }
   const R cpd = (R)m.cpd, cmd = (R)m.cmd;
   // anode: c+ = 0; cathode: d c+/dn = 0 (wall value = node value)
   if (edge) G.set5(QP, p, ins ? p[4] : -p[4] - third * kp.c0, ins ? p[2] : -p[2] + third * cpd);
-
-#pragma unroll
-  for (int i = 0; i < 5; ++i) D.put(QN + i, o, n[i]);
   // anode: d c-/dn = 0; cathode: c- = 0
   if (edge) G.set5(QN, n, ins ? n[4] : -n[4] + third * cmd, ins ? n[2] : -n[2] - third * kp.c0);
 
   {  // h: Eq. (27)-(32), with d(phi u)/dt of Eq. (58)
-    const uint32_t jo = (uint32_t)y * kp.pitch + x;
     const uint32_t jpl = kp.cells;
     const R Jx = (R)(m.phi * m.u[0]), Jy = (R)(m.phi * m.u[1]);
     const R dJ[2] = {Jx - *elem(jprev, jo), Jy - *elem(jprev, jpl + jo)};
@@ -396,8 +438,9 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
     R f[9], p[5], n[5], t4[4];
     pull9(Ph, QF, k, y, f);
     const uint32_t r0 = Ph.row(y + 1);
-    p[0] = Ph.at(QP, r0 + x);
-    n[0] = Ph.at(QN, r0 + x);
+    // (the ion rest populations of 16-bit storage are read by the update)
+    p[0] = IonRest<S>::value ? R(0) : Ph.at(QP, r0 + x);
+    n[0] = IonRest<S>::value ? R(0) : Ph.at(QN, r0 + x);
     const R g0 = Pg.at(0, r0 + x);
     pull4(Ph, QP, k, y, t4);
     p[1] = t4[0]; p[2] = t4[1]; p[3] = t4[2]; p[4] = t4[3];
@@ -509,9 +552,9 @@ __global__ void k_moments(const S* __restrict__ src, const S* __restrict__ srcg,
   pull4(Pg, 0, k, y, g4);
   const uint32_t r0 = Ph.row(y + 1);
   pull4(Ph, QP, k, y, t4);
-  const R Pd = Ph.at(QP, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
   pull4(Ph, QN, k, y, t4);
-  const R Qd = Ph.at(QN, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Qd = (R)ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
   const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
   mom[c] = sum9(h);
   mom[np + c] = psi_of(g4);
@@ -547,9 +590,9 @@ __device__ inline void hood(const R* __restrict__ mom, const KP<R>& kp, int x, i
 }
 
 // Macroscopic fields (FP64 output, [10][ny][nx]), absolute values.
-template <class S, class R>
-__global__ void k_fields(const S* __restrict__ src, const R* __restrict__ mom,
-                         double* __restrict__ out, const KP<R> kp) {
+template <class S, class R, class T0>
+__global__ void k_fields(const S* __restrict__ src, const T0* __restrict__ h0x,
+                         const R* __restrict__ mom, double* __restrict__ out, const KP<R> kp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
   const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
@@ -559,9 +602,9 @@ __global__ void k_fields(const S* __restrict__ src, const R* __restrict__ mom,
   pull9(Ph, QF, k, y, f);
   const uint32_t r0 = Ph.row(y + 1);
   pull4(Ph, QP, k, y, t4);
-  const R Pd = Ph.at(QP, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
   pull4(Ph, QN, k, y, t4);
-  const R Qd = Ph.at(QN, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Qd = (R)ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
   Macro<R> m;
   macro(phi9, psi9, Pd, Qd, f, kp, m);
   const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
@@ -697,13 +740,18 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
     }
   }
   *elem(h0x, (uint32_t)y * kp.pitch + x) = (T0)hrest;
+  const uint32_t jo = (uint32_t)y * kp.pitch + x;
   for (int i = 0; i < 5; ++i) {
     const double cu = cx[i] * ux + cy[i] * uy;
-    put(QP + i, i, w5[i] * cp * (1.0 + 3.0 * cu));
-    put(QN + i, i, w5[i] * cm * (1.0 + 3.0 * cu));
+    if (i == 0 && IonRest<S>::value) {
+      *elem(h0x, kp.cells + jo) = (T0)(w5[0] * (cp - sp.c0));
+      *elem(h0x, 2 * kp.cells + jo) = (T0)(w5[0] * (cm - sp.c0));
+    } else {
+      put(QP + i, i, w5[i] * cp * (1.0 + 3.0 * cu));
+      put(QN + i, i, w5[i] * cm * (1.0 + 3.0 * cu));
+    }
     put(QG + i, i, i == 0 ? -2.0 / 3.0 * psi : psi / 6.0);
   }
-  const uint32_t jo = (uint32_t)y * kp.pitch + x;
   *elem(jprev, jo) = (R)(phi * ux);
   *elem(jprev, kp.cells + jo) = (R)(phi * uy);
 }
@@ -730,9 +778,9 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
     const uint32_t r0 = Ph.row(y + 1);
     const double h0 = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
     pull4(Ph, QP, k, y, t4);
-    const double Pd = (double)Ph.at(QP, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
+    const double Pd = ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
     pull4(Ph, QN, k, y, t4);
-    const double Qd = (double)Ph.at(QN, r0 + x) + t4[0] + t4[1] + t4[2] + t4[3];
+    const double Qd = ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
     pull4(Pg, 0, k, y, g4);
     double phid = h0;
     for (int i = 1; i < 9; ++i) phid += (double)h[i];

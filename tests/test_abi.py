@@ -40,9 +40,13 @@ def test_defaults_and_bytes():
     pop, aux = lbm_ehd.lbm_ehd_required_bytes(p)
     # (phi u)(t-1) in FP32 and two time levels of the rest population of h in FP64
     assert pop == 33 * 130 * 128 * 4 and aux == 128 * 128 * (2 * 4 + 2 * 8)
+    # 16-bit storage: two time levels of the rest populations of h, p and n
+    pop, aux = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(precision="fp16"))
+    assert pop == 33 * 130 * 128 * 2 and aux == 128 * 128 * (2 * 4 + 2 * 3 * 8)
     # 32 moving planes + rest of h + (phi u), each read and written once
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp32") == 2 * 32 * 4 + 2 * 8 + 2 * 8
-    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 2 * 33 * 2 + 2 * 8 + 2 * 8
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 2 * 31 * 2 + 2 * 3 * 8 + 2 * 8
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("bf16") == 2 * 31 * 2 + 2 * 3 * 8 + 2 * 8
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp64") == 2 * 32 * 8 + 2 * 8 + 2 * 16
 
 

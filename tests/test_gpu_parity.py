@@ -55,6 +55,25 @@ def test_config1_droplet_fp32_storage(precision):
     assert abs(sim.diagnostics()["D"] - D) <= 1e-5
 
 
+# 16-bit storage on the same case (measured: FP16 D 4.4e-6, fields <= 8.4e-4
+# but E_x 1.2e-2, a small component; BF16 D 4.4e-5, fields <= 3.8e-2).
+BARS_16 = {"fp16": dict(D=1e-4, fields=3e-3), "bf16": dict(D=1e-3, fields=0.1)}
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_config1_droplet_16bit_storage(precision):
+    cfg = workloads.config1()
+    p, d = cfg["params"], cfg["droplet"]
+    sim = run_gpu(p, precision, droplet=d, presolve=cfg["presolve"], steps=cfg["steps"])
+    o = run_oracle(p, droplet=d, presolve=cfg["presolve"], steps=cfg["steps"])
+    errs = rel_l2(sim.fields(), o.fields(), p, FIELDS8)
+    _report("config1 %s" % precision, errs)
+    for k, e in errs.items():
+        assert e <= BARS_16[precision]["fields"], k
+    D = oracle.deformation(o.fields()["phi"])[0]
+    assert abs(sim.diagnostics()["D"] - D) <= BARS_16[precision]["D"]
+
+
 def _ragged(**over):
     p = workloads.lattice_params(70, 12.0, nx=100)
     p.update(over)
