@@ -187,6 +187,7 @@ def bench_batched(args):
     b.close()
     for s in sims:
         s.close()
+    print("batch of %d done in %.1f s" % (len(members), wall), file=sys.stderr, flush=True)
     # baseline: each member alone in FP32, timed over a few steps, scaled
     seq = 0.0
     for m in members:
@@ -243,6 +244,9 @@ def _serve_trace(trace, budget, block):
                                    r["params"]["nx"] * r["params"]["ny"] * r["steps"],
                                    inf["state"], inf["diag"]["D"])
                 srv.release(rid)
+                if len(done) % 32 == 0:
+                    print("served %d/%d requests" % (len(done), len(trace)), file=sys.stderr,
+                          flush=True)
         if running == 0 and queued == 0 and k < len(pending):
             time.sleep(max(0.0, pending[k]["arrival"] - (time.perf_counter() - t0)))
     makespan = time.perf_counter() - t0
@@ -266,6 +270,13 @@ def bench_serving(args):
     work = sum(v[1] for v in done.values())
     glups = work / span / 1e9
     failed = sum(1 for v in done.values() if v[2] != lbm_ehd.REQ_DONE)
+    # error of the served FP16 results against the same request run alone in
+    # plain FP32, on every 32nd request
+    errs = []
+    for r in trace[::32]:
+        D32, _ = _alone_D(r, "fp32", r["steps"])
+        errs.append(abs(done[r["name"]][3] - D32))
+    print("checked %d served results against FP32 alone" % len(errs), file=sys.stderr, flush=True)
     # a sub-saturation trace: the same requests, arrival rate for ~70 % load
     mean_work = work / len(trace)
     rate_sub = 0.7 * glups * 1e9 / mean_work
@@ -287,6 +298,7 @@ def bench_serving(args):
         "p50_s": round(float(np.percentile(lat, 50)), 3),
         "throughput_req_per_s": round(len(trace) / span, 3), "aggregate_glups": round(glups, 3),
         "makespan_s": round(span, 2), "max_running": maxrun, "failed": failed,
+        "D_err_vs_fp32_alone_max": max(errs), "D_err_requests": len(errs),
         "sub_saturation": sub,
     }
     print(json.dumps(line), flush=True)

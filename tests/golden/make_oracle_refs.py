@@ -1,14 +1,15 @@
-"""Write the stored oracle references for the long FP32 comparisons.
+"""Write the stored oracle references for the long comparisons.
 
 Runs only the CPU oracle (``oracle/``) on the 512 x 512 droplet cases (radius
 80, W = 4; eps_r in {0.5, 2} x mu_r in {0.5, 2} x Ca_E in {0.25, 1}) for
-20 000 steps, and the 512 x 512, W = 5 restriction of the 2048 x 2048 case,
-and stores per case:
+20 000 steps, on the 512 x 512, W = 5 restriction of the 2048 x 2048 case,
+and on the three smallest members of the 64-droplet batched sweep (10 000
+steps), and stores per case:
   - the deformation factor D (Eq. 63) every 500 steps,
   - the L2 norms of rho_e and |u| every 500 steps,
   - phi, psi, c+, c-, rho_e, u_x, u_y, p on every 8th row and column at the end.
 Usage: python tests/golden/make_oracle_refs.py [case-name ...]
-Each case takes ~15 min on 8 cores.
+Each 512 x 512 case takes ~15 min on 8 cores, a batch member ~1 min.
 """
 from __future__ import annotations
 
@@ -34,7 +35,14 @@ def cases():
     out = {c["name"]: c for c in workloads.config2_points()}
     r = workloads.scaled_restriction()
     out[r["name"]] = r
+    for m in smallest_batch_members():
+        out[m["name"]] = m
     return out
+
+
+def smallest_batch_members(k=3):
+    ms = sorted(workloads.config4_members(), key=lambda m: m["params"]["nx"])[:k]
+    return [dict(m, presolve=0) for m in ms]
 
 
 def run(case):

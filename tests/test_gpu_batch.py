@@ -121,3 +121,47 @@ def test_batch_rejects_bad_members():
     with pytest.raises(lbm_ehd.LbmError):
         b.remove(c)
     b.close()
+
+
+# The three smallest members of the 64-droplet batched sweep (grids 129^2-136^2,
+# 10 000 steps), run as one FP16-storage batch in an autotuned launch shape,
+# against stored oracle references (tests/golden/make_oracle_refs.py): D every
+# 500 steps within 1e-3 (measured: see the printed line).
+SMALLEST = sorted(workloads.config4_members(), key=lambda m: m["params"]["nx"])[:3]
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_smallest_batch_members_fp16_against_oracle():
+    refs = []
+    for m in SMALLEST:
+        path = os.path.join(GOLDEN, m["name"] + ".npz")
+        if not os.path.exists(path):
+            pytest.skip("no stored oracle reference " + path)
+        refs.append(np.load(path))
+    sims = []
+    for m in SMALLEST:
+        d = m["droplet"]
+        s = lbm_ehd.Simulation(dict(m["params"], precision="fp16"), device="cuda:0")
+        s.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"])
+        sims.append(s)
+    b = lbm_ehd.Batch(sims)
+    t = refs[0]["t"]
+    D = [[s.diagnostics()["D"]] for s in sims]
+    taken = b.autotune(10)[2]
+    done = taken
+    for k in t[1:]:
+        b.run(int(k) - done)
+        done = int(k)
+        for j, s in enumerate(sims):
+            D[j].append(s.diagnostics()["D"])
+    assert taken <= t[1]
+    for j, m in enumerate(SMALLEST):
+        err = np.max(np.abs(np.array(D[j]) - refs[j]["D"]))
+        rn = np.linalg.norm(sims[j].fields(("rhoe",))["rhoe"])
+        print("%s fp16 batched: max |D - D_oracle| = %.2e (D_end %.4e), ||rho_e|| rel err %.2e"
+              % (m["name"], err, D[j][-1], abs(rn - refs[j]["rhoe_l2"][-1]) /
+                 refs[j]["rhoe_l2"][-1]), flush=True)
+        assert err <= 1e-3
+    b.close()
+    for s in sims:
+        s.close()

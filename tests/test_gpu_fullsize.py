@@ -1,0 +1,75 @@
+"""Parity at the full 2048 x 2048 size (droplet radius 320, W = 5), in the
+launch shape the throughput benchmark times (the library's default for this
+grid).
+
+* FP64 and FP32 storage against the CPU oracle after 20 steps, every field of
+  every node (the oracle does this size in seconds with its threads).
+* 16-bit storage against the FP64 storage form of this library after 5000
+  steps (a consistency check between forms, not an oracle comparison: the
+  oracle would need hours for 5000 steps at this size): the deformation
+  factor D, and the conservation sums.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_common import rel_l2, run_gpu, run_oracle  # noqa: E402
+
+from paper_2501_04920_amd import workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+ALL10 = ("phi", "psi", "cp", "cm", "rhoe", "ux", "uy", "p", "Ex", "Ey")
+BENCH_LAUNCH = (4, 8)  # waves per workgroup, rows per band at 2048^2
+
+
+def _case():
+    cfg = workloads.config3()
+    return cfg["params"], cfg["droplet"]
+
+
+@pytest.fixture(scope="module")
+def oracle_20():
+    p, d = _case()
+    o = run_oracle(p, droplet=d, steps=20)
+    f = o.fields()
+    del o
+    return f
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_2048_against_oracle_20_steps(oracle_20, precision, bar):
+    p, d = _case()
+    sim = run_gpu(p, precision, droplet=d)
+    assert sim.launch == BENCH_LAUNCH
+    sim.step(20)
+    errs = rel_l2(sim.fields(), oracle_20, p, ALL10)
+    sim.close()
+    print("2048 %s: %s" % (precision, " ".join("%s=%.2e" % kv for kv in errs.items())),
+          flush=True)
+    for k, e in errs.items():
+        assert e <= bar, k
+
+
+def test_2048_16bit_forms_against_fp64_form_5k_steps():
+    p, d = _case()
+    out = {}
+    for prec in ("fp64", "fp16", "bf16"):
+        sim = run_gpu(p, prec, droplet=d)
+        assert sim.launch == BENCH_LAUNCH
+        sim.step(5000)
+        out[prec] = sim.diagnostics()
+        sim.close()
+    ref = out["fp64"]
+    for prec in ("fp16", "bf16"):
+        dD = abs(out[prec]["D"] - ref["D"])
+        dphi = abs(out[prec]["sum_phi"] - ref["sum_phi"]) / ref["sum_phi"]
+        print("2048 %s vs fp64 after 5000 steps: D %.3e vs %.3e (err %.2e), sum_phi rel %.1e"
+              % (prec, out[prec]["D"], ref["D"], dD, dphi), flush=True)
+        assert out[prec]["nonfinite"] == 0
+        assert dphi <= 1e-12
+        if prec == "fp16":
+            assert dD <= 1e-3
