@@ -381,10 +381,10 @@ LBM_API const char *lbm_ehd_last_error(void);
 /* Algorithmic HBM bytes one lattice update moves in the fused sweep, each
  * item read and written once: the 32 moving populations in the storage type
  * (with 16-bit storage: 30, the rest populations of the two ions being kept
- * in FP64, plus the line of the reference phase of h), the FP64 rest
- * populations (h0; with 16-bit storage also p0 and n0) and (phi u)(t-1) in
- * the arithmetic type.  FP64 560, FP32 288, FP32 storage with FP64
- * arithmetic 304, FP16 and BF16 188. */
+ * in FP64, plus the lines of the reference phase of h and the reference
+ * potential of g), the FP64 rest populations (h0; with 16-bit storage also
+ * p0 and n0) and (phi u)(t-1) in the arithmetic type.  FP64 560, FP32 288,
+ * FP32 storage with FP64 arithmetic 304, FP16 and BF16 192. */
 LBM_API double lbm_ehd_bytes_per_lup(int32_t precision);
 
 /* Measurement helper, not part of the method: copy `bytes` (a multiple of

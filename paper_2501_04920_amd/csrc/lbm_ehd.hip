@@ -156,7 +156,6 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.rstride = (uint32_t)(NPOP * h->pitch);
   k.cells = (uint32_t)((long long)p.ny * h->pitch);
   k.pop_bytes = (uint32_t)h->pop_bytes;
-  k.g_bytes = (uint32_t)(h->pop_bytes - (size_t)QG * h->pitch * elem_size(p.precision));
   k.reaction = p.reaction;
   k.poisson_form = p.poisson_form;
   k.flow = p.flow;
@@ -303,29 +302,28 @@ struct Form {
   // type T0 for readback).  Scratch is allocated on first use (room for
   // FP64 planes): a simulation that only steps holds its state and nothing
   // else.
+  // `gsrc` is the buffer holding the current g set (NULL: the state buffer).
   template <class RF>
-  static lbm_status moments_as(lbm_ehd* h, const S* srcg) {
+  static lbm_status moments_as(lbm_ehd* h, const S* gsrc) {
     if (!h->mom) HIP_TRY(hipMalloc(&h->mom, 3 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
     const KP<RF> kp = make_kp<RF>(h);
     const S* src = buf(h, h->cur);
-    if (!srcg) srcg = gset(h, h->cur);
-    hipLaunchKernelGGL((k_moments<S, RF, T0>), grid2(h), dim3(64), 0, h->stream, src, srcg,
+    if (!gsrc) gsrc = src;
+    hipLaunchKernelGGL((k_moments<S, RF, T0>), grid2(h), dim3(64), 0, h->stream, src, gsrc,
                        h0(h, h->cur), static_cast<RF*>(h->mom), kp);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
-  static lbm_status moments(lbm_ehd* h, const S* srcg) { return moments_as<R>(h, srcg); }
+  static lbm_status moments(lbm_ehd* h, const S* gsrc) { return moments_as<R>(h, gsrc); }
 
-  // The g set of buffer i: population QG of row 0 (rows keep their stride).
-  static S* gset(lbm_ehd* h, int i) { return buf(h, i) + (size_t)QG * h->pitch; }
-
-  // `iters` g-only sweeps.  The g set ping-pongs between the state buffer and
-  // the g lines of the other buffer, which the next sweep overwrites anyway;
-  // returns (in *gsrc) where the latest g lives.
+  // `iters` g-only sweeps.  The g set (its five lines and, with 16-bit
+  // storage, the line of its reference potential) ping-pongs between the
+  // state buffer and the same lines of the other buffer, which the next
+  // sweep overwrites anyway; returns (in *gsrc) the buffer holding the latest g.
   static lbm_status poisson(lbm_ehd* h, int iters, const S** gsrc) {
     const KP<R> kp = make_kp<R>(h);
-    S* gA = gset(h, h->cur);
-    S* gB = gset(h, 1 - h->cur);
+    S* gA = buf(h, h->cur);
+    S* gB = buf(h, 1 - h->cur);
     S* from = gA;
     for (int it = 0; it < iters; ++it) {
       lbm_status st = moments(h, from);
@@ -341,13 +339,18 @@ struct Form {
   }
 
   // Bring the latest g back into the state buffer: the five g lines of
-  // every row.
+  // every row, and the reference line with 16-bit storage.
   static lbm_status settle_g(lbm_ehd* h, const S* gsrc) {
-    S* gA = gset(h, h->cur);
-    if (gsrc != gA) {
+    S* A = buf(h, h->cur);
+    if (gsrc != A) {
       const size_t row = (size_t)NPOP * h->pitch * sizeof(S);
-      HIP_TRY(hipMemcpy2DAsync(gA, row, gsrc, row, 5 * (size_t)h->pitch * sizeof(S),
-                               (size_t)h->P.ny + 2, hipMemcpyDeviceToDevice, h->stream));
+      const size_t line = (size_t)h->pitch;
+      HIP_TRY(hipMemcpy2DAsync(A + QG * line, row, gsrc + QG * line, row,
+                               5 * line * sizeof(S), (size_t)h->P.ny + 2,
+                               hipMemcpyDeviceToDevice, h->stream));
+      if (LocalG<S>::value)
+        HIP_TRY(hipMemcpy2DAsync(A + QRG * line, row, gsrc + QRG * line, row, line * sizeof(S),
+                                 (size_t)h->P.ny + 2, hipMemcpyDeviceToDevice, h->stream));
     }
     return LBM_OK;
   }
@@ -398,7 +401,7 @@ struct Form {
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
     hipLaunchKernelGGL((k_row_sums<S, R, T0>), dim3(h->P.ny), dim3(256), 0, h->stream, src,
-                       gset(h, h->cur), h0(h, h->cur), h->part, kp);
+                       h0(h, h->cur), h->part, kp);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, h->part, h->P.ny, h->red);
     HIP_TRY(hipGetLastError());
@@ -559,16 +562,16 @@ void free_scratch(lbm_ehd* h) {
 
 // Default launch shape of the sweep for a grid: strips of 256 columns (four
 // waves in step) where the grid is that wide, and the tallest band (the h/g
-// rows above and below a band are read twice) that still puts about 8192
-// wavefronts in flight.  Measured on MI355X at 2048^2 (GLUPS, bands of 4 /
-// 8 / 16 rows): FP32 17.2 / 17.0 / 16.7, FP16 27.1 / 27.9 / 27.9, FP64 9.5 /
-// 9.4 / 9.4 with four waves; one wave 15.8-16.0 in FP32, two 16.3-16.8,
-// eight 16.6-17.6; bands of 64 rows leave too few workgroups (12.9-13.8).
+// rows above and below a band are read twice) that still gives every SIMD
+// four wavefronts (4096 on the 256 CUs).  Measured on MI355X at 2048^2
+// (GLUPS, bands of 4 / 8 / 16 rows): four waves FP32 16.1 / 16.2 / 16.4,
+// FP16 21.5 / 22.1 / 22.4; two waves FP32 15.4 / 14.9 / 15.9; eight waves
+// FP32 15.7 / 16.2 / 16.4, FP16 21.2 / 22.2 / 22.4.
 void default_launch(const lbm_ehd_params* p, int* waves, int* tile_rows) {
   *waves = p->nx >= 256 ? 4 : (p->nx >= 128 ? 2 : 1);
   const long long strips = (p->nx + 64 * *waves - 1) / (64 * *waves);
   int rows = 32;
-  while (rows > 2 && strips * *waves * ((p->ny + rows - 1) / rows) < 8192) rows /= 2;
+  while (rows > 2 && strips * *waves * ((p->ny + rows - 1) / rows) < 4096) rows /= 2;
   *tile_rows = std::min(rows, p->ny);
 }
 
@@ -1205,10 +1208,10 @@ lbm_status lbm_ehd_batch_destroy(lbm_ehd_batch* b) {
 double lbm_ehd_bytes_per_lup(int32_t precision) {
   const size_t s = elem_size(precision);
   if (!s) return 0.0;
-  // the moving populations (32; with 16-bit storage 30, plus the reference
-  // phase of h), the FP64 rest populations and (phi u)(t-1), each read once
-  // and written once
-  const double lines = local_h(precision) ? NPOP - 3 + 1 : NPOP - 1;
+  // the moving populations (32; with 16-bit storage 30, plus the lines of
+  // the reference phase of h and the reference potential of g), the FP64
+  // rest populations and (phi u)(t-1), each read once and written once
+  const double lines = local_h(precision) ? NPOP - 3 + 2 : NPOP - 1;
   return 2.0 * lines * s + 2.0 * rest_bytes(precision) + 2.0 * 2.0 * arith_size(precision);
 }
 

@@ -37,6 +37,9 @@
 //      without source, and the anti-bounce-back at both electrodes, so the
 //      pulled deviations are the stored ones (no reference shift) and the g
 //      update is the same MRT collision applied to deviations alone.
+//   With 16-bit storage the moving h and g populations are further stored
+//   relative to node-local references (LocalH, LocalG) and the rest
+//   populations of p and n are kept in FP64 planes (IonRest).
 // All arithmetic works on deviations: phi' = phi - 1/2, P' = sum p - c0,
 // Q' = sum n - c0, psi' = psi - psi_lin.  The charge density q (P' - Q') and
 // the reaction (solved for R directly) never subtract two numbers near c0,
@@ -73,7 +76,7 @@ struct KP {
   int nx, ny, pitch, walls;
   uint32_t rstride;             // elements per lattice row of a buffer, 33 * pitch
   uint32_t cells;               // elements per aux plane, ny * pitch
-  uint32_t pop_bytes, g_bytes;  // sizes of a population buffer and of a g set
+  uint32_t pop_bytes;           // size of a population buffer
   int reaction, poisson_form, flow, ion_force;
   int mask_f, mask_h, mask_p, mask_n, mask_g;
   R rho_v, drho, eta_v, deta, eps_v, deps, mu_v, dmu, m_ratio;
@@ -262,6 +265,24 @@ template <class S>
 constexpr int rest_planes() {
   return IonRest<S>::value ? 3 : 1;
 }
+// 16-bit storage keeps the moving g populations relative to w_i times the
+// potential psi'~ of the node they arrive at, and g0 relative to its share
+// (w_0 - 1) psi'~ of its own node, like h (psi' = psi - psi_lin, rounded to
+// the storage type and stored by each node in line QRG, the line of p0,
+// which that storage keeps in FP64).  The stored deviations are then the
+// non-equilibrium parts only, about a hundred times smaller than psi'/6:
+// rounded to 16 bits, psi'/6 itself is a noise source that the Poisson
+// iteration amplifies by the condition number of the Laplacian.
+template <class S>
+struct LocalG {
+  static constexpr bool value = IonRest<S>::value;
+};
+constexpr int QRG = QP;
+// Scale set of line a: the reference line of g is scaled like g.
+template <class S>
+__device__ inline int line_set(int a) {
+  return LocalG<S>::value && a == QRG ? 4 : set_of(a);
+}
 // lattice weights of Eq. (25), for the references above
 __device__ constexpr float W9F[9] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
                                      1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
@@ -276,38 +297,35 @@ __device__ inline double h_from(double dev, int i, double phit) {
   return __builtin_fma((double)W9F[i], phit, dev);
 }
 
-// A population buffer (or its g set) seen through a buffer descriptor:
-// population q (counted from the view's base; `qoff` is the population index
-// of that base, for the set scale) at element offset `off` = row(r) + x.
+// A population buffer seen through a buffer descriptor: line q of the row
+// at element offset `off` = row(r) + x.
 template <class S, class R>
 struct PopView {
   Rsrc rs;
   const KP<R>* kp;
-  int qoff;
   __device__ inline uint32_t row(int r) const { return (uint32_t)r * kp->rstride; }
   // offset of the ion lines with 16-bit storage (see the deviation form)
   __device__ inline R ofs(int q) const {
-    const int a = q + qoff;
-    if (!LocalH<S>::value || a < QP || a >= QG) return R(0);
-    return kp->iofs[a - QP];
+    if (!LocalH<S>::value || q < QP || q >= QG || q == QRG) return R(0);
+    return kp->iofs[q - QP];
   }
   __device__ inline R at(int q, uint32_t off) const {
     R v = Codec<S, R>::ld(rs, off * (uint32_t)sizeof(S),
                           (uint32_t)q * kp->pitch * (uint32_t)sizeof(S));
-    if (Scaled<S>::value) v *= kp->isc[set_of(q + qoff)];
+    if (Scaled<S>::value) v *= kp->isc[line_set<S>(q)];
     return v + ofs(q);
   }
   __device__ inline void put(int q, uint32_t off, R v) const {
     v -= ofs(q);
-    if (Scaled<S>::value) v *= kp->sc[set_of(q + qoff)];
+    if (Scaled<S>::value) v *= kp->sc[line_set<S>(q)];
     Codec<S, R>::st(rs, off * (uint32_t)sizeof(S), (uint32_t)q * kp->pitch * (uint32_t)sizeof(S),
                     v);
   }
-  // the value v takes once stored in plane q (and loaded back)
+  // the value v takes once stored in line q (and loaded back)
   __device__ inline R stored(int q, R v) const {
     const R o = ofs(q);
     if (Scaled<S>::value) {
-      const int k = set_of(q + qoff);
+      const int k = line_set<S>(q);
       return stored_as<S, R>((v - o) * kp->sc[k]) * kp->isc[k] + o;
     }
     return stored_as<S, R>(v - o) + o;
@@ -388,10 +406,18 @@ __device__ inline void inv5(const R m[5], R x[5]) {
   x[0] = m[0] - m[3] - m[4];
 }
 
-// Reciprocals: correctly rounded division in FP64; in FP32 the hardware
-// reciprocal (v_rcp_f32, within 1 ulp), which is far inside the FP32 error
-// budget and saves the ten-instruction IEEE division sequence.
-__device__ inline double recip(double x) { return 1.0 / x; }
+// Reciprocals of the per-node rates and properties (positive, O(1e-3..1e3)).
+// FP64: the hardware estimate (v_rcp_f64) refined by two Newton steps, each
+// of which squares the relative error, so the result is within an ulp or so
+// of 1/x; five instructions instead of the ~eleven of the IEEE division
+// sequence (scaling for denormal and huge operands, which these never are).
+// FP32: the hardware reciprocal (v_rcp_f32, within 1 ulp), far inside the
+// FP32 error budget.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+  return __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+}
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 template <class R>
@@ -626,13 +652,14 @@ __device__ inline void collide_ion(W x[5], W cd, R mu, R itau, int mask, W sign,
   inv5(mo, x);
 }
 
-// Poisson source S_psi of Eq. (44) (or its variable-eps form), in W.
+// Poisson source S_psi of Eq. (44) (or its variable-eps form), in W;
+// ieps = 1 / eps.
 template <class W, class R>
-__device__ inline W poisson_source(R rhoe, R eps, const R geps[2], const R gpsi[2],
+__device__ inline W poisson_source(R rhoe, R ieps, const R geps[2], const R gpsi[2],
                                    const KP<R>& kp) {
   W s = (W)rhoe;
   if (kp.poisson_form) s += (W)geps[0] * (W)gpsi[0] + (W)geps[1] * (W)gpsi[1];
-  return s / (W)eps;
+  return s * (W)ieps;
 }
 
 // g: Eq. (44)-(47) on deviations from the uncharged steady state (see the

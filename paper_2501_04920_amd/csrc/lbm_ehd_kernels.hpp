@@ -98,6 +98,27 @@ __device__ inline double ion_rest(const PopView<S, R>& P, const T0* __restrict__
   return (double)P.at(q0, P.row(y + 1) + x);
 }
 
+// Directions 1..4 of the g set of node (xc, yy), as deviations from the
+// uncharged steady state (with 16-bit storage: stored relative to psi'~ / 6
+// of the node itself, see LocalG).
+template <class S, class R>
+__device__ inline void pull_g(const PopView<S, R>& P, Cols k, int yy, R x[4]) {
+  pull4(P, QG, k, yy, x);
+  if (LocalG<S>::value) {
+    const R t = P.at(QRG, P.row(yy + 1) + k.c) * R(1.0 / 6.0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] += t;
+  }
+}
+// g0 of node (x, yy), as a deviation.
+template <class S, class R>
+__device__ inline R g_rest(const PopView<S, R>& P, int x, int yy) {
+  const uint32_t o = P.row(yy + 1) + x;
+  R g0 = P.at(QG, o);
+  if (LocalG<S>::value) g0 -= R(2.0 / 3.0) * P.at(QRG, o);
+  return g0;
+}
+
 template <class R>
 __device__ inline R sum9(const R h[9]) {
   return h[0] + h[1] + h[2] + h[3] + h[4] + h[5] + h[6] + h[7] + h[8];
@@ -184,6 +205,42 @@ struct Ghosts {
   }
 };
 
+// Store the post-collision g of node (x, y) (deviations, g[0..4]) with the
+// electrode rules.  psi9 is the psi' neighbourhood: with 16-bit storage each
+// moving population is stored relative to psi'~ / 6 of the node it arrives
+// at (the node itself for the populations an electrode sends back), g0
+// relative to -2/3 psi'~ of the node, and the node stores its own psi'~.
+template <class S, class R>
+__device__ inline void store_g(const PopView<S, R>& D, const KP<R>& kp, int x, int y, Cols k,
+                               const R g[5], const R psi9[9]) {
+  const uint32_t o = D.row(y + 1) + x;
+  const Ghosts<S, R> G{D, kp, y, k};
+  const bool edge = y == 0 || y == kp.ny - 1;
+  if (!LocalG<S>::value) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) D.put(QG + i, o, g[i]);
+    // psi = dpsi at the anode, 0 at the cathode: -x*_opp in deviation form
+    if (edge) G.set5(QG, g, -g[4], -g[2]);
+    return;
+  }
+  R t[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) t[i] = D.stored(QRG, psi9[i]);
+  if (kp.walls != WALL_PERIODIC) {
+    if (y == 0) t[4] = t[0];
+    if (y == kp.ny - 1) t[2] = t[0];
+  }
+  D.put(QRG, o, t[0]);
+  const R sixth = R(1.0 / 6.0);
+  R e[5];
+  e[0] = g[0] + R(2.0 / 3.0) * t[0];
+#pragma unroll
+  for (int i = 1; i < 5; ++i) e[i] = g[i] - t[i] * sixth;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) D.put(QG + i, o, e[i]);
+  if (edge) G.set5(QG, e, -g[4] - t[0] * sixth, -g[2] - t[0] * sixth);
+}
+
 // Per-node update once the pulled populations and the phi'/psi'
 // neighbourhood are known: macroscopic quantities, then the five collisions,
 // each stored as soon as it is done.  h and g (directions 1-4) of the node
@@ -253,18 +310,15 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   }
   if (edge) G.set9(QF, f);
 
-  {  // g: Eq. (44)-(47); psi = dpsi at the anode, 0 at the cathode
+  {  // g: Eq. (44)-(47)
     R g4[4];
     hg.g4(g4);
     W gw[5] = {(W)g0, (W)g4[0], (W)g4[1], (W)g4[2], (W)g4[3]};
-    collide_g(gw, m.psid, poisson_source<W>(m.rhoe, m.eps, m.geps, m.gpsi, kpw), kpw);
+    collide_g(gw, m.psid, poisson_source<W>(m.rhoe, m.ieps, m.geps, m.gpsi, kpw), kpw);
     R g[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      g[i] = (R)gw[i];
-      D.put(QG + i, o, g[i]);
-    }
-    if (edge) G.set5(QG, g, -g[4], -g[2]);
+    for (int i = 0; i < 5; ++i) g[i] = (R)gw[i];
+    store_g(D, kp, x, y, k, g, psi9);
   }
 
   collide_ion(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
@@ -374,8 +428,7 @@ struct SweepLds {
 // of one simulation, walked down row by row by the whole workgroup.
 template <class S, class R, class T0, int NW>
 __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>& L,
-                                  const S* __restrict__ src,
-                                  const S* __restrict__ srcg, S* __restrict__ dst,
+                                  const S* __restrict__ src, S* __restrict__ dst,
                                   R* __restrict__ jprev, const T0* __restrict__ h0x,
                                   T0* __restrict__ h0dst, const KP<R>& kp,
                                   const KP<typename WorkOf<S>::type>& kpw, int x0, int y0,
@@ -389,9 +442,8 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
   const int x = x0 + (valid ? lane : 0);
   const Cols k = cols_of(x, nx);
   const bool periodic = kp.walls == WALL_PERIODIC;
-  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
-  const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
-  const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp, 0};
+  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp};
+  const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp};
 
   // halo column handled by lanes 0 (left) and 1 (right)
   const int xh = lane == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + w == nx ? 0 : x0 + w);
@@ -407,7 +459,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
       R hh[9], gg[4];
       T0 hh0;
       pull_h(Ph, h0x, kh, ys, hh, &hh0);
-      pull4(Pg, 0, kh, ys, gg);
+      pull_g(Ph, kh, ys, gg);
       L.phi[sl][kcol] = phi_of<W>((W)hh0, hh);
       L.psi[sl][kcol] = psi_of(gg);
     }
@@ -415,7 +467,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
       R h[9], g4[4];
       T0 h0;
       pull_h(Ph, h0x, k, ys, h, &h0);
-      pull4(Pg, 0, k, ys, g4);
+      pull_g(Ph, k, ys, g4);
       L.phi[sl][lane + 1] = phi_of<W>((W)h0, h);
       L.psi[sl][lane + 1] = psi_of(g4);
       const int b = (yy - y0 + 2) & 1;
@@ -441,7 +493,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
     // (the ion rest populations of 16-bit storage are read by the update)
     p[0] = IonRest<S>::value ? R(0) : Ph.at(QP, r0 + x);
     n[0] = IonRest<S>::value ? R(0) : Ph.at(QN, r0 + x);
-    const R g0 = Pg.at(0, r0 + x);
+    const R g0 = g_rest(Ph, x, y);
     pull4(Ph, QP, k, y, t4);
     p[1] = t4[0]; p[2] = t4[1]; p[3] = t4[2]; p[4] = t4[3];
     pull4(Ph, QN, k, y, t4);
@@ -530,7 +582,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
   const SimDesc<S, R, T0>& sd = sims[tl.sim];
   const int a = (sd.cur + flip) & 1;
   const S* src = sd.pop[a];
-  sweep_tile<S, R, T0, NW>(L, src, src + (size_t)QG * sd.kp.pitch, sd.pop[1 - a], sd.jprev,
+  sweep_tile<S, R, T0, NW>(L, src, sd.pop[1 - a], sd.jprev,
                            sd.h0[a], sd.h0[1 - a], sd.kp, sd.kpw, tl.x0, tl.y0, tl.yend);
 }
 
@@ -540,17 +592,16 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
 
 // phi', psi' and rho_e = e0 (P' - Q') of every node into compact planes.
 template <class S, class R, class T0>
-__global__ void k_moments(const S* __restrict__ src, const S* __restrict__ srcg,
+__global__ void k_moments(const S* __restrict__ src, const S* __restrict__ gsrc,
                           const T0* __restrict__ h0x, R* __restrict__ mom, const KP<R> kp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
-  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
-  const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
+  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp};
+  const PopView<S, R> Pg{make_rsrc(gsrc, kp.pop_bytes), &kp};
   const Cols k = cols_of(x, kp.nx);
   R h[9], g4[4], t4[4];
   pull_h(Ph, h0x, k, y, h);
-  pull4(Pg, 0, k, y, g4);
-  const uint32_t r0 = Ph.row(y + 1);
+  pull_g(Pg, k, y, g4);
   pull4(Ph, QP, k, y, t4);
   const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
   pull4(Ph, QN, k, y, t4);
@@ -595,12 +646,11 @@ __global__ void k_fields(const S* __restrict__ src, const T0* __restrict__ h0x,
                          const R* __restrict__ mom, double* __restrict__ out, const KP<R> kp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
-  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
+  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp};
   const Cols k = cols_of(x, kp.nx);
   R phi9[9], psi9[9], f[9], t4[4];
   hood(mom, kp, x, y, phi9, psi9);
   pull9(Ph, QF, k, y, f);
-  const uint32_t r0 = Ph.row(y + 1);
   pull4(Ph, QP, k, y, t4);
   const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
   pull4(Ph, QN, k, y, t4);
@@ -622,39 +672,30 @@ __global__ void k_fields(const S* __restrict__ src, const T0* __restrict__ h0x,
   out[9 * np + c] = m.E[1];
 }
 
-// One g-only sweep (phi and rho_e held fixed): reads g from srcg, writes dstg.
+// One g-only sweep (phi and rho_e held fixed): reads the g set of buffer
+// gsrc, writes that of buffer gdst (the other lines of gdst are untouched).
 template <class S, class R>
-__global__ void k_poisson(const S* __restrict__ srcg, S* __restrict__ dstg,
+__global__ void k_poisson(const S* __restrict__ gsrc, S* __restrict__ gdst,
                           const R* __restrict__ mom, const KP<R> kp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
-  const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
-  const PopView<S, R> DG{make_rsrc(dstg, kp.g_bytes), &kp, QG};
+  const PopView<S, R> Pg{make_rsrc(gsrc, kp.pop_bytes), &kp};
+  const PopView<S, R> DG{make_rsrc(gdst, kp.pop_bytes), &kp};
   const Cols k = cols_of(x, kp.nx);
   R phi9[9], psi9[9], g4[4];
   hood(mom, kp, x, y, phi9, psi9);
   const long long np = (long long)kp.nx * kp.ny;
   const long long c = (long long)y * kp.nx + x;
-  pull4(Pg, 0, k, y, g4);
-  const uint32_t r0 = Pg.row(y + 1);
-  R g[5] = {Pg.at(0, r0 + x), g4[0], g4[1], g4[2], g4[3]};
+  pull_g(Pg, k, y, g4);
+  R g[5] = {g_rest(Pg, x, y), g4[0], g4[1], g4[2], g4[3]};
   const R eps = (R(0.5) + phi9[0]) * kp.deps + kp.eps_v;
   R gphi[2], gpsi[2];
   grad_lap<R>(phi9, gphi, nullptr);
   grad_lap<R>(psi9, gpsi, nullptr);
   gpsi[1] += kp.psi_slope;
   const R geps[2] = {kp.deps * gphi[0], kp.deps * gphi[1]};
-  collide_g(g, psi9[0], poisson_source<R>(mom[2 * np + c], eps, geps, gpsi, kp), kp);
-  const uint32_t o = DG.row(y + 1) + x;
-  for (int i = 0; i < 5; ++i) DG.put(i, o, g[i]);
-  const uint32_t top = DG.row(kp.ny + 1);
-  if (kp.walls == WALL_PERIODIC) {
-    if (y == kp.ny - 1) DG.put(2, k.c, g[2]);
-    if (y == 0) DG.put(4, top + k.c, g[4]);
-  } else {
-    if (y == 0) DG.put(2, k.c, -g[4]);
-    if (y == kp.ny - 1) DG.put(4, top + k.c, -g[2]);
-  }
+  collide_g(g, psi9[0], poisson_source<R>(mom[2 * np + c], recip(eps), geps, gpsi, kp), kp);
+  store_g(DG, kp, x, y, k, g, psi9);
 }
 
 // SplitMix64 (Steele, Lea, Flood 2014): output number n (n >= 1) of the
@@ -712,7 +753,7 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
   const double w9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const double w5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
-  const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp, 0};
+  const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp};
   auto put = [&](int q, int i, double v) {
     int xs = x - cx[i];
     xs = xs < 0 ? xs + kp.nx : (xs >= kp.nx ? xs - kp.nx : xs);
@@ -741,6 +782,15 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
   }
   *elem(h0x, (uint32_t)y * kp.pitch + x) = (T0)hrest;
   const uint32_t jo = (uint32_t)y * kp.pitch + x;
+  // g: this node's reference potential psi'~ (16-bit storage; 0 otherwise)
+  double tg = 0.0;
+  if (LocalG<S>::value) {
+    const double psi_lin =
+        kp.walls == WALL_PERIODIC ? 0.0 : sp.dpsi * (kp.ny - 0.5 - y) / kp.ny;
+    const R t = D.stored(QRG, (R)(psi - psi_lin));
+    D.put(QRG, D.row(y + 1) + x, t);
+    tg = (double)t;
+  }
   for (int i = 0; i < 5; ++i) {
     const double cu = cx[i] * ux + cy[i] * uy;
     if (i == 0 && IonRest<S>::value) {
@@ -750,7 +800,7 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
       put(QP + i, i, w5[i] * cp * (1.0 + 3.0 * cu));
       put(QN + i, i, w5[i] * cm * (1.0 + 3.0 * cu));
     }
-    put(QG + i, i, i == 0 ? -2.0 / 3.0 * psi : psi / 6.0);
+    put(QG + i, i, i == 0 ? -2.0 / 3.0 * (psi - tg) : (psi - tg) / 6.0);
   }
   *elem(jprev, jo) = (R)(phi * ux);
   *elem(jprev, kp.cells + jo) = (R)(phi * uy);
@@ -762,26 +812,23 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
 constexpr int NSUM = 7;
 template <class S, class R, class T0>
 __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
-                                                  const S* __restrict__ srcg,
                                                   const T0* __restrict__ h0x,
                                                   double* __restrict__ part, const KP<R> kp) {
   __shared__ double sh[NSUM][256];
   const int y = blockIdx.x, t = threadIdx.x;
-  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, 0};
-  const PopView<S, R> Pg{make_rsrc(srcg, kp.g_bytes), &kp, QG};
+  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp};
   double acc[NSUM] = {0, 0, 0, 0, 0, 0, 0};
   const double c0 = (double)kp.c0;
   for (int x = t; x < kp.nx; x += 256) {
     const Cols k = cols_of(x, kp.nx);
     R h[9], t4[4], g4[4];
     pull_h(Ph, h0x, k, y, h);
-    const uint32_t r0 = Ph.row(y + 1);
     const double h0 = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
     pull4(Ph, QP, k, y, t4);
     const double Pd = ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
     pull4(Ph, QN, k, y, t4);
     const double Qd = ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
-    pull4(Pg, 0, k, y, g4);
+    pull_g(Ph, k, y, g4);
     double phid = h0;
     for (int i = 1; i < 9; ++i) phid += (double)h[i];
     const double phi = 0.5 + phid;

@@ -198,8 +198,10 @@ lbm_status lbm_ehd_server_advance(lbm_ehd_server* s, int32_t* running, int32_t* 
     }
     if (block > 0) {
       st = lbm_ehd_batch_run(s->batch, block);
-      if (st) st = serr(st, std::string("run: ") + lbm_ehd_last_error());
-      for (int64_t id : s->running) s->req[id].steps_done += block;
+      if (st)
+        st = serr(st, std::string("run: ") + lbm_ehd_last_error());
+      else
+        for (int64_t id : s->running) s->req[id].steps_done += block;
     }
   }
   if (running) *running = (int32_t)s->running.size();

@@ -45,8 +45,8 @@ def test_defaults_and_bytes():
     assert pop == 33 * 130 * 128 * 2 and aux == 128 * 128 * (2 * 4 + 2 * 3 * 8)
     # 32 moving planes + rest of h + (phi u), each read and written once
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp32") == 2 * 32 * 4 + 2 * 8 + 2 * 8
-    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 2 * 31 * 2 + 2 * 3 * 8 + 2 * 8
-    assert lbm_ehd.lbm_ehd_bytes_per_lup("bf16") == 2 * 31 * 2 + 2 * 3 * 8 + 2 * 8
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 2 * 32 * 2 + 2 * 3 * 8 + 2 * 8
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("bf16") == 2 * 32 * 2 + 2 * 3 * 8 + 2 * 8
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp64") == 2 * 32 * 8 + 2 * 8 + 2 * 16
 
 

@@ -23,7 +23,7 @@ from paper_2501_04920_amd import workloads  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 ALL10 = ("phi", "psi", "cp", "cm", "rhoe", "ux", "uy", "p", "Ex", "Ey")
-BENCH_LAUNCH = (4, 8)  # waves per workgroup, rows per band at 2048^2
+BENCH_LAUNCH = (4, 16)  # waves per workgroup, rows per band at 2048^2
 
 
 def _case():
