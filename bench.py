@@ -311,7 +311,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="fp32",
                     choices=["fp64", "fp32", "fp32f64", "fp16", "bf16"])
-    ap.add_argument("--n", type=int, default=2048, help="grid n x n (radius n / 6.4)")
+    ap.add_argument("--n", type=int, default=2048,
+                    help="grid n x n (radius n / 6.4, W = 5; 128: the 128^2 parity case, W = 4)")
     ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--waves", type=int, default=0,
                     help="wavefronts per sweep workgroup (1, 2, 4, 8; 0 = library default)")
@@ -359,6 +360,8 @@ def main():
     n = args.n
     if n == 2048:
         cfg = workloads.config3()
+    elif n == 128:
+        cfg = workloads.config1()       # the 128^2 parity case (W = 4)
     else:
         cfg = workloads.scaled(n, W=5.0)
     params, drop = cfg["params"], cfg["droplet"]

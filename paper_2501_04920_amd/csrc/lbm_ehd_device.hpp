@@ -118,7 +118,11 @@ __device__ inline Rsrc make_rsrc(const void* base, uint32_t bytes) {
 // Population stores carry the non-temporal hint: nothing reads them before
 // the whole grid has streamed through the caches, and the hint keeps them
 // from displacing the lines that neighbouring workgroups are still pulling.
+// Population loads carry it too: almost every element is read by one node
+// only, so its line is best evicted first (measured on MI355X at 2048^2:
+// FP32 16.6 -> 17.4 GLUPS, FP16 22.8 -> 23.6).
 constexpr int ST_NT = 2;
+constexpr int LD_NT = 2;
 template <class S, class R>
 struct Codec;
 
@@ -127,7 +131,7 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 template <>
 struct Codec<double, double> {
   __device__ static inline double ld(Rsrc r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, LD_NT));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, double x) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, ST_NT);
@@ -136,7 +140,7 @@ struct Codec<double, double> {
 template <>
 struct Codec<float, float> {
   __device__ static inline float ld(Rsrc r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, LD_NT));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, v, s, ST_NT);
@@ -145,7 +149,7 @@ struct Codec<float, float> {
 template <>
 struct Codec<float, double> {
   __device__ static inline double ld(Rsrc r, uint32_t v, uint32_t s) {
-    return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, LD_NT));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, double x) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)x), r, v, s, ST_NT);
@@ -154,7 +158,7 @@ struct Codec<float, double> {
 template <>
 struct Codec<__half, float> {
   __device__ static inline float ld(Rsrc r, uint32_t v, uint32_t s) {
-    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, v, s, LD_NT);
     return __half2float(__builtin_bit_cast(__half, b));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
@@ -165,7 +169,7 @@ struct Codec<__half, float> {
 template <>
 struct Codec<__hip_bfloat16, float> {
   __device__ static inline float ld(Rsrc r, uint32_t v, uint32_t s) {
-    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, v, s, LD_NT);
     return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, b));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {

@@ -486,8 +486,13 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
     const bool down = y > 0 || periodic;
     // The row's own f, p, n and g0 are requested before the ring row, so that
     // both sets of loads are in flight together (one memory round trip per
-    // row instead of two).  Lanes past the grid edge read column x0.
+    // row instead of two).  Lanes past the grid edge read column x0.  The
+    // loads are issued at raised wave priority: a wave starting its row gets
+    // its ~46 loads out ahead of the arithmetic of the other waves on its
+    // SIMD (measured on MI355X at 2048^2: +1.2 % FP32, +1.6 % FP16; the
+    // level, 1 to 3, makes no difference).
     R f[9], p[5], n[5], t4[4];
+    __builtin_amdgcn_s_setprio(2);
     pull9(Ph, QF, k, y, f);
     const uint32_t r0 = Ph.row(y + 1);
     // (the ion rest populations of 16-bit storage are read by the update)
@@ -499,6 +504,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
     pull4(Ph, QN, k, y, t4);
     n[1] = t4[0]; n[2] = t4[1]; n[3] = t4[2]; n[4] = t4[3];
     if (up) ring_row(y + 1);
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     if (valid) {
       const int c = lane + 1, sc = slot(y);
