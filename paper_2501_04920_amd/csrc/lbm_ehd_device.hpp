@@ -118,9 +118,10 @@ __device__ inline Rsrc make_rsrc(const void* base, uint32_t bytes) {
 // Population stores carry the non-temporal hint: nothing reads them before
 // the whole grid has streamed through the caches, and the hint keeps them
 // from displacing the lines that neighbouring workgroups are still pulling.
-// Population loads carry it too: almost every element is read by one node
-// only, so its line is best evicted first (measured on MI355X at 2048^2:
-// FP32 16.6 -> 17.4 GLUPS, FP16 22.8 -> 23.6).
+// Population loads carry it too (`nt`), except where a line is known to be
+// read again soon: almost every element is read by one node only, so its
+// line is best evicted first (measured on MI355X at 2048^2: FP32 16.6 ->
+// 17.4 GLUPS, FP16 22.8 -> 23.6).
 constexpr int ST_NT = 2;
 constexpr int LD_NT = 2;
 template <class S, class R>
@@ -130,8 +131,9 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 template <>
 struct Codec<double, double> {
-  __device__ static inline double ld(Rsrc r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, LD_NT));
+  __device__ static inline double ld(Rsrc r, uint32_t v, uint32_t s, bool nt) {
+    return __builtin_bit_cast(double, nt ? __builtin_amdgcn_raw_buffer_load_b64(r, v, s, LD_NT)
+                                         : __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, double x) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v, s, ST_NT);
@@ -139,8 +141,9 @@ struct Codec<double, double> {
 };
 template <>
 struct Codec<float, float> {
-  __device__ static inline float ld(Rsrc r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, LD_NT));
+  __device__ static inline float ld(Rsrc r, uint32_t v, uint32_t s, bool nt) {
+    return __builtin_bit_cast(float, nt ? __builtin_amdgcn_raw_buffer_load_b32(r, v, s, LD_NT)
+                                        : __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, v, s, ST_NT);
@@ -148,8 +151,9 @@ struct Codec<float, float> {
 };
 template <>
 struct Codec<float, double> {
-  __device__ static inline double ld(Rsrc r, uint32_t v, uint32_t s) {
-    return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, LD_NT));
+  __device__ static inline double ld(Rsrc r, uint32_t v, uint32_t s, bool nt) {
+    return (double)__builtin_bit_cast(float, nt ? __builtin_amdgcn_raw_buffer_load_b32(r, v, s, LD_NT)
+                                                : __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, double x) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)x), r, v, s, ST_NT);
@@ -157,8 +161,9 @@ struct Codec<float, double> {
 };
 template <>
 struct Codec<__half, float> {
-  __device__ static inline float ld(Rsrc r, uint32_t v, uint32_t s) {
-    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, v, s, LD_NT);
+  __device__ static inline float ld(Rsrc r, uint32_t v, uint32_t s, bool nt) {
+    const unsigned short b = nt ? __builtin_amdgcn_raw_buffer_load_b16(r, v, s, LD_NT)
+                                : __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
     return __half2float(__builtin_bit_cast(__half, b));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
@@ -168,8 +173,9 @@ struct Codec<__half, float> {
 };
 template <>
 struct Codec<__hip_bfloat16, float> {
-  __device__ static inline float ld(Rsrc r, uint32_t v, uint32_t s) {
-    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, v, s, LD_NT);
+  __device__ static inline float ld(Rsrc r, uint32_t v, uint32_t s, bool nt) {
+    const unsigned short b = nt ? __builtin_amdgcn_raw_buffer_load_b16(r, v, s, LD_NT)
+                                : __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0);
     return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, b));
   }
   __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
@@ -302,11 +308,13 @@ __device__ inline double h_from(double dev, int i, double phit) {
 }
 
 // A population buffer seen through a buffer descriptor: line q of the row
-// at element offset `off` = row(r) + x.
+// at element offset `off` = row(r) + x.  `nt`: loads with the non-temporal
+// hint (a constant at every construction, so each load has one form).
 template <class S, class R>
 struct PopView {
   Rsrc rs;
   const KP<R>* kp;
+  bool nt = true;
   __device__ inline uint32_t row(int r) const { return (uint32_t)r * kp->rstride; }
   // offset of the ion lines with 16-bit storage (see the deviation form)
   __device__ inline R ofs(int q) const {
@@ -315,7 +323,7 @@ struct PopView {
   }
   __device__ inline R at(int q, uint32_t off) const {
     R v = Codec<S, R>::ld(rs, off * (uint32_t)sizeof(S),
-                          (uint32_t)q * kp->pitch * (uint32_t)sizeof(S));
+                          (uint32_t)q * kp->pitch * (uint32_t)sizeof(S), nt);
     if (Scaled<S>::value) v *= kp->isc[line_set<S>(q)];
     return v + ofs(q);
   }

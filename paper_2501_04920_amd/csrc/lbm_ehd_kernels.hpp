@@ -443,6 +443,8 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
   const Cols k = cols_of(x, nx);
   const bool periodic = kp.walls == WALL_PERIODIC;
   const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp};
+  // the ring rows that the neighbouring bands pull too are loaded cached
+  const PopView<S, R> Pc{make_rsrc(src, kp.pop_bytes), &kp, false};
   const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp};
 
   // halo column handled by lanes 0 (left) and 1 (right)
@@ -451,31 +453,43 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
   const int kcol = lane == 0 ? 0 : w + 1;
 
   auto slot = [&](int yy) { return (yy - y0 + 1) % RING; };
-  // phi', psi' of row yy into the ring; each thread's own pulls are parked in LDS
+  // phi', psi' of row yy into the ring; each thread's own pulls are parked
+  // in LDS.  The h and g lines of the two ring rows at each end of the band
+  // are also pulled by the neighbouring band (which the tile order puts on
+  // the same XCD soon after), so they are loaded cached; the others
+  // non-temporal.  Measured on MI355X at 2048^2 against all non-temporal:
+  // FP32 +1.7 % (bands of 16) / +3.1 % (bands of 8), FP64 +1.1 %, FP16 -0.4 %;
+  // caching every ring row: FP32 +2.7 %, FP16 -2.6 %, FP64 -4 %.
   auto ring_row = [&](int yy) {
     const int ys = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
     const int sl = slot(yy);
-    if (lane < 2) {
-      R hh[9], gg[4];
-      T0 hh0;
-      pull_h(Ph, h0x, kh, ys, hh, &hh0);
-      pull_g(Ph, kh, ys, gg);
-      L.phi[sl][kcol] = phi_of<W>((W)hh0, hh);
-      L.psi[sl][kcol] = psi_of(gg);
-    }
-    if (valid) {
-      R h[9], g4[4];
-      T0 h0;
-      pull_h(Ph, h0x, k, ys, h, &h0);
-      pull_g(Ph, k, ys, g4);
-      L.phi[sl][lane + 1] = phi_of<W>((W)h0, h);
-      L.psi[sl][lane + 1] = psi_of(g4);
-      const int b = (yy - y0 + 2) & 1;
+    auto pulls = [&](const PopView<S, R>& V) {
+      if (lane < 2) {
+        R hh[9], gg[4];
+        T0 hh0;
+        pull_h(V, h0x, kh, ys, hh, &hh0);
+        pull_g(V, kh, ys, gg);
+        L.phi[sl][kcol] = phi_of<W>((W)hh0, hh);
+        L.psi[sl][kcol] = psi_of(gg);
+      }
+      if (valid) {
+        R h[9], g4[4];
+        T0 h0;
+        pull_h(V, h0x, k, ys, h, &h0);
+        pull_g(V, k, ys, g4);
+        L.phi[sl][lane + 1] = phi_of<W>((W)h0, h);
+        L.psi[sl][lane + 1] = psi_of(g4);
+        const int b = (yy - y0 + 2) & 1;
 #pragma unroll
-      for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = h[i];
+        for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = h[i];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = g4[i];
-    }
+        for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = g4[i];
+      }
+    };
+    if (yy <= y0 || yy >= yend - 1)
+      pulls(Pc);
+    else
+      pulls(Ph);
   };
 
   if (y0 > 0 || periodic) ring_row(y0 - 1);
