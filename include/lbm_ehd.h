@@ -178,6 +178,9 @@ typedef struct {
                               length along the field (y) through the phi-weighted
                               centroid and across it, from the phi = 1/2 crossings
                               (NaN when no droplet is found) */
+  int64_t presolve_iters;  /* g-only sweeps of the last pre-solve since init */
+  double presolve_residual;/* its convergence residual (lbm_ehd_presolve_to; NaN
+                              after lbm_ehd_presolve or none) */
 } lbm_ehd_diag;
 
 typedef struct lbm_ehd lbm_ehd; /* opaque handle */
@@ -227,6 +230,23 @@ LBM_API lbm_status lbm_ehd_init_fields(lbm_ehd *h, const double *phi, const doub
 /* `iters` g-only sweeps of Eq. (44) with phi and rho_e held fixed (Poisson
  * pre-solve).  Enqueues work. */
 LBM_API lbm_status lbm_ehd_presolve(lbm_ehd *h, int32_t iters);
+
+/* Poisson pre-solve to a tolerance: g-only sweeps as in lbm_ehd_presolve
+ * until the convergence residual falls below `tol`, or `max_iters` sweeps.
+ * The paper states no stopping rule (Sec. 4.2 fixes only theta).  The
+ * residual is the FP64 relative change of the potential over one sweep,
+ * ||psi_{k+1} - psi_k||_2 / ||psi_{k+1}||_2, divided by the per-sweep decay
+ * rate of the slowest mode of the Poisson LBE, pi^2 theta / ny^2 (a
+ * diffusion with coefficient theta between electrodes ny apart), so that it
+ * estimates the remaining relative error of psi.  It is formed from FP64
+ * per-row sums in a fixed order (the same on every run) every
+ * `check_every` sweeps.  *iters (sweeps done) and *residual (last residual)
+ * may be NULL; both are also reported by lbm_ehd_diagnostics.  Synchronises
+ * at each check.  LBM_EINVAL unless tol > 0, max_iters >= 1 and
+ * check_every >= 1; LBM_ESTATE before init; LBM_ENONFINITE if the potential
+ * is not finite. */
+LBM_API lbm_status lbm_ehd_presolve_to(lbm_ehd *h, double tol, int32_t max_iters,
+                                       int32_t check_every, int32_t *iters, double *residual);
 
 /* One time step (poisson_iters extra g sweeps, then the fused sweep of all
  * five equations).  Enqueues work. */

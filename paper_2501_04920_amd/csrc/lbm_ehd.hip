@@ -78,6 +78,8 @@ struct lbm_ehd {
   void* mom = nullptr;      // phi, psi, rho_e planes (arithmetic type), [3][ny][nx]
   double* fld = nullptr;    // [10][ny][nx]
   double* part = nullptr;   // [ny][NSUM]
+  int64_t presolve_iters = 0;     // g-only sweeps of the last pre-solve
+  double presolve_residual = NAN; // its convergence residual (NaN: not measured)
   double* red = nullptr;    // [NSUM]
   double* line = nullptr;   // [2 ny + 2 nx]
   double* upl = nullptr;    // uploaded initial fields [6][ny][nx]
@@ -403,8 +405,61 @@ struct Form {
     hipLaunchKernelGGL((k_row_sums<S, R, T0>), dim3(h->P.ny), dim3(256), 0, h->stream, src,
                        h0(h, h->cur), h->part, kp);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, h->part, h->P.ny, h->red);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, h->part, h->P.ny, NSUM,
+                       h->red);
     HIP_TRY(hipGetLastError());
+    return LBM_OK;
+  }
+
+  // g-only sweeps until the convergence residual falls below tol (checked
+  // every `every` sweeps) or max_iters sweeps are done.  The residual is the
+  // FP64 relative change of psi over the last sweep, ||psi_k+1 - psi_k|| /
+  // ||psi_k+1||, divided by the per-sweep decay rate of the slowest mode of
+  // the Poisson LBE (a diffusion with coefficient theta between electrodes a
+  // distance ny apart: pi^2 theta / ny^2), which estimates the distance to
+  // the converged potential.  Both g sets are at hand: the sweeps ping-pong
+  // between the buffers, so the other one holds the sweep before.
+  static lbm_status presolve_to(lbm_ehd* h, double tol, int max_iters, int every, int* done,
+                                double* residual) {
+    const KP<R> kp = make_kp<R>(h);
+    const KP<W> kpw = make_kp<W>(h);
+    S* A = buf(h, h->cur);
+    S* B = buf(h, 1 - h->cur);
+    const S* from = A;
+    const double theta = h->P.theta > 0 ? h->P.theta : 0.3;
+    const double rate = M_PI * M_PI * theta / ((double)h->P.ny * h->P.ny);
+    int k = 0;
+    double r = NAN;
+    while (k < max_iters) {
+      const int n = std::min(every, max_iters - k);
+      for (int i = 0; i < n; ++i) {
+        lbm_status st = moments(h, from);
+        if (st) return st;
+        S* to = from == A ? B : A;
+        hipLaunchKernelGGL((k_poisson<S, R>), grid2(h), dim3(64), 0, h->stream, from, to,
+                           static_cast<const R*>(h->mom), kp);
+        HIP_TRY(hipGetLastError());
+        from = to;
+      }
+      k += n;
+      const S* older = from == A ? B : A;
+      hipLaunchKernelGGL((k_psi_change_rows<S, W>), dim3(h->P.ny), dim3(256), 0, h->stream,
+                         from, older, h->part, kpw);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, h->part, h->P.ny, 2,
+                         h->red);
+      HIP_TRY(hipGetLastError());
+      double sums[2];
+      HIP_TRY(hipMemcpyAsync(sums, h->red, sizeof sums, hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      r = sums[1] > 0 ? std::sqrt(sums[0] / sums[1]) / rate : 0.0;
+      if (!std::isfinite(r)) return fail(LBM_ENONFINITE, "potential contains NaN or Inf");
+      if (r < tol) break;
+    }
+    lbm_status st = settle_g(h, from);
+    if (st) return st;
+    *done = k;
+    *residual = r;
     return LBM_OK;
   }
 };
@@ -785,6 +840,8 @@ lbm_status lbm_ehd_init_droplet(lbm_ehd* h, double xc, double yc, double radius,
   lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::init(h, sp); });
   if (st) return st;
   h->step = 0;
+  h->presolve_iters = 0;
+  h->presolve_residual = NAN;
   h->ready = true;
   return LBM_OK;
 }
@@ -814,6 +871,8 @@ lbm_status lbm_ehd_init_fields(lbm_ehd* h, const double* phi, const double* cp,
   if (st) return st;
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->step = 0;
+  h->presolve_iters = 0;
+  h->presolve_residual = NAN;
   h->ready = true;
   return LBM_OK;
 }
@@ -823,7 +882,27 @@ lbm_status lbm_ehd_presolve(lbm_ehd* h, int32_t iters) {
   if (!h->ready) return fail(LBM_ESTATE, "presolve before init");
   if (iters < 0) return fail(LBM_EINVAL, "iters < 0");
   if (iters == 0) return LBM_OK;
+  h->presolve_iters = iters;
+  h->presolve_residual = NAN;
   return dispatch(h, [&](auto F) { return decltype(F)::presolve(h, iters); });
+}
+
+lbm_status lbm_ehd_presolve_to(lbm_ehd* h, double tol, int32_t max_iters, int32_t check_every,
+                               int32_t* iters, double* residual) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h->ready) return fail(LBM_ESTATE, "presolve before init");
+  if (!(tol > 0) || max_iters < 1 || check_every < 1)
+    return fail(LBM_EINVAL, "need tol > 0, max_iters >= 1, check_every >= 1");
+  int done = 0;
+  double r = NAN;
+  lbm_status st = dispatch(
+      h, [&](auto F) { return decltype(F)::presolve_to(h, tol, max_iters, check_every, &done, &r); });
+  if (st) return st;
+  h->presolve_iters = done;
+  h->presolve_residual = r;
+  if (iters) *iters = done;
+  if (residual) *residual = r;
+  return LBM_OK;
 }
 
 lbm_status lbm_ehd_step(lbm_ehd* h) {
@@ -881,6 +960,8 @@ lbm_status lbm_ehd_diagnostics(lbm_ehd* h, lbm_ehd_diag* out) {
   out->sum_p = r[2];
   out->sum_n = r[3];
   out->nonfinite = (int64_t)r[6];
+  out->presolve_iters = h->presolve_iters;
+  out->presolve_residual = h->presolve_residual;
   out->D = out->L = out->H = NAN;
   if (out->nonfinite) return fail(LBM_ENONFINITE, "state contains NaN or Inf");
   if (r[0] > 0) {

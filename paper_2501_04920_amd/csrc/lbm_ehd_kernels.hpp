@@ -871,12 +871,53 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
   if (t < NSUM) part[(long long)y * NSUM + t] = sh[t][0];
 }
 
-__global__ void k_sum_rows(const double* __restrict__ part, int ny, double* __restrict__ out) {
-  if (threadIdx.x < NSUM) {
+// Column sums of the per-row partial sums [ny][ncol] (ncol <= 64), rows in
+// order.
+__global__ void k_sum_rows(const double* __restrict__ part, int ny, int ncol,
+                           double* __restrict__ out) {
+  if ((int)threadIdx.x < ncol) {
     double a = 0.0;
-    for (int y = 0; y < ny; ++y) a += part[(long long)y * NSUM + threadIdx.x];
+    for (int y = 0; y < ny; ++y) a += part[(long long)y * ncol + threadIdx.x];
     out[threadIdx.x] = a;
   }
+}
+
+// FP64 sums of one row for the convergence residual of the g-only sweeps:
+// [sum (psi_new - psi_old)^2, sum psi_new^2], psi from the g sets of two
+// buffers (the latest sweep and the one before).  Same fixed-shape tree as
+// k_row_sums.
+template <class S, class R>
+__global__ __launch_bounds__(256) void k_psi_change_rows(const S* __restrict__ gnew,
+                                                         const S* __restrict__ gold,
+                                                         double* __restrict__ part,
+                                                         const KP<R> kp) {
+  __shared__ double sh[2][256];
+  const int y = blockIdx.x, t = threadIdx.x;
+  const PopView<S, R> Pn{make_rsrc(gnew, kp.pop_bytes), &kp};
+  const PopView<S, R> Po{make_rsrc(gold, kp.pop_bytes), &kp};
+  const double psi_lin =
+      kp.walls == WALL_PERIODIC ? 0.0 : (double)kp.dpsi * (kp.ny - 0.5 - y) / kp.ny;
+  double dd = 0.0, nn = 0.0;
+  for (int x = t; x < kp.nx; x += 256) {
+    const Cols k = cols_of(x, kp.nx);
+    R gn[4], go[4];
+    pull_g(Pn, k, y, gn);
+    pull_g(Po, k, y, go);
+    const double pn = psi_lin + (double)psi_of(gn), po = psi_lin + (double)psi_of(go);
+    dd += (pn - po) * (pn - po);
+    nn += pn * pn;
+  }
+  sh[0][t] = dd;
+  sh[1][t] = nn;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      sh[0][t] += sh[0][t + s];
+      sh[1][t] += sh[1][t + s];
+    }
+    __syncthreads();
+  }
+  if (t < 2) part[(long long)y * 2 + t] = sh[t][0];
 }
 
 // Plain copy through buffer descriptors (measurement helper).  Each lane

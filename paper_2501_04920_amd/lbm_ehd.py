@@ -80,6 +80,7 @@ class lbm_ehd_diag(ctypes.Structure):
         ("sum_p", ctypes.c_double), ("sum_n", ctypes.c_double),
         ("nonfinite", ctypes.c_int64),
         ("D", ctypes.c_double), ("L", ctypes.c_double), ("H", ctypes.c_double),
+        ("presolve_iters", ctypes.c_int64), ("presolve_residual", ctypes.c_double),
     ]
 
 
@@ -124,6 +125,8 @@ def lib() -> ctypes.CDLL:
                                      ctypes.c_double, ctypes.c_uint64],
             "lbm_ehd_init_fields": [vp, _dp, _dp, _dp, _dp, _dp, _dp],
             "lbm_ehd_presolve": [vp, ctypes.c_int32],
+            "lbm_ehd_presolve_to": [vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                    P(ctypes.c_int32), P(ctypes.c_double)],
             "lbm_ehd_step": [vp],
             "lbm_ehd_run": [vp, ctypes.c_int64],
             "lbm_ehd_get_fields": [vp, ctypes.c_uint32, _dp, ctypes.c_size_t],
@@ -231,6 +234,14 @@ def lbm_ehd_init_fields(h, ny, nx, phi, cp, cm, psi, ux=None, uy=None):
 
 def lbm_ehd_presolve(h, iters: int):
     _check(lib().lbm_ehd_presolve(h, int(iters)))
+
+
+def lbm_ehd_presolve_to(h, tol: float, max_iters: int, check_every: int = 100):
+    """Returns (sweeps done, last convergence residual)."""
+    it, r = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib().lbm_ehd_presolve_to(h, float(tol), int(max_iters), int(check_every),
+                                      ctypes.byref(it), ctypes.byref(r)))
+    return it.value, r.value
 
 
 def lbm_ehd_step(h):
@@ -411,6 +422,10 @@ class Simulation:
     def presolve(self, iters):
         lbm_ehd_presolve(self.handle, iters)
         return self
+
+    def presolve_to(self, tol, max_iters, check_every=100):
+        """(sweeps done, convergence residual) of a pre-solve to `tol`."""
+        return lbm_ehd_presolve_to(self.handle, tol, max_iters, check_every)
 
     def step(self, n=1):
         lbm_ehd_run(self.handle, n)

@@ -29,8 +29,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_sizes_match_header_layout():
     # int32 block then doubles, no padding surprises
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 16 * 4 + 22 * 8
-    assert ctypes.sizeof(lbm_ehd.lbm_ehd_diag) == 9 * 8
-    assert ctypes.sizeof(lbm_ehd.lbm_ehd_request_info) == 8 + 4 + 4 + 2 * 8 + 3 * 8 + 8 + 9 * 8
+    assert ctypes.sizeof(lbm_ehd.lbm_ehd_diag) == 11 * 8
+    assert ctypes.sizeof(lbm_ehd.lbm_ehd_request_info) == 8 + 4 + 4 + 2 * 8 + 3 * 8 + 8 + 11 * 8
 
 
 def test_defaults_and_bytes():

@@ -168,6 +168,59 @@ def test_translating_interface_init_fields_fp64():
     assert max(errs.values()) <= 1e-10
 
 
+def _psi_residual(psi_new, psi_old, p):
+    theta = p.get("theta") or 0.3
+    rate = np.pi ** 2 * theta / p["ny"] ** 2
+    return np.linalg.norm(psi_new - psi_old) / np.linalg.norm(psi_new) / rate
+
+
+def test_presolve_to_tolerance_fp64():
+    """Pre-solve to a tolerance: the sweeps done, the fields after them and
+    the residual (a plain formula of the potential before and after the last
+    sweep) against the oracle run for the same number of sweeps."""
+    cfg = workloads.config1()
+    p, d = cfg["params"], cfg["droplet"]
+    sim = run_gpu(p, "fp64", droplet=d)
+    k, r = sim.presolve_to(1e-8, 3000, check_every=100)
+    assert k % 100 == 0 and 100 <= k <= 3000 and (r < 1e-8 or k == 3000)
+    diag = sim.diagnostics()
+    assert diag["presolve_iters"] == k and diag["presolve_residual"] == r
+    o = run_oracle(p, droplet=d, presolve=k - 1)
+    psi_before = o.fields()["psi"]
+    o.presolve(1)
+    ref = o.fields()
+    r_ref = _psi_residual(ref["psi"], psi_before, p)
+    print("presolve_to: %d sweeps, residual %.4e (oracle %.4e)" % (k, r, r_ref), flush=True)
+    # psi agrees to ~1e-13 while one sweep changes it by ~r * rate ~ 1e-12
+    assert abs(r - r_ref) <= 5e-2 * r_ref
+    errs = rel_l2(sim.fields(), ref, p, ALL10)
+    assert max(errs.values()) <= 1e-10, errs
+    # a looser tolerance stops at the first check where it holds
+    sim2 = run_gpu(p, "fp64", droplet=d)
+    k2, r2 = sim2.presolve_to(r * 1e3, 3000, check_every=50)
+    assert k2 <= k and r2 < r * 1e3
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_presolve_to_other_storage(precision):
+    """The same pre-solve in FP32 and FP16 storage: FP32 follows FP64; with
+    16-bit storage the residual levels off at the storage's rounding and the
+    pre-solve runs to max_iters (the potential still matches FP64 closely)."""
+    cfg = workloads.config1()
+    p, d = cfg["params"], cfg["droplet"]
+    ref = run_gpu(p, "fp64", droplet=d)
+    k64, r64 = ref.presolve_to(1e-8, 2000, check_every=100)
+    sim = run_gpu(p, precision, droplet=d)
+    k, r = sim.presolve_to(1e-8, 2000, check_every=100)
+    print("presolve_to %s: %d sweeps, residual %.3e (fp64: %d, %.3e)" % (precision, k, r, k64, r64),
+          flush=True)
+    assert np.isfinite(r)
+    if precision == "fp32":
+        assert abs(k - k64) <= 200
+    errs = rel_l2(sim.fields(), ref.fields(), p, ("psi", "rhoe"))
+    assert errs["psi"] <= (1e-6 if precision == "fp32" else 1e-3), errs
+
+
 def test_presolve_fp64():
     cfg = workloads.config1()
     p, d = cfg["params"], cfg["droplet"]
@@ -264,9 +317,16 @@ def test_error_paths():
         sim.step(1)
     assert e.value.code == lbm_ehd.LBM_ESTATE
     with pytest.raises(lbm_ehd.LbmError) as e:
+        sim.presolve_to(1e-6, 10)
+    assert e.value.code == lbm_ehd.LBM_ESTATE
+    with pytest.raises(lbm_ehd.LbmError) as e:
         sim.init_droplet(15.5, 15.5, 40.0)   # crosses the electrodes
     assert e.value.code == lbm_ehd.LBM_EINVAL
     sim.init_droplet(15.5, 15.5, 5.0)
+    for bad in ((0.0, 10, 1), (1e-6, 0, 1), (1e-6, 10, 0)):
+        with pytest.raises(lbm_ehd.LbmError) as e:
+            sim.presolve_to(*bad)
+        assert e.value.code == lbm_ehd.LBM_EINVAL
     out = np.empty(10)
     import ctypes
     code = lbm_ehd.lib().lbm_ehd_get_fields(sim.handle, 0x3FF,
