@@ -24,8 +24,9 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (all 5 LB eqs/cell) at 2048² vs HBM roofline; sweep solves/hr; p99 latency"
 HBM_PEAK_GBS = 8000.0
 PMC_FILE = os.path.join(ROOT, "profiles", "sweep_hbm_traffic.json")
+# the device code of the sweep; the launch shape is recorded beside the counts
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_04920_amd", "csrc", f)
-                  for f in ("lbm_ehd_device.hpp", "lbm_ehd_kernels.hpp", "lbm_ehd.hip")]
+                  for f in ("lbm_ehd_device.hpp", "lbm_ehd_kernels.hpp")]
 
 
 def kernel_hash() -> str:
@@ -36,9 +37,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, waves: int, tile_rows: int):
     """HBM bytes per sweep launch from the committed rocprofv3 counter runs,
-    or None if they were taken on another version of the kernel."""
+    or None if they were taken on another version of the kernel or in
+    another launch shape."""
     try:
         with open(PMC_FILE) as fh:
             rec = json.load(fh)
@@ -47,7 +49,9 @@ def measured_traffic(workload: str):
     if rec.get("kernel_hash") != kernel_hash():
         return None
     ent = rec.get("workloads", {}).get(workload)
-    return None if ent is None else ent.get("bytes_per_launch")
+    if ent is None or (ent.get("waves"), ent.get("tile_rows")) != (waves, tile_rows):
+        return None
+    return ent.get("bytes_per_launch")
 
 
 def cpu_baseline(params, drop, steps: int):
@@ -102,7 +106,7 @@ def copy_calibration(gib: float, reps: int, width: int):
                       "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
 
 
-def summarize_pmc(paths, workload: str):
+def summarize_pmc(paths, workload: str, waves: int, tile_rows: int):
     """Turn four rocprofv3 --pmc CSVs (sweep FETCH_SIZE, sweep WRITE_SIZE, copy
     FETCH_SIZE, copy WRITE_SIZE; KiB per dispatch) into HBM bytes per sweep
     launch, each counter scaled by what it reads for the copy kernel of known
@@ -129,6 +133,7 @@ def summarize_pmc(paths, workload: str):
     if rec.get("kernel_hash") != kernel_hash():
         rec = {"kernel_hash": kernel_hash(), "workloads": {}}
     rec["workloads"][workload] = {
+        "waves": waves, "tile_rows": tile_rows,
         "fetch_bytes": round(fetch), "write_bytes": round(write),
         "bytes_per_launch": round(fetch + write),
         "fetch_scale": round(kf, 4), "write_scale": round(kw, 4)}
@@ -336,7 +341,10 @@ def main():
     ap.add_argument("--sub", type=int, default=1, help="also run the ~70 %% load trace")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc, "droplet-%d-%s" % (args.n, args.precision))
+        if not (args.waves and args.tile_rows):
+            sys.exit("--summarize-pmc needs the --waves and --tile-rows of the counter runs")
+        summarize_pmc(args.summarize_pmc, "droplet-%d-%s" % (args.n, args.precision),
+                      args.waves, args.tile_rows)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -400,7 +408,7 @@ def main():
     bpl = lbm_ehd.lbm_ehd_bytes_per_lup(args.precision)
     achieved = bpl * cells / (kern_ms * 1e-3) / 1e9
     diag = sim.diagnostics()
-    traffic = measured_traffic(workload)
+    traffic = measured_traffic(workload, waves, tile_rows)
     line = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,

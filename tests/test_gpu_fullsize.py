@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 
 ALL10 = ("phi", "psi", "cp", "cm", "rhoe", "ux", "uy", "p", "Ex", "Ey")
 # waves per workgroup, rows per band: the library's default at 2048^2
-BENCH_LAUNCH = {"fp64": (4, 16), "fp32": (4, 8), "fp16": (8, 16), "bf16": (8, 16)}
+BENCH_LAUNCH = {"fp64": (4, 16), "fp32": (8, 8), "fp16": (8, 16), "bf16": (8, 16)}
 
 
 def _case():
