@@ -442,7 +442,15 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
   const int x = x0 + (valid ? lane : 0);
   const Cols k = cols_of(x, nx);
   const bool periodic = kp.walls == WALL_PERIODIC;
-  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp};
+  // Non-temporal population loads pay off where a strip's row of one line
+  // spans at least 1 KB.  In narrower strips the column-shifted pulls at the
+  // strip edges reach into cache lines that the neighbouring strip also
+  // reads, and evict-first makes HBM serve them twice.  Measured on MI355X:
+  // single grids with 1-2 KB strips gain 4-14 % (FP32 512^2 to 2048^2, FP16
+  // 2048^2); the batched FP16 droplets of 128^2 to 1024^2 lose 23 % in
+  // 128-byte strips and 9 % in 512-byte ones.
+  constexpr bool kNT = 64 * NW * sizeof(S) >= 1024;
+  const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp, kNT};
   // the ring rows that the neighbouring bands pull too are loaded cached
   const PopView<S, R> Pc{make_rsrc(src, kp.pop_bytes), &kp, false};
   const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp};
@@ -454,12 +462,14 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
 
   auto slot = [&](int yy) { return (yy - y0 + 1) % RING; };
   // phi', psi' of row yy into the ring; each thread's own pulls are parked
-  // in LDS.  The h and g lines of the two ring rows at each end of the band
-  // are also pulled by the neighbouring band (which the tile order puts on
-  // the same XCD soon after), so they are loaded cached; the others
-  // non-temporal.  Measured on MI355X at 2048^2 against all non-temporal:
-  // FP32 +1.7 % (bands of 16) / +3.1 % (bands of 8), FP64 +1.1 %, FP16 -0.4 %;
-  // caching every ring row: FP32 +2.7 %, FP16 -2.6 %, FP64 -4 %.
+  // in LDS.  With 4- and 8-byte storage the h and g lines of the two ring
+  // rows at each end of the band, which the neighbouring band (put on the
+  // same XCD soon after by the tile order) pulls too, are loaded cached; the
+  // others non-temporal.  Measured on MI355X at 2048^2 against all
+  // non-temporal: FP32 +1.7 % (bands of 16) / +3.1 % (bands of 8), FP64
+  // +1.1 %, FP16 -0.4 % (and -7 % for the batched FP16 droplets of 128^2 to
+  // 1024^2, whose short bands make most ring rows edge rows); caching every
+  // ring row: FP32 +2.7 %, FP16 -2.6 %, FP64 -4 %.
   auto ring_row = [&](int yy) {
     const int ys = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
     const int sl = slot(yy);
@@ -486,7 +496,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
         for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = g4[i];
       }
     };
-    if (yy <= y0 || yy >= yend - 1)
+    if (kNT && sizeof(S) >= 4 && (yy <= y0 || yy >= yend - 1))
       pulls(Pc);
     else
       pulls(Ph);
