@@ -30,10 +30,17 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2501_04920_amd", "csrc", f)
 
 
 def kernel_hash() -> str:
+    """Hash of the sweep's device code, comments and blank lines left out."""
+    import re
+
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            src = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in src.splitlines():
+            code = line.split("//", 1)[0].strip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

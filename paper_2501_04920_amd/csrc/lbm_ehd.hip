@@ -615,17 +615,17 @@ void free_scratch(lbm_ehd* h) {
   }
 }
 
-// Default launch shape of the sweep for a grid: strips of 256 columns (four
-// waves in step) where the grid is that wide, 512 (eight waves) with FP32
-// arithmetic on grids that wide (with FP64 arithmetic only two waves fit on a
-// SIMD: FP32 storage with FP64 arithmetic 16.9 GLUPS at 4 x 8, 15.5 at
-// 8 x 8), and the tallest band (the h/g rows above
-// and below a band are read twice) that still gives every SIMD four
-// wavefronts (4096 on the 256 CUs), eight with FP32 storage.  Measured on
-// MI355X at 2048^2 (GLUPS; waves x rows per band): FP32 18.1 (8 x 8), 17.9
-// (4 x 8), 17.5 (4 x 4), 17.4 (8 x 4), 15.8 (2 x 8), 14.9 (1 x 8); FP16 24.1
-// (8 x 16), 24.0 (4 x 16), 23.4 (8 x 8), 18.3 (4 x 32); BF16 24.5 (8 x 16),
-// 24.2 (4 x 16); FP64 10.0 (4 x 16), 9.8 (8 x 16).
+// Default launch shape of the sweep for a grid.  Strips are 64 columns per
+// wave: four waves (256 columns) where the grid is that wide, eight (512)
+// with FP32 arithmetic where the grid is that wide (with FP64 arithmetic only
+// two waves fit on a SIMD, and eight-wave workgroups lose 9 %).  Bands are
+// the tallest (the h and g rows just outside a band are read twice) that
+// still put four wavefronts per SIMD in flight (4096 on the 256 CUs), eight
+// per SIMD with FP32 storage.  Measured on MI355X at 2048^2 (GLUPS; waves x
+// rows per band): FP32 18.1 (8 x 8), 17.9 (4 x 8), 17.5 (4 x 4), 17.4 (8 x 4),
+// 15.8 (2 x 8), 14.9 (1 x 8); FP32 storage with FP64 arithmetic 16.9 (4 x 8),
+// 15.5 (8 x 8); FP16 24.1 (8 x 16), 24.0 (4 x 16), 23.4 (8 x 8), 18.3
+// (4 x 32); BF16 24.5 (8 x 16), 24.2 (4 x 16); FP64 10.0 (4 x 16), 9.8 (8 x 16).
 void default_launch(const lbm_ehd_params* p, int* waves, int* tile_rows) {
   *waves = p->nx >= 256 ? 4 : (p->nx >= 128 ? 2 : 1);
   if (arith_size(p->precision) == 4 && p->nx >= 512) *waves = 8;

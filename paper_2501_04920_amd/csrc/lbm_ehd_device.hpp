@@ -67,7 +67,6 @@ namespace lbm {
 constexpr int NPOP = 33;
 enum { QF = 0, QH = 9, QP = 18, QN = 23, QG = 28 };
 enum { WALL_ELECTRODES = 0, WALL_INSULATING = 1, WALL_PERIODIC = 2 };
-constexpr int TILE_W = 64;  // one wavefront of columns per workgroup
 constexpr int RING = 5;     // rows of phi/psi kept in LDS
 
 // Kernel constants, in the arithmetic type R.

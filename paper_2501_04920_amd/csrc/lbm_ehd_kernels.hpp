@@ -1,7 +1,8 @@
 // lbm_ehd_kernels.hpp -- kernels of the five-equation sweep and its helpers.
 //
-// k_sweep is the hot path: one pass over the grid advances f, h, p, n and g
-// by one time step (pull streaming fused with the collisions).  Each
+// k_sweep_batch is the hot path: one pass over the grid (or over the grids
+// of a batch) advances f, h, p, n and g by one time step (pull streaming
+// fused with the collisions).  Each
 // workgroup of NW wavefronts owns a strip of 64 NW columns of a band of rows
 // and walks down the band, one row per barrier, so that its waves read each
 // row's lines together (the pull shifts and strip edges then fall in lines
@@ -13,7 +14,7 @@
 // 64 NW + 2 columns, the two halo columns by threads 0 and 1) and each thread
 // parks the pulled h and g of its node in LDS for the row's own update.
 // Every population is read once and written once per step; only h and g of
-// the two halo columns and of the rows above a band are read twice.
+// the two halo columns and of the rows just outside a band are read twice.
 #pragma once
 
 #include "lbm_ehd_device.hpp"
