@@ -27,8 +27,9 @@
  *   7. velocity and pressure, Eq. (56)-(57); d(phi u)/dt by Eq. (58)
  *   8. MRT collisions of f (Eq. 51-55), h (Eq. 27-32), p and n (Eq. 34-40,
  *      on D2Q5), g (Eq. 44-47)
- *   9. streaming, periodic in x, with halfway wall rules at the electrodes
- *      (Eq. 64 and the boundary conditions of the 1-D test in Sec. 5.1)
+ *   9. streaming, periodic in x (or between side walls), with halfway wall
+ *      rules at the electrodes (Eq. 64 and the boundary conditions of the 1-D
+ *      test in Sec. 5.1)
  *
  * Readings taken where the paper is silent, garbled or inconsistent:
  *   - ions use the D2Q5 lattice (weights of Eq. 26, matrix N of Eq. 46);
@@ -53,6 +54,15 @@
  *     anti-bounces back with the concentration of the wall node itself;
  *   - stencil ghosts: phi mirrored across the wall, psi odd about the wall
  *     value; grad(rho) and grad(eps) follow from grad(phi) by Eq. (61);
+ *   - optional side walls (the other boundaries of Eq. 64: u = 0, zero normal
+ *     derivative of c+, c- and psi), halfway between lattice columns at
+ *     x = -1/2 and x = nx - 1/2: f bounces back (u = 0); h reflects
+ *     specularly (the mirror image of the domain, a neutral wall with zero
+ *     phi flux, consistent with the mirrored stencil ghosts); the ion and
+ *     potential populations bounce back, which for D2Q5 is the same as
+ *     specular reflection (zero flux); the stencil ghosts mirror phi and psi.
+ *     Where the mirror image of an h population's source lies beyond an
+ *     electrode (a corner), h bounces back;
  *   - the unit normal grad(phi)/|grad(phi)| of Eq. (1) and (32) is undefined
  *     where grad(phi) = 0, which happens where lambda of Eq. (2) is not
  *     small (the centre of a droplet, phi < 1 there); next to such a point
@@ -125,6 +135,7 @@ typedef struct {
   int32_t poisson_iters; /* extra g-only sweeps before every step */
   int32_t mask_f, mask_h, mask_p, mask_n, mask_g; /* MRT rows relaxed with 1/tau */
   int32_t poisson_norm;  /* 1: source weights w_i/(1 - w_0); 0: w_i as printed in Eq. (44) */
+  int32_t side_walls;    /* 0: periodic in x; 1: side walls of Eq. (64) at x = -1/2, nx - 1/2 */
   double rho_v, rho_r;   /* density of the outer (v) phase and ratio l/v, Eq. (60) */
   double eta_v, eta_r;   /* dynamic viscosity and ratio */
   double M_phi, W, zeta; /* Allen-Cahn mobility, interface width, surface tension */
@@ -154,6 +165,7 @@ typedef struct {
   long step;
   double M9i[81], N5i[25];
   int opp9[9], opp5[5];
+  int mirx9[9];  /* direction with c_x reversed */
 } orc_state;
 
 /* Macroscopic quantities at one node, steps 3-7. */
@@ -366,9 +378,12 @@ static inline int wrapx(const orc_state *s, int x) { return (x % s->nx + s->nx) 
 
 enum { GHOST_MIRROR = 0, GHOST_ODD = 1 };
 
-/* Field value at (x, y), y possibly one row outside the domain. */
+/* Field value at (x, y), x or y possibly one step outside the domain. */
 static double field_at(const orc_state *s, const double *f, int ghost, int x, int y) {
-  x = wrapx(s, x);
+  if (s->P.side_walls)
+    x = x < 0 ? 0 : (x >= s->nx ? s->nx - 1 : x); /* mirrored across a side wall */
+  else
+    x = wrapx(s, x);
   if (y >= 0 && y < s->ny) return f[cidx(s, x, y)];
   if (s->P.walls == WALLS_PERIODIC) return f[cidx(s, x, (y % s->ny + s->ny) % s->ny)];
   int yin = y < 0 ? 0 : s->ny - 1;
@@ -653,9 +668,28 @@ static void stream_set(orc_state *s, int set, int q) {
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x)
       for (int i = 0; i < q; ++i) {
-        int sx = wrapx(s, x - cx[i]);
+        int sx = x - cx[i];
         int sy = y - cy[i];
         double v;
+        if (s->P.side_walls && (sx < 0 || sx >= nx)) {
+          const int *opp = q == 9 ? s->opp9 : s->opp5;
+          int my = sy;   /* row of the mirror image of the source */
+          if (s->P.walls == WALLS_PERIODIC) my = (my + ny) % ny;
+          if (set == OF_H && my >= 0 && my < ny) {
+            /* phase field: specular reflection, the population of the mirror
+             * image of the source, direction mirrored in x */
+            s->pop[(set + i) * nc + cidx(s, x, y)] =
+                s->post[(set + s->mirx9[i]) * nc + cidx(s, x, my)];
+          } else {
+            /* u = 0 (and a corner for h): bounce-back of the node's own
+             * opposite population; for the D2Q5 sets (no diagonals) the
+             * same as specular reflection */
+            s->pop[(set + i) * nc + cidx(s, x, y)] =
+                s->post[(set + opp[i]) * nc + cidx(s, x, y)];
+          }
+          continue;
+        }
+        sx = wrapx(s, sx);
         if (sy >= 0 && sy < ny)
           v = s->post[(set + i) * nc + cidx(s, sx, sy)];
         else if (s->P.walls == WALLS_PERIODIC)
@@ -756,8 +790,10 @@ ORC_API orc_state *orc_create(const orc_params *p) {
     return NULL;
   }
   for (int i = 0; i < 9; ++i)
-    for (int j = 0; j < 9; ++j)
+    for (int j = 0; j < 9; ++j) {
       if (CX9[j] == -CX9[i] && CY9[j] == -CY9[i]) s->opp9[i] = j;
+      if (CX9[j] == -CX9[i] && CY9[j] == CY9[i]) s->mirx9[i] = j;
+    }
   for (int i = 0; i < 5; ++i)
     for (int j = 0; j < 5; ++j)
       if (CX5[j] == -CX5[i] && CY5[j] == -CY5[i]) s->opp5[i] = j;

@@ -277,3 +277,98 @@ def test_droplet_case_is_well_conditioned(orc, n_eps, grows):
         assert dphi > 1e-9
     else:
         assert dphi < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Side walls (the other boundaries of Eq. 64: u = 0, zero normal derivative
+# of c+, c- and psi), halfway between lattice columns
+# --------------------------------------------------------------------------
+def test_side_walls_are_invisible_to_x_uniform_states(orc):
+    """A state that does not vary in x (flat interface, charged ions, a
+    potential with structure in y; fluid at rest) feels nothing from walls
+    whose conditions it already meets: the box gives the periodic result
+    exactly (specular reflection of h, zero-flux ions and potential)."""
+    ny, nx = 48, 12
+    y = _rows(ny, nx)
+    phi = 0.5 * (1 + np.tanh(2 * (y - 20.3) / 4.0))
+    psi = 0.9 * (ny - 0.5 - y) / ny + 0.02 * np.sin(y / 5.0)
+    cp = 1.0 + 0.1 * np.cos(y / 7.0)
+    out = []
+    for side in (0, 1):
+        o = orc.Oracle(dict(nx=nx, ny=ny, dpsi=0.9, q=1e-4, side_walls=side, eps_r=2.0,
+                            rho_r=2.0, mu_r=0.5, flow=0))
+        o.init_fields(phi, cp, 1.0, psi)
+        o.step(200)
+        out.append(o.fields())
+    for k in ("phi", "psi", "cp", "cm", "rhoe"):
+        a, b = out[0][k], out[1][k]
+        assert abs(a - b).max() <= 1e-13 * max(abs(a).max(), 1e-30), k
+        assert abs(b - b[:, :1]).max() <= 1e-13 * max(abs(b).max(), 1e-30), k
+
+
+def test_side_walls_keep_the_mirror_symmetry_of_a_centred_droplet(orc):
+    """A noise-free droplet centred between the side walls stays mirror
+    symmetric in x (u_x antisymmetric), and the walls stop the flow: u_x
+    and the normal derivatives vanish across them to the stencil's order."""
+    p = dict(workloads.lattice_params(48, 8.0, nx=40), side_walls=1)
+    o = orc.Oracle(p)
+    o.init_droplet(19.5, 23.5, 8.0, 0.0, 0, presolve=50)
+    o.step(300)
+    f = o.fields()
+    for k, sign in (("phi", 1), ("psi", 1), ("cp", 1), ("cm", 1), ("rhoe", 1), ("uy", 1),
+                    ("p", 1), ("ux", -1)):
+        a = f[k]
+        scale = abs(a).max()
+        assert scale > 0
+        assert abs(a - sign * a[:, ::-1]).max() <= 1e-11 * scale, k
+    # the flow is confined: no net x momentum and small wall-tangent velocity
+    assert abs(f["ux"].sum()) <= 1e-12 * abs(f["ux"]).sum()
+
+
+def test_side_wall_ion_diffusion_follows_the_image_solution(orc):
+    """Zero field, ion-tight electrodes, ions only: a pulse next to a side
+    wall diffuses as the pulse plus its mirror image across the wall (the
+    zero-flux wall at x = -1/2 reflects it), and the content is conserved."""
+    ny, nx, vth, mu = 4, 160, 0.025, 1.0
+    o = orc.Oracle(dict(nx=nx, ny=ny, dpsi=0.0, q=0.0, flow=0, reaction=0, walls=1,
+                        side_walls=1, mu_v=mu, v_th=vth))
+    x = np.ones((ny, 1)) * np.arange(nx, dtype=float)[None, :]
+    s0, x0, T = 4.0, 6.0, 1500
+    D = vth * mu
+
+    def image_sol(var):
+        return np.exp(-(x - x0) ** 2 / (2 * var)) + np.exp(-(x + 1 + x0) ** 2 / (2 * var))
+
+    c_init = 1.0 + image_sol(s0 ** 2)
+    o.init_fields(0.0, c_init, 1.0, 0.0)
+    o.step(T)
+    c = o.fields()["cp"]
+    ref = 1.0 + image_sol(s0 ** 2 + 2 * D * T) * s0 / np.sqrt(s0 ** 2 + 2 * D * T)
+    assert abs(c.sum() / c_init.sum() - 1) < 1e-12
+    dev, dref = c - 1.0, ref - 1.0
+    assert np.linalg.norm(dev - dref) / np.linalg.norm(dref) < 1e-2
+    # a periodic box would have sent half of the pulse to the far edge
+    assert dev[:, -20:].max() < 1e-6 * dev.max()
+
+
+def test_poiseuille_between_side_walls(orc):
+    """u = 0 at the side walls (bounce-back of f): a body force along y in a
+    y-periodic channel between the side walls gives the exact parabola with
+    the walls at x = -1/2 and nx - 1/2 (tau = 0.875, where halfway
+    bounce-back puts the wall exactly there)."""
+    nx, ny, g = 24, 4, 1e-6
+    tau = 0.875
+    nu = (tau - 0.5) / 3.0
+    o = orc.Oracle(dict(nx=nx, ny=ny, walls=2, side_walls=1, dpsi=0.0, q=0.0, reaction=0,
+                        eta_v=nu, rho_v=1.0, force_y=g))
+    o.init_fields(0.0, 1.0, 1.0, 0.0)
+    o.step(20000)
+    uy = o.fields()["uy"][0]
+    xx = np.arange(nx, dtype=float)
+    ref = g / (2 * nu) * (xx + 0.5) * (nx - 0.5 - xx)
+    assert np.abs(uy - ref).max() <= 1e-6 * ref.max()
+    # the cross-flow is a compressibility effect of the scheme (~|u|^2), mirror
+    # antisymmetric across the channel
+    ux = o.fields()["ux"][0]
+    assert np.abs(ux).max() <= 1e-5 * ref.max()
+    assert np.abs(ux + ux[::-1]).max() <= 1e-12 * ref.max()
