@@ -102,7 +102,13 @@ typedef struct {
                               g update per step) */
   int32_t mask_f, mask_h, mask_p, mask_n, mask_g; /* bit k set: MRT row k relaxes with
                               1/tau (Eq. 30, 37, 47, 55); other rows relax with s_free */
-  int32_t reserved;        /* must be 0 */
+  int32_t side_walls;      /* 0: periodic in x; 1: the other boundaries of Eq. (64),
+                              walls halfway at x = -1/2 and x = nx - 1/2 with u = 0
+                              (f bounces back), zero normal derivative of c+, c-
+                              and psi (ion and potential populations bounce back,
+                              zero flux) and of phi (h reflects specularly, a
+                              neutral wall; bounce-back at the corners); the
+                              stencils see the wall column mirrored */
   double rho_v, rho_r;     /* density, outer phase; ratio (Eq. 60) */
   double eta_v, eta_r;     /* dynamic viscosity; tau_f = 1/2 + eta/(rho c_s^2), Eq. (55) */
   double M_phi;            /* phase-field mobility; tau_h = 1/2 + M_phi/c_s^2, Eq. (30) */

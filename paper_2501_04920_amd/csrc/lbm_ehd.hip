@@ -155,6 +155,7 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.ny = p.ny;
   k.pitch = h->pitch;
   k.walls = p.walls;
+  k.side_walls = p.side_walls;
   k.rstride = (uint32_t)(NPOP * h->pitch);
   k.cells = (uint32_t)((long long)p.ny * h->pitch);
   k.pop_bytes = (uint32_t)h->pop_bytes;
@@ -269,30 +270,40 @@ struct Form {
     return LBM_OK;
   }
 
-  template <int NW>
+  template <int NW, bool SW>
   static void launch_nw(const void* descs, const BatchTile* tiles, int ntiles, int flip,
                         hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep_batch<S, R, T0, NW>), dim3(ntiles), dim3(64 * NW), 0, st,
+    hipLaunchKernelGGL((k_sweep_batch<S, R, T0, NW, SW>), dim3(ntiles), dim3(64 * NW), 0, st,
                        static_cast<const Desc*>(descs), tiles, ntiles / 8, flip);
   }
 
-  // One fused sweep over the tiles `tiles` (a multiple of 8) of the members
-  // described by `descs`; `flip` = 1 swaps every member's buffers.
-  static lbm_status launch_tiles(int waves, const void* descs, const BatchTile* tiles,
-                                 int ntiles, int flip, hipStream_t st) {
+  template <bool SW>
+  static void launch_sw(int waves, const void* descs, const BatchTile* tiles, int ntiles,
+                        int flip, hipStream_t st) {
     switch (waves) {
-      case 8: launch_nw<8>(descs, tiles, ntiles, flip, st); break;
-      case 4: launch_nw<4>(descs, tiles, ntiles, flip, st); break;
-      case 2: launch_nw<2>(descs, tiles, ntiles, flip, st); break;
-      default: launch_nw<1>(descs, tiles, ntiles, flip, st); break;
+      case 8: launch_nw<8, SW>(descs, tiles, ntiles, flip, st); break;
+      case 4: launch_nw<4, SW>(descs, tiles, ntiles, flip, st); break;
+      case 2: launch_nw<2, SW>(descs, tiles, ntiles, flip, st); break;
+      default: launch_nw<1, SW>(descs, tiles, ntiles, flip, st); break;
     }
+  }
+
+  // One fused sweep over the tiles `tiles` (a multiple of 8) of the members
+  // described by `descs`; `flip` = 1 swaps every member's buffers; `side`:
+  // some member has side walls.
+  static lbm_status launch_tiles(int waves, bool side, const void* descs,
+                                 const BatchTile* tiles, int ntiles, int flip, hipStream_t st) {
+    if (side)
+      launch_sw<true>(waves, descs, tiles, ntiles, flip, st);
+    else
+      launch_sw<false>(waves, descs, tiles, ntiles, flip, st);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
 
   static lbm_status sweep(lbm_ehd* h) {
-    lbm_status st = launch_tiles(h->waves, h->d_desc, h->d_tiles, h->ntiles,
-                                 h->cur ^ h->desc_cur, h->stream);
+    lbm_status st = launch_tiles(h->waves, h->P.side_walls != 0, h->d_desc, h->d_tiles,
+                                 h->ntiles, h->cur ^ h->desc_cur, h->stream);
     if (st) return st;
     h->cur = 1 - h->cur;
     return LBM_OK;
@@ -536,7 +547,9 @@ struct BatchForm {
   }
 
   static lbm_status launch(lbm_ehd_batch* b, int flip) {
-    return F::launch_tiles(b->waves, b->d_desc, b->d_tiles, b->ntiles, flip, b->stream);
+    bool side = false;
+    for (const lbm_ehd* m : b->sims) side = side || m->P.side_walls != 0;
+    return F::launch_tiles(b->waves, side, b->d_desc, b->d_tiles, b->ntiles, flip, b->stream);
   }
 };
 
@@ -573,7 +586,7 @@ lbm_status validate(const lbm_ehd_params* p) {
   if ((double)NPOP * (p->ny + 2) * pitch_of(p->nx) * elem_size(p->precision) >= 4294967296.0)
     return fail(LBM_EINVAL, "grid too large: a population buffer must stay below 4 GiB");
   if (p->walls < 0 || p->walls > 2) return fail(LBM_EINVAL, "unknown walls");
-  if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+  if (p->side_walls != 0 && p->side_walls != 1) return fail(LBM_EINVAL, "side_walls: 0 or 1");
   if (p->poisson_iters < 0) return fail(LBM_EINVAL, "poisson_iters < 0");
   if (!finite_all({p->rho_v, p->rho_r, p->eta_v, p->eta_r, p->M_phi, p->W, p->zeta, p->theta,
                    p->dpsi, p->eps_v, p->eps_r, p->mu_v, p->mu_r, p->m_ratio, p->v_th, p->c0,
@@ -832,6 +845,8 @@ lbm_status lbm_ehd_init_droplet(lbm_ehd* h, double xc, double yc, double radius,
   if (h->P.walls != LBM_PERIODIC && radius > 0 &&
       (yc - radius < -0.5 || yc + radius > h->P.ny - 0.5))
     return fail(LBM_EINVAL, "droplet crosses an electrode");
+  if (h->P.side_walls && radius > 0 && (xc - radius < -0.5 || xc + radius > h->P.nx - 0.5))
+    return fail(LBM_EINVAL, "droplet crosses a side wall");
   InitSpec sp;
   std::memset(&sp, 0, sizeof sp);
   sp.xc = xc;

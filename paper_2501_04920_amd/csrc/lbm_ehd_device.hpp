@@ -91,6 +91,7 @@ struct KP {
   R iofs[10];        // 16-bit storage: offsets of the p and n lines (see above)
   R force_x, force_y;
   R sc[5], isc[5];   // binary16 storage: power-of-two scale of each set (f h p n g)
+  int side_walls;    // 1: walls at x = -1/2 and nx - 1/2 (else periodic in x)
 };
 
 // Population set of plane q: 0 f, 1 h, 2 p, 3 n, 4 g.

@@ -17,6 +17,8 @@
 // the two halo columns and of the rows just outside a band are read twice.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_ehd_device.hpp"
 
 namespace lbm {
@@ -27,60 +29,98 @@ __device__ inline const T* elem(const T* base, uint32_t e) {
 }
 
 // Offsets of the pull sources of node (xc, yy): the population arriving along
-// c_i comes from (xc - c_ix, yy - c_iy).
+// c_i comes from (xc - c_ix, yy - c_iy).  With side walls (halfway at
+// x = -1/2 and nx - 1/2) the populations whose source lies beyond a wall are
+// read elsewhere (see the pulls): lw / rw mark the wall columns.  ColsP is
+// the form without side walls, whose flags are compile-time false (the
+// plain sweep: the flags alone, even when constant, change how the 16-bit
+// sweeps are scheduled, and cost 1.6 % on MI355X at 2048^2).
 struct Cols {
   int c, m, p;  // xc, xc - 1, xc + 1 (periodic in x)
+  bool lw, rw;  // xc is next to the left / right side wall
 };
+struct ColsP {
+  int c, m, p;
+  static constexpr bool lw = false, rw = false;
+};
+template <bool SW>
+using ColsOf = typename std::conditional<SW, Cols, ColsP>::type;
 
-__device__ inline Cols cols_of(int xc, int nx) {
-  Cols k;
+template <bool SW>
+__device__ inline ColsOf<SW> cols_for(int xc, int nx, int side) {
+  ColsOf<SW> k;
   k.c = xc;
   k.m = xc == 0 ? nx - 1 : xc - 1;
   k.p = xc == nx - 1 ? 0 : xc + 1;
+  if constexpr (SW) {
+    k.lw = side && xc == 0;
+    k.rw = side && xc == nx - 1;
+  }
   return k;
 }
 
-template <class S, class R>
-__device__ inline void pull9(const PopView<S, R>& P, int q0, Cols k, int yy, R x[9]) {
+__device__ inline Cols cols_of(int xc, int nx, int side) { return cols_for<true>(xc, nx, side); }
+
+// The f set of node (xc, yy).  At a side wall f bounces back (u = 0): the
+// populations coming through the wall are the node's own opposite ones,
+// read through the same line's load by shifting the offset to the other
+// line (lines are pitch apart within a row).
+template <class S, class R, class K>
+__device__ inline void pull9(const PopView<S, R>& P, int q0, K k, int yy, R x[9]) {
   const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
-  x[0] = P.at(q0 + 0, r0 + k.c);
-  x[1] = P.at(q0 + 1, r0 + k.m);
+  const uint32_t pc = P.kp->pitch, own = r0 + k.c;
+  x[0] = P.at(q0 + 0, own);
+  x[1] = P.at(q0 + 1, k.lw ? own + 2 * pc : r0 + k.m);  // <- 3
   x[2] = P.at(q0 + 2, rm + k.c);
-  x[3] = P.at(q0 + 3, r0 + k.p);
+  x[3] = P.at(q0 + 3, k.rw ? own - 2 * pc : r0 + k.p);  // <- 1
   x[4] = P.at(q0 + 4, rp + k.c);
-  x[5] = P.at(q0 + 5, rm + k.m);
-  x[6] = P.at(q0 + 6, rm + k.p);
-  x[7] = P.at(q0 + 7, rp + k.p);
-  x[8] = P.at(q0 + 8, rp + k.m);
+  x[5] = P.at(q0 + 5, k.lw ? own + 2 * pc : rm + k.m);  // <- 7
+  x[6] = P.at(q0 + 6, k.rw ? own + 2 * pc : rm + k.p);  // <- 8
+  x[7] = P.at(q0 + 7, k.rw ? own - 2 * pc : rp + k.p);  // <- 5
+  x[8] = P.at(q0 + 8, k.lw ? own - 2 * pc : rp + k.m);  // <- 6
 }
 
 // Directions 1..4 of a D2Q5 set (the rest population is pulled separately).
-template <class S, class R>
-__device__ inline void pull4(const PopView<S, R>& P, int q0, Cols k, int yy, R x[4]) {
+// At a side wall the ion and potential populations bounce back (zero flux;
+// on D2Q5 the same as specular reflection).
+template <class S, class R, class K>
+__device__ inline void pull4(const PopView<S, R>& P, int q0, K k, int yy, R x[4]) {
   const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
-  x[0] = P.at(q0 + 1, r0 + k.m);
+  const uint32_t pc = P.kp->pitch, own = r0 + k.c;
+  x[0] = P.at(q0 + 1, k.lw ? own + 2 * pc : r0 + k.m);  // <- 3
   x[1] = P.at(q0 + 2, rm + k.c);
-  x[2] = P.at(q0 + 3, r0 + k.p);
+  x[2] = P.at(q0 + 3, k.rw ? own - 2 * pc : r0 + k.p);  // <- 1
   x[3] = P.at(q0 + 4, rp + k.c);
 }
 
 // The h set of node (xc, yy): h0 from the rest plane (in place; also
-// returned in its own wider type), h1..h8 pulled.
-template <class S, class R, class T0>
-__device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x, Cols k,
+// returned in its own wider type), h1..h8 pulled.  At a side wall h reflects
+// specularly: the population coming through the wall is that of the mirror
+// image of its source, i.e. the wall column's population in the x-mirrored
+// direction one row up or down; where that row lies beyond an electrode (a
+// corner), h bounces back.
+template <class S, class R, class T0, class K>
+__device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x, K k,
                               int yy, R x[9], T0* h0 = nullptr) {
   const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
-  const T0 r = *elem(h0x, (uint32_t)yy * P.kp->pitch + k.c);
+  const uint32_t pc = P.kp->pitch, own = r0 + k.c;
+  const bool ywalls = P.kp->walls != WALL_PERIODIC;
+  const bool bot = ywalls && yy == 0, top = ywalls && yy == P.kp->ny - 1;
+  const T0 r = *elem(h0x, (uint32_t)yy * pc + k.c);
   if (h0) *h0 = r;
   x[0] = (R)r;
-  x[1] = P.at(QH + 1, r0 + k.m);
+  x[1] = P.at(QH + 1, k.lw ? own + 2 * pc : r0 + k.m);                    // <- 3
   x[2] = P.at(QH + 2, rm + k.c);
-  x[3] = P.at(QH + 3, r0 + k.p);
+  x[3] = P.at(QH + 3, k.rw ? own - 2 * pc : r0 + k.p);                    // <- 1
   x[4] = P.at(QH + 4, rp + k.c);
-  x[5] = P.at(QH + 5, rm + k.m);
-  x[6] = P.at(QH + 6, rm + k.p);
-  x[7] = P.at(QH + 7, rp + k.p);
-  x[8] = P.at(QH + 8, rp + k.m);
+  x[5] = P.at(QH + 5, !k.lw ? rm + k.m : (bot ? own + 2 * pc : rm + k.c + pc));  // <- 6 / 7
+  // at the right wall the load is based at line 5: in the bottom ghost row
+  // (row 0) of a y-periodic box the specular source rm + c - pc of line 6
+  // would be a negative offset, which the buffer's range check reads as zero
+  x[6] = !k.rw ? P.at(QH + 6, rm + k.p)
+               : P.at(QH + 5, bot ? own + 3 * pc : rm + k.c);  // <- 5 / 8
+  x[7] = P.at(QH + 7, !k.rw ? rp + k.p : (top ? own - 2 * pc : rp + k.c + pc));  // <- 8 / 5
+  x[8] = P.at(QH + 8, !k.lw ? rp + k.m : (top ? own - 2 * pc : rp + k.c - pc));  // <- 7 / 6
   if (LocalH<S>::value) {
     const R t = P.at(QH, r0 + k.c);  // the node's own reference phase
 #pragma unroll
@@ -102,8 +142,8 @@ __device__ inline double ion_rest(const PopView<S, R>& P, const T0* __restrict__
 // Directions 1..4 of the g set of node (xc, yy), as deviations from the
 // uncharged steady state (with 16-bit storage: stored relative to psi'~ / 6
 // of the node itself, see LocalG).
-template <class S, class R>
-__device__ inline void pull_g(const PopView<S, R>& P, Cols k, int yy, R x[4]) {
+template <class S, class R, class K>
+__device__ inline void pull_g(const PopView<S, R>& P, K k, int yy, R x[4]) {
   pull4(P, QG, k, yy, x);
   if (LocalG<S>::value) {
     const R t = P.at(QRG, P.row(yy + 1) + k.c) * R(1.0 / 6.0);
@@ -171,12 +211,12 @@ __device__ inline void ghost_row(const RP phc[3], const R psc[3], RP phg[3], R p
 // node x is pulled at step t+1 from ghost column x - c_ix; in a periodic box
 // the ghost row receives the populations leaving the opposite edge.  Values
 // are deviations (the wall rules below are written for them).
-template <class S, class R>
+template <class S, class R, class K>
 struct Ghosts {
   const PopView<S, R>& D;
   const KP<R>& kp;
   int y;
-  Cols k;
+  K k;
   __device__ inline uint32_t top() const { return D.row(kp.ny + 1); }
   // D2Q9 set starting at plane q0 (f or h): bounce-back at walls
   __device__ inline void set9(int q0, const R x[9]) const {
@@ -211,11 +251,11 @@ struct Ghosts {
 // moving population is stored relative to psi'~ / 6 of the node it arrives
 // at (the node itself for the populations an electrode sends back), g0
 // relative to -2/3 psi'~ of the node, and the node stores its own psi'~.
-template <class S, class R>
-__device__ inline void store_g(const PopView<S, R>& D, const KP<R>& kp, int x, int y, Cols k,
+template <class S, class R, class K>
+__device__ inline void store_g(const PopView<S, R>& D, const KP<R>& kp, int x, int y, K k,
                                const R g[5], const R psi9[9]) {
   const uint32_t o = D.row(y + 1) + x;
-  const Ghosts<S, R> G{D, kp, y, k};
+  const Ghosts<S, R, K> G{D, kp, y, k};
   const bool edge = y == 0 || y == kp.ny - 1;
   if (!LocalG<S>::value) {
 #pragma unroll
@@ -227,6 +267,8 @@ __device__ inline void store_g(const PopView<S, R>& D, const KP<R>& kp, int x, i
   R t[5];
 #pragma unroll
   for (int i = 0; i < 5; ++i) t[i] = D.stored(QRG, psi9[i]);
+  if (k.lw) t[3] = t[0];
+  if (k.rw) t[1] = t[0];
   if (kp.walls != WALL_PERIODIC) {
     if (y == 0) t[4] = t[0];
     if (y == kp.ny - 1) t[2] = t[0];
@@ -253,11 +295,11 @@ __device__ inline void store_g(const PopView<S, R>& D, const KP<R>& kp, int x, i
 // -x*_opp + 2 wbar (c_w - c0), i.e. -x*_opp - c0/3 for c_w = 0 and
 // -x*_opp + c'/3 for c_w = c(node); for g the linear potential meets the
 // electrode potentials exactly, so the rule is -x*_opp.
-template <class S, class R, class T0, class HG>
+template <class S, class R, class T0, class HG, class K>
 __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev,
                                    const T0* __restrict__ h0src, T0* __restrict__ h0dst,
                                    const KP<R>& kp, const KP<typename WorkOf<S>::type>& kpw, int x,
-                                   int y, Cols k, const typename WorkOf<S>::type phi9[9],
+                                   int y, K k, const typename WorkOf<S>::type phi9[9],
                                    const R psi9[9], R f[9], R p[5], R n[5], R g0,
                                    const HG& hg) {
   // Working type W: the wide type (FP64 with FP32 storage) for the
@@ -298,7 +340,7 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
 
   const uint32_t o = D.row(y + 1) + x;
   const bool edge = y == 0 || y == kp.ny - 1;
-  const Ghosts<S, R> G{D, kp, y, k};
+  const Ghosts<S, R, K> G{D, kp, y, k};
   const bool ins = kp.walls == WALL_INSULATING;
   const R third = R(1) / R(3);
 
@@ -380,7 +422,12 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     if (LocalH<S>::value) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) t[i] = D.stored(QH, (R)phi9[i]);
-      if (kp.walls != WALL_PERIODIC) {
+      // a population sent through a side wall arrives, reflected, at the
+      // mirror image of its destination: the node itself, or its neighbour
+      // up or down
+      if (k.lw) { t[3] = t[0]; t[6] = t[2]; t[7] = t[4]; }
+      if (k.rw) { t[1] = t[0]; t[5] = t[2]; t[8] = t[4]; }
+      if (kp.walls != WALL_PERIODIC) {  // (after the side walls: corners)
         if (y == 0) t[4] = t[7] = t[8] = t[0];
         if (y == kp.ny - 1) t[2] = t[5] = t[6] = t[0];
       }
@@ -427,7 +474,7 @@ struct SweepLds {
 
 // One tile of the fused sweep: columns [x0, x0 + 64 NW) of rows [y0, yend)
 // of one simulation, walked down row by row by the whole workgroup.
-template <class S, class R, class T0, int NW>
+template <class S, class R, class T0, int NW, bool SW>
 __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>& L,
                                   const S* __restrict__ src, S* __restrict__ dst,
                                   R* __restrict__ jprev, const T0* __restrict__ h0x,
@@ -441,7 +488,9 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
   const int lane = threadIdx.x;
   const bool valid = lane < w;
   const int x = x0 + (valid ? lane : 0);
-  const Cols k = cols_of(x, nx);
+  // side walls are compiled in only where a member of the launch has them
+  const bool side = SW && kp.side_walls;
+  const ColsOf<SW> k = cols_for<SW>(x, nx, kp.side_walls);
   const bool periodic = kp.walls == WALL_PERIODIC;
   // Non-temporal population loads pay off where a strip's row of one line
   // spans at least 1 KB.  In narrower strips the column-shifted pulls at the
@@ -456,9 +505,11 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
   const PopView<S, R> Pc{make_rsrc(src, kp.pop_bytes), &kp, false};
   const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp};
 
-  // halo column handled by lanes 0 (left) and 1 (right)
-  const int xh = lane == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + w == nx ? 0 : x0 + w);
-  const Cols kh = cols_of(xh, nx);
+  // halo column handled by lanes 0 (left) and 1 (right); beyond a side wall
+  // the stencils see the mirror image, i.e. the wall column itself
+  const int xh = lane == 0 ? (x0 == 0 ? (side ? 0 : nx - 1) : x0 - 1)
+                           : (x0 + w == nx ? (side ? nx - 1 : 0) : x0 + w);
+  const ColsOf<SW> kh = cols_for<SW>(xh, nx, kp.side_walls);
   const int kcol = lane == 0 ? 0 : w + 1;
 
   auto slot = [&](int yy) { return (yy - y0 + 1) % RING; };
@@ -596,13 +647,15 @@ struct BatchTile {
 // a contiguous run of them, so that the workgroups running together on an
 // XCD hold neighbouring strips of the same rows and the cache lines they
 // share are fetched from HBM once.  `flip` = 1 swaps every member's buffers
-// (odd steps of a captured block).
+// (odd steps of a captured block).  SW compiles in the side walls, which
+// the launch needs when any member has them: their per-lane address and
+// reference selects cost 2-6 % on MI355X at 2048^2 where no member does.
 //
 // At least four waves per SIMD are asked of the register allocator (two with
 // FP64 arithmetic): with the FP64 working type of FP32 storage it otherwise
 // settles on 144 VGPRs (three waves); four waves with a few spilled
 // registers are up to 18 % faster on MI355X at 2048^2.
-template <class S, class R, class T0, int NW>
+template <class S, class R, class T0, int NW, bool SW>
 __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
     const SimDesc<S, R, T0>* __restrict__ sims,
@@ -613,8 +666,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
   const SimDesc<S, R, T0>& sd = sims[tl.sim];
   const int a = (sd.cur + flip) & 1;
   const S* src = sd.pop[a];
-  sweep_tile<S, R, T0, NW>(L, src, sd.pop[1 - a], sd.jprev,
-                           sd.h0[a], sd.h0[1 - a], sd.kp, sd.kpw, tl.x0, tl.y0, tl.yend);
+  sweep_tile<S, R, T0, NW, SW>(L, src, sd.pop[1 - a], sd.jprev, sd.h0[a], sd.h0[1 - a], sd.kp,
+                               sd.kpw, tl.x0, tl.y0, tl.yend);
 }
 
 // ---------------------------------------------------------------------------
@@ -629,7 +682,7 @@ __global__ void k_moments(const S* __restrict__ src, const S* __restrict__ gsrc,
   if (x >= kp.nx) return;
   const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp};
   const PopView<S, R> Pg{make_rsrc(gsrc, kp.pop_bytes), &kp};
-  const Cols k = cols_of(x, kp.nx);
+  const Cols k = cols_of(x, kp.nx, kp.side_walls);
   R h[9], g4[4], t4[4];
   pull_h(Ph, h0x, k, y, h);
   pull_g(Pg, k, y, g4);
@@ -648,8 +701,9 @@ template <class R>
 __device__ inline void hood(const R* __restrict__ mom, const KP<R>& kp, int x, int y,
                             R phi9[9], R psi9[9]) {
   const long long np = (long long)kp.nx * kp.ny;
-  const Cols k = cols_of(x, kp.nx);
-  const int cols[3] = {k.m, k.c, k.p};
+  const Cols k = cols_of(x, kp.nx, kp.side_walls);
+  // beyond a side wall: the mirror image, the wall column itself
+  const int cols[3] = {k.lw ? k.c : k.m, k.c, k.rw ? k.c : k.p};
   R ph[3][3], ps[3][3];  // [row: down, centre, up][col]
   const bool periodic = kp.walls == WALL_PERIODIC;
   for (int r = 0; r < 3; ++r) {
@@ -678,7 +732,7 @@ __global__ void k_fields(const S* __restrict__ src, const T0* __restrict__ h0x,
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
   const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp};
-  const Cols k = cols_of(x, kp.nx);
+  const Cols k = cols_of(x, kp.nx, kp.side_walls);
   R phi9[9], psi9[9], f[9], t4[4];
   hood(mom, kp, x, y, phi9, psi9);
   pull9(Ph, QF, k, y, f);
@@ -712,7 +766,7 @@ __global__ void k_poisson(const S* __restrict__ gsrc, S* __restrict__ gdst,
   if (x >= kp.nx) return;
   const PopView<S, R> Pg{make_rsrc(gsrc, kp.pop_bytes), &kp};
   const PopView<S, R> DG{make_rsrc(gdst, kp.pop_bytes), &kp};
-  const Cols k = cols_of(x, kp.nx);
+  const Cols k = cols_of(x, kp.nx, kp.side_walls);
   R phi9[9], psi9[9], g4[4];
   hood(mom, kp, x, y, phi9, psi9);
   const long long np = (long long)kp.nx * kp.ny;
@@ -785,12 +839,30 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
                         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const double w5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
   const PopView<S, R> D{make_rsrc(dst, kp.pop_bytes), &kp};
+  // Behind a side wall the pull reads the wall column instead (see the
+  // pulls): f, the ions and g in the opposite direction at the node itself;
+  // h in the x-mirrored direction one row up or down (at a corner, the
+  // opposite direction at the node itself).
+  const int opp9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  const int mir9[9] = {0, 3, 2, 1, 4, 6, 5, 8, 7};
+  const int opp5[5] = {0, 3, 4, 1, 2};
   auto put = [&](int q, int i, double v) {
-    int xs = x - cx[i];
-    xs = xs < 0 ? xs + kp.nx : (xs >= kp.nx ? xs - kp.nx : xs);
-    const int ys = y - cy[i];
-    const double ref = plane_ref(q, ys, kp.ny, kp.walls, sp.c0, sp.dpsi, sp.a_g);
-    D.put(q, D.row(ys + 1) + xs, (R)(v - ref));
+    const int xs = x - cx[i], ys = y - cy[i];
+    int qt = q, xt = xs, yt = ys;
+    if (kp.side_walls && (xs < 0 || xs >= kp.nx)) {
+      const bool corner = kp.walls != WALL_PERIODIC && (ys < 0 || ys >= kp.ny);
+      xt = x;
+      if (q >= QH && q < QP && !corner) {
+        qt = q - i + mir9[i];
+      } else {
+        qt = q - i + (q < QP ? opp9[i] : opp5[i]);
+        yt = y;
+      }
+    } else {
+      xt = xs < 0 ? xs + kp.nx : (xs >= kp.nx ? xs - kp.nx : xs);
+    }
+    const double ref = plane_ref(qt, yt, kp.ny, kp.walls, sp.c0, sp.dpsi, sp.a_g);
+    D.put(qt, D.row(yt + 1) + xt, (R)(v - ref));
   };
   // h: the rest population (which does not move) takes phi minus what the
   // eight stored moving populations hold, so that phi is exact from the start
@@ -851,7 +923,7 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
   double acc[NSUM] = {0, 0, 0, 0, 0, 0, 0};
   const double c0 = (double)kp.c0;
   for (int x = t; x < kp.nx; x += 256) {
-    const Cols k = cols_of(x, kp.nx);
+    const Cols k = cols_of(x, kp.nx, kp.side_walls);
     R h[9], t4[4], g4[4];
     pull_h(Ph, h0x, k, y, h);
     const double h0 = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
@@ -910,7 +982,7 @@ __global__ __launch_bounds__(256) void k_psi_change_rows(const S* __restrict__ g
       kp.walls == WALL_PERIODIC ? 0.0 : (double)kp.dpsi * (kp.ny - 0.5 - y) / kp.ny;
   double dd = 0.0, nn = 0.0;
   for (int x = t; x < kp.nx; x += 256) {
-    const Cols k = cols_of(x, kp.nx);
+    const Cols k = cols_of(x, kp.nx, kp.side_walls);
     R gn[4], go[4];
     pull_g(Pn, k, y, gn);
     pull_g(Po, k, y, go);

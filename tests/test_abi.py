@@ -52,7 +52,7 @@ def test_defaults_and_bytes():
 
 @pytest.mark.parametrize("bad", [dict(nx=1), dict(v_th=0.0), dict(eta_v=0.0), dict(M_phi=0.0),
                                  dict(theta=-0.1), dict(precision=7), dict(walls=5),
-                                 dict(W=float("nan")), dict(s_free=2.0), dict(reserved=1), dict(n_eps=-1.0),
+                                 dict(W=float("nan")), dict(s_free=2.0), dict(side_walls=2), dict(n_eps=-1.0),
                                  dict(nx=20000, ny=20000)])
 def test_invalid_parameters_rejected(bad):
     p = lbm_ehd.make_params(**bad)

@@ -94,6 +94,10 @@ VARIANTS = {
     "no_ion_force": dict(ion_force=0),
     "s_free": dict(s_free=1.3),
     "body_force": dict(force_x=2e-6, force_y=-1e-6),
+    "side_walls": dict(side_walls=1),
+    "side_walls_insulating": dict(side_walls=1, walls=1),
+    "side_walls_periodic_y": dict(side_walls=1, walls=2, force_y=1e-6),
+    "side_walls_poisson_iters": dict(side_walls=1, poisson_iters=2, eps_r=4.0),
 }
 
 
@@ -114,7 +118,8 @@ def test_ragged_grid_variants_fp64(name):
 # or are sent back), Poisson sub-iterations (the g set and its reference line
 # ping-pong between the buffers) and the literal Poisson form.  Measured
 # after 300 steps: fields <= 2e-3 (FP16), <= 4e-2 (BF16).
-VARIANTS_16 = ("base", "periodic", "insulating", "poisson_iters", "literal_poisson")
+VARIANTS_16 = ("base", "periodic", "insulating", "poisson_iters", "literal_poisson",
+               "side_walls", "side_walls_periodic_y")
 
 
 @pytest.mark.parametrize("precision,bar", [("fp16", 1e-2), ("bf16", 0.1)])
