@@ -133,11 +133,26 @@ def test_ragged_grid_variants_16bit(name, precision, bar):
     assert max(errs.values()) <= bar
 
 
+@pytest.mark.parametrize("name", ["side_walls", "side_walls_periodic_y"])
+def test_ragged_side_walls_fp32(name):
+    """FP32 storage (FP64 working type) with side walls against the oracle:
+    the FP32 bar."""
+    p, d = _ragged(**VARIANTS[name])
+    sim = run_gpu(p, "fp32", droplet=d, presolve=20, steps=300)
+    o = run_oracle(p, droplet=d, presolve=20, steps=300)
+    errs = rel_l2(sim.fields(), o.fields(), p, ALL10)
+    _report("ragged fp32 %s" % name, errs)
+    assert max(errs.values()) <= 2e-5
+
+
+@pytest.mark.parametrize("side_walls", [0, 1])
 @pytest.mark.parametrize("shape", [(2, 8), (3, 17), (65, 9), (128, 3)])
-def test_small_and_odd_shapes_fp64(shape):
+def test_small_and_odd_shapes_fp64(shape, side_walls):
+    """Grids narrower than a strip or a band; with side walls, nx = 2 makes
+    every node a wall node."""
     nx, ny = shape
     p = workloads.lattice_params(ny, 2.0, nx=nx)
-    p.update(walls=2 if ny < 8 else 0)
+    p.update(walls=2 if ny < 8 else 0, side_walls=side_walls)
     y = np.arange(ny)[:, None] * np.ones((1, nx))
     x = np.ones((ny, 1)) * np.arange(nx)[None, :]
     rng = np.random.default_rng(nx * 1000 + ny)
@@ -154,7 +169,7 @@ def test_small_and_odd_shapes_fp64(shape):
     sim = run_gpu(p, "fp64", fields=fields, steps=20)
     o = run_oracle(p, fields=fields, steps=20)
     errs = rel_l2(sim.fields(), o.fields(), p, ALL10)
-    _report("shape %s" % (shape,), errs)
+    _report("shape %s side walls %d" % (shape, side_walls), errs)
     assert max(errs.values()) <= 1e-10
 
 
@@ -266,13 +281,16 @@ def test_bitwise_repeatable_fp32():
         assert np.array_equal(a[k], b[k]), k
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
-def test_launch_shape_does_not_change_results(precision):
+@pytest.mark.parametrize("precision,side_walls",
+                         [("fp64", 0), ("fp32", 0), ("fp16", 0), ("fp64", 1), ("fp16", 1)])
+def test_launch_shape_does_not_change_results(precision, side_walls):
     """Every node runs the same arithmetic whatever the strip width (waves
     per workgroup) and band height: results are bitwise equal.  300 x 70
-    leaves a ragged last strip for every width and a short last band."""
+    leaves a ragged last strip for every width and a short last band; with
+    side walls the wall columns fall in the first and the ragged last strip."""
     p = workloads.lattice_params(70, 12.0)
     p["nx"] = 300
+    p["side_walls"] = side_walls
     d = dict(xc=149.5, yc=34.5, radius=12.0, noise=1e-3, seed=3)
     ref = None
     for waves, rows in ((1, 1), (1, 7), (2, 16), (4, 3), (4, 32), (8, 5), (8, 70)):
@@ -302,10 +320,11 @@ def test_set_launch_rejects_bad_shapes():
     sim.close()
 
 
+@pytest.mark.parametrize("side_walls", [0, 1])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "bf16"])
-def test_sum_phi_conserved(precision):
+def test_sum_phi_conserved(precision, side_walls):
     cfg = workloads.config1()
-    p, d = cfg["params"], cfg["droplet"]
+    p, d = dict(cfg["params"], side_walls=side_walls), cfg["droplet"]
     sim = run_gpu(p, precision, droplet=d, presolve=0, steps=0)
     s0 = sim.diagnostics()["sum_phi"]
     sim.step(1000)
