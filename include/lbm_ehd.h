@@ -109,6 +109,11 @@ typedef struct {
                               zero flux) and of phi (h reflects specularly, a
                               neutral wall; bounce-back at the corners); the
                               stencils see the wall column mirrored */
+  int32_t local_field;     /* 0: E = -grad psi by the stencil of Eq. (59);
+                              1: E = sum_i c_i g_i / (c_s^2 tau_g) from the node's
+                              incoming g (Eq. 50), and grad psi = -E wherever it
+                              enters (forces, reaction, ion drift, Poisson source) */
+  int32_t reserved;        /* must be 0 */
   double rho_v, rho_r;     /* density, outer phase; ratio (Eq. 60) */
   double eta_v, eta_r;     /* dynamic viscosity; tau_f = 1/2 + eta/(rho c_s^2), Eq. (55) */
   double M_phi;            /* phase-field mobility; tau_h = 1/2 + M_phi/c_s^2, Eq. (30) */

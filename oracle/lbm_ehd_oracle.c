@@ -136,6 +136,7 @@ typedef struct {
   int32_t mask_f, mask_h, mask_p, mask_n, mask_g; /* MRT rows relaxed with 1/tau */
   int32_t poisson_norm;  /* 1: source weights w_i/(1 - w_0); 0: w_i as printed in Eq. (44) */
   int32_t side_walls;    /* 0: periodic in x; 1: side walls of Eq. (64) at x = -1/2, nx - 1/2 */
+  int32_t local_field;   /* 0: E = -grad psi by Eq. (59); 1: E from the g populations, Eq. (50) */
   double rho_v, rho_r;   /* density of the outer (v) phase and ratio l/v, Eq. (60) */
   double eta_v, eta_r;   /* dynamic viscosity and ratio */
   double M_phi, W, zeta; /* Allen-Cahn mobility, interface width, surface tension */
@@ -423,6 +424,19 @@ static void compute_moments(orc_state *s) {
   }
 }
 
+/* Eq. (50): the field from the first moment of the node's incoming g,
+ * E = sum_i c_i g_i / (c_s^2 tau_g). */
+static void field_from_g(const orc_state *s, size_t c, double tau_g, double *E) {
+  double ex = 0.0, ey = 0.0;
+  for (int i = 1; i < 5; ++i) {
+    double g = s->pop[(OF_G + i) * s->nc + c];
+    ex += CX5[i] * g;
+    ey += CY5[i] * g;
+  }
+  E[0] = ex / (CS2 * tau_g);
+  E[1] = ey / (CS2 * tau_g);
+}
+
 /* Steps 3-7 at one node.  Needs the moment fields of the current time. */
 static void macro_at(const orc_state *s, int x, int y, macro_t *m) {
   const orc_params *P = &s->P;
@@ -453,11 +467,18 @@ static void macro_at(const orc_state *s, int x, int y, macro_t *m) {
   m->delta = P->q * (m->mup + m->mum) / m->eps;
   m->gamma = P->gamma_v * P->eps_v / m->eps;
 
-  /* Finite differences, Eq. (59); E = -grad psi, Eq. (9). */
+  /* Finite differences, Eq. (59); E = -grad psi, Eq. (9), or with the local
+   * field E from Eq. (50) and grad psi = -E wherever it appears. */
   stencil(s, s->phi, GHOST_MIRROR, x, y, m->gphi, &m->lphi);
-  stencil(s, s->psi, GHOST_ODD, x, y, m->gpsi, NULL);
-  m->E[0] = -m->gpsi[0];
-  m->E[1] = -m->gpsi[1];
+  if (P->local_field) {
+    field_from_g(s, c, m->tau_g, m->E);
+    m->gpsi[0] = -m->E[0];
+    m->gpsi[1] = -m->E[1];
+  } else {
+    stencil(s, s->psi, GHOST_ODD, x, y, m->gpsi, NULL);
+    m->E[0] = -m->gpsi[0];
+    m->E[1] = -m->gpsi[1];
+  }
 
   /* Ions, Eq. (5), (6), (8), (41)-(43). */
   double Emag = sqrt(m->E[0] * m->E[0] + m->E[1] * m->E[1]);
@@ -614,7 +635,14 @@ static void poisson_collide_at(orc_state *s, int x, int y, mrt_memo *mm) {
   double rhoe = P->q * (s->sp[c] - s->sn[c]);
   double gphi[2], gpsi[2];
   stencil(s, s->phi, GHOST_MIRROR, x, y, gphi, NULL);
-  stencil(s, s->psi, GHOST_ODD, x, y, gpsi, NULL);
+  if (P->local_field) {
+    double E[2];
+    field_from_g(s, c, tau_g, E);
+    gpsi[0] = -E[0];
+    gpsi[1] = -E[1];
+  } else {
+    stencil(s, s->psi, GHOST_ODD, x, y, gpsi, NULL);
+  }
   double geps[2] = {(eps_l - P->eps_v) * gphi[0], (eps_l - P->eps_v) * gphi[1]};
   double Spsi = P->poisson_form ? (rhoe + geps[0] * gpsi[0] + geps[1] * gpsi[1]) / eps
                                 : rhoe / eps;

@@ -118,6 +118,10 @@ std::vector<BatchTile> tile_list(const std::vector<const lbm_ehd*>& sims, int wa
   return tl;
 }
 
+// The extended sweep (side walls, local field of Eq. 50) is compiled
+// separately from the plain one.
+bool needs_ext(const lbm_ehd_params& p) { return p.side_walls != 0 || p.local_field != 0; }
+
 // Offset of the +y / -y g references from psi_lin / 6: the steady
 // post-collision g of the uncharged potential carries (1/s_2 - 1) G / 6 in
 // the +y population and minus that in the -y one, with s_2 the rate of the
@@ -156,6 +160,7 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.pitch = h->pitch;
   k.walls = p.walls;
   k.side_walls = p.side_walls;
+  k.local_field = p.local_field;
   k.rstride = (uint32_t)(NPOP * h->pitch);
   k.cells = (uint32_t)((long long)p.ny * h->pitch);
   k.pop_bytes = (uint32_t)h->pop_bytes;
@@ -270,39 +275,39 @@ struct Form {
     return LBM_OK;
   }
 
-  template <int NW, bool SW>
+  template <int NW, bool EXT>
   static void launch_nw(const void* descs, const BatchTile* tiles, int ntiles, int flip,
                         hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep_batch<S, R, T0, NW, SW>), dim3(ntiles), dim3(64 * NW), 0, st,
+    hipLaunchKernelGGL((k_sweep_batch<S, R, T0, NW, EXT>), dim3(ntiles), dim3(64 * NW), 0, st,
                        static_cast<const Desc*>(descs), tiles, ntiles / 8, flip);
   }
 
-  template <bool SW>
-  static void launch_sw(int waves, const void* descs, const BatchTile* tiles, int ntiles,
+  template <bool EXT>
+  static void launch_ext(int waves, const void* descs, const BatchTile* tiles, int ntiles,
                         int flip, hipStream_t st) {
     switch (waves) {
-      case 8: launch_nw<8, SW>(descs, tiles, ntiles, flip, st); break;
-      case 4: launch_nw<4, SW>(descs, tiles, ntiles, flip, st); break;
-      case 2: launch_nw<2, SW>(descs, tiles, ntiles, flip, st); break;
-      default: launch_nw<1, SW>(descs, tiles, ntiles, flip, st); break;
+      case 8: launch_nw<8, EXT>(descs, tiles, ntiles, flip, st); break;
+      case 4: launch_nw<4, EXT>(descs, tiles, ntiles, flip, st); break;
+      case 2: launch_nw<2, EXT>(descs, tiles, ntiles, flip, st); break;
+      default: launch_nw<1, EXT>(descs, tiles, ntiles, flip, st); break;
     }
   }
 
   // One fused sweep over the tiles `tiles` (a multiple of 8) of the members
-  // described by `descs`; `flip` = 1 swaps every member's buffers; `side`:
-  // some member has side walls.
-  static lbm_status launch_tiles(int waves, bool side, const void* descs,
+  // described by `descs`; `flip` = 1 swaps every member's buffers; `ext`:
+  // some member has side walls or the local field (the extended sweep).
+  static lbm_status launch_tiles(int waves, bool ext, const void* descs,
                                  const BatchTile* tiles, int ntiles, int flip, hipStream_t st) {
-    if (side)
-      launch_sw<true>(waves, descs, tiles, ntiles, flip, st);
+    if (ext)
+      launch_ext<true>(waves, descs, tiles, ntiles, flip, st);
     else
-      launch_sw<false>(waves, descs, tiles, ntiles, flip, st);
+      launch_ext<false>(waves, descs, tiles, ntiles, flip, st);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
 
   static lbm_status sweep(lbm_ehd* h) {
-    lbm_status st = launch_tiles(h->waves, h->P.side_walls != 0, h->d_desc, h->d_tiles,
+    lbm_status st = launch_tiles(h->waves, needs_ext(h->P), h->d_desc, h->d_tiles,
                                  h->ntiles, h->cur ^ h->desc_cur, h->stream);
     if (st) return st;
     h->cur = 1 - h->cur;
@@ -547,9 +552,9 @@ struct BatchForm {
   }
 
   static lbm_status launch(lbm_ehd_batch* b, int flip) {
-    bool side = false;
-    for (const lbm_ehd* m : b->sims) side = side || m->P.side_walls != 0;
-    return F::launch_tiles(b->waves, side, b->d_desc, b->d_tiles, b->ntiles, flip, b->stream);
+    bool ext = false;
+    for (const lbm_ehd* m : b->sims) ext = ext || needs_ext(m->P);
+    return F::launch_tiles(b->waves, ext, b->d_desc, b->d_tiles, b->ntiles, flip, b->stream);
   }
 };
 
@@ -587,6 +592,8 @@ lbm_status validate(const lbm_ehd_params* p) {
     return fail(LBM_EINVAL, "grid too large: a population buffer must stay below 4 GiB");
   if (p->walls < 0 || p->walls > 2) return fail(LBM_EINVAL, "unknown walls");
   if (p->side_walls != 0 && p->side_walls != 1) return fail(LBM_EINVAL, "side_walls: 0 or 1");
+  if (p->local_field != 0 && p->local_field != 1) return fail(LBM_EINVAL, "local_field: 0 or 1");
+  if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
   if (p->poisson_iters < 0) return fail(LBM_EINVAL, "poisson_iters < 0");
   if (!finite_all({p->rho_v, p->rho_r, p->eta_v, p->eta_r, p->M_phi, p->W, p->zeta, p->theta,
                    p->dpsi, p->eps_v, p->eps_r, p->mu_v, p->mu_r, p->m_ratio, p->v_th, p->c0,

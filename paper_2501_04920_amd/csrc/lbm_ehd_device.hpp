@@ -92,6 +92,7 @@ struct KP {
   R force_x, force_y;
   R sc[5], isc[5];   // binary16 storage: power-of-two scale of each set (f h p n g)
   int side_walls;    // 1: walls at x = -1/2 and nx - 1/2 (else periodic in x)
+  int local_field;   // 1: E from the g populations (Eq. 50), else -grad psi (Eq. 59)
 };
 
 // Population set of plane q: 0 f, 1 h, 2 p, 3 n, 4 g.
@@ -478,13 +479,25 @@ __device__ inline R reaction_rate(R delta, R c0, R c0sq, R Fm1, R Pd, R Qd) {
   return R(2) * delta * Cn * recip(B + sqrt(B * B + R(4) * AC));
 }
 
+// Eq. (50): the field from the first moment of the node's incoming g,
+// E = sum_i c_i g_i / (c_s^2 tau_g), from its deviations g1'..g4'.  The
+// references of the uncharged field carry psi_lin(y -+ 1) / 6 -+ a_g in the
+// +-y populations, i.e. a y moment of 2 a_g - psi_slope / 3 (the applied
+// field exactly, dpsi / ny, when that moment relaxes with 1 / tau_g).
+template <class W, class R>
+__device__ inline void field_from_g(const R g4[4], const KP<W>& kp, W E[2]) {
+  const W s = W(3) * kp.inv_tau_g;
+  E[0] = s * ((W)g4[0] - (W)g4[2]);
+  E[1] = s * (((W)g4[1] - (W)g4[3]) + (W(2) * kp.a_g - kp.psi_slope * (W(1) / W(3))));
+}
+
 // phi9 comes in the type RP of the phase ring (FP64 with FP32 storage): the
 // chemical potential of Eq. (13) is the small difference of a double-well
 // term and kappa lap(phi), each ~50 times larger near equilibrium, so phi',
 // its stencils and mu_phi are formed in RP and rounded to R afterwards.
 template <class R, class RP>
 __device__ inline void macro(const RP phi9[9], const R psi9[9], R Pd, R Qd, const R f[9],
-                             const KP<R>& kp, Macro<R>& m) {
+                             const KP<R>& kp, Macro<R>& m, const R* Eloc = nullptr) {
   m.phid = (R)phi9[0];
   const RP phiw = RP(0.5) + phi9[0];
   const R phi = (R)phiw;
@@ -502,16 +515,24 @@ __device__ inline void macro(const RP phi9[9], const R psi9[9], R Pd, R Qd, cons
   m.itau_f = recip(R(0.5) + R(3) * eta * inv_rho);
   m.itau_p = recip(R(0.5) + kp.three_vth * m.mup);
   m.itau_n = recip(R(0.5) + kp.three_vth * m.mum);
-  // Eq. (59), (9); the linear part of psi contributes its exact gradient
+  // Eq. (59), (9); the linear part of psi contributes its exact gradient.
+  // With the local field (Eq. 50, given in Eloc) grad psi = -E throughout.
   RP gph[2], lph;
   grad_lap<RP>(phi9, gph, &lph);
   m.gphi[0] = (R)gph[0];
   m.gphi[1] = (R)gph[1];
   m.lphi = (R)lph;
-  grad_lap<R>(psi9, m.gpsi, nullptr);
-  m.gpsi[1] += kp.psi_slope;
-  m.E[0] = -m.gpsi[0];
-  m.E[1] = -m.gpsi[1];
+  if (Eloc) {
+    m.E[0] = Eloc[0];
+    m.E[1] = Eloc[1];
+    m.gpsi[0] = -Eloc[0];
+    m.gpsi[1] = -Eloc[1];
+  } else {
+    grad_lap<R>(psi9, m.gpsi, nullptr);
+    m.gpsi[1] += kp.psi_slope;
+    m.E[0] = -m.gpsi[0];
+    m.E[1] = -m.gpsi[1];
+  }
   // Eq. (5), (6), (41)-(43), (8)
   const R E2 = m.E[0] * m.E[0] + m.E[1] * m.E[1];
   if (kp.reaction) {

@@ -32,9 +32,9 @@ __device__ inline const T* elem(const T* base, uint32_t e) {
 // c_i comes from (xc - c_ix, yy - c_iy).  With side walls (halfway at
 // x = -1/2 and nx - 1/2) the populations whose source lies beyond a wall are
 // read elsewhere (see the pulls): lw / rw mark the wall columns.  ColsP is
-// the form without side walls, whose flags are compile-time false (the
-// plain sweep: the flags alone, even when constant, change how the 16-bit
-// sweeps are scheduled, and cost 1.6 % on MI355X at 2048^2).
+// the form of the plain sweep (no side walls, no local field), whose flags
+// are compile-time false: the flags alone, even when constant, change how
+// the 16-bit sweeps are scheduled, and cost 1.6 % on MI355X at 2048^2.
 struct Cols {
   int c, m, p;  // xc, xc - 1, xc + 1 (periodic in x)
   bool lw, rw;  // xc is next to the left / right side wall
@@ -43,16 +43,16 @@ struct ColsP {
   int c, m, p;
   static constexpr bool lw = false, rw = false;
 };
-template <bool SW>
-using ColsOf = typename std::conditional<SW, Cols, ColsP>::type;
+template <bool EXT>
+using ColsOf = typename std::conditional<EXT, Cols, ColsP>::type;
 
-template <bool SW>
-__device__ inline ColsOf<SW> cols_for(int xc, int nx, int side) {
-  ColsOf<SW> k;
+template <bool EXT>
+__device__ inline ColsOf<EXT> cols_for(int xc, int nx, int side) {
+  ColsOf<EXT> k;
   k.c = xc;
   k.m = xc == 0 ? nx - 1 : xc - 1;
   k.p = xc == nx - 1 ? 0 : xc + 1;
-  if constexpr (SW) {
+  if constexpr (EXT) {
     k.lw = side && xc == 0;
     k.rw = side && xc == nx - 1;
   }
@@ -335,8 +335,19 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   }
   const W Pd = pw[0] + pw[1] + pw[2] + pw[3] + pw[4];
   const W Qd = nw[0] + nw[1] + nw[2] + nw[3] + nw[4];
+  // the local field of Eq. (50), from the node's incoming g (extended sweep)
+  W Eg[2];
+  const W* Eloc = nullptr;
+  if constexpr (std::is_same<K, Cols>::value) {
+    if (kp.local_field) {
+      R gl[4];
+      hg.g4(gl);
+      field_from_g(gl, kpw, Eg);
+      Eloc = Eg;
+    }
+  }
   Macro<W> m;
-  macro(phi9, ps9, Pd, Qd, fw, kpw, m);
+  macro(phi9, ps9, Pd, Qd, fw, kpw, m, Eloc);
 
   const uint32_t o = D.row(y + 1) + x;
   const bool edge = y == 0 || y == kp.ny - 1;
@@ -474,7 +485,7 @@ struct SweepLds {
 
 // One tile of the fused sweep: columns [x0, x0 + 64 NW) of rows [y0, yend)
 // of one simulation, walked down row by row by the whole workgroup.
-template <class S, class R, class T0, int NW, bool SW>
+template <class S, class R, class T0, int NW, bool EXT>
 __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>& L,
                                   const S* __restrict__ src, S* __restrict__ dst,
                                   R* __restrict__ jprev, const T0* __restrict__ h0x,
@@ -488,9 +499,10 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
   const int lane = threadIdx.x;
   const bool valid = lane < w;
   const int x = x0 + (valid ? lane : 0);
-  // side walls are compiled in only where a member of the launch has them
-  const bool side = SW && kp.side_walls;
-  const ColsOf<SW> k = cols_for<SW>(x, nx, kp.side_walls);
+  // side walls and the local field are compiled in only where a member of
+  // the launch has them
+  const bool side = EXT && kp.side_walls;
+  const ColsOf<EXT> k = cols_for<EXT>(x, nx, kp.side_walls);
   const bool periodic = kp.walls == WALL_PERIODIC;
   // Non-temporal population loads pay off where a strip's row of one line
   // spans at least 1 KB.  In narrower strips the column-shifted pulls at the
@@ -509,7 +521,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
   // the stencils see the mirror image, i.e. the wall column itself
   const int xh = lane == 0 ? (x0 == 0 ? (side ? 0 : nx - 1) : x0 - 1)
                            : (x0 + w == nx ? (side ? nx - 1 : 0) : x0 + w);
-  const ColsOf<SW> kh = cols_for<SW>(xh, nx, kp.side_walls);
+  const ColsOf<EXT> kh = cols_for<EXT>(xh, nx, kp.side_walls);
   const int kcol = lane == 0 ? 0 : w + 1;
 
   auto slot = [&](int yy) { return (yy - y0 + 1) % RING; };
@@ -647,15 +659,16 @@ struct BatchTile {
 // a contiguous run of them, so that the workgroups running together on an
 // XCD hold neighbouring strips of the same rows and the cache lines they
 // share are fetched from HBM once.  `flip` = 1 swaps every member's buffers
-// (odd steps of a captured block).  SW compiles in the side walls, which
-// the launch needs when any member has them: their per-lane address and
-// reference selects cost 2-6 % on MI355X at 2048^2 where no member does.
+// (odd steps of a captured block).  EXT compiles in the side walls and the
+// local field of Eq. (50), which the launch needs when any member has one:
+// the per-lane address and reference selects of the side walls cost 2-6 %
+// on MI355X at 2048^2 where no member needs them.
 //
 // At least four waves per SIMD are asked of the register allocator (two with
 // FP64 arithmetic): with the FP64 working type of FP32 storage it otherwise
 // settles on 144 VGPRs (three waves); four waves with a few spilled
 // registers are up to 18 % faster on MI355X at 2048^2.
-template <class S, class R, class T0, int NW, bool SW>
+template <class S, class R, class T0, int NW, bool EXT>
 __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
     const SimDesc<S, R, T0>* __restrict__ sims,
@@ -666,7 +679,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
   const SimDesc<S, R, T0>& sd = sims[tl.sim];
   const int a = (sd.cur + flip) & 1;
   const S* src = sd.pop[a];
-  sweep_tile<S, R, T0, NW, SW>(L, src, sd.pop[1 - a], sd.jprev, sd.h0[a], sd.h0[1 - a], sd.kp,
+  sweep_tile<S, R, T0, NW, EXT>(L, src, sd.pop[1 - a], sd.jprev, sd.h0[a], sd.h0[1 - a], sd.kp,
                                sd.kpw, tl.x0, tl.y0, tl.yend);
 }
 
@@ -740,8 +753,16 @@ __global__ void k_fields(const S* __restrict__ src, const T0* __restrict__ h0x,
   const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
   pull4(Ph, QN, k, y, t4);
   const R Qd = (R)ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  R Eg[2];
+  const R* Eloc = nullptr;
+  if (kp.local_field) {
+    R g4[4];
+    pull_g(Ph, k, y, g4);
+    field_from_g(g4, kp, Eg);
+    Eloc = Eg;
+  }
   Macro<R> m;
-  macro(phi9, psi9, Pd, Qd, f, kp, m);
+  macro(phi9, psi9, Pd, Qd, f, kp, m, Eloc);
   const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
   const double psi_lin =
       kp.walls == WALL_PERIODIC ? 0.0 : (double)kp.dpsi * (kp.ny - 0.5 - y) / kp.ny;
@@ -776,8 +797,15 @@ __global__ void k_poisson(const S* __restrict__ gsrc, S* __restrict__ gdst,
   const R eps = (R(0.5) + phi9[0]) * kp.deps + kp.eps_v;
   R gphi[2], gpsi[2];
   grad_lap<R>(phi9, gphi, nullptr);
-  grad_lap<R>(psi9, gpsi, nullptr);
-  gpsi[1] += kp.psi_slope;
+  if (kp.local_field) {
+    R E[2];
+    field_from_g(g4, kp, E);
+    gpsi[0] = -E[0];
+    gpsi[1] = -E[1];
+  } else {
+    grad_lap<R>(psi9, gpsi, nullptr);
+    gpsi[1] += kp.psi_slope;
+  }
   const R geps[2] = {kp.deps * gphi[0], kp.deps * gphi[1]};
   collide_g(g, psi9[0], poisson_source<R>(mom[2 * np + c], recip(eps), geps, gpsi, kp), kp);
   store_g(DG, kp, x, y, k, g, psi9);

@@ -39,6 +39,7 @@ class lbm_ehd_params(ctypes.Structure):
         ("mask_f", ctypes.c_int32), ("mask_h", ctypes.c_int32),
         ("mask_p", ctypes.c_int32), ("mask_n", ctypes.c_int32),
         ("mask_g", ctypes.c_int32), ("side_walls", ctypes.c_int32),
+        ("local_field", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("rho_v", ctypes.c_double), ("rho_r", ctypes.c_double),
         ("eta_v", ctypes.c_double), ("eta_r", ctypes.c_double),
         ("M_phi", ctypes.c_double), ("W", ctypes.c_double), ("zeta", ctypes.c_double),

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     # int32 block then doubles, no padding surprises
-    assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 16 * 4 + 22 * 8
+    assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 18 * 4 + 22 * 8
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_diag) == 11 * 8
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_request_info) == 8 + 4 + 4 + 2 * 8 + 3 * 8 + 8 + 11 * 8
 
@@ -52,7 +52,8 @@ def test_defaults_and_bytes():
 
 @pytest.mark.parametrize("bad", [dict(nx=1), dict(v_th=0.0), dict(eta_v=0.0), dict(M_phi=0.0),
                                  dict(theta=-0.1), dict(precision=7), dict(walls=5),
-                                 dict(W=float("nan")), dict(s_free=2.0), dict(side_walls=2), dict(n_eps=-1.0),
+                                 dict(W=float("nan")), dict(s_free=2.0), dict(side_walls=2), dict(local_field=2), dict(reserved=1),
+                                 dict(n_eps=-1.0),
                                  dict(nx=20000, ny=20000)])
 def test_invalid_parameters_rejected(bad):
     p = lbm_ehd.make_params(**bad)
@@ -104,3 +105,26 @@ def test_footprint_covers_state_and_scratch():
     # state, then FP64 moment and field planes for readback
     assert fp >= 2 * pop + aux + 300 * 200 * (3 * 8 + 10 * 8)
     assert fp < 2 * pop + aux + 300 * 200 * (3 * 8 + 10 * 8) + (1 << 20)
+
+
+def test_enclosure_workload_groups():
+    """The enclosure recipe gives back the Sec. 6 groups: Ca_E = 0.241,
+    W0 = 5.6893, beta = 0.5643 at d = 2 mm and 1 kV, radius d / 4, W = Cn d;
+    a gap and a voltage move W0 as d^2 / dpsi with Ca_E held."""
+    c = workloads.enclosure(256)
+    p, d = c["params"], c["droplet"]
+    n = p["ny"]
+    assert (p["nx"], p["side_walls"], p["poisson_form"], p["walls"]) == (256, 1, 0, 0)
+    assert d["radius"] == 64.0 and math.isclose(p["W"], 0.015 * 256)
+    assert math.isclose(p["eps_v"] * p["dpsi"] ** 2 * d["radius"] / (p["zeta"] * n * n), 0.241,
+                        rel_tol=1e-12)
+    assert math.isclose(p["q"] * p["c0"] * n * n / (p["eps_v"] * p["dpsi"]), 5.6893,
+                        rel_tol=1e-12)
+    assert math.isclose(math.sqrt(p["dpsi"] * p["gamma_v"] / n * 5.6893), 0.5643, rel_tol=1e-12)
+    assert (p["rho_r"], p["eps_r"], p["mu_r"], p["m_ratio"]) == (2.0, 0.5, 5.0, 1.0)
+    w = workloads.enclosure(256, d_mm=1.0, kv=0.5)
+    assert math.isclose(w["groups"]["W0"], 5.6893 * 0.25 / 0.5, rel_tol=1e-12)
+    assert math.isclose(w["groups"]["Ca_E"], 0.241)
+    # the library accepts the case (the droplet clears the side walls)
+    pop, aux = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(**p))
+    assert pop > 0

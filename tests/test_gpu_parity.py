@@ -98,6 +98,10 @@ VARIANTS = {
     "side_walls_insulating": dict(side_walls=1, walls=1),
     "side_walls_periodic_y": dict(side_walls=1, walls=2, force_y=1e-6),
     "side_walls_poisson_iters": dict(side_walls=1, poisson_iters=2, eps_r=4.0),
+    "local_field": dict(local_field=1),
+    "local_field_literal_poisson": dict(local_field=1, poisson_form=0, eps_r=4.0),
+    "local_field_periodic": dict(local_field=1, walls=2, poisson_iters=1),
+    "local_field_side_walls": dict(local_field=1, side_walls=1, walls=1),
 }
 
 
@@ -119,7 +123,7 @@ def test_ragged_grid_variants_fp64(name):
 # ping-pong between the buffers) and the literal Poisson form.  Measured
 # after 300 steps: fields <= 2e-3 (FP16), <= 4e-2 (BF16).
 VARIANTS_16 = ("base", "periodic", "insulating", "poisson_iters", "literal_poisson",
-               "side_walls", "side_walls_periodic_y")
+               "side_walls", "side_walls_periodic_y", "local_field", "local_field_periodic")
 
 
 @pytest.mark.parametrize("precision,bar", [("fp16", 1e-2), ("bf16", 0.1)])
@@ -133,10 +137,11 @@ def test_ragged_grid_variants_16bit(name, precision, bar):
     assert max(errs.values()) <= bar
 
 
-@pytest.mark.parametrize("name", ["side_walls", "side_walls_periodic_y"])
-def test_ragged_side_walls_fp32(name):
-    """FP32 storage (FP64 working type) with side walls against the oracle:
-    the FP32 bar."""
+@pytest.mark.parametrize("name", ["side_walls", "side_walls_periodic_y", "local_field",
+                                  "local_field_side_walls"])
+def test_ragged_extended_sweep_fp32(name):
+    """FP32 storage (FP64 working type) on the extended sweep (side walls,
+    the local field of Eq. 50) against the oracle: the FP32 bar."""
     p, d = _ragged(**VARIANTS[name])
     sim = run_gpu(p, "fp32", droplet=d, presolve=20, steps=300)
     o = run_oracle(p, droplet=d, presolve=20, steps=300)

@@ -108,6 +108,34 @@ def test_linear_potential_between_uncharged_electrodes(orc):
     assert abs(f["Ey"] - dpsi / ny).max() < 1e-12 and abs(f["Ex"]).max() < 1e-14
 
 
+def test_local_field_of_eq50(orc):
+    """Eq. (50): E from the first moment of the node's g.  It is exact on the
+    linear potential between uncharged electrodes, and on the uniform-charge
+    parabola, whose field is linear in y, wall rows included; there the
+    stencil of Eq. (59) is only first order (its mirrored ghost misses the
+    curvature), which the same state shows."""
+    ny, nx, dpsi = 32, 4, 0.7
+    o = orc.Oracle(dict(nx=nx, ny=ny, dpsi=dpsi, q=0.0, flow=0, local_field=1))
+    o.init_fields(0.0, 1.0, 1.0, 0.0)
+    o.presolve(12000)
+    f = o.fields()
+    assert abs(f["Ey"] - dpsi / ny).max() < 1e-13 and abs(f["Ex"]).max() < 1e-15
+    ny, dpsi, a, q = 32, 0.5, 0.1, 1e-3
+    rho = 2 * q * a
+    y = np.arange(ny)
+    exact = dpsi / ny - rho / 2 * (ny - 1 - 2 * y)     # -psi' of the parabola (eps = 1)
+    err = {}
+    for lf in (1, 0):
+        o = orc.Oracle(dict(nx=nx, ny=ny, dpsi=dpsi, q=q, flow=0, local_field=lf))
+        o.init_fields(0.0, 1.0 + a, 1.0 - a, 0.0)
+        o.presolve(30000)
+        f = o.fields()
+        assert abs(f["Ex"]).max() < 1e-15
+        err[lf] = abs(f["Ey"][:, 0] - exact) / abs(exact).max()
+    assert err[1].max() < 1e-12
+    assert err[0][4:-4].max() < 1e-12 and err[0].max() > 1e-3
+
+
 @pytest.mark.parametrize("norm", [1, 0])
 def test_uniform_charge_gives_parabola(orc, norm):
     """psi'' = -rho_e / eps for a uniform charge; with the source weights as
