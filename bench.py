@@ -225,6 +225,73 @@ def bench_batched(args):
     print(json.dumps(line), flush=True)
 
 
+ENCLOSURE_STUDY = (
+    [("eps_r", e) for e in (0.5, 1.0, 2.0, 5.0, 10.0, 50.0)]
+    + [("mu_r", m) for m in (0.25, 0.5, 1.0, 2.0, 10.0)]
+    + [("d_mm", 0.5), ("d_mm", 1.0), ("kv", 0.5), ("kv", 0.25)])
+
+
+def bench_enclosure(args):
+    """The paper's parameter study of Sec. 6 as one batched job: the enclosure
+    (256^2, side walls, Sec. 6 defaults) at each point of an eps_r scan, a
+    mu_r scan and four conduction numbers W0 (gap d and voltage), advanced to
+    the steady droplet (160 000 steps) in one launch per step: study solves
+    per hour and the steady deformation factor of every point."""
+    import torch
+
+    from paper_2501_04920_amd import lbm_ehd, workloads
+
+    cases = [workloads.enclosure(args.enclosure_n, **{k: v}) for k, v in ENCLOSURE_STUDY]
+    steps = args.study_steps or cases[0]["steps"]
+    sims = []
+    t_init = time.perf_counter()
+    for c in cases:
+        p, d = c["params"], c["droplet"]
+        s = lbm_ehd.Simulation(dict(p, precision=args.precision), device="cuda:0")
+        s.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"],
+                       presolve=c["presolve"])
+        sims.append(s)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t_init
+    b = lbm_ehd.Batch(sims)
+    t0 = time.perf_counter()
+    waves, rows, taken = b.autotune(10)
+    left, done = steps - taken, taken
+    while left > 0:
+        k = min(left, 40000)
+        b.run(k)
+        b.synchronize()
+        left -= k
+        done += k
+        print("enclosure study: %d of %d steps (%.1f s)" % (done, steps, time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    cells = sum(c["params"]["nx"] * c["params"]["ny"] for c in cases)
+    D = [s.diagnostics()["D"] for s in sims]
+    bad = sum(s.diagnostics()["nonfinite"] for s in sims)
+    b.close()
+    for s in sims:
+        s.close()
+    line = {
+        "metric": "sweep solves/hr", "value": round(len(cases) * 3600.0 / wall, 1),
+        "unit": "solves/hr", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(wall / steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp32f64": "f64", "fp16": "f32",
+                  "bf16": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "enclosure-study-%d-points-%d" % (len(cases), args.enclosure_n),
+                   "cells": cells, "storage": args.precision, "waves": waves,
+                   "tile_rows": rows, "autotune_steps": taken,
+                   "presolve_sweeps": cases[0]["presolve"]},
+        "aggregate_glups": round(cells * steps / wall / 1e9, 3),
+        "init_and_presolve_s": round(t_init, 2),
+        "steady_D": {"%s=%g" % kv: round(x, 5) for kv, x in zip(ENCLOSURE_STUDY, D)},
+        "nonfinite": int(bad),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def _serve_trace(trace, budget, block):
     """Replay a trace in real time through the request server; returns
     per-request (latency s, cells x steps) and the makespan."""
@@ -336,8 +403,13 @@ def main():
     ap.add_argument("--copy-width", type=int, default=4, choices=[4, 16])
     ap.add_argument("--summarize-pmc", nargs=4, metavar="CSV",
                     help="sweep FETCH, sweep WRITE, copy FETCH, copy WRITE counter files")
-    ap.add_argument("--form", default="single", choices=["single", "batched", "serving"],
-                    help="single simulation (default), batched sweep or request server")
+    ap.add_argument("--form", default="single",
+                    choices=["single", "batched", "serving", "enclosure"],
+                    help="single simulation (default), batched sweep, request server, or "
+                         "the paper's enclosure parameter study as one batch")
+    ap.add_argument("--enclosure-n", type=int, default=256)
+    ap.add_argument("--study-steps", type=int, default=0,
+                    help="steps of the enclosure study (0: to the steady droplet, 160 000)")
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=10000)
     ap.add_argument("--seq-steps", type=int, default=100)
@@ -366,6 +438,9 @@ def main():
         return
     if args.form == "serving":
         bench_serving(args)
+        return
+    if args.form == "enclosure":
+        bench_enclosure(args)
         return
 
     import torch

@@ -3,10 +3,11 @@
 Runs only the CPU oracle (``oracle/``) on the 512 x 512 droplet cases (radius
 80, W = 4; eps_r in {0.5, 2} x mu_r in {0.5, 2} x Ca_E in {0.25, 1}) for
 20 000 steps, on the 512 x 512, W = 5 restriction of the 2048 x 2048 case,
-and on the three smallest members of the 64-droplet batched sweep (10 000
-steps), and stores per case:
-  - the deformation factor D (Eq. 63) every 500 steps,
-  - the L2 norms of rho_e and |u| every 500 steps,
+on the three smallest members of the 64-droplet batched sweep (10 000
+steps), and on the paper's enclosure at 256 x 256 (Sec. 6 defaults, 160 000
+steps to the steady droplet), and stores per case:
+  - the deformation factor D (Eq. 63) every 500 steps (4000 for the enclosure),
+  - the L2 norms of rho_e and |u| at the same steps,
   - phi, psi, c+, c-, rho_e, u_x, u_y, p on every 8th row and column at the end.
 Usage: python tests/golden/make_oracle_refs.py [case-name ...]
 Each 512 x 512 case takes ~15 min on 8 cores, a batch member ~1 min.
@@ -37,6 +38,8 @@ def cases():
     out[r["name"]] = r
     for m in smallest_batch_members():
         out[m["name"]] = m
+    e = workloads.enclosure(256)
+    out[e["name"]] = dict(e, every=4000)
     return out
 
 
@@ -49,12 +52,12 @@ def run(case):
     p, d = case["params"], case["droplet"]
     o = oracle.Oracle(p)
     o.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"], presolve=case["presolve"])
-    steps = case["steps"]
+    steps, every = case["steps"], case.get("every", EVERY)
     t, D, rn, un = [], [], [], []
     t0 = time.time()
-    for k in range(0, steps + 1, EVERY):
+    for k in range(0, steps + 1, every):
         if k:
-            o.step(EVERY)
+            o.step(every)
         f = o.fields()
         t.append(k)
         D.append(oracle.deformation(f["phi"])[0])

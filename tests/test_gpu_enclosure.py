@@ -1,0 +1,102 @@
+"""The paper's own workload (Sec. 6, Fig. 3): a droplet of radius d / 4 in a
+closed square enclosure, electrodes at the bottom and top, side walls, at
+256 x 256 (radius 64, W = Cn d = 3.84), with the Sec. 6 defaults.
+
+* GPU against the CPU oracle at this shape: every field after 1000 steps
+  (FP64 within 1e-10, FP32 within 2e-5), with the printed Poisson source of
+  Eq. 44 (the workload's) and with the variable-eps source of Eq. 7;
+* the long run to the steady droplet (160 000 steps) against the stored
+  oracle reference, per storage form;
+* the trends of the steady deformation that Sec. 6 reports.
+"""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_common import rel_l2, run_gpu, run_oracle  # noqa: E402
+from test_gpu_long import _errors, _ref, _run  # noqa: E402
+
+from paper_2501_04920_amd import lbm_ehd, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+ALL10 = ("phi", "psi", "cp", "cm", "rhoe", "ux", "uy", "p", "Ex", "Ey")
+
+
+@pytest.mark.parametrize("poisson_form", [0, 1])
+def test_enclosure_against_oracle(poisson_form):
+    case = workloads.enclosure(256, poisson_form=poisson_form)
+    p, d = case["params"], case["droplet"]
+    o = run_oracle(p, droplet=d, presolve=2000, steps=1000).fields()
+    for precision, bar in (("fp64", 1e-10), ("fp32", 2e-5)):
+        sim = run_gpu(p, precision, droplet=d, presolve=2000, steps=1000)
+        errs = rel_l2(sim.fields(), o, p, ALL10)
+        sim.close()
+        print("%s %s: %s" % (case["name"], precision,
+                             " ".join("%s=%.2e" % kv for kv in errs.items())), flush=True)
+        assert max(errs.values()) <= bar, precision
+
+
+# After 160 000 steps (the steady droplet): D absolute, the norms of rho_e and
+# |u| and the subsampled end fields rel-L2.
+LONG_BAR = {
+    "fp64": dict(D=1e-10, rhoe_l2=1e-10, u_l2=1e-10, phi=1e-10, psi=1e-10, cp=1e-10,
+                 cm=1e-10, rhoe=1e-10, ux=1e-10, uy=1e-10, p=1e-10),
+    "fp32": dict(D=1e-5, rhoe_l2=2e-5, u_l2=2e-5, phi=2e-5, psi=2e-5, cp=2e-5, cm=2e-5,
+                 rhoe=2e-5, ux=2e-5, uy=2e-5, p=2e-5),
+    "fp16": dict(D=1e-3),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_enclosure_steady_droplet_against_oracle(precision):
+    case = workloads.enclosure(256)
+    ref = _ref(case["name"])
+    e = _errors(case, ref, *_run(case, precision, ref))
+    for k, bar in LONG_BAR[precision].items():
+        assert e[k] <= bar, (k, e[k], bar)
+
+
+# Points of the parameter study of Sec. 6 (FP32, 160 000 steps).  Measured
+# steady D: default +0.048; W0 = 0.36, 1.42, 22.8: +0.0085, +0.025, +0.060;
+# mu_r = 0.5, 1: -0.0115, +0.0003; eps_r = 50: -0.024.
+TREND_POINTS = {
+    "default": {},
+    "W0=0.36": dict(d_mm=0.5),
+    "W0=1.42": dict(d_mm=1.0),
+    "W0=22.8": dict(kv=0.25),
+    "mu_r=0.5": dict(mu_r=0.5),
+    "mu_r=1": dict(mu_r=1.0),
+    "eps_r=50": dict(eps_r=50.0),
+}
+
+
+def test_enclosure_trends_of_sec6():
+    """Sec. 6: prolate at the defaults; D grows with the conduction number W0
+    and is close to zero below W0 = 1; oblate at mu_r = 0.5, nearly
+    undeformed at mu_r = 1, prolate at mu_r = 5; oblate at eps_r = 50.
+    All points run as one batch."""
+    sims = {}
+    for name, kw in TREND_POINTS.items():
+        case = workloads.enclosure(256, **kw)
+        d = case["droplet"]
+        sim = lbm_ehd.Simulation(dict(case["params"], precision="fp32"), device="cuda:0")
+        sim.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"],
+                         presolve=case["presolve"])
+        sims[name] = sim
+    b = lbm_ehd.Batch(list(sims.values()))
+    b.run(workloads.enclosure(256)["steps"])
+    b.synchronize()
+    D = {k: s.diagnostics()["D"] for k, s in sims.items()}
+    b.close()
+    for s in sims.values():
+        s.close()
+    print("enclosure steady D: " + " ".join("%s %+.4f" % kv for kv in D.items()), flush=True)
+    assert D["default"] > 0.03
+    assert D["W0=0.36"] < D["W0=1.42"] < D["default"] < D["W0=22.8"]
+    assert D["W0=0.36"] < 0.015
+    assert D["mu_r=0.5"] < -0.005
+    assert abs(D["mu_r=1"]) < 0.005
+    assert D["eps_r=50"] < -0.01
