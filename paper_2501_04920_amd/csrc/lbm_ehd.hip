@@ -96,13 +96,20 @@ struct lbm_ehd {
 
 namespace {
 
+// The extended sweep (side walls, local field of Eq. 50) is compiled
+// separately from the plain one.
+bool needs_ext(const lbm_ehd_params& p) { return p.side_walls != 0 || p.local_field != 0; }
+
 // Tile list of a set of simulations: larger ones first, each band by band
 // across its strips of 64 * waves columns, padded with empty tiles to a
 // multiple of 8 (the sweep gives each XCD one contiguous run of tiles).
+// `form` -1 takes every simulation (and never returns an empty list); 0 and
+// 1 take only those on the plain or on the extended sweep (possibly none).
 std::vector<BatchTile> tile_list(const std::vector<const lbm_ehd*>& sims, int waves,
-                                 int tile_rows) {
-  std::vector<int> order(sims.size());
-  for (size_t i = 0; i < sims.size(); ++i) order[i] = (int)i;
+                                 int tile_rows, int form = -1) {
+  std::vector<int> order;
+  for (size_t i = 0; i < sims.size(); ++i)
+    if (form < 0 || (int)needs_ext(sims[i]->P) == form) order.push_back((int)i);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
     return (long long)sims[a]->P.nx * sims[a]->P.ny > (long long)sims[c]->P.nx * sims[c]->P.ny;
   });
@@ -114,13 +121,9 @@ std::vector<BatchTile> tile_list(const std::vector<const lbm_ehd*>& sims, int wa
     for (int y0 = 0; y0 < P.ny; y0 += tr)
       for (int x0 = 0; x0 < P.nx; x0 += tw) tl.push_back({i, x0, y0, std::min(y0 + tr, P.ny)});
   }
-  while (tl.empty() || tl.size() % 8) tl.push_back({-1, 0, 0, 0});
+  while ((form < 0 && tl.empty()) || tl.size() % 8) tl.push_back({-1, 0, 0, 0});
   return tl;
 }
-
-// The extended sweep (side walls, local field of Eq. 50) is compiled
-// separately from the plain one.
-bool needs_ext(const lbm_ehd_params& p) { return p.side_walls != 0 || p.local_field != 0; }
 
 // Offset of the +y / -y g references from psi_lin / 6: the steady
 // post-collision g of the uncharged potential carries (1/s_2 - 1) G / 6 in
@@ -501,7 +504,8 @@ struct lbm_ehd_batch {
   BatchTile* d_tiles = nullptr;
   size_t tiles_cap = 0;           // tiles
   BatchTile* h_tiles = nullptr;   // pinned staging of the tile list
-  int ntiles = 0;                 // padded to a multiple of 8
+  int ntiles = 0;                 // tiles of the plain-sweep members, then
+  int ntiles_ext = 0;             // of the extended-sweep ones (each padded to a multiple of 8)
   bool dirty = true;              // descriptors / tiles / graph must be rebuilt
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -530,9 +534,16 @@ struct BatchForm {
     }
     Desc* hd = static_cast<Desc*>(b->h_desc);
     for (size_t i = 0; i < n; ++i) hd[i] = F::desc(b->sims[i]);
-    const std::vector<BatchTile> tl =
-        tile_list(std::vector<const lbm_ehd*>(b->sims.begin(), b->sims.end()), b->waves,
-                  b->tile_rows);
+    // members on the plain and on the extended sweep get launches of their
+    // own, so that every member runs the code it runs alone (bitwise the
+    // same results)
+    const std::vector<const lbm_ehd*> ms(b->sims.begin(), b->sims.end());
+    std::vector<BatchTile> tl = tile_list(ms, b->waves, b->tile_rows, 0);
+    const std::vector<BatchTile> te = tile_list(ms, b->waves, b->tile_rows, 1);
+    b->ntiles = (int)tl.size();
+    b->ntiles_ext = (int)te.size();
+    tl.insert(tl.end(), te.begin(), te.end());
+    if (tl.empty()) tl.push_back({-1, 0, 0, 0});
     if (tl.size() > b->tiles_cap) {
       (void)hipFree(b->d_tiles);
       (void)hipHostFree(b->h_tiles);
@@ -543,7 +554,6 @@ struct BatchForm {
       b->tiles_cap = tl.size();
     }
     std::copy(tl.begin(), tl.end(), b->h_tiles);
-    b->ntiles = (int)tl.size();
     HIP_TRY(hipMemcpyAsync(b->d_desc, b->h_desc, n * sizeof(Desc), hipMemcpyHostToDevice,
                            b->stream));
     HIP_TRY(hipMemcpyAsync(b->d_tiles, b->h_tiles, tl.size() * sizeof(BatchTile),
@@ -552,9 +562,13 @@ struct BatchForm {
   }
 
   static lbm_status launch(lbm_ehd_batch* b, int flip) {
-    bool ext = false;
-    for (const lbm_ehd* m : b->sims) ext = ext || needs_ext(m->P);
-    return F::launch_tiles(b->waves, ext, b->d_desc, b->d_tiles, b->ntiles, flip, b->stream);
+    lbm_status st = LBM_OK;
+    if (b->ntiles > 0)
+      st = F::launch_tiles(b->waves, false, b->d_desc, b->d_tiles, b->ntiles, flip, b->stream);
+    if (!st && b->ntiles_ext > 0)
+      st = F::launch_tiles(b->waves, true, b->d_desc, b->d_tiles + b->ntiles, b->ntiles_ext,
+                           flip, b->stream);
+    return st;
   }
 };
 
