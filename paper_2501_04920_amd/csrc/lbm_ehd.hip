@@ -96,20 +96,22 @@ struct lbm_ehd {
 
 namespace {
 
-// The extended sweep (side walls, local field of Eq. 50) is compiled
-// separately from the plain one.
-bool needs_ext(const lbm_ehd_params& p) { return p.side_walls != 0 || p.local_field != 0; }
+// Form of the sweep a simulation runs on, each compiled separately: 0 plain,
+// 1 with side walls, 2 with side walls and the local field of Eq. (50).
+int sweep_form(const lbm_ehd_params& p) {
+  return p.local_field ? 2 : (p.side_walls ? 1 : 0);
+}
 
 // Tile list of a set of simulations: larger ones first, each band by band
 // across its strips of 64 * waves columns, padded with empty tiles to a
 // multiple of 8 (the sweep gives each XCD one contiguous run of tiles).
-// `form` -1 takes every simulation (and never returns an empty list); 0 and
-// 1 take only those on the plain or on the extended sweep (possibly none).
+// `form` -1 takes every simulation (and never returns an empty list); 0, 1
+// and 2 only those on that form of the sweep (possibly none).
 std::vector<BatchTile> tile_list(const std::vector<const lbm_ehd*>& sims, int waves,
                                  int tile_rows, int form = -1) {
   std::vector<int> order;
   for (size_t i = 0; i < sims.size(); ++i)
-    if (form < 0 || (int)needs_ext(sims[i]->P) == form) order.push_back((int)i);
+    if (form < 0 || sweep_form(sims[i]->P) == form) order.push_back((int)i);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
     return (long long)sims[a]->P.nx * sims[a]->P.ny > (long long)sims[c]->P.nx * sims[c]->P.ny;
   });
@@ -278,14 +280,14 @@ struct Form {
     return LBM_OK;
   }
 
-  template <int NW, bool EXT>
+  template <int NW, int EXT>
   static void launch_nw(const void* descs, const BatchTile* tiles, int ntiles, int flip,
                         hipStream_t st) {
     hipLaunchKernelGGL((k_sweep_batch<S, R, T0, NW, EXT>), dim3(ntiles), dim3(64 * NW), 0, st,
                        static_cast<const Desc*>(descs), tiles, ntiles / 8, flip);
   }
 
-  template <bool EXT>
+  template <int EXT>
   static void launch_ext(int waves, const void* descs, const BatchTile* tiles, int ntiles,
                         int flip, hipStream_t st) {
     switch (waves) {
@@ -297,20 +299,22 @@ struct Form {
   }
 
   // One fused sweep over the tiles `tiles` (a multiple of 8) of the members
-  // described by `descs`; `flip` = 1 swaps every member's buffers; `ext`:
-  // some member has side walls or the local field (the extended sweep).
-  static lbm_status launch_tiles(int waves, bool ext, const void* descs,
+  // described by `descs`, all on sweep form `form`; `flip` = 1 swaps every
+  // member's buffers.
+  static lbm_status launch_tiles(int waves, int form, const void* descs,
                                  const BatchTile* tiles, int ntiles, int flip, hipStream_t st) {
-    if (ext)
-      launch_ext<true>(waves, descs, tiles, ntiles, flip, st);
+    if (form == 2)
+      launch_ext<2>(waves, descs, tiles, ntiles, flip, st);
+    else if (form == 1)
+      launch_ext<1>(waves, descs, tiles, ntiles, flip, st);
     else
-      launch_ext<false>(waves, descs, tiles, ntiles, flip, st);
+      launch_ext<0>(waves, descs, tiles, ntiles, flip, st);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
 
   static lbm_status sweep(lbm_ehd* h) {
-    lbm_status st = launch_tiles(h->waves, needs_ext(h->P), h->d_desc, h->d_tiles,
+    lbm_status st = launch_tiles(h->waves, sweep_form(h->P), h->d_desc, h->d_tiles,
                                  h->ntiles, h->cur ^ h->desc_cur, h->stream);
     if (st) return st;
     h->cur = 1 - h->cur;
@@ -504,8 +508,8 @@ struct lbm_ehd_batch {
   BatchTile* d_tiles = nullptr;
   size_t tiles_cap = 0;           // tiles
   BatchTile* h_tiles = nullptr;   // pinned staging of the tile list
-  int ntiles = 0;                 // tiles of the plain-sweep members, then
-  int ntiles_ext = 0;             // of the extended-sweep ones (each padded to a multiple of 8)
+  int ntiles[3] = {0, 0, 0};      // tiles of the members on sweep form 0, 1, 2, in that
+                                  // order (each padded to a multiple of 8)
   bool dirty = true;              // descriptors / tiles / graph must be rebuilt
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -534,15 +538,15 @@ struct BatchForm {
     }
     Desc* hd = static_cast<Desc*>(b->h_desc);
     for (size_t i = 0; i < n; ++i) hd[i] = F::desc(b->sims[i]);
-    // members on the plain and on the extended sweep get launches of their
-    // own, so that every member runs the code it runs alone (bitwise the
-    // same results)
+    // members on each form of the sweep get a launch of their own, so that
+    // every member runs the code it runs alone (bitwise the same results)
     const std::vector<const lbm_ehd*> ms(b->sims.begin(), b->sims.end());
-    std::vector<BatchTile> tl = tile_list(ms, b->waves, b->tile_rows, 0);
-    const std::vector<BatchTile> te = tile_list(ms, b->waves, b->tile_rows, 1);
-    b->ntiles = (int)tl.size();
-    b->ntiles_ext = (int)te.size();
-    tl.insert(tl.end(), te.begin(), te.end());
+    std::vector<BatchTile> tl;
+    for (int form = 0; form < 3; ++form) {
+      const std::vector<BatchTile> t = tile_list(ms, b->waves, b->tile_rows, form);
+      b->ntiles[form] = (int)t.size();
+      tl.insert(tl.end(), t.begin(), t.end());
+    }
     if (tl.empty()) tl.push_back({-1, 0, 0, 0});
     if (tl.size() > b->tiles_cap) {
       (void)hipFree(b->d_tiles);
@@ -562,13 +566,16 @@ struct BatchForm {
   }
 
   static lbm_status launch(lbm_ehd_batch* b, int flip) {
-    lbm_status st = LBM_OK;
-    if (b->ntiles > 0)
-      st = F::launch_tiles(b->waves, false, b->d_desc, b->d_tiles, b->ntiles, flip, b->stream);
-    if (!st && b->ntiles_ext > 0)
-      st = F::launch_tiles(b->waves, true, b->d_desc, b->d_tiles + b->ntiles, b->ntiles_ext,
-                           flip, b->stream);
-    return st;
+    int first = 0;
+    for (int form = 0; form < 3; ++form) {
+      if (b->ntiles[form] > 0) {
+        const lbm_status st = F::launch_tiles(b->waves, form, b->d_desc, b->d_tiles + first,
+                                              b->ntiles[form], flip, b->stream);
+        if (st) return st;
+      }
+      first += b->ntiles[form];
+    }
+    return LBM_OK;
   }
 };
 

@@ -43,16 +43,22 @@ struct ColsP {
   int c, m, p;
   static constexpr bool lw = false, rw = false;
 };
-template <bool EXT>
-using ColsOf = typename std::conditional<EXT, Cols, ColsP>::type;
+// the form of the sweep that also has the local field of Eq. (50)
+struct ColsL : Cols {};
 
-template <bool EXT>
+// Column type of sweep form EXT: 0 plain, 1 side walls, 2 side walls and the
+// local field.
+template <int EXT>
+using ColsOf = typename std::conditional<
+    EXT == 0, ColsP, typename std::conditional<EXT == 1, Cols, ColsL>::type>::type;
+
+template <int EXT>
 __device__ inline ColsOf<EXT> cols_for(int xc, int nx, int side) {
   ColsOf<EXT> k;
   k.c = xc;
   k.m = xc == 0 ? nx - 1 : xc - 1;
   k.p = xc == nx - 1 ? 0 : xc + 1;
-  if constexpr (EXT) {
+  if constexpr (EXT != 0) {
     k.lw = side && xc == 0;
     k.rw = side && xc == nx - 1;
   }
@@ -335,10 +341,11 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   }
   const W Pd = pw[0] + pw[1] + pw[2] + pw[3] + pw[4];
   const W Qd = nw[0] + nw[1] + nw[2] + nw[3] + nw[4];
-  // the local field of Eq. (50), from the node's incoming g (extended sweep)
+  // the local field of Eq. (50), from the node's incoming g (its own form
+  // of the sweep)
   W Eg[2];
   const W* Eloc = nullptr;
-  if constexpr (std::is_same<K, Cols>::value) {
+  if constexpr (std::is_same<K, ColsL>::value) {
     if (kp.local_field) {
       R gl[4];
       hg.g4(gl);
@@ -485,7 +492,7 @@ struct SweepLds {
 
 // One tile of the fused sweep: columns [x0, x0 + 64 NW) of rows [y0, yend)
 // of one simulation, walked down row by row by the whole workgroup.
-template <class S, class R, class T0, int NW, bool EXT>
+template <class S, class R, class T0, int NW, int EXT>
 __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>& L,
                                   const S* __restrict__ src, S* __restrict__ dst,
                                   R* __restrict__ jprev, const T0* __restrict__ h0x,
@@ -501,7 +508,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
   const int x = x0 + (valid ? lane : 0);
   // side walls and the local field are compiled in only where a member of
   // the launch has them
-  const bool side = EXT && kp.side_walls;
+  const bool side = EXT != 0 && kp.side_walls;
   const ColsOf<EXT> k = cols_for<EXT>(x, nx, kp.side_walls);
   const bool periodic = kp.walls == WALL_PERIODIC;
   // Non-temporal population loads pay off where a strip's row of one line
@@ -659,16 +666,17 @@ struct BatchTile {
 // a contiguous run of them, so that the workgroups running together on an
 // XCD hold neighbouring strips of the same rows and the cache lines they
 // share are fetched from HBM once.  `flip` = 1 swaps every member's buffers
-// (odd steps of a captured block).  EXT compiles in the side walls and the
-// local field of Eq. (50), which the launch needs when any member has one:
-// the per-lane address and reference selects of the side walls cost 2-6 %
-// on MI355X at 2048^2 where no member needs them.
+// (odd steps of a captured block).  EXT selects the form: 0 plain, 1 with
+// the side walls, 2 with the side walls and the local field of Eq. (50); a
+// launch covers members of one form.  The per-lane address and reference
+// selects of the side walls cost 2-6 % on MI355X at 2048^2, and the local
+// field's code another ~13 % (more spills) where it is compiled in.
 //
 // At least four waves per SIMD are asked of the register allocator (two with
 // FP64 arithmetic): with the FP64 working type of FP32 storage it otherwise
 // settles on 144 VGPRs (three waves); four waves with a few spilled
 // registers are up to 18 % faster on MI355X at 2048^2.
-template <class S, class R, class T0, int NW, bool EXT>
+template <class S, class R, class T0, int NW, int EXT>
 __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
     const SimDesc<S, R, T0>* __restrict__ sims,
