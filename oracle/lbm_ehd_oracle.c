@@ -18,7 +18,8 @@
  *   3. phase-interpolated properties, Eq. (61); relaxation times Eq. (30),
  *      (37), (47), (55); delta and gamma of Eq. (5)-(6)
  *   4. isotropic finite differences for grad(phi), lap(phi), grad(psi),
- *      Eq. (59) and the Laplacian that follows it; E = -grad(psi), Eq. (9)
+ *      Eq. (59) and the Laplacian that follows it; E = -grad(psi), Eq. (9),
+ *      or (option) the local field of Eq. (50) from the node's g
  *   5. ion concentrations by the explicit solve of Eq. (41)-(43) (the root
  *      of Eq. 42 in a cancellation-free form), reaction R of Eq. (5)-(6),
  *      charge density Eq. (8)
@@ -72,7 +73,11 @@
  *     (default n_eps = 1e-4 in lattice units, far below the interface's
  *     |grad(phi)| ~ 1/W); n_eps = 0 selects the bare form, taken as 0 where
  *     |grad(phi)| < 1e-12;
- *   - d(phi u)/dt at the first step uses (phi u)(t-1) = 0.
+ *   - d(phi u)/dt at the first step uses (phi u)(t-1) = 0;
+ *   - with the local field of Eq. (50), grad(psi) = -E wherever it enters
+ *     (forces, reaction, ion drift, Poisson source, g-only sweeps), and
+ *     tau_g is taken as printed whatever rate the g masks give the first
+ *     moments.
  */
 #include <math.h>
 #include <stdint.h>

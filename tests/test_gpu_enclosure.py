@@ -7,11 +7,13 @@ closed square enclosure, electrodes at the bottom and top, side walls, at
   Eq. 44 (the workload's) and with the variable-eps source of Eq. 7;
 * the long run to the steady droplet (160 000 steps) against the stored
   oracle reference, per storage form;
-* the trends of the steady deformation that Sec. 6 reports.
+* the trends of the steady deformation and of the heterocharge layers that
+  Sec. 6 reports.
 """
 import os
 import sys
 
+import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
@@ -61,7 +63,9 @@ def test_enclosure_steady_droplet_against_oracle(precision):
 
 # Points of the parameter study of Sec. 6 (FP32, 160 000 steps).  Measured
 # steady D: default +0.048; W0 = 0.36, 1.42, 22.8: +0.0085, +0.025, +0.060;
-# mu_r = 0.5, 1: -0.0115, +0.0003; eps_r = 50: -0.024.
+# mu_r = 0.5, 1: -0.0115, +0.0003; eps_r = 50: -0.024.  Heterocharge layer
+# at x = 8 (rows to 1/e of the wall value) at W0 = 0.36, 1.42, 5.69, 22.8:
+# 82, 69, 26, 9; peak |rho_e| / (q c0): 5.6, 5.0, 2.5, 1.3.
 TREND_POINTS = {
     "default": {},
     "W0=0.36": dict(d_mm=0.5),
@@ -73,11 +77,23 @@ TREND_POINTS = {
 }
 
 
+def _heterocharge(sim, params):
+    """Rows from the anode to where rho_e at column 8 falls to 1/e of its
+    wall value, the wall values at both electrodes, and the peak |rho_e|,
+    in units of q c0."""
+    r = sim.fields(("rhoe",))["rhoe"] / (params["q"] * params["c0"])
+    col = r[:, 8]
+    rows = int(np.argmax(np.abs(col) < abs(col[0]) / np.e))
+    return rows, col[0], col[-1], float(np.abs(r).max())
+
+
 def test_enclosure_trends_of_sec6():
     """Sec. 6: prolate at the defaults; D grows with the conduction number W0
     and is close to zero below W0 = 1; oblate at mu_r = 0.5, nearly
-    undeformed at mu_r = 1, prolate at mu_r = 5; oblate at eps_r = 50.
-    All points run as one batch."""
+    undeformed at mu_r = 1, prolate at mu_r = 5; oblate at eps_r = 50.  As
+    W0 grows the heterocharge layers (negative at the anode, positive at the
+    cathode) get thinner and the charge cloud weaker.  All points run as one
+    batch."""
     sims = {}
     for name, kw in TREND_POINTS.items():
         case = workloads.enclosure(256, **kw)
@@ -90,10 +106,19 @@ def test_enclosure_trends_of_sec6():
     b.run(workloads.enclosure(256)["steps"])
     b.synchronize()
     D = {k: s.diagnostics()["D"] for k, s in sims.items()}
+    w0 = ("W0=0.36", "W0=1.42", "default", "W0=22.8")
+    het = {k: _heterocharge(sims[k], workloads.enclosure(256, **TREND_POINTS[k])["params"])
+           for k in w0}
     b.close()
     for s in sims.values():
         s.close()
     print("enclosure steady D: " + " ".join("%s %+.4f" % kv for kv in D.items()), flush=True)
+    print("heterocharge (rows, anode, cathode, peak): " +
+          " ".join("%s %s" % (k, tuple(round(v, 4) for v in het[k])) for k in w0), flush=True)
+    for k in w0:
+        assert het[k][1] < 0 < het[k][2]
+    assert het[w0[0]][0] > het[w0[1]][0] > het[w0[2]][0] > het[w0[3]][0]
+    assert het[w0[0]][3] > het[w0[1]][3] > het[w0[2]][3] > het[w0[3]][3]
     assert D["default"] > 0.03
     assert D["W0=0.36"] < D["W0=1.42"] < D["default"] < D["W0=22.8"]
     assert D["W0=0.36"] < 0.015
