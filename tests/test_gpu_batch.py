@@ -24,17 +24,17 @@ MEMBERS = [(64, 64, 10.0, 2.0, 1.0, 0.5), (100, 70, 12.0, 0.5, 2.0, 0.25),
            (37, 41, 6.0, 1.0, 1.0, 0.5)]
 
 
-def _member(i, precision, side_walls=0):
+def _member(i, precision, options=None):
     nx, ny, r, er, mr, ca = MEMBERS[i]
     p = workloads.lattice_params(ny, r, nx=nx, eps_r=er, mu_r=mr, Ca_E=ca)
-    sim = lbm_ehd.Simulation(dict(p, precision=precision, side_walls=side_walls),
+    sim = lbm_ehd.Simulation(dict(p, precision=precision, **(options or {})),
                              device="cuda:0")
     sim.init_droplet((nx - 1) / 2 + 0.3, (ny - 1) / 2 - 0.2, r, 1e-3, 11 + i, presolve=6)
     return sim, p
 
 
-def _alone(i, precision, steps, side_walls=0):
-    sim, p = _member(i, precision, side_walls)
+def _alone(i, precision, steps, options=None):
+    sim, p = _member(i, precision, options)
     sim.step(steps)
     f = sim.fields()
     sim.close()
@@ -62,18 +62,19 @@ def test_batch_equals_members_alone(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
-def test_batch_mixing_side_walls_equals_members_alone(precision):
-    """One member with side walls puts the whole launch on the side-wall form
-    of the sweep; the members without them still give bitwise what they give
-    alone (on the plain form), and the walled members what they give alone."""
-    walls = [1, 0, 1, 0, 0]
-    sims = [_member(i, precision, w)[0] for i, w in enumerate(walls)]
+def test_batch_mixing_sweep_forms_equals_members_alone(precision):
+    """Members on the three forms of the sweep (plain, side walls, side walls
+    with the local field of Eq. 50) in one batch: each form is launched over
+    its own members, and every member gives bitwise what it gives alone."""
+    options = [dict(side_walls=1), {}, dict(local_field=1), dict(side_walls=1, local_field=1),
+               {}]
+    sims = [_member(i, precision, o)[0] for i, o in enumerate(options)]
     b = lbm_ehd.Batch(sims)
     b.set_launch(2, 8).set_graph_steps(8)
     b.run(21)
     b.synchronize()
     for i, s in enumerate(sims):
-        _same(s.fields(), _alone(i, precision, 21, walls[i]), "member %d" % i)
+        _same(s.fields(), _alone(i, precision, 21, options[i]), "member %d" % i)
     b.close()
 
 

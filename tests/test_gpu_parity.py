@@ -123,7 +123,8 @@ def test_ragged_grid_variants_fp64(name):
 # ping-pong between the buffers) and the literal Poisson form.  Measured
 # after 300 steps: fields <= 2e-3 (FP16), <= 4e-2 (BF16).
 VARIANTS_16 = ("base", "periodic", "insulating", "poisson_iters", "literal_poisson",
-               "side_walls", "side_walls_periodic_y", "local_field", "local_field_periodic")
+               "side_walls", "side_walls_periodic_y", "local_field", "local_field_periodic",
+               "local_field_side_walls")
 
 
 @pytest.mark.parametrize("precision,bar", [("fp16", 1e-2), ("bf16", 0.1)])
