@@ -92,6 +92,11 @@ struct lbm_ehd {
   BatchTile* d_tiles = nullptr;
   int ntiles = 0;
   int desc_cur = 0;
+  // g-only sweeps replayed from a captured graph (pre-solves): a block of
+  // sweeps starting from the state buffer, per state buffer, captured on a
+  // private stream (never the legacy default one)
+  hipGraphExec_t pre_exec[2] = {nullptr, nullptr};
+  hipStream_t cap = nullptr;
 };
 
 namespace {
@@ -341,26 +346,76 @@ struct Form {
   }
   static lbm_status moments(lbm_ehd* h, const S* gsrc) { return moments_as<R>(h, gsrc); }
 
-  // `iters` g-only sweeps.  The g set (its five lines and, with 16-bit
+  // One g-only sweep on stream `st`: phi', psi', rho_e of the state with g
+  // from `from`, then g from `from` into `to`.
+  static lbm_status g_sweep(lbm_ehd* h, const S* from, S* to, hipStream_t st) {
+    const KP<R> kp = make_kp<R>(h);
+    hipLaunchKernelGGL((k_moments<S, R, T0>), grid2(h), dim3(64), 0, st, buf(h, h->cur), from,
+                       h0(h, h->cur), static_cast<R*>(h->mom), kp);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_poisson<S, R>), grid2(h), dim3(64), 0, st, from, to,
+                       static_cast<const R*>(h->mom), kp);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+  }
+
+  // `n` g-only sweeps from the g in `from`, which is left pointing at the
+  // buffer holding the latest g.  The g set (its five lines and, with 16-bit
   // storage, the line of its reference potential) ping-pongs between the
   // state buffer and the same lines of the other buffer, which the next
-  // sweep overwrites anyway; returns (in *gsrc) the buffer holding the latest g.
-  static lbm_status poisson(lbm_ehd* h, int iters, const S** gsrc) {
-    const KP<R> kp = make_kp<R>(h);
-    S* gA = buf(h, h->cur);
-    S* gB = buf(h, 1 - h->cur);
-    S* from = gA;
-    for (int it = 0; it < iters; ++it) {
-      lbm_status st = moments(h, from);
+  // sweep overwrites anyway.  Each sweep is two small kernels, launch-bound
+  // on small grids (3-4 us per launch at 256^2), so from the state buffer
+  // whole blocks of PRE_BLOCK sweeps (even: a block ends in the buffer it
+  // started from) are replayed from a graph captured once per state buffer.
+  static constexpr int PRE_BLOCK = 64;
+  static lbm_status g_sweeps(lbm_ehd* h, const S*& from, int n) {
+    S* A = buf(h, h->cur);
+    S* B = buf(h, 1 - h->cur);
+    if (!h->mom) HIP_TRY(hipMalloc(&h->mom, 3 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
+    if (from == A && n >= 2 * PRE_BLOCK) {
+      hipGraphExec_t& exec = h->pre_exec[h->cur];
+      if (!exec) {
+        if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        const S* f = A;
+        lbm_status cst = LBM_OK;
+        for (int i = 0; i < PRE_BLOCK && !cst; ++i) {
+          S* to = f == A ? B : A;
+          cst = g_sweep(h, f, to, h->cap);
+          f = to;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->cap, &g);
+        if (!cst && e == hipSuccess) {
+          const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+          if (ie != hipSuccess) {
+            exec = nullptr;
+            cst = fail(LBM_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ie));
+          }
+        } else if (!cst) {
+          cst = fail(LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        if (g) (void)hipGraphDestroy(g);
+        if (cst) return cst;
+      }
+      for (; n >= PRE_BLOCK; n -= PRE_BLOCK) HIP_TRY(hipGraphLaunch(exec, h->stream));
+    }
+    for (int it = 0; it < n; ++it) {
+      S* to = from == A ? B : A;
+      lbm_status st = g_sweep(h, from, to, h->stream);
       if (st) return st;
-      S* to = from == gA ? gB : gA;
-      hipLaunchKernelGGL((k_poisson<S, R>), grid2(h), dim3(64), 0, h->stream, from, to,
-                         static_cast<const R*>(h->mom), kp);
-      HIP_TRY(hipGetLastError());
       from = to;
     }
-    *gsrc = from;
     return LBM_OK;
+  }
+
+  // `iters` g-only sweeps from the state; returns (in *gsrc) the buffer
+  // holding the latest g.
+  static lbm_status poisson(lbm_ehd* h, int iters, const S** gsrc) {
+    const S* from = buf(h, h->cur);
+    lbm_status st = g_sweeps(h, from, iters);
+    *gsrc = from;
+    return st;
   }
 
   // Bring the latest g back into the state buffer: the five g lines of
@@ -444,7 +499,6 @@ struct Form {
   // between the buffers, so the other one holds the sweep before.
   static lbm_status presolve_to(lbm_ehd* h, double tol, int max_iters, int every, int* done,
                                 double* residual) {
-    const KP<R> kp = make_kp<R>(h);
     const KP<W> kpw = make_kp<W>(h);
     S* A = buf(h, h->cur);
     S* B = buf(h, 1 - h->cur);
@@ -455,15 +509,8 @@ struct Form {
     double r = NAN;
     while (k < max_iters) {
       const int n = std::min(every, max_iters - k);
-      for (int i = 0; i < n; ++i) {
-        lbm_status st = moments(h, from);
-        if (st) return st;
-        S* to = from == A ? B : A;
-        hipLaunchKernelGGL((k_poisson<S, R>), grid2(h), dim3(64), 0, h->stream, from, to,
-                           static_cast<const R*>(h->mom), kp);
-        HIP_TRY(hipGetLastError());
-        from = to;
-      }
+      lbm_status st = g_sweeps(h, from, n);
+      if (st) return st;
       k += n;
       const S* older = from == A ? B : A;
       hipLaunchKernelGGL((k_psi_change_rows<S, W>), dim3(h->P.ny), dim3(256), 0, h->stream,
@@ -641,6 +688,9 @@ lbm_status validate(const lbm_ehd_params* p) {
 }
 
 void free_scratch(lbm_ehd* h) {
+  for (hipGraphExec_t& e : h->pre_exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   (void)hipFree(h->d_desc);
   (void)hipFree(h->d_tiles);
   (void)hipFree(h->mom);

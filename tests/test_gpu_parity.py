@@ -247,6 +247,31 @@ def test_presolve_to_other_storage(precision):
     assert errs["psi"] <= (1e-6 if precision == "fp32" else 1e-3), errs
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp16"])
+def test_presolve_graph_replays_match_direct_sweeps(precision):
+    """A long pre-solve replays a captured block of 64 g-only sweeps; the same
+    sweeps in short calls (under two blocks each, launched one by one) give
+    bitwise the same state.  Graphs of both state buffers are replayed
+    several times, with steps (eager work) between the pre-solves."""
+    p, d = _ragged()
+    a = run_gpu(p, precision, droplet=d)
+    b = run_gpu(p, precision, droplet=d)
+    for n, steps in ((300, 7), (200, 6), (256, 0)):
+        a.presolve(n)
+        left = n
+        while left:
+            k = min(left, 100)
+            b.presolve(k)
+            left -= k
+        fa, fb = a.fields(), b.fields()
+        for k in ALL10:
+            assert np.array_equal(fa[k], fb[k]), (n, k)
+        a.step(steps)
+        b.step(steps)
+    a.close()
+    b.close()
+
+
 def test_presolve_fp64():
     cfg = workloads.config1()
     p, d = cfg["params"], cfg["droplet"]
