@@ -113,7 +113,8 @@ typedef struct {
                               1: E = sum_i c_i g_i / (c_s^2 tau_g) from the node's
                               incoming g (Eq. 50), and grad psi = -E wherever it
                               enters (forces, reaction, ion drift, Poisson source) */
-  int32_t reserved;        /* must be 0 */
+  int32_t poisson_max;     /* with poisson_tol > 0: at most this many g-only sweeps
+                              per step */
   double rho_v, rho_r;     /* density, outer phase; ratio (Eq. 60) */
   double eta_v, eta_r;     /* dynamic viscosity; tau_f = 1/2 + eta/(rho c_s^2), Eq. (55) */
   double M_phi;            /* phase-field mobility; tau_h = 1/2 + M_phi/c_s^2, Eq. (30) */
@@ -130,6 +131,11 @@ typedef struct {
   double gamma_v;          /* Onsager constant of Eq. (6) in the outer phase; gamma ~ 1/eps */
   double force_x, force_y; /* external body-force density added to F (tests) */
   double s_free;           /* rate of the MRT rows not in the masks (1.0 in Sec. 6) */
+  double poisson_tol;      /* > 0: converged-Poisson mode.  Before every step, g-only
+                              sweeps in groups of poisson_iters (>= 1) until the
+                              convergence residual of lbm_ehd_presolve_to falls below
+                              poisson_tol, or poisson_max sweeps (each check
+                              synchronises the stream); 0: poisson_iters fixed sweeps */
   double n_eps;            /* the unit normal grad(phi)/|grad(phi)| of Eq. (1), (32) is
                               evaluated as grad(phi)/sqrt(|grad(phi)|^2 + n_eps^2)
                               (default 1e-4): the bare form is undefined where
@@ -259,7 +265,9 @@ LBM_API lbm_status lbm_ehd_presolve(lbm_ehd *h, int32_t iters);
 LBM_API lbm_status lbm_ehd_presolve_to(lbm_ehd *h, double tol, int32_t max_iters,
                                        int32_t check_every, int32_t *iters, double *residual);
 
-/* One time step (poisson_iters extra g sweeps, then the fused sweep of all
+/* One time step (poisson_iters extra g sweeps, or with poisson_tol > 0 g sweeps
+ * to that tolerance, whose count and residual the diagnostics report as those
+ * of the last pre-solve; then the fused sweep of all
  * five equations).  Enqueues work. */
 LBM_API lbm_status lbm_ehd_step(lbm_ehd *h);
 

@@ -436,7 +436,16 @@ struct Form {
   }
 
   static lbm_status step(lbm_ehd* h) {
-    if (h->P.poisson_iters > 0) {
+    if (h->P.poisson_tol > 0) {
+      // converged-Poisson mode: g-only sweeps to the tolerance first
+      int done = 0;
+      double r = NAN;
+      lbm_status st = presolve_to(h, h->P.poisson_tol, h->P.poisson_max, h->P.poisson_iters,
+                                  &done, &r);
+      if (st) return st;
+      h->presolve_iters = done;
+      h->presolve_residual = r;
+    } else if (h->P.poisson_iters > 0) {
       const S* g = nullptr;
       lbm_status st = poisson(h, h->P.poisson_iters, &g);
       if (st) return st;
@@ -661,7 +670,9 @@ lbm_status validate(const lbm_ehd_params* p) {
   if (p->walls < 0 || p->walls > 2) return fail(LBM_EINVAL, "unknown walls");
   if (p->side_walls != 0 && p->side_walls != 1) return fail(LBM_EINVAL, "side_walls: 0 or 1");
   if (p->local_field != 0 && p->local_field != 1) return fail(LBM_EINVAL, "local_field: 0 or 1");
-  if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+  if (!(p->poisson_tol >= 0)) return fail(LBM_EINVAL, "poisson_tol must be >= 0");
+  if (p->poisson_tol > 0 && (p->poisson_iters < 1 || p->poisson_max < 1))
+    return fail(LBM_EINVAL, "poisson_tol > 0 needs poisson_iters >= 1 and poisson_max >= 1");
   if (p->poisson_iters < 0) return fail(LBM_EINVAL, "poisson_iters < 0");
   if (!finite_all({p->rho_v, p->rho_r, p->eta_v, p->eta_r, p->M_phi, p->W, p->zeta, p->theta,
                    p->dpsi, p->eps_v, p->eps_r, p->mu_v, p->mu_r, p->m_ratio, p->v_th, p->c0,
@@ -1169,7 +1180,8 @@ lbm_status batch_check_member(const lbm_ehd_batch* b, const lbm_ehd* h) {
   if (!h) return fail(LBM_EINVAL, "NULL member");
   if (!h->ready) return fail(LBM_ESTATE, "batch member not initialised");
   if (h->P.precision != b->precision) return fail(LBM_EINVAL, "batch members differ in precision");
-  if (h->P.poisson_iters != 0) return fail(LBM_EINVAL, "batch members need poisson_iters = 0");
+  if (h->P.poisson_iters != 0 || h->P.poisson_tol > 0)
+    return fail(LBM_EINVAL, "batch members need poisson_iters = 0 and poisson_tol = 0");
   if (std::find(b->sims.begin(), b->sims.end(), h) != b->sims.end())
     return fail(LBM_EINVAL, "simulation is already a batch member");
   int dev = -1;

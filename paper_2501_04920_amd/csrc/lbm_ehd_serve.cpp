@@ -160,7 +160,8 @@ lbm_status lbm_ehd_server_submit(lbm_ehd_server* s, const lbm_ehd_params* p, dou
                                  int64_t nsteps, int64_t* id) {
   if (!s || !p || !id) return serr(LBM_EINVAL, "NULL argument");
   if (nsteps < 0) return serr(LBM_EINVAL, "nsteps < 0");
-  if (p->poisson_iters != 0) return serr(LBM_EINVAL, "served requests need poisson_iters = 0");
+  if (p->poisson_iters != 0 || p->poisson_tol > 0)
+    return serr(LBM_EINVAL, "served requests need poisson_iters = 0 and poisson_tol = 0");
   Request r;
   r.P = *p;
   lbm_status st = lbm_ehd_footprint_bytes(p, &r.footprint);

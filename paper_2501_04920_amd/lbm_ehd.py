@@ -39,7 +39,7 @@ class lbm_ehd_params(ctypes.Structure):
         ("mask_f", ctypes.c_int32), ("mask_h", ctypes.c_int32),
         ("mask_p", ctypes.c_int32), ("mask_n", ctypes.c_int32),
         ("mask_g", ctypes.c_int32), ("side_walls", ctypes.c_int32),
-        ("local_field", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("local_field", ctypes.c_int32), ("poisson_max", ctypes.c_int32),
         ("rho_v", ctypes.c_double), ("rho_r", ctypes.c_double),
         ("eta_v", ctypes.c_double), ("eta_r", ctypes.c_double),
         ("M_phi", ctypes.c_double), ("W", ctypes.c_double), ("zeta", ctypes.c_double),
@@ -49,7 +49,8 @@ class lbm_ehd_params(ctypes.Structure):
         ("m_ratio", ctypes.c_double), ("v_th", ctypes.c_double),
         ("c0", ctypes.c_double), ("q", ctypes.c_double), ("gamma_v", ctypes.c_double),
         ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
-        ("s_free", ctypes.c_double), ("n_eps", ctypes.c_double),
+        ("s_free", ctypes.c_double), ("poisson_tol", ctypes.c_double),
+        ("n_eps", ctypes.c_double),
     ]
 
 

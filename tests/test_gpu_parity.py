@@ -272,6 +272,35 @@ def test_presolve_graph_replays_match_direct_sweeps(precision):
     b.close()
 
 
+def test_converged_poisson_mode_fp64():
+    """poisson_tol > 0: before every step, g-only sweeps in groups of
+    poisson_iters until the convergence residual is below the tolerance (or
+    poisson_max sweeps).  The residual holds every step, and the oracle,
+    replaying the sweep counts the GPU reports step by step, gives the same
+    fields."""
+    tol, cap = 1e-3, 300
+    p, d = _ragged(poisson_iters=3, poisson_tol=tol, poisson_max=cap, eps_r=4.0)
+    sim = run_gpu(p, "fp64", droplet=d, presolve=10)
+    op = {k: v for k, v in p.items() if k not in ("poisson_tol", "poisson_max")}
+    op["poisson_iters"] = 0
+    o = run_oracle(op, droplet=d, presolve=10)
+    counts = []
+    for _ in range(40):
+        sim.step(1)
+        dg = sim.diagnostics()
+        k, r = dg["presolve_iters"], dg["presolve_residual"]
+        assert k % 3 == 0 and (r < tol or k == cap), (k, r)
+        counts.append(k)
+        o.presolve(k)
+        o.step(1)
+    print("sweeps per step:", counts, flush=True)
+    assert max(counts) > 3
+    errs = rel_l2(sim.fields(), o.fields(), p, ALL10)
+    _report("converged Poisson", errs)
+    assert max(errs.values()) <= 1e-10
+    sim.close()
+
+
 def test_presolve_fp64():
     cfg = workloads.config1()
     p, d = cfg["params"], cfg["droplet"]
