@@ -228,13 +228,13 @@ def bench_batched(args):
 ENCLOSURE_STUDY = (
     [("eps_r", e) for e in (0.5, 1.0, 2.0, 5.0, 10.0, 50.0)]
     + [("mu_r", m) for m in (0.25, 0.5, 1.0, 2.0, 10.0)]
-    + [("d_mm", 0.5), ("d_mm", 1.0), ("kv", 0.5), ("kv", 0.25)])
+    + [("d_mm", 0.5), ("d_mm", 1.0), ("d_mm", 4.0), ("kv", 0.5), ("kv", 0.25)])
 
 
 def bench_enclosure(args):
     """The paper's parameter study of Sec. 6 as one batched job: the enclosure
     (256^2, side walls, Sec. 6 defaults) at each point of an eps_r scan, a
-    mu_r scan and four conduction numbers W0 (gap d and voltage), advanced to
+    mu_r scan and five further conduction numbers W0 (gap d and voltage), advanced to
     the steady droplet (160 000 steps) in one launch per step: study solves
     per hour and the steady deformation factor of every point."""
     import torch
