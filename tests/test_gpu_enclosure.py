@@ -71,7 +71,9 @@ def test_enclosure_steady_droplet_against_oracle(precision):
 # default (2 mm) +0.048; W0 = 0.36, 1.42, 22.76: +0.0085, +0.025, +0.060;
 # mu_r = 0.5, 1: -0.0115, +0.0003; eps_r = 50: -0.024.  Heterocharge layer
 # at x = 8 (rows to 1/e of the wall value) at W0 = 0.36, 1.42, 5.69, 22.76:
-# 82, 69, 26, 9; peak |rho_e| / (q c0): 5.6, 5.0, 2.5, 1.3.
+# 82, 69, 26, 9; peak |rho_e| / (q c0): 5.6, 5.0, 2.5, 1.3.  Mean |rho_e| /
+# (q c0) in the droplet's core (r < R/2): 1.7e-3 at 2 mm and 1 kV, 0.30 at
+# 2 mm and 10 kV (beta = 0.5643), 1e-4 at 8 mm and 10 kV (beta = 1.1286).
 TREND_POINTS = {
     "default": {},
     "W0=0.36": dict(d_mm=0.5),
@@ -80,6 +82,8 @@ TREND_POINTS = {
     "mu_r=0.5": dict(mu_r=0.5),
     "mu_r=1": dict(mu_r=1.0),
     "eps_r=50": dict(eps_r=50.0),
+    "2mm-10kV": dict(d_mm=2.0, kv=10.0),
+    "8mm-10kV": dict(d_mm=8.0, kv=10.0),
 }
 
 
@@ -93,13 +97,24 @@ def _heterocharge(sim, params):
     return rows, col[0], col[-1], float(np.abs(r).max())
 
 
+def _core_charge(sim, case):
+    """Mean |rho_e| / (q c0) within half the droplet radius of its centre."""
+    p, d = case["params"], case["droplet"]
+    r = np.abs(sim.fields(("rhoe",))["rhoe"]) / (p["q"] * p["c0"])
+    yy, xx = np.mgrid[0:p["ny"], 0:p["nx"]]
+    return float(r[np.hypot(xx - d["xc"], yy - d["yc"]) < d["radius"] / 2].mean())
+
+
 def test_enclosure_trends_of_sec6():
     """Sec. 6: prolate at the defaults; D grows with the conduction number W0
     and is close to zero below W0 = 1; oblate at mu_r = 0.5, nearly
     undeformed at mu_r = 1, prolate at mu_r = 5; oblate at eps_r = 50.  As
     W0 grows the heterocharge layers (negative at the anode, positive at the
-    cathode) get thinner and the charge cloud weaker.  All points run as one
-    batch."""
+    cathode) get thinner and the charge cloud weaker.  At d = 2 mm
+    (beta = 0.5643) raising the voltage to 10 kV removes the electroneutral
+    core of the droplet (the saturation state); at d = 8 mm (beta = 1.1286)
+    the core stays neutral at 10 kV (the ohmic state).  All points run as
+    one batch."""
     sims = {}
     for name, kw in TREND_POINTS.items():
         case = workloads.enclosure(256, **kw)
@@ -115,10 +130,13 @@ def test_enclosure_trends_of_sec6():
     w0 = ("W0=0.36", "W0=1.42", "default", "W0=22.8")
     het = {k: _heterocharge(sims[k], workloads.enclosure(256, **TREND_POINTS[k])["params"])
            for k in w0}
+    core = {k: _core_charge(sims[k], workloads.enclosure(256, **TREND_POINTS[k]))
+            for k in ("default", "2mm-10kV", "8mm-10kV")}
     b.close()
     for s in sims.values():
         s.close()
     print("enclosure steady D: " + " ".join("%s %+.4f" % kv for kv in D.items()), flush=True)
+    print("droplet core charge: " + " ".join("%s %.2e" % kv for kv in core.items()), flush=True)
     print("heterocharge (rows, anode, cathode, peak): " +
           " ".join("%s %s" % (k, tuple(round(v, 4) for v in het[k])) for k in w0), flush=True)
     for k in w0:
@@ -131,3 +149,5 @@ def test_enclosure_trends_of_sec6():
     assert D["mu_r=0.5"] < -0.005
     assert abs(D["mu_r=1"]) < 0.005
     assert D["eps_r=50"] < -0.01
+    assert core["default"] < 0.01 and core["8mm-10kV"] < 0.01
+    assert core["2mm-10kV"] > 0.1
