@@ -103,7 +103,8 @@ FP32_BAR = dict(rhoe_l2=2e-5, u_l2=2e-5, phi=2e-5, psi=2e-5, cp=2e-5, cm=2e-5, r
 # Per storage form on the W = 5 restriction, after 20 000 steps: FP64 within
 # 1e-10 and FP32 storage within 2e-5 on every field; D within 1e-3 for the
 # 16-bit forms (measured: FP16 2.5e-5; BF16 1.6e-3, an expected failure: its
-# 8-bit significand leaves the populations too coarse for 20 000 steps).
+# 8-bit significand rounds the f populations, stored relative to 0, too
+# coarsely for 20 000 steps; with f alone in binary16 it is 2.8e-5).
 FORM_BAR = {
     "fp64": dict(D=1e-10, rhoe_l2=1e-10, u_l2=1e-10, phi=1e-10, psi=1e-10, cp=1e-10, cm=1e-10,
                  rhoe=1e-10, ux=1e-10, uy=1e-10, p=1e-10),
