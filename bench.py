@@ -234,9 +234,11 @@ ENCLOSURE_STUDY = (
 def bench_enclosure(args):
     """The paper's parameter study of Sec. 6 as one batched job: the enclosure
     (256^2, side walls, Sec. 6 defaults) at each point of an eps_r scan, a
-    mu_r scan and five further conduction numbers W0 (gap d and voltage), advanced to
-    the steady droplet (160 000 steps) in one launch per step: study solves
-    per hour and the steady deformation factor of every point."""
+    mu_r scan and five further conduction numbers W0 (gap d and voltage),
+    advanced to the steady droplet (160 000 steps) in one launch per step:
+    study solves per hour, and the steady deformation factor and charge
+    observables of every point."""
+    import numpy as np
     import torch
 
     from paper_2501_04920_amd import lbm_ehd, workloads
@@ -274,6 +276,18 @@ def bench_enclosure(args):
     cells = sum(c["params"]["nx"] * c["params"]["ny"] for c in cases)
     D = [s.diagnostics()["D"] for s in sims]
     bad = sum(s.diagnostics()["nonfinite"] for s in sims)
+    # charge observables of Sec. 6, in units of q c0: rows from the anode to
+    # where rho_e at column 8 falls to 1/e of its wall value (heterocharge
+    # layer), and the mean |rho_e| within half the droplet radius (zero in
+    # the ohmic state's electroneutral core)
+    layer, core = [], []
+    for c, s in zip(cases, sims):
+        p, d = c["params"], c["droplet"]
+        r = s.fields(("rhoe",))["rhoe"] / (p["q"] * p["c0"])
+        col = r[:, 8]
+        layer.append(int(np.argmax(np.abs(col) < abs(col[0]) / np.e)))
+        yy, xx = np.mgrid[0:p["ny"], 0:p["nx"]]
+        core.append(float(np.abs(r[np.hypot(xx - d["xc"], yy - d["yc"]) < d["radius"] / 2]).mean()))
     b.close()
     for s in sims:
         s.close()
@@ -292,6 +306,8 @@ def bench_enclosure(args):
         "aggregate_glups": round(cells * steps / wall / 1e9, 3),
         "init_and_presolve_s": round(t_init, 2),
         "steady_D": {"%s=%g" % kv: round(x, 5) for kv, x in zip(ENCLOSURE_STUDY, D)},
+        "heterocharge_rows": {"%s=%g" % kv: x for kv, x in zip(ENCLOSURE_STUDY, layer)},
+        "core_charge": {"%s=%g" % kv: float("%.3g" % x) for kv, x in zip(ENCLOSURE_STUDY, core)},
         "nonfinite": int(bad),
     }
     print(json.dumps(line), flush=True)
