@@ -298,10 +298,13 @@ LBM_API lbm_status lbm_ehd_get_launch(const lbm_ehd *h, int32_t *waves, int32_t 
 
 /*
  * Batched sweeps.  Several initialised simulations of any grid sizes, with
- * the same storage precision and poisson_iters = 0, are advanced together:
- * each step is ONE kernel launch over the tiles of all members (each tile
- * runs the single-simulation tile code on its own member), and whole blocks
- * of steps are captured once in a HIP graph and replayed.  Every member's
+ * the same storage precision, poisson_iters = 0 and poisson_tol = 0, are
+ * advanced together: each step is ONE kernel launch over the tiles of all
+ * members (each tile runs the single-simulation tile code on its own
+ * member), and whole blocks of steps are captured once in a HIP graph and
+ * replayed.  The sweep has three compiled forms (plain; with side walls;
+ * with side walls and the local field); members of different forms are
+ * launched separately, one launch per form present.  Every member's
  * arithmetic is the same as when it steps alone, so its results are bitwise
  * those of lbm_ehd_run.
  *
@@ -317,7 +320,7 @@ typedef struct lbm_ehd_batch lbm_ehd_batch;
  * must not be the legacy default stream (graphs cannot be captured there);
  * NULL: the batch creates its own blocking stream of default priority,
  * ordered with the default stream and destroyed with the batch.  LBM_EINVAL on mixed precisions, members with
- * poisson_iters != 0, duplicates or members on another device; LBM_ESTATE if
+ * poisson_iters != 0 or poisson_tol > 0, duplicates or members on another device; LBM_ESTATE if
  * a member is not initialised. */
 LBM_API lbm_status lbm_ehd_batch_create(lbm_ehd *const *sims, int32_t n, void *stream,
                                         lbm_ehd_batch **out);
