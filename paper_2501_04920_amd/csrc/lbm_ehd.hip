@@ -346,12 +346,17 @@ struct Form {
   }
   static lbm_status moments(lbm_ehd* h, const S* gsrc) { return moments_as<R>(h, gsrc); }
 
-  // One g-only sweep on stream `st`: phi', psi', rho_e of the state with g
-  // from `from`, then g from `from` into `to`.
-  static lbm_status g_sweep(lbm_ehd* h, const S* from, S* to, hipStream_t st) {
+  // One g-only sweep on stream `st`: the moment planes of the state with g
+  // from `from` (all of phi', psi', rho_e if `full`, else psi' alone: phi and
+  // rho_e do not change in g-only sweeps), then g from `from` into `to`.
+  static lbm_status g_sweep(lbm_ehd* h, const S* from, S* to, hipStream_t st, bool full) {
     const KP<R> kp = make_kp<R>(h);
-    hipLaunchKernelGGL((k_moments<S, R, T0>), grid2(h), dim3(64), 0, st, buf(h, h->cur), from,
-                       h0(h, h->cur), static_cast<R*>(h->mom), kp);
+    if (full)
+      hipLaunchKernelGGL((k_moments<S, R, T0>), grid2(h), dim3(64), 0, st, buf(h, h->cur), from,
+                         h0(h, h->cur), static_cast<R*>(h->mom), kp);
+    else
+      hipLaunchKernelGGL((k_psi_plane<S, R>), grid2(h), dim3(64), 0, st, from,
+                         static_cast<R*>(h->mom), kp);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_poisson<S, R>), grid2(h), dim3(64), 0, st, from, to,
                        static_cast<const R*>(h->mom), kp);
@@ -372,6 +377,13 @@ struct Form {
     S* A = buf(h, h->cur);
     S* B = buf(h, 1 - h->cur);
     if (!h->mom) HIP_TRY(hipMalloc(&h->mom, 3 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
+    // the first sweep refreshes every moment plane, the later ones psi' alone
+    for (int first = 0; first < 2 && n > 0; ++first, --n) {
+      S* to = from == A ? B : A;
+      lbm_status st = g_sweep(h, from, to, h->stream, first == 0);
+      if (st) return st;
+      from = to;
+    }
     if (from == A && n >= 2 * PRE_BLOCK) {
       hipGraphExec_t& exec = h->pre_exec[h->cur];
       if (!exec) {
@@ -381,7 +393,7 @@ struct Form {
         lbm_status cst = LBM_OK;
         for (int i = 0; i < PRE_BLOCK && !cst; ++i) {
           S* to = f == A ? B : A;
-          cst = g_sweep(h, f, to, h->cap);
+          cst = g_sweep(h, f, to, h->cap, false);
           f = to;
         }
         hipGraph_t g = nullptr;
@@ -402,7 +414,7 @@ struct Form {
     }
     for (int it = 0; it < n; ++it) {
       S* to = from == A ? B : A;
-      lbm_status st = g_sweep(h, from, to, h->stream);
+      lbm_status st = g_sweep(h, from, to, h->stream, false);
       if (st) return st;
       from = to;
     }

@@ -717,6 +717,20 @@ __global__ void k_moments(const S* __restrict__ src, const S* __restrict__ gsrc,
   mom[2 * np + c] = kp.q * (Pd - Qd);
 }
 
+// psi' of every node into its moment plane (the g-only sweeps of a
+// pre-solve, where phi' and rho_e stay as k_moments left them): the same
+// value k_moments writes there, from the g lines alone.
+template <class S, class R>
+__global__ void k_psi_plane(const S* __restrict__ gsrc, R* __restrict__ mom, const KP<R> kp) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= kp.nx) return;
+  const PopView<S, R> Pg{make_rsrc(gsrc, kp.pop_bytes), &kp};
+  const Cols k = cols_of(x, kp.nx, kp.side_walls);
+  R g4[4];
+  pull_g(Pg, k, y, g4);
+  mom[(long long)kp.nx * kp.ny + (long long)y * kp.nx + x] = psi_of(g4);
+}
+
 // phi' / psi' neighbourhood of (x, y) from the compact moment planes.
 template <class R>
 __device__ inline void hood(const R* __restrict__ mom, const KP<R>& kp, int x, int y,
