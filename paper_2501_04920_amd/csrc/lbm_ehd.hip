@@ -543,6 +543,10 @@ struct Form {
       double sums[2];
       HIP_TRY(hipMemcpyAsync(sums, h->red, sizeof sums, hipMemcpyDeviceToHost, h->stream));
       HIP_TRY(hipStreamSynchronize(h->stream));
+      // (checked before the ratio: a NaN sum would fail `sums[1] > 0` and read
+      // as a converged potential)
+      if (!std::isfinite(sums[0]) || !std::isfinite(sums[1]))
+        return fail(LBM_ENONFINITE, "potential contains NaN or Inf");
       r = sums[1] > 0 ? std::sqrt(sums[0] / sums[1]) / rate : 0.0;
       if (!std::isfinite(r)) return fail(LBM_ENONFINITE, "potential contains NaN or Inf");
       if (r < tol) break;

@@ -394,6 +394,36 @@ def test_sum_phi_conserved(precision, side_walls):
     assert abs(s1 / s0 - 1) < 1e-12
 
 
+def test_nonfinite_state_is_reported():
+    """A NaN in the state (one cell of the initial phi) spreads and is
+    reported: lbm_ehd_diagnostics returns LBM_ENONFINITE (after filling its
+    output, which the binding passes on with nonfinite > 0), and a pre-solve
+    to a tolerance stops with LBM_ENONFINITE."""
+    import ctypes
+
+    n = 64
+    p = workloads.lattice_params(n, 10.0)
+    y, x = np.mgrid[0:n, 0:n]
+    phi = 0.5 * (1 + np.tanh(2 * (10.0 - np.hypot(x - 31.5, y - 31.5)) / p["W"]))
+    psi = p["dpsi"] * (n - 0.5 - y) / n
+    clean = lbm_ehd.Simulation(dict(p, precision="fp32"), device="cuda:0")
+    clean.init_fields(phi, 1.0, 1.0, psi)
+    clean.step(5)
+    assert clean.diagnostics()["nonfinite"] == 0
+    clean.close()
+    phi[20, 30] = np.nan
+    sim = lbm_ehd.Simulation(dict(p, precision="fp32"), device="cuda:0")
+    sim.init_fields(phi, 1.0, 1.0, psi)
+    sim.step(5)
+    d = lbm_ehd.lbm_ehd_diag()
+    assert lbm_ehd.lib().lbm_ehd_diagnostics(sim.handle, ctypes.byref(d)) == lbm_ehd.LBM_ENONFINITE
+    assert d.nonfinite > 0 and sim.diagnostics()["nonfinite"] == d.nonfinite
+    with pytest.raises(lbm_ehd.LbmError) as e:
+        sim.presolve_to(1e-6, 1000, 100)
+    assert e.value.code == lbm_ehd.LBM_ENONFINITE
+    sim.close()
+
+
 def test_error_paths():
     p = workloads.lattice_params(32, 5.0)
     sim = lbm_ehd.Simulation(dict(p, precision="fp32"), device="cuda:0")
