@@ -287,6 +287,22 @@ LBM_API lbm_status lbm_ehd_diagnostics(lbm_ehd *h, lbm_ehd_diag *out);
 /* Current step count. */
 LBM_API int64_t lbm_ehd_time(const lbm_ehd *h);
 
+/*
+ * Checkpoint and resume.  The state of a simulation (its current population
+ * buffer, the aux buffer with (phi u)(t-1) and the FP64 rest populations,
+ * the step count) fits in *bytes of host memory.  lbm_ehd_save_state copies
+ * it out (synchronises); lbm_ehd_load_state copies a saved state into a
+ * simulation created with the same grid and storage precision (other
+ * parameters may differ) and makes it current: the simulation then
+ * continues bitwise as the saved one would have.  The buffer is caller-owned.
+ * Not for members of a batch (remove them first).  LBM_EINVAL on a NULL
+ * argument or a state of another grid, precision or layout; LBM_ERANGE if
+ * the buffer is too small; LBM_ESTATE if saving before init.
+ */
+LBM_API lbm_status lbm_ehd_state_bytes(const lbm_ehd *h, size_t *bytes);
+LBM_API lbm_status lbm_ehd_save_state(lbm_ehd *h, void *buffer, size_t bytes);
+LBM_API lbm_status lbm_ehd_load_state(lbm_ehd *h, const void *buffer, size_t bytes);
+
 /* Launch shape of the fused sweep: `waves` wavefronts per workgroup (1, 2 or
  * or 8; a workgroup owns a strip of 64 * waves columns and walks down a band of
  * `tile_rows` rows, tile_rows >= 1, clamped to ny).  Results do not depend on

@@ -1138,6 +1138,72 @@ lbm_status lbm_ehd_get_launch(const lbm_ehd* h, int32_t* waves, int32_t* tile_ro
   return LBM_OK;
 }
 
+namespace {
+
+// Header of a saved state.
+struct SavedState {
+  uint64_t magic;
+  int32_t nx, ny, precision, pitch;
+  int64_t step;
+  int32_t cur, reserved;
+  uint64_t pop_bytes, aux_bytes;
+};
+constexpr uint64_t STATE_MAGIC = 0x3130455441545345ull;  // "ESTATE01"
+
+}  // namespace
+
+lbm_status lbm_ehd_state_bytes(const lbm_ehd* h, size_t* bytes) {
+  if (!h || !bytes) return fail(LBM_EINVAL, "NULL argument");
+  *bytes = sizeof(SavedState) + h->pop_bytes + h->aux_bytes;
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_save_state(lbm_ehd* h, void* buffer, size_t bytes) {
+  if (!h || !buffer) return fail(LBM_EINVAL, "NULL argument");
+  if (!h->ready) return fail(LBM_ESTATE, "save before init");
+  const size_t need = sizeof(SavedState) + h->pop_bytes + h->aux_bytes;
+  if (bytes < need) return fail(LBM_ERANGE, "state buffer too small");
+  SavedState hd;
+  std::memset(&hd, 0, sizeof hd);
+  hd.magic = STATE_MAGIC;
+  hd.nx = h->P.nx;
+  hd.ny = h->P.ny;
+  hd.precision = h->P.precision;
+  hd.pitch = h->pitch;
+  hd.step = h->step;
+  hd.cur = h->cur;
+  hd.pop_bytes = h->pop_bytes;
+  hd.aux_bytes = h->aux_bytes;
+  char* out = static_cast<char*>(buffer);
+  std::memcpy(out, &hd, sizeof hd);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(out + sizeof hd, h->pop[h->cur], h->pop_bytes, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(out + sizeof hd + h->pop_bytes, h->aux, h->aux_bytes, hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_load_state(lbm_ehd* h, const void* buffer, size_t bytes) {
+  if (!h || !buffer) return fail(LBM_EINVAL, "NULL argument");
+  if (bytes < sizeof(SavedState)) return fail(LBM_ERANGE, "state buffer too small");
+  SavedState hd;
+  std::memcpy(&hd, buffer, sizeof hd);
+  if (hd.magic != STATE_MAGIC) return fail(LBM_EINVAL, "not a saved state");
+  if (hd.nx != h->P.nx || hd.ny != h->P.ny || hd.precision != h->P.precision ||
+      hd.pitch != h->pitch || hd.pop_bytes != h->pop_bytes || hd.aux_bytes != h->aux_bytes ||
+      (hd.cur != 0 && hd.cur != 1))
+    return fail(LBM_EINVAL, "state of another grid, precision or layout");
+  if (bytes < sizeof hd + hd.pop_bytes + hd.aux_bytes)
+    return fail(LBM_ERANGE, "state buffer too small");
+  const char* in = static_cast<const char*>(buffer);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(h->pop[hd.cur], in + sizeof hd, hd.pop_bytes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->aux, in + sizeof hd + hd.pop_bytes, hd.aux_bytes, hipMemcpyHostToDevice));
+  h->cur = hd.cur;
+  h->step = hd.step;
+  h->ready = true;
+  return LBM_OK;
+}
+
 lbm_status lbm_ehd_synchronize(lbm_ehd* h) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   HIP_TRY(hipStreamSynchronize(h->stream));

@@ -135,6 +135,9 @@ def lib() -> ctypes.CDLL:
             "lbm_ehd_diagnostics": [vp, P(lbm_ehd_diag)],
             "lbm_ehd_synchronize": [vp],
             "lbm_ehd_destroy": [vp],
+            "lbm_ehd_state_bytes": [vp, P(ctypes.c_size_t)],
+            "lbm_ehd_save_state": [vp, vp, ctypes.c_size_t],
+            "lbm_ehd_load_state": [vp, vp, ctypes.c_size_t],
             "lbm_ehd_set_launch": [vp, ctypes.c_int32, ctypes.c_int32],
             "lbm_ehd_get_launch": [vp, P(ctypes.c_int32), P(ctypes.c_int32)],
             "lbm_ehd_batch_create": [P(vp), ctypes.c_int32, vp, P(vp)],
@@ -267,6 +270,23 @@ def lbm_ehd_diagnostics(h) -> lbm_ehd_diag:
     if code not in (LBM_OK, LBM_ENONFINITE):
         _check(code)
     return d
+
+
+def lbm_ehd_state_bytes(h) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().lbm_ehd_state_bytes(h, ctypes.byref(n)))
+    return n.value
+
+
+def lbm_ehd_save_state(h) -> np.ndarray:
+    buf = np.empty(lbm_ehd_state_bytes(h), dtype=np.uint8)
+    _check(lib().lbm_ehd_save_state(h, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+    return buf
+
+
+def lbm_ehd_load_state(h, state: np.ndarray):
+    state = np.ascontiguousarray(state, dtype=np.uint8)
+    _check(lib().lbm_ehd_load_state(h, state.ctypes.data_as(ctypes.c_void_p), state.size))
 
 
 def lbm_ehd_time(h) -> int:
@@ -451,6 +471,16 @@ class Simulation:
 
     def synchronize(self):
         lbm_ehd_synchronize(self.handle)
+
+    def save_state(self) -> np.ndarray:
+        """Checkpoint: the whole state as host bytes."""
+        return lbm_ehd_save_state(self.handle)
+
+    def load_state(self, state: np.ndarray):
+        """Resume from save_state() of a simulation of the same grid and
+        storage precision."""
+        lbm_ehd_load_state(self.handle, state)
+        return self
 
     def set_launch(self, waves: int, tile_rows: int):
         lbm_ehd_set_launch(self.handle, waves, tile_rows)

@@ -394,6 +394,39 @@ def test_sum_phi_conserved(precision, side_walls):
     assert abs(s1 / s0 - 1) < 1e-12
 
 
+@pytest.mark.parametrize("precision,steps", [("fp64", 50), ("fp32", 51), ("fp16", 51)])
+def test_checkpoint_resume_is_bitwise(precision, steps):
+    """A saved state loaded into a fresh simulation (even or odd step count,
+    so either buffer holds the state) continues bitwise as the original; the
+    original rewound to its checkpoint repeats itself bitwise; a state of
+    another grid or precision is rejected."""
+    p, d = _ragged(side_walls=1) if precision == "fp16" else _ragged()
+    a = run_gpu(p, precision, droplet=d, presolve=10, steps=steps)
+    state = a.save_state()
+    a.step(30)
+    fa = a.fields()
+    b = lbm_ehd.Simulation(dict(p, precision=precision), device="cuda:0")
+    b.load_state(state)
+    assert b.time == steps
+    b.step(30)
+    fb = b.fields()
+    a.load_state(state).step(30)
+    fa2 = a.fields()
+    for k in ALL10:
+        assert np.array_equal(fa[k], fb[k]), k
+        assert np.array_equal(fa[k], fa2[k]), k
+    other = lbm_ehd.Simulation(dict(p, precision="fp64" if precision != "fp64" else "fp32"),
+                               device="cuda:0")
+    with pytest.raises(lbm_ehd.LbmError) as e:
+        other.load_state(state)
+    assert e.value.code == lbm_ehd.LBM_EINVAL
+    with pytest.raises(lbm_ehd.LbmError) as e:
+        b.load_state(state[:100])
+    assert e.value.code == lbm_ehd.LBM_ERANGE
+    for s in (a, b, other):
+        s.close()
+
+
 def test_nonfinite_state_is_reported():
     """A NaN in the state (one cell of the initial phi) spreads and is
     reported: lbm_ehd_diagnostics returns LBM_ENONFINITE (after filling its
