@@ -129,3 +129,13 @@ def test_enclosure_workload_groups():
     # the library accepts the case (the droplet clears the side walls)
     pop, aux = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(**p))
     assert pop > 0
+
+
+def test_state_calls_reject_null_arguments():
+    """Checkpoint calls validate their arguments on the host."""
+    L = lbm_ehd.lib()
+    n = ctypes.c_size_t()
+    assert L.lbm_ehd_state_bytes(None, ctypes.byref(n)) == lbm_ehd.LBM_EINVAL
+    buf = (ctypes.c_ubyte * 64)()
+    assert L.lbm_ehd_save_state(None, buf, 64) == lbm_ehd.LBM_EINVAL
+    assert L.lbm_ehd_load_state(None, buf, 64) == lbm_ehd.LBM_EINVAL
