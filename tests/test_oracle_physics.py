@@ -400,3 +400,34 @@ def test_poiseuille_between_side_walls(orc):
     ux = o.fields()["ux"][0]
     assert np.abs(ux).max() <= 1e-5 * ref.max()
     assert np.abs(ux + ux[::-1]).max() <= 1e-12 * ref.max()
+
+
+def test_side_walls_act_as_mirrors_without_flow(orc):
+    """With the fluid held at rest (no-slip is not a mirror condition), the
+    side walls of a y-periodic box are mirrors for everything else: specular
+    reflection of h, zero flux of c+ and c-, zero normal derivative of psi,
+    and mirrored stencil columns.  A box of width n then evolves exactly as
+    the left half of a periodic box of width 2n that holds the state and its
+    mirror image, here with a droplet cut by the wall and a charge cloud
+    beside it, both varying in x and y."""
+    nx, ny = 16, 24
+    yy, xx = np.mgrid[0:ny, 0:nx].astype(float)
+    phi = 0.5 * (1 + np.tanh(2 * (6.0 - np.hypot(xx - 2.3, yy - 11.6)) / 4.0))
+    cp = 1.0 + 0.3 * np.exp(-((xx - 1.0) ** 2 + (yy - 5.0) ** 2) / 8.0)
+
+    def mirrored(a):
+        return np.concatenate([a, a[:, ::-1]], axis=1)
+
+    out = []
+    for side, ph, c in ((1, phi, cp), (0, mirrored(phi), mirrored(cp))):
+        o = orc.Oracle(dict(nx=ph.shape[1], ny=ny, walls=2, side_walls=side, dpsi=0.0,
+                            q=1e-3, eps_r=2.0, mu_r=0.5, reaction=1, flow=0))
+        o.init_fields(ph, c, 1.0, 0.0)
+        o.step(400)
+        out.append(o.fields())
+    box, wide = out
+    assert abs(box["phi"] - phi).max() > 0.05          # the droplet does move
+    for k in ("phi", "psi", "cp", "cm", "rhoe", "Ex", "Ey"):
+        scale = abs(box[k]).max()
+        assert scale > 0, k
+        assert abs(box[k] - wide[k][:, :nx]).max() <= 1e-12 * scale, k
