@@ -139,3 +139,24 @@ def test_state_calls_reject_null_arguments():
     buf = (ctypes.c_ubyte * 64)()
     assert L.lbm_ehd_save_state(None, buf, 64) == lbm_ehd.LBM_EINVAL
     assert L.lbm_ehd_load_state(None, buf, 64) == lbm_ehd.LBM_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built HIP library every entry point raises: there is no
+    CPU fallback."""
+    monkeypatch.setattr(lbm_ehd, "_lib", None)
+    monkeypatch.setattr(lbm_ehd, "LIB_PATH", os.path.join(ROOT, "no-such-dir", "liblbm_ehd.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        lbm_ehd.lbm_ehd_params_default()
+
+
+def test_product_code_never_reaches_the_oracle():
+    """The package (binding, workloads, HIP sources) neither imports, loads
+    nor links the CPU oracle, which is test infrastructure only."""
+    pkg = os.path.join(ROOT, "paper_2501_04920_amd")
+    pat = re.compile(r"import\s+oracle|from\s+oracle|lbm_ehd_oracle|oracle[/\\]|\boracle\.[A-Za-z_]")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not pat.search(src), os.path.join(dirpath, f)
