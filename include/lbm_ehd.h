@@ -54,13 +54,22 @@ typedef int32_t lbm_status;
 #define LBM_ERANGE (-6)     /* caller buffer too small */
 
 /* Storage and arithmetic precision.  Populations are always stored as
- * deviations from a fixed reference state (h: w_i/2, p and n: wbar_i c0, g:
- * the equilibrium of the uncharged linear potential, f: 0). */
+ * deviations from a reference state (h: w_i/2, p and n: wbar_i c0, g: the
+ * equilibrium of the uncharged linear potential, f: 0; 16-bit storage adds
+ * node-local references).  The rest populations that carry the conserved
+ * contents (h0; with 16-bit storage also p0 and n0) are kept in FP64 in
+ * every form, so that each collision conserves phi and the ion contents to
+ * FP64 rounding. */
 #define LBM_FP64 0       /* FP64 storage, FP64 arithmetic */
-#define LBM_FP32 1       /* FP32 storage, FP32 arithmetic */
+#define LBM_FP32 1       /* FP32 storage.  Arithmetic: FP64 for the phase
+                            ring and its stencils, the macroscopic quantities
+                            and all five collisions; the FP64 results are
+                            rounded once, to FP32, when stored.  (phi u)(t-1)
+                            is kept in FP32. */
 #define LBM_FP16_STORE 2 /* binary16 storage, FP32 arithmetic */
 #define LBM_BF16_STORE 3 /* bfloat16 storage, FP32 arithmetic */
-#define LBM_FP32_F64 5   /* FP32 storage, FP64 arithmetic */
+#define LBM_FP32_F64 5   /* FP32 storage, FP64 arithmetic throughout, and
+                            (phi u)(t-1) in FP64 */
 
 /* Boundary conditions in y. */
 #define LBM_ELECTRODES 0 /* Eq. (64a): anode/cathode with ion conditions of Sec. 5.1 */
@@ -142,6 +151,13 @@ typedef struct {
                               grad(phi) = 0 and lambda is not small (a droplet's centre),
                               and there it turns rounding into O(1e-5) changes of phi.
                               0: bare form, taken as 0 where |grad(phi)| < 1e-12 */
+  int32_t diag_every;      /* > 0: watchdog.  lbm_ehd_step and lbm_ehd_run check
+                              the state whenever the step count reaches a multiple
+                              of diag_every (the FP64 invariant sums and non-finite
+                              count of lbm_ehd_diagnostics; each check
+                              synchronises the stream) and return LBM_ENONFINITE
+                              as soon as a cell is not finite.  0: no checks */
+  int32_t reserved;        /* 0 */
 } lbm_ehd_params;
 
 /*
@@ -267,11 +283,17 @@ LBM_API lbm_status lbm_ehd_presolve_to(lbm_ehd *h, double tol, int32_t max_iters
 
 /* One time step (poisson_iters extra g sweeps, or with poisson_tol > 0 g sweeps
  * to that tolerance, whose count and residual the diagnostics report as those
- * of the last pre-solve; then the fused sweep of all
- * five equations).  Enqueues work. */
+ * of the last pre-solve; then the fused sweep of all five equations).
+ * Enqueues work (the watchdog of diag_every synchronises at its checks).
+ * LBM_ESTATE before init or for a member of a batch; LBM_ENONFINITE from the
+ * watchdog. */
 LBM_API lbm_status lbm_ehd_step(lbm_ehd *h);
 
-/* nsteps time steps.  Enqueues work. */
+/* nsteps time steps, as many lbm_ehd_step calls.  With poisson_iters = 0 and
+ * poisson_tol = 0, whole blocks of 16 steps are replayed from a HIP graph
+ * captured at the first such block (one graph per parity of the current
+ * buffer; dropped by lbm_ehd_set_launch), bitwise the same as launching the
+ * steps one by one.  Enqueues work; errors as lbm_ehd_step. */
 LBM_API lbm_status lbm_ehd_run(lbm_ehd *h, int64_t nsteps);
 
 /* Macroscopic fields at the current time, FP64, layout [field][ny][nx] for
@@ -292,12 +314,19 @@ LBM_API int64_t lbm_ehd_time(const lbm_ehd *h);
  * buffer, the aux buffer with (phi u)(t-1) and the FP64 rest populations,
  * the step count) fits in *bytes of host memory.  lbm_ehd_save_state copies
  * it out (synchronises); lbm_ehd_load_state copies a saved state into a
- * simulation created with the same grid and storage precision (other
- * parameters may differ) and makes it current: the simulation then
- * continues bitwise as the saved one would have.  The buffer is caller-owned.
- * Not for members of a batch (remove them first).  LBM_EINVAL on a NULL
- * argument or a state of another grid, precision or layout; LBM_ERANGE if
- * the buffer is too small; LBM_ESTATE if saving before init.
+ * simulation created with the same grid and storage precision and makes it
+ * current.  The populations are stored as deviations from references that
+ * depend on some parameters: the wall types (walls, side_walls), dpsi, c0,
+ * the offset of the g references (theta, mask_g, s_free) and, with 16-bit
+ * storage, the ion line offsets (c0, gamma_v, mu_v, m_ratio, reaction) and
+ * the binary16 scales.  The saved state records them, and a load into a
+ * simulation whose references differ is refused (LBM_EINVAL): the same bytes
+ * would stand for another physical state.  Other parameters may differ; with
+ * all parameters equal the simulation continues bitwise as the saved one
+ * would have.  The buffer is caller-owned.  LBM_ESTATE for a member of a
+ * batch (remove it first) or when saving before init; LBM_EINVAL on a NULL
+ * argument or a state of another grid, precision, layout or references;
+ * LBM_ERANGE if the buffer is too small.
  */
 LBM_API lbm_status lbm_ehd_state_bytes(const lbm_ehd *h, size_t *bytes);
 LBM_API lbm_status lbm_ehd_save_state(lbm_ehd *h, void *buffer, size_t bytes);
@@ -324,11 +353,15 @@ LBM_API lbm_status lbm_ehd_get_launch(const lbm_ehd *h, int32_t *waves, int32_t 
  * arithmetic is the same as when it steps alone, so its results are bitwise
  * those of lbm_ehd_run.
  *
- * The batch keeps pointers to its members: they must outlive it (or be
- * removed first).  While in a batch, members are stepped on the batch's
- * stream and must not be stepped on their own; their step counters and
- * current buffers are kept up to date, so lbm_ehd_get_fields and
- * lbm_ehd_diagnostics work on them after lbm_ehd_batch_synchronize.
+ * The batch keeps pointers to its members (lbm_ehd_destroy of a member
+ * removes it from its batch first).  A simulation belongs to at most one
+ * batch.  While in a batch, members are stepped on the batch's stream only:
+ * lbm_ehd_step, lbm_ehd_run, lbm_ehd_presolve, lbm_ehd_presolve_to,
+ * lbm_ehd_init_droplet, lbm_ehd_init_fields, lbm_ehd_load_state and
+ * lbm_ehd_set_launch return LBM_ESTATE for a member.  Their step counters
+ * and current buffers are kept up to date, so lbm_ehd_get_fields,
+ * lbm_ehd_diagnostics and lbm_ehd_save_state work on them after
+ * lbm_ehd_batch_synchronize.
  */
 typedef struct lbm_ehd_batch lbm_ehd_batch;
 

@@ -97,6 +97,13 @@ struct lbm_ehd {
   // private stream (never the legacy default one)
   hipGraphExec_t pre_exec[2] = {nullptr, nullptr};
   hipStream_t cap = nullptr;
+  // Blocks of RUN_BLOCK fused sweeps replayed from a captured graph
+  // (lbm_ehd_run), one per parity of cur against desc_cur; dropped when the
+  // launch shape changes.
+  hipGraphExec_t run_exec[2] = {nullptr, nullptr};
+  // The batch this simulation belongs to (NULL: none).  A member is stepped
+  // by its batch only.
+  lbm_ehd_batch* batch = nullptr;
 };
 
 namespace {
@@ -271,6 +278,10 @@ struct Form {
   // the launch shape changes; never inside a step).
   static lbm_status prepare_sweep(lbm_ehd* h) {
     HIP_TRY(hipStreamSynchronize(h->stream));
+    for (hipGraphExec_t& e : h->run_exec) {
+      if (e) (void)hipGraphExecDestroy(e);
+      e = nullptr;
+    }
     const Desc d = desc(h);
     const std::vector<BatchTile> tl = tile_list({h}, h->waves, h->tile_rows);
     (void)hipFree(h->d_tiles);
@@ -467,6 +478,55 @@ struct Form {
     return sweep(h);
   }
 
+  // `n` time steps.  Steps without extra g-only sweeps are fused sweeps
+  // alone: whole blocks of RUN_BLOCK of them (even, so a block ends in the
+  // buffer it started from) are replayed from a graph captured once per
+  // parity of the state buffer; on small grids a step is a few microseconds
+  // of kernel and launch-bound otherwise.
+  static constexpr int RUN_BLOCK = 16;
+  static lbm_status steps(lbm_ehd* h, int64_t n) {
+    if (h->P.poisson_tol > 0 || h->P.poisson_iters > 0) {
+      for (int64_t i = 0; i < n; ++i) {
+        lbm_status st = step(h);
+        if (st) return st;
+      }
+      return LBM_OK;
+    }
+    if (n >= RUN_BLOCK) {
+      const int par = h->cur ^ h->desc_cur;
+      hipGraphExec_t& exec = h->run_exec[par];
+      if (!exec) {
+        // captured (not run) on a private stream: the handle's stream may be
+        // the legacy default one, which cannot be captured
+        if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        lbm_status cst = LBM_OK;
+        for (int i = 0; i < RUN_BLOCK && !cst; ++i)
+          cst = launch_tiles(h->waves, sweep_form(h->P), h->d_desc, h->d_tiles, h->ntiles,
+                             par ^ (i & 1), h->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->cap, &g);
+        if (!cst && e == hipSuccess) {
+          const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+          if (ie != hipSuccess) {
+            exec = nullptr;
+            cst = fail(LBM_EDEVICE, std::string("graph instantiation: ") + hipGetErrorString(ie));
+          }
+        } else if (!cst) {
+          cst = fail(LBM_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        if (g) (void)hipGraphDestroy(g);
+        if (cst) return cst;
+      }
+      for (; n >= RUN_BLOCK; n -= RUN_BLOCK) HIP_TRY(hipGraphLaunch(exec, h->stream));
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      lbm_status st = sweep(h);
+      if (st) return st;
+    }
+    return LBM_OK;
+  }
+
   static lbm_status presolve(lbm_ehd* h, int iters) {
     const S* g = nullptr;
     lbm_status st = poisson(h, iters, &g);
@@ -498,14 +558,15 @@ struct Form {
     return LBM_OK;
   }
 
-  static lbm_status sums(lbm_ehd* h) {
+  // FP64 sums of the current state: per-row partials into `part` [ny][NSUM],
+  // their column sums in row order into `red` [NSUM].
+  static lbm_status sums_into(lbm_ehd* h, double* part, double* red) {
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
     hipLaunchKernelGGL((k_row_sums<S, R, T0>), dim3(h->P.ny), dim3(256), 0, h->stream, src,
-                       h0(h, h->cur), h->part, kp);
+                       h0(h, h->cur), part, kp);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, h->part, h->P.ny, NSUM,
-                       h->red);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, part, h->P.ny, NSUM, red);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -690,6 +751,7 @@ lbm_status validate(const lbm_ehd_params* p) {
   if (p->poisson_tol > 0 && (p->poisson_iters < 1 || p->poisson_max < 1))
     return fail(LBM_EINVAL, "poisson_tol > 0 needs poisson_iters >= 1 and poisson_max >= 1");
   if (p->poisson_iters < 0) return fail(LBM_EINVAL, "poisson_iters < 0");
+  if (p->diag_every < 0) return fail(LBM_EINVAL, "diag_every < 0");
   if (!finite_all({p->rho_v, p->rho_r, p->eta_v, p->eta_r, p->M_phi, p->W, p->zeta, p->theta,
                    p->dpsi, p->eps_v, p->eps_r, p->mu_v, p->mu_r, p->m_ratio, p->v_th, p->c0,
                    p->q, p->gamma_v, p->force_x, p->force_y, p->s_free, p->n_eps}))
@@ -716,6 +778,8 @@ lbm_status validate(const lbm_ehd_params* p) {
 
 void free_scratch(lbm_ehd* h) {
   for (hipGraphExec_t& e : h->pre_exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  for (hipGraphExec_t& e : h->run_exec)
     if (e) (void)hipGraphExecDestroy(e);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   (void)hipFree(h->d_desc);
@@ -783,6 +847,40 @@ bool span(const double* v, int n, double start, double* len) {
   if (std::isnan(hi) || std::isnan(lo)) return false;
   *len = hi - lo;
   return true;
+}
+
+// Entry points that move or replace a simulation's state refuse members of
+// a batch: the batch holds uploaded descriptors (current buffer, step) and a
+// captured graph of them, which such a call would make stale.
+lbm_status not_member(const lbm_ehd* h, const char* what) {
+  if (h->batch)
+    return fail(LBM_ESTATE, std::string(what) + ": the simulation is a member of a batch "
+                                                "(remove it from the batch first)");
+  return LBM_OK;
+}
+
+// FP64 invariant sums of the current state into out[NSUM] (the layout of
+// k_row_sums), with the per-row partials in `part` [ny][NSUM] and the
+// result in `red` [NSUM]; synchronises.
+lbm_status read_sums(lbm_ehd* h, double* part, double* red, double out[NSUM]) {
+  lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::sums_into(h, part, red); });
+  if (st) return st;
+  HIP_TRY(hipMemcpyAsync(out, red, NSUM * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+// The watchdog of lbm_ehd_params.diag_every: check the state when the step
+// count is a multiple of diag_every.
+lbm_status watchdog(lbm_ehd* h) {
+  if (h->P.diag_every <= 0 || h->step % h->P.diag_every) return LBM_OK;
+  double r[NSUM];
+  lbm_status st = read_sums(h, h->part, h->red, r);
+  if (st) return st;
+  if (r[6] != 0 || !std::isfinite(r[0]) || !std::isfinite(r[1]))
+    return fail(LBM_ENONFINITE, "watchdog: " + std::to_string((long long)r[6]) +
+                                    " cells not finite at step " + std::to_string(h->step));
+  return LBM_OK;
 }
 
 }  // namespace
@@ -945,6 +1043,7 @@ lbm_status lbm_ehd_create(const lbm_ehd_params* p, const lbm_ehd_device* dev, lb
 lbm_status lbm_ehd_init_droplet(lbm_ehd* h, double xc, double yc, double radius, double noise,
                                 uint64_t seed) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (lbm_status ms = not_member(h, "init")) return ms;
   if (!finite_all({xc, yc, radius, noise})) return fail(LBM_EINVAL, "non-finite argument");
   if (noise < 0 || noise >= 1) return fail(LBM_EINVAL, "noise must lie in [0, 1)");
   if (h->P.walls != LBM_PERIODIC && radius > 0 &&
@@ -973,6 +1072,7 @@ lbm_status lbm_ehd_init_fields(lbm_ehd* h, const double* phi, const double* cp,
                                const double* cm, const double* psi, const double* ux,
                                const double* uy) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (lbm_status ms = not_member(h, "init")) return ms;
   if (!phi || !cp || !cm || !psi) return fail(LBM_EINVAL, "phi, cp, cm and psi are required");
   const size_t nc = (size_t)h->P.nx * h->P.ny;
   if (!h->upl) HIP_TRY(hipMalloc(&h->upl, 6 * nc * sizeof(double)));
@@ -1002,6 +1102,7 @@ lbm_status lbm_ehd_init_fields(lbm_ehd* h, const double* phi, const double* cp,
 
 lbm_status lbm_ehd_presolve(lbm_ehd* h, int32_t iters) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (lbm_status ms = not_member(h, "presolve")) return ms;
   if (!h->ready) return fail(LBM_ESTATE, "presolve before init");
   if (iters < 0) return fail(LBM_EINVAL, "iters < 0");
   if (iters == 0) return LBM_OK;
@@ -1013,6 +1114,7 @@ lbm_status lbm_ehd_presolve(lbm_ehd* h, int32_t iters) {
 lbm_status lbm_ehd_presolve_to(lbm_ehd* h, double tol, int32_t max_iters, int32_t check_every,
                                int32_t* iters, double* residual) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (lbm_status ms = not_member(h, "presolve")) return ms;
   if (!h->ready) return fail(LBM_ESTATE, "presolve before init");
   if (!(tol > 0) || max_iters < 1 || check_every < 1)
     return fail(LBM_EINVAL, "need tol > 0, max_iters >= 1, check_every >= 1");
@@ -1028,20 +1130,23 @@ lbm_status lbm_ehd_presolve_to(lbm_ehd* h, double tol, int32_t max_iters, int32_
   return LBM_OK;
 }
 
-lbm_status lbm_ehd_step(lbm_ehd* h) {
-  if (!h) return fail(LBM_EINVAL, "handle is NULL");
-  if (!h->ready) return fail(LBM_ESTATE, "step before init");
-  lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::step(h); });
-  if (st) return st;
-  h->step += 1;
-  return LBM_OK;
-}
+lbm_status lbm_ehd_step(lbm_ehd* h) { return lbm_ehd_run(h, 1); }
 
 lbm_status lbm_ehd_run(lbm_ehd* h, int64_t nsteps) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
-  for (int64_t i = 0; i < nsteps; ++i) {
-    lbm_status st = lbm_ehd_step(h);
+  if (!h->ready) return fail(LBM_ESTATE, "step before init");
+  lbm_status st = not_member(h, "step");
+  if (st) return st;
+  while (nsteps > 0) {
+    // up to the next multiple of diag_every, where the watchdog checks
+    int64_t n = nsteps;
+    if (h->P.diag_every > 0) n = std::min<int64_t>(n, h->P.diag_every - h->step % h->P.diag_every);
+    st = dispatch(h, [&](auto F) { return decltype(F)::steps(h, n); });
+    if (st) return st;
+    h->step += n;
+    nsteps -= n;
+    st = watchdog(h);
     if (st) return st;
   }
   return LBM_OK;
@@ -1072,11 +1177,9 @@ lbm_status lbm_ehd_get_fields(lbm_ehd* h, uint32_t mask, double* out, size_t n_d
 lbm_status lbm_ehd_diagnostics(lbm_ehd* h, lbm_ehd_diag* out) {
   if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
   if (!h->ready) return fail(LBM_ESTATE, "diagnostics before init");
-  lbm_status st = dispatch(h, [&](auto F) { return decltype(F)::sums(h); });
-  if (st) return st;
   double r[NSUM];
-  HIP_TRY(hipMemcpyAsync(r, h->red, sizeof r, hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(hipStreamSynchronize(h->stream));
+  lbm_status st = read_sums(h, h->part, h->red, r);
+  if (st) return st;
   out->step = h->step;
   out->sum_phi = r[0];
   out->sum_rhoe = r[1];
@@ -1123,6 +1226,7 @@ int64_t lbm_ehd_time(const lbm_ehd* h) { return h ? h->step : -1; }
 
 lbm_status lbm_ehd_set_launch(lbm_ehd* h, int32_t waves, int32_t tile_rows) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (lbm_status ms = not_member(h, "set_launch")) return ms;
   if (waves != 1 && waves != 2 && waves != 4 && waves != 8)
     return fail(LBM_EINVAL, "waves must be 1, 2, 4 or 8");
   if (tile_rows < 1) return fail(LBM_EINVAL, "tile_rows must be >= 1");
@@ -1140,6 +1244,32 @@ lbm_status lbm_ehd_get_launch(const lbm_ehd* h, int32_t* waves, int32_t* tile_ro
 
 namespace {
 
+// What the stored deviations of a state are measured against: the wall
+// types (which also fix the reference potential's shape), the anode
+// potential, c0, the offset a_g of the g references, the ion line offsets
+// and the binary16 scales.  A state read with other values would stand for
+// another physical state.
+struct RefSig {
+  int32_t walls, side_walls;
+  double dpsi, c0, a_g;
+  double iofs[10], sc[5];
+};
+
+RefSig ref_sig(const lbm_ehd* h) {
+  RefSig r;
+  std::memset(&r, 0, sizeof r);
+  const KP<double> k = make_kp<double>(h);
+  r.walls = h->P.walls;
+  r.side_walls = h->P.side_walls;
+  r.dpsi = h->P.dpsi;
+  r.c0 = h->P.c0;
+  r.a_g = k.a_g;
+  if (elem_size(h->P.precision) == 2)  // the offsets and scales are used by 16-bit storage only
+    for (int i = 0; i < 10; ++i) r.iofs[i] = k.iofs[i];
+  for (int i = 0; i < 5; ++i) r.sc[i] = k.sc[i];
+  return r;
+}
+
 // Header of a saved state.
 struct SavedState {
   uint64_t magic;
@@ -1147,8 +1277,9 @@ struct SavedState {
   int64_t step;
   int32_t cur, reserved;
   uint64_t pop_bytes, aux_bytes;
+  RefSig ref;
 };
-constexpr uint64_t STATE_MAGIC = 0x3130455441545345ull;  // "ESTATE01"
+constexpr uint64_t STATE_MAGIC = 0x3230455441545345ull;  // "ESTATE02"
 
 }  // namespace
 
@@ -1174,6 +1305,7 @@ lbm_status lbm_ehd_save_state(lbm_ehd* h, void* buffer, size_t bytes) {
   hd.cur = h->cur;
   hd.pop_bytes = h->pop_bytes;
   hd.aux_bytes = h->aux_bytes;
+  hd.ref = ref_sig(h);
   char* out = static_cast<char*>(buffer);
   std::memcpy(out, &hd, sizeof hd);
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1184,6 +1316,7 @@ lbm_status lbm_ehd_save_state(lbm_ehd* h, void* buffer, size_t bytes) {
 
 lbm_status lbm_ehd_load_state(lbm_ehd* h, const void* buffer, size_t bytes) {
   if (!h || !buffer) return fail(LBM_EINVAL, "NULL argument");
+  if (lbm_status ms = not_member(h, "load_state")) return ms;
   if (bytes < sizeof(SavedState)) return fail(LBM_ERANGE, "state buffer too small");
   SavedState hd;
   std::memcpy(&hd, buffer, sizeof hd);
@@ -1192,6 +1325,11 @@ lbm_status lbm_ehd_load_state(lbm_ehd* h, const void* buffer, size_t bytes) {
       hd.pitch != h->pitch || hd.pop_bytes != h->pop_bytes || hd.aux_bytes != h->aux_bytes ||
       (hd.cur != 0 && hd.cur != 1))
     return fail(LBM_EINVAL, "state of another grid, precision or layout");
+  const RefSig mine = ref_sig(h);
+  if (std::memcmp(&hd.ref, &mine, sizeof mine) != 0)
+    return fail(LBM_EINVAL,
+                "state stored against other references (walls, side walls, dpsi, c0, theta and "
+                "the g rates, or the 16-bit ion offsets and scales differ)");
   if (bytes < sizeof hd + hd.pop_bytes + hd.aux_bytes)
     return fail(LBM_ERANGE, "state buffer too small");
   const char* in = static_cast<const char*>(buffer);
@@ -1213,6 +1351,7 @@ lbm_status lbm_ehd_synchronize(lbm_ehd* h) {
 
 lbm_status lbm_ehd_destroy(lbm_ehd* h) {
   if (!h) return LBM_OK;
+  if (h->batch) (void)lbm_ehd_batch_remove(h->batch, h);  // waits for the batch's work
   (void)hipStreamSynchronize(h->stream);
   free_scratch(h);
   delete h;
@@ -1261,6 +1400,7 @@ lbm_status batch_prepare(lbm_ehd_batch* b) {
 lbm_status batch_check_member(const lbm_ehd_batch* b, const lbm_ehd* h) {
   if (!h) return fail(LBM_EINVAL, "NULL member");
   if (!h->ready) return fail(LBM_ESTATE, "batch member not initialised");
+  if (h->batch && h->batch != b) return fail(LBM_EINVAL, "simulation is a member of another batch");
   if (h->P.precision != b->precision) return fail(LBM_EINVAL, "batch members differ in precision");
   if (h->P.poisson_iters != 0 || h->P.poisson_tol > 0)
     return fail(LBM_EINVAL, "batch members need poisson_iters = 0 and poisson_tol = 0");
@@ -1316,6 +1456,7 @@ lbm_status lbm_ehd_batch_create(lbm_ehd* const* sims, int32_t n, void* stream,
       return fail(st, msg);
     }
     b->sims.push_back(sims[i]);
+    sims[i]->batch = b;
   }
   *out = b;
   return LBM_OK;
@@ -1329,6 +1470,7 @@ lbm_status lbm_ehd_batch_add(lbm_ehd_batch* b, lbm_ehd* h) {
   // the member's own pending work must be done before the batch stream uses it
   if (h->stream != b->stream) HIP_TRY(hipStreamSynchronize(h->stream));
   b->sims.push_back(h);
+  h->batch = b;
   b->dirty = true;
   return LBM_OK;
 }
@@ -1340,6 +1482,7 @@ lbm_status lbm_ehd_batch_remove(lbm_ehd_batch* b, lbm_ehd* h) {
   // the member's state must be complete before it is used on its own stream
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->sims.erase(it);
+  h->batch = nullptr;
   b->dirty = true;
   return LBM_OK;
 }
@@ -1469,6 +1612,7 @@ lbm_status lbm_ehd_batch_synchronize(lbm_ehd_batch* b) {
 lbm_status lbm_ehd_batch_destroy(lbm_ehd_batch* b) {
   if (!b) return LBM_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (lbm_ehd* h : b->sims) h->batch = nullptr;
   batch_drop_graph(b);
   (void)hipFree(b->d_desc);
   (void)hipFree(b->d_tiles);

@@ -50,7 +50,7 @@ class lbm_ehd_params(ctypes.Structure):
         ("c0", ctypes.c_double), ("q", ctypes.c_double), ("gamma_v", ctypes.c_double),
         ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
         ("s_free", ctypes.c_double), ("poisson_tol", ctypes.c_double),
-        ("n_eps", ctypes.c_double),
+        ("n_eps", ctypes.c_double), ("diag_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     # int32 block then doubles, no padding surprises
-    assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 18 * 4 + 23 * 8
+    assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 18 * 4 + 23 * 8 + 2 * 4
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_diag) == 11 * 8
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_request_info) == 8 + 4 + 4 + 2 * 8 + 3 * 8 + 8 + 11 * 8
 
@@ -54,7 +54,7 @@ def test_defaults_and_bytes():
                                  dict(theta=-0.1), dict(precision=7), dict(walls=5),
                                  dict(W=float("nan")), dict(s_free=2.0), dict(side_walls=2), dict(local_field=2), dict(poisson_tol=-1.0),
                                  dict(poisson_tol=1e-3), dict(poisson_tol=1e-3, poisson_iters=1),
-                                 dict(n_eps=-1.0),
+                                 dict(n_eps=-1.0), dict(diag_every=-1),
                                  dict(nx=20000, ny=20000)])
 def test_invalid_parameters_rejected(bad):
     p = lbm_ehd.make_params(**bad)
