@@ -73,6 +73,118 @@ def test_laplace_law(orc):
     assert abs(slope / zeta - 1) < 0.08
 
 
+def test_translating_interface_with_density_contrast(orc):
+    """Two flat interfaces of a rho_r = 2 layer in a y-periodic box, no
+    surface tension or field, all moving at U across the interfaces: the
+    layer must translate rigidly at U (Galilean invariance).  This pins the
+    density terms of the pressure-based scheme, the 1/2 u.grad(rho) of
+    Eq. (57) and u.grad(rho) in the forcing of Eq. (54): with the pressure
+    term dropped the velocity is 50 % off within 2000 steps and the layer
+    loses its shape, with its sign flipped 113 % (planted in the oracle)."""
+    ny, nx, W, U, T = 64, 4, 4.0, 0.01, 2000
+    y = _rows(ny, nx)
+    phi = 0.5 * (1 + np.tanh(2 * (y - 16) / W)) * 0.5 * (1 + np.tanh(2 * (48 - y) / W))
+    o = orc.Oracle(dict(nx=nx, ny=ny, walls=2, q=0.0, dpsi=0.0, rho_r=2.0, zeta=0.0, W=W,
+                        eta_v=0.1))
+    o.init_fields(phi, 1.0, 1.0, 0.0, 0.0, U)
+    o.step(T)
+    f = o.fields()
+    assert abs(f["uy"] - U).max() <= 0.03 * U      # measured 1.9e-2
+    assert abs(f["ux"]).max() <= 1e-15
+    moved = np.roll(phi[:, 0], int(round(U * T)))  # 20 rows up
+    assert abs(f["phi"][:, 0] - moved).max() <= 0.015   # measured 7.5e-3
+    assert np.ptp(f["p"]) <= 2e-4                  # measured 7.8e-5 (rho U^2 = 1e-4)
+
+
+# --------------------------------------------------------------------------
+# Electric forces (Eq. 14)
+# --------------------------------------------------------------------------
+def test_coulomb_force_balances_the_pressure_gradient(orc):
+    """A uniformly charged layer at rest between the electrodes (ion-tight
+    walls; ions so slow that the charge stays uniform; converged Poisson)
+    reaches hydrostatic balance: the pressure gradient equals the Coulomb
+    force density rho_e E of Eq. (14) in every interior row.  E itself
+    follows the closed form of the uniform-charge parabola.  A flipped sign
+    of rho_e E gives a residual of 2 (planted in the oracle)."""
+    ny, nx, dpsi, a, q = 32, 4, 0.5, 0.1, 1e-3
+    o = orc.Oracle(dict(nx=nx, ny=ny, dpsi=dpsi, q=q, walls=1, reaction=0, ion_force=0,
+                        mu_v=1e-5, v_th=1e4, eta_v=0.1, zeta=0.0))
+    y = _rows(ny, nx)
+    o.init_fields(0.0, 1.0 + a, 1.0 - a, dpsi * (ny - 0.5 - y) / ny)
+    o.presolve(30000)
+    o.step(16000)
+    f = o.fields()
+    rho, E, p = f["rhoe"][:, 0], f["Ey"][:, 0], f["p"][:, 0]
+    assert abs(rho / (2 * q * a) - 1).max() < 1e-3
+    yy = np.arange(ny)
+    Ec = dpsi / ny - q * a * (ny - 1 - 2 * yy)       # E = -psi' of the parabola
+    assert abs(E - Ec)[1:-1].max() <= 2e-5 * abs(Ec).max()
+    F = rho * E
+    dpdy = (p[2:] - p[:-2]) / 2                      # exact for the quadratic p
+    res = (dpdy - F[1:-1]) / abs(F).max()
+    assert abs(res[1:-1]).max() <= 1e-5              # measured 5e-7
+    assert abs(f["uy"]).max() < 1e-7
+
+
+def test_dielectric_force_gives_the_maxwell_pressure_jump(orc):
+    """A flat eps_r = 4 layer normal to the field, no free charge, no
+    surface tension, converged variable-eps Poisson (eps E = D uniform).
+    The polarisation force -1/2 |E|^2 grad(eps) of Eq. (14) is balanced by
+    the pressure, whose jump across the layer is the closed form
+    -1/2 int E^2 d(eps) = 1/2 D^2 (1/eps_top - 1/eps_bottom), whatever the
+    profile.  A factor 2 on the term gives +106 %, a flipped sign -203 %
+    (planted in the oracle)."""
+    ny, nx, W, epsr = 64, 4, 8.0, 4.0
+    y = _rows(ny, nx)
+    phi = 0.5 * (1 + np.tanh(2 * (y - (ny - 1) / 2) / W))
+    o = orc.Oracle(dict(nx=nx, ny=ny, dpsi=1.0, q=0.0, eps_r=epsr, zeta=0.0, W=W, eta_v=0.5))
+    o.init_fields(phi, 1.0, 1.0, (ny - 0.5 - y) / ny)
+    o.presolve(30000)
+    o.step(16000)
+    f = o.fields()
+    ph, E, p = f["phi"][:, 0], f["Ey"][:, 0], f["p"][:, 0]
+    D = (1.0 + (epsr - 1.0) * ph) * E
+    assert np.ptp(D) <= 0.03 * D.mean()              # measured 2.2 %
+    jump = p[-4:].mean() - p[:4].mean()
+    expect = 0.5 * D.mean() ** 2 * (1.0 / (epsr * 1.0) - 1.0 / 1.0)
+    assert abs(jump / expect - 1) <= 0.02            # measured 0.8 %
+    assert abs(f["uy"]).max() < 1e-7
+
+
+# --------------------------------------------------------------------------
+# Initial state
+# --------------------------------------------------------------------------
+def test_initial_droplet_profile(orc):
+    """The initial droplet is 1/2 [1 + tanh(2 (R - r)/W)] around the given
+    centre: 1/2 exactly on the circle r = R (lattice points of the 3-4-5
+    triangle), 1/2 (1 +- tanh 1) at r = R -+ W/2, and everywhere the profile
+    whose normal slope is 4 phi (1 - phi)/W (Eq. 2).  A width off by a
+    factor 2 gives 0.7311 instead of 0.8808 (planted in the oracle)."""
+    n, R, W = 64, 5.0, 2.0
+    o = orc.Oracle(dict(nx=n, ny=n, W=W, q=0.0, dpsi=0.0))
+    o.init_droplet(32.0, 32.0, R)
+    ph = o.fields()["phi"]
+    for yx in ((36, 35), (35, 36), (32, 37), (28, 29), (27, 32)):     # r = 5
+        assert abs(ph[yx] - 0.5) <= 1e-15
+    t1 = np.tanh(1.0)
+    assert abs(ph[32, 36] - 0.5 * (1 + t1)) <= 1e-15                  # r = 4 = R - W/2
+    assert abs(ph[32, 38] - 0.5 * (1 - t1)) <= 1e-15                  # r = 6 = R + W/2
+    yy, xx = np.mgrid[0:n, 0:n]
+    r = np.hypot(xx - 32.0, yy - 32.0)
+    z = 0.5 * W * np.arctanh(np.clip(2 * ph - 1, -1 + 1e-15, 1 - 1e-15))
+    ok = (r > 1) & (np.abs(r - R) < 4)
+    assert abs((R - r - z)[ok]).max() <= 1e-9
+    # a wide interface, where central differences resolve it: along the x
+    # axis the slope is d phi/dr = -4 phi (1 - phi)/W
+    n, R, W = 160, 40.0, 16.0
+    o = orc.Oracle(dict(nx=n, ny=n, W=W, q=0.0, dpsi=0.0))
+    o.init_droplet(80.0, 80.0, R)
+    x = o.fields()["phi"][80, 80 + 20:80 + 61]      # r = 20 .. 60
+    slope = (x[2:] - x[:-2]) / 2
+    exact = -4 * x[1:-1] * (1 - x[1:-1]) / W
+    assert abs(slope - exact).max() <= 0.01 * abs(exact).max()
+
+
 # --------------------------------------------------------------------------
 # Allen-Cahn (Eq. 27-33)
 # --------------------------------------------------------------------------
