@@ -61,8 +61,20 @@ def measured_traffic(workload: str, waves: int, tile_rows: int):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(params, drop, steps: int):
-    """The CPU oracle (plain FP64 C, OpenMP) on the same grid, few steps."""
+def _omp_threads(n: int):
+    """Set the OpenMP thread count of the oracle's runtime (libgomp, already
+    loaded by the oracle); returns the previous count."""
+    import ctypes
+
+    gomp = ctypes.CDLL("libgomp.so.1")
+    prev = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(int(n))
+    return prev
+
+
+def cpu_baseline(params, drop, steps: int, steps_1t: int):
+    """The CPU oracle (plain FP64 C, OpenMP) on the same grid, few steps, on
+    the host's threads and on one thread."""
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -73,10 +85,19 @@ def cpu_baseline(params, drop, steps: int):
     o.step(steps)
     dt = time.perf_counter() - t0
     cells = params["nx"] * params["ny"]
-    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": "%dx%d droplet case, %d steps after 1 warm-up step, FP64, %.1f s"
-                      % (params["nx"], params["ny"], steps, dt)}
+    out = {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
+           "kind": "oracle",
+           "sample": "%dx%d droplet case, %d steps after 1 warm-up step, FP64, %.1f s"
+                     % (params["nx"], params["ny"], steps, dt)}
+    if steps_1t > 0:
+        prev = _omp_threads(1)
+        t0 = time.perf_counter()
+        o.step(steps_1t)
+        dt1 = time.perf_counter() - t0
+        _omp_threads(prev)
+        out["one_core"] = {"value": cells * steps_1t / dt1 / 1e6, "unit": "MLUPS", "cores": 1,
+                           "sample": "%d further steps on one thread, %.1f s" % (steps_1t, dt1)}
+    return out
 
 
 def copy_calibration(gib: float, reps: int, width: int):
@@ -223,6 +244,63 @@ def bench_batched(args):
         "D_err_vs_fp32_alone_max": max(errs), "D_err_members": list(range(0, len(members), 8)),
     }
     print(json.dumps(line), flush=True)
+
+
+def batched_summary(members=64, steps=10000):
+    """The batched form as timed in the default run: the 64 droplets of
+    128^2-1024^2 (seeded Latin hypercube), FP16 storage, autotuned launch
+    shape, `steps` steps each, from created members to the last step."""
+    import torch
+
+    from paper_2501_04920_amd import lbm_ehd, workloads
+
+    ms = workloads.config4_members(count=members, steps=steps)
+    sims = []
+    for m in ms:
+        p, d = m["params"], m["droplet"]
+        s = lbm_ehd.Simulation(dict(p, precision="fp16"), device="cuda:0")
+        s.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"])
+        sims.append(s)
+    torch.cuda.synchronize()
+    b = lbm_ehd.Batch(sims)
+    t0 = time.perf_counter()
+    waves, rows, taken = b.autotune(10)
+    b.run(steps - taken)
+    b.synchronize()
+    wall = time.perf_counter() - t0
+    cells = sum(m["params"]["nx"] * m["params"]["ny"] for m in ms)
+    bad = sum(s.diagnostics()["nonfinite"] for s in sims)
+    b.close()
+    for s in sims:
+        s.close()
+    return {"metric": "sweep solves/hr", "value": round(len(ms) * 3600.0 / wall, 1),
+            "unit": "solves/hr", "wall_s": round(wall, 3),
+            "workload": "batched-%d-droplets-128-1024-%dsteps" % (len(ms), steps),
+            "storage": "fp16", "cells": cells, "aggregate_glups": round(cells * steps / wall / 1e9, 3),
+            "waves": waves, "tile_rows": rows, "autotune_steps": taken, "nonfinite": int(bad)}
+
+
+def serving_summary(requests=64, rate=20.0, budget_gib=64.0, block=256):
+    """The serving form as timed in the default run: the first `requests`
+    requests of the seeded trace (Poisson arrivals at `rate` per second,
+    grids 64^2-2048^2, 2k-50k steps), replayed in real time through the
+    request server (HBM admission, continuous batching, FP16 storage)."""
+    import numpy as np
+
+    from paper_2501_04920_amd import lbm_ehd, workloads
+
+    trace = workloads.config5_trace(count=requests, rate=rate)
+    done, span, maxrun = _serve_trace(trace, int(budget_gib * (1 << 30)), block)
+    lat = np.array([v[0] for v in done.values()])
+    work = sum(v[1] for v in done.values())
+    failed = sum(1 for v in done.values() if v[2] != lbm_ehd.REQ_DONE)
+    return {"metric": "p99 latency", "value": round(float(np.percentile(lat, 99)), 3), "unit": "s",
+            "p50_s": round(float(np.percentile(lat, 50)), 3),
+            "throughput_req_per_s": round(len(trace) / span, 3),
+            "aggregate_glups": round(work / span / 1e9, 3), "makespan_s": round(span, 2),
+            "workload": "serving-%d-requests-64-2048-rate%g" % (len(trace), rate),
+            "storage": "fp16", "hbm_budget_gib": budget_gib, "max_running": maxrun,
+            "failed": failed}
 
 
 ENCLOSURE_STUDY = (
@@ -414,6 +492,12 @@ def main():
     ap.add_argument("--n", type=int, default=2048,
                     help="grid n x n (radius n / 6.4, W = 5; 128: the 128^2 parity case, W = 4)")
     ap.add_argument("--cpu-steps", type=int, default=64)
+    ap.add_argument("--cpu-steps-1t", type=int, default=4,
+                    help="further oracle steps on one thread (0: skip)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="leave out the batched and serving sub-objects of the default line")
+    ap.add_argument("--form-requests", type=int, default=64,
+                    help="requests of the serving sub-object (first of the seeded trace)")
     ap.add_argument("--waves", type=int, default=0,
                     help="wavefronts per sweep workgroup (1, 2, 4, 8; 0 = library default)")
     ap.add_argument("--tile-rows", type=int, default=0,
@@ -508,8 +592,15 @@ def main():
 
     cells = params["nx"] * params["ny"]
     mlups = cells * args.steps / wall / 1e6
-    bpl = lbm_ehd.lbm_ehd_bytes_per_lup(args.precision)
-    achieved = bpl * cells / (kern_ms * 1e-3) / 1e9
+    # algorithmic bytes per lattice update: the 33 populations read and
+    # written once in the storage type, plus (phi u)(t-1) read and written
+    # (FP32; FP64 in the FP64 forms); the layout's own count (FP64 rest
+    # populations, reference lines) is reported beside it
+    s_bytes = {"fp64": 8, "fp32": 4, "fp32f64": 4, "fp16": 2, "bf16": 2}[args.precision]
+    j_bytes = 8 if args.precision in ("fp64", "fp32f64") else 4
+    alg = 2 * 33 * s_bytes + 2 * 2 * j_bytes
+    design = lbm_ehd.lbm_ehd_bytes_per_lup(args.precision)
+    achieved = alg * cells / (kern_ms * 1e-3) / 1e9
     diag = sim.diagnostics()
     traffic = measured_traffic(workload, waves, tile_rows)
     line = {
@@ -523,16 +614,24 @@ def main():
         "config": {"workload": workload, "nx": params["nx"], "ny": params["ny"],
                    "radius": drop["radius"], "W": params["W"], "storage": args.precision,
                    "poisson_sweeps_per_step": 1 + params["poisson_iters"],
-                   "bytes_per_lup": bpl, "waves": waves, "tile_rows": tile_rows},
+                   "bytes_per_lup": alg, "layout_bytes_per_lup": design, "waves": waves,
+                   "tile_rows": tile_rows},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_sweep_batch",
-                     "kernel_ms": round(kern_ms, 5)},
+                     "kernel_ms": round(kern_ms, 5),
+                     "layout_frac": round(design * cells / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "check": {"sum_phi": diag["sum_phi"], "nonfinite": diag["nonfinite"]},
     }
     sim.close()
+    print("single: %.1f MLUPS, kernel %.4f ms" % (mlups, kern_ms), file=sys.stderr, flush=True)
+    if not args.no_forms:
+        line["batched"] = batched_summary()
+        print("batched: %s solves/hr" % line["batched"]["value"], file=sys.stderr, flush=True)
+        line["serving"] = serving_summary(requests=args.form_requests)
+        print("serving: p99 %s s" % line["serving"]["value"], file=sys.stderr, flush=True)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(params, drop, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(params, drop, args.cpu_steps, args.cpu_steps_1t)
     print(json.dumps(line), flush=True)
 
 
