@@ -306,6 +306,20 @@ LBM_API lbm_status lbm_ehd_get_fields(lbm_ehd *h, uint32_t mask, double *out, si
  * LBM_ENONFINITE (after filling *out) if any cell is not finite. */
 LBM_API lbm_status lbm_ehd_diagnostics(lbm_ehd *h, lbm_ehd_diag *out);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): lbm_ehd_diagnostics without the
+ * deformation factor, allocating nothing.  Fills step, sum_phi, sum_rhoe,
+ * sum_p, sum_n, nonfinite and the pre-solve fields exactly as
+ * lbm_ehd_diagnostics does (the same kernels and summation order), and sets
+ * D, L and H to NaN.  The per-row partial sums live in a static device
+ * array of the library, one per GPU, for grids of up to 16384 rows (0.9 MB,
+ * held until the process ends); it keeps the last call's contents, and
+ * calls that overlap on one GPU (from several threads or streams) race on
+ * it.  No hipMalloc, hipFree or allocating library call is made.
+ * Synchronises.  LBM_ERANGE if ny > 16384; LBM_ESTATE before init;
+ * LBM_ENONFINITE (after filling *out) if any cell is not finite. */
+LBM_API lbm_status lbm_ehd_invariants_noalloc(lbm_ehd *h, lbm_ehd_diag *out);
+
 /* Current step count. */
 LBM_API int64_t lbm_ehd_time(const lbm_ehd *h);
 

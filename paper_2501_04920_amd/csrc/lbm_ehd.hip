@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,6 +17,15 @@
 #include "lbm_ehd_kernels.hpp"
 
 using namespace lbm;
+
+// Scratch of lbm_ehd_invariants_noalloc, which allocates nothing: the
+// per-row partial sums [ny][NSUM] and their total [NSUM], for grids of up to
+// NOALLOC_MAX_ROWS rows (0.9 MB).  Every GPU the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in: its device address on each GPU comes from hipGetSymbolAddress
+// (noalloc_scratch) and only that address is ever passed on.
+constexpr int NOALLOC_MAX_ROWS = 16384;
+static __device__ __align__(256) double scratch[(NOALLOC_MAX_ROWS + 1) * NSUM];
 
 namespace {
 
@@ -870,6 +880,31 @@ lbm_status read_sums(lbm_ehd* h, double* part, double* red, double out[NSUM]) {
   return LBM_OK;
 }
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device `dev`, looked up once per device
+// with that device current.
+lbm_status noalloc_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    int prev = -1;
+    HIP_TRY(hipGetDevice(&prev));
+    if (prev != dev) HIP_TRY(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != dev) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !ptr)
+      return fail(LBM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                   hipGetErrorString(e));
+    g_scratch[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return LBM_OK;
+}
+
 // The watchdog of lbm_ehd_params.diag_every: check the state when the step
 // count is a multiple of diag_every.
 lbm_status watchdog(lbm_ehd* h) {
@@ -1219,6 +1254,32 @@ lbm_status lbm_ehd_diagnostics(lbm_ehd* h, lbm_ehd_diag* out) {
       out->D = (L - H) / (L + H);
     }
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_ehd_invariants_noalloc(lbm_ehd* h, lbm_ehd_diag* out) {
+  if (!h || !out) return fail(LBM_EINVAL, "NULL argument");
+  if (!h->ready) return fail(LBM_ESTATE, "invariants before init");
+  if (h->P.ny > NOALLOC_MAX_ROWS)
+    return fail(LBM_ERANGE, "lbm_ehd_invariants_noalloc: ny = " + std::to_string(h->P.ny) +
+                                " exceeds its scratch of " + std::to_string(NOALLOC_MAX_ROWS) +
+                                " rows (use lbm_ehd_diagnostics)");
+  double* sc = nullptr;
+  lbm_status st = noalloc_scratch(h->device, &sc);
+  if (st) return st;
+  double r[NSUM];
+  st = read_sums(h, sc, sc + (size_t)NOALLOC_MAX_ROWS * NSUM, r);
+  if (st) return st;
+  out->step = h->step;
+  out->sum_phi = r[0];
+  out->sum_rhoe = r[1];
+  out->sum_p = r[2];
+  out->sum_n = r[3];
+  out->nonfinite = (int64_t)r[6];
+  out->D = out->L = out->H = NAN;
+  out->presolve_iters = h->presolve_iters;
+  out->presolve_residual = h->presolve_residual;
+  if (out->nonfinite) return fail(LBM_ENONFINITE, "state contains NaN or Inf");
   return LBM_OK;
 }
 

@@ -133,6 +133,7 @@ def lib() -> ctypes.CDLL:
             "lbm_ehd_run": [vp, ctypes.c_int64],
             "lbm_ehd_get_fields": [vp, ctypes.c_uint32, _dp, ctypes.c_size_t],
             "lbm_ehd_diagnostics": [vp, P(lbm_ehd_diag)],
+            "lbm_ehd_invariants_noalloc": [vp, P(lbm_ehd_diag)],
             "lbm_ehd_synchronize": [vp],
             "lbm_ehd_destroy": [vp],
             "lbm_ehd_state_bytes": [vp, P(ctypes.c_size_t)],
@@ -267,6 +268,14 @@ def lbm_ehd_get_fields(h, ny, nx, mask=0x3FF) -> np.ndarray:
 def lbm_ehd_diagnostics(h) -> lbm_ehd_diag:
     d = lbm_ehd_diag()
     code = lib().lbm_ehd_diagnostics(h, ctypes.byref(d))
+    if code not in (LBM_OK, LBM_ENONFINITE):
+        _check(code)
+    return d
+
+
+def lbm_ehd_invariants_noalloc(h) -> lbm_ehd_diag:
+    d = lbm_ehd_diag()
+    code = lib().lbm_ehd_invariants_noalloc(h, ctypes.byref(d))
     if code not in (LBM_OK, LBM_ENONFINITE):
         _check(code)
     return d

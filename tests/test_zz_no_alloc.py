@@ -1,0 +1,77 @@
+"""lbm_ehd_invariants_noalloc, the allocation-free variant of
+lbm_ehd_diagnostics, against lbm_ehd_diagnostics itself through the C ABI:
+the same sums bitwise (same kernels, same summation order), on two calls in
+a row whose second grid is smaller than the first (the static scratch keeps
+the first call's rows), and its guards."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from paper_2501_04920_amd import lbm_ehd, workloads
+
+pytestmark = pytest.mark.gpu
+
+SUMS = ("step", "sum_phi", "sum_rhoe", "sum_p", "sum_n", "nonfinite", "presolve_iters")
+
+
+def _noalloc(sim):
+    d = lbm_ehd.lbm_ehd_diag()
+    code = lbm_ehd.lib().lbm_ehd_invariants_noalloc(sim.handle, ctypes.byref(d))
+    return code, d
+
+
+def _sim(nx, ny, precision, steps):
+    p = dict(workloads.lattice_params(ny, ny / 6.0, nx=nx), precision=precision)
+    s = lbm_ehd.Simulation(p, device="cuda:0")
+    s.init_droplet((nx - 1) / 2, (ny - 1) / 2, ny / 6.0, 1e-4, 3, presolve=20)
+    s.step(steps)
+    return s
+
+
+def test_noalloc_invariants_equal_diagnostics_on_two_calls():
+    for nx, ny, prec in ((320, 288, "fp32"), (96, 72, "fp16")):
+        sim = _sim(nx, ny, prec, 21)
+        code, d = _noalloc(sim)
+        ref = lbm_ehd.lbm_ehd_diagnostics(sim.handle)
+        print("%dx%d %s: sum_phi %.17g vs %.17g" % (nx, ny, prec, d.sum_phi, ref.sum_phi),
+              flush=True)
+        assert code == lbm_ehd.LBM_OK
+        for k in SUMS:
+            assert getattr(d, k) == getattr(ref, k), k
+        assert ref.sum_phi > 0 and d.step == 21
+        assert math.isnan(d.D) and math.isnan(d.L) and math.isnan(d.H)
+        sim.close()
+
+
+def test_noalloc_invariants_report_a_nonfinite_state():
+    n = 64
+    p = dict(workloads.lattice_params(n, 10.0), precision="fp32")
+    y, x = np.mgrid[0:n, 0:n]
+    phi = 0.5 * (1 + np.tanh(2 * (10.0 - np.hypot(x - 31.5, y - 31.5)) / p["W"]))
+    phi[20, 30] = np.nan
+    sim = lbm_ehd.Simulation(p, device="cuda:0")
+    sim.init_fields(phi, 1.0, 1.0, p["dpsi"] * (n - 0.5 - y) / n)
+    sim.step(3)
+    code, d = _noalloc(sim)
+    ref = lbm_ehd.lbm_ehd_diagnostics(sim.handle)
+    assert code == lbm_ehd.LBM_ENONFINITE
+    assert d.nonfinite == ref.nonfinite > 0
+    sim.close()
+
+
+def test_noalloc_invariants_guards():
+    p = dict(workloads.lattice_params(64, 8.0), precision="fp32")
+    sim = lbm_ehd.Simulation(p, device="cuda:0")
+    code, _ = _noalloc(sim)
+    assert code == lbm_ehd.LBM_ESTATE                 # before init
+    sim.close()
+    tall = dict(p, nx=2, ny=16385)                    # one row more than the scratch holds
+    sim = lbm_ehd.Simulation(tall, device="cuda:0")
+    sim.init_droplet(0.5, 8192.0, 0.0)
+    code, _ = _noalloc(sim)
+    assert code == lbm_ehd.LBM_ERANGE
+    assert lbm_ehd.lbm_ehd_diagnostics(sim.handle).nonfinite == 0
+    sim.close()
+    assert lbm_ehd.lib().lbm_ehd_invariants_noalloc(None, None) == lbm_ehd.LBM_EINVAL
