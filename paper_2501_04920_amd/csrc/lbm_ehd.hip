@@ -62,6 +62,9 @@ bool local_h(int prec) { return elem_size(prec) == 2; }
 size_t rest_bytes(int prec) { return 8 * (local_h(prec) ? 3 : 1); }
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+// lines per lattice row of a population buffer: 33, and a 34th with bfloat16
+// storage (the second line of the reference momentum of f, see LocalF)
+int lines_of(int prec) { return prec == LBM_BF16_STORE ? NPOP + 1 : NPOP; }
 
 bool finite_all(std::initializer_list<double> v) {
   for (double d : v)
@@ -188,7 +191,7 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.walls = p.walls;
   k.side_walls = p.side_walls;
   k.local_field = p.local_field;
-  k.rstride = (uint32_t)(NPOP * h->pitch);
+  k.rstride = (uint32_t)(lines_of(p.precision) * h->pitch);
   k.cells = (uint32_t)((long long)p.ny * h->pitch);
   k.pop_bytes = (uint32_t)h->pop_bytes;
   k.reaction = p.reaction;
@@ -456,7 +459,7 @@ struct Form {
   static lbm_status settle_g(lbm_ehd* h, const S* gsrc) {
     S* A = buf(h, h->cur);
     if (gsrc != A) {
-      const size_t row = (size_t)NPOP * h->pitch * sizeof(S);
+      const size_t row = (size_t)lbm::lines_of<S>() * h->pitch * sizeof(S);
       const size_t line = (size_t)h->pitch;
       HIP_TRY(hipMemcpy2DAsync(A + QG * line, row, gsrc + QG * line, row,
                                5 * line * sizeof(S), (size_t)h->P.ny + 2,
@@ -752,7 +755,8 @@ lbm_status validate(const lbm_ehd_params* p) {
   if ((long long)p->nx * p->ny > (1LL << 31)) return fail(LBM_EINVAL, "grid too large");
   if (!elem_size(p->precision)) return fail(LBM_EINVAL, "unknown precision");
   // kernels address a population buffer with 32-bit byte offsets
-  if ((double)NPOP * (p->ny + 2) * pitch_of(p->nx) * elem_size(p->precision) >= 4294967296.0)
+  if ((double)lines_of(p->precision) * (p->ny + 2) * pitch_of(p->nx) * elem_size(p->precision) >=
+      4294967296.0)
     return fail(LBM_EINVAL, "grid too large: a population buffer must stay below 4 GiB");
   if (p->walls < 0 || p->walls > 2) return fail(LBM_EINVAL, "unknown walls");
   if (p->side_walls != 0 && p->side_walls != 1) return fail(LBM_EINVAL, "side_walls: 0 or 1");
@@ -999,7 +1003,8 @@ lbm_status lbm_ehd_required_bytes(const lbm_ehd_params* p, size_t* pop_bytes,
   lbm_status st = validate(p);
   if (st) return st;
   const size_t pitch = pitch_of(p->nx);
-  if (pop_bytes) *pop_bytes = (size_t)NPOP * (p->ny + 2) * pitch * elem_size(p->precision);
+  if (pop_bytes)
+    *pop_bytes = (size_t)lines_of(p->precision) * (p->ny + 2) * pitch * elem_size(p->precision);
   if (aux_bytes)
     *aux_bytes =
         (size_t)p->ny * pitch * (2 * arith_size(p->precision) + 2 * rest_bytes(p->precision));
@@ -1688,9 +1693,11 @@ double lbm_ehd_bytes_per_lup(int32_t precision) {
   const size_t s = elem_size(precision);
   if (!s) return 0.0;
   // the moving populations (32; with 16-bit storage 30, plus the lines of
-  // the reference phase of h and the reference potential of g), the FP64
-  // rest populations and (phi u)(t-1), each read once and written once
-  const double lines = local_h(precision) ? NPOP - 3 + 2 : NPOP - 1;
+  // the reference phase of h and the reference potential of g, and with
+  // bfloat16 storage the two lines of the reference momentum of f), the
+  // FP64 rest populations and (phi u)(t-1), each read once and written once
+  const double lines = local_h(precision) ? NPOP - 3 + 2 + (lines_of(precision) - NPOP) * 2
+                                          : NPOP - 1;
   return 2.0 * lines * s + 2.0 * rest_bytes(precision) + 2.0 * 2.0 * arith_size(precision);
 }
 

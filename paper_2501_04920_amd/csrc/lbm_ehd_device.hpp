@@ -73,7 +73,7 @@ constexpr int RING = 5;     // rows of phi/psi kept in LDS
 template <class R>
 struct KP {
   int nx, ny, pitch, walls;
-  uint32_t rstride;             // elements per lattice row of a buffer, 33 * pitch
+  uint32_t rstride;             // elements per lattice row of a buffer, lines * pitch
   uint32_t cells;               // elements per aux plane, ny * pitch
   uint32_t pop_bytes;           // size of a population buffer
   int reaction, poisson_form, flow, ion_force;
@@ -292,6 +292,46 @@ struct LocalG {
   static constexpr bool value = IonRest<S>::value;
 };
 constexpr int QRG = QP;
+// bfloat16 storage (an 8-bit significand) also keeps the moving f relative
+// to their dominant term, 3 w_i c_i . J~ with J~ = rho u of the node that sent
+// them (at the step it sent them, rounded to the storage type and stored by
+// that node in lines QJX and QJY): relative to 0 the velocity term of the
+// equilibrium, ~3 w_i rho c_i . u, is rounded at ~2e-3 every step, which is
+// where that storage's whole deformation error came from.  QJX is the line
+// of n0 (kept in FP64 by that storage); QJY is a 34th line.  Populations that
+// pass through a ghost row (reflected at an electrode, or wrapped in a
+// y-periodic box) are stored relative to 0.
+template <class S>
+struct LocalF {
+  static constexpr bool value = false;
+};
+template <>
+struct LocalF<__hip_bfloat16> {
+  static constexpr bool value = true;
+};
+constexpr int QJX = QN, QJY = NPOP;
+// lines per lattice row of a buffer
+template <class S>
+constexpr int lines_of() {
+  return LocalF<S>::value ? NPOP + 1 : NPOP;
+}
+// Reference of moving f population i (1..8) for the momentum (jx, jy) of its
+// sender: 3 w_i c_i . J, the same expression for the sender and the receiver.
+template <class R>
+__device__ inline R f_ref(int i, R jx, R jy) {
+  const R a = R(1.0 / 3.0), b = R(1.0 / 12.0);
+  switch (i) {
+    case 1: return a * jx;
+    case 2: return a * jy;
+    case 3: return -(a * jx);
+    case 4: return -(a * jy);
+    case 5: return b * (jx + jy);
+    case 6: return b * (jy - jx);
+    case 7: return -(b * (jx + jy));
+    case 8: return b * (jx - jy);
+  }
+  return R(0);
+}
 // Scale set of line a: the reference line of g is scaled like g.
 template <class S>
 __device__ inline int line_set(int a) {
@@ -323,6 +363,7 @@ struct PopView {
   // offset of the ion lines with 16-bit storage (see the deviation form)
   __device__ inline R ofs(int q) const {
     if (!LocalH<S>::value || q < QP || q >= QG || q == QRG) return R(0);
+    if (LocalF<S>::value && q == QJX) return R(0);
     return kp->iofs[q - QP];
   }
   __device__ inline R at(int q, uint32_t off) const {

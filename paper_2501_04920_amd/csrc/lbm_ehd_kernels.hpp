@@ -86,6 +86,44 @@ __device__ inline void pull9(const PopView<S, R>& P, int q0, K k, int yy, R x[9]
   x[8] = P.at(q0 + 8, k.lw ? own - 2 * pc : rp + k.m);  // <- 6
 }
 
+// The f set of node (xc, yy) as pulled by pull9, with the references of
+// bfloat16 storage added back (LocalF): 3 w_i c_i . J~ of the node that sent
+// population i, read at the same buffer position as the population (lines
+// QJX, QJY); 0 for populations that come through a ghost row; for one
+// reflected at a side wall (the node's own population of the opposite
+// direction) the node's own reference of that direction.
+template <class S, class R, class K>
+__device__ inline void pull_f(const PopView<S, R>& P, K k, int yy, R x[9]) {
+  pull9(P, QF, k, yy, x);
+  if constexpr (LocalF<S>::value) {
+    const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
+    const bool gd = yy == 0, gu = yy == P.kp->ny - 1;  // sources in a ghost row
+    const uint32_t own = r0 + k.c;
+    R ox = R(0), oy = R(0);
+    if (k.lw || k.rw) {
+      ox = P.at(QJX, own);
+      oy = P.at(QJY, own);
+    }
+    // direction i pulled from element offset `off` (ghost: reference 0), or
+    // at a side wall (`bb`) the node's own population of direction `opp`
+    auto add = [&](int i, uint32_t off, bool ghost, bool bb, int opp) {
+      if (bb) {
+        x[i] += f_ref(opp, ox, oy);
+      } else if (!ghost) {
+        x[i] += f_ref(i, P.at(QJX, off), P.at(QJY, off));
+      }
+    };
+    add(1, r0 + k.m, false, k.lw, 3);
+    add(2, rm + k.c, gd, false, 4);
+    add(3, r0 + k.p, false, k.rw, 1);
+    add(4, rp + k.c, gu, false, 2);
+    add(5, rm + k.m, gd, k.lw, 7);
+    add(6, rm + k.p, gd, k.rw, 8);
+    add(7, rp + k.p, gu, k.rw, 5);
+    add(8, rp + k.m, gu, k.lw, 6);
+  }
+}
+
 // Directions 1..4 of a D2Q5 set (the rest population is pulled separately).
 // At a side wall the ion and potential populations bounce back (zero flux;
 // on D2Q5 the same as specular reflection).
@@ -367,10 +405,20 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   // f first: its nine wide populations are then free for the rest
   collide_f(fw, m, kpw);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    f[i] = (R)fw[i];
-    D.put(QF + i, o, f[i]);
+  for (int i = 0; i < 9; ++i) f[i] = (R)fw[i];
+  if constexpr (LocalF<S>::value) {
+    // this node's momentum, the reference of the moving f it sends
+    const R jx = D.stored(QJX, (R)(m.rho * m.u[0])), jy = D.stored(QJY, (R)(m.rho * m.u[1]));
+    D.put(QJX, o, jx);
+    D.put(QJY, o, jy);
+    D.put(QF, o, f[0]);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) D.put(QF + i, o, f[i] - f_ref(i, jx, jy));
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) D.put(QF + i, o, f[i]);
   }
+  // the ghost rows hold f relative to 0
   if (edge) G.set9(QF, f);
 
   {  // g: Eq. (44)-(47)
@@ -595,7 +643,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
     // level, 1 to 3, makes no difference).
     R f[9], p[5], n[5], t4[4];
     __builtin_amdgcn_s_setprio(2);
-    pull9(Ph, QF, k, y, f);
+    pull_f(Ph, k, y, f);
     const uint32_t r0 = Ph.row(y + 1);
     // (the ion rest populations of 16-bit storage are read by the update)
     p[0] = IonRest<S>::value ? R(0) : Ph.at(QP, r0 + x);
@@ -777,7 +825,7 @@ __global__ void k_fields(const S* __restrict__ src, const T0* __restrict__ h0x,
   const Cols k = cols_of(x, kp.nx, kp.side_walls);
   R phi9[9], psi9[9], f[9], t4[4];
   hood(mom, kp, x, y, phi9, psi9);
-  pull9(Ph, QF, k, y, f);
+  pull_f(Ph, k, y, f);
   pull4(Ph, QP, k, y, t4);
   const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
   pull4(Ph, QN, k, y, t4);
@@ -942,6 +990,12 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
   }
   *elem(h0x, (uint32_t)y * kp.pitch + x) = (T0)hrest;
   const uint32_t jo = (uint32_t)y * kp.pitch + x;
+  // bfloat16 storage: every node's reference momentum starts at 0, so the
+  // initial f above are stored relative to 0 as written
+  if (LocalF<S>::value) {
+    D.put(QJX, D.row(y + 1) + x, R(0));
+    D.put(QJY, D.row(y + 1) + x, R(0));
+  }
   // g: this node's reference potential psi'~ (16-bit storage; 0 otherwise)
   double tg = 0.0;
   if (LocalG<S>::value) {

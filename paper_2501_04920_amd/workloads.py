@@ -115,11 +115,14 @@ def enclosure(n: int = 256, *, d_mm=2.0, kv=1.0, eps_r=0.5, mu_r=5.0, rho_r=2.0,
     and O ~ dpsi / d, anchored at the d = 2 mm, 1 kV values; Ca_E is among
     the values the paper holds fixed, so it stays 0.241 unless given.
 
-    The Poisson source is the printed one of Eq. 44 (rho_e / eps,
-    poisson_form = 0): with it the steady deformations follow the trends
-    Sec. 6 reports for eps_r (prolate at 0.5, oblate at 50) and mu_r
-    (oblate at 0.5, negligible at 1, prolate at 5); the variable-eps source
-    of Eq. 7 turns the eps_r = 50 droplet prolate.  The droplet is steady
+    The Poisson source is the constant-eps source rho_e / eps of Eq. 44
+    (poisson_form = 0) with the library's normalised source weights
+    w_i / (1 - w_0) (poisson_norm = 1; Eq. 44 prints w_i): with it the
+    steady deformations follow the trends Sec. 6 reports for eps_r (prolate
+    at 0.5, oblate at 50) and mu_r (oblate at 0.5, negligible at 1, prolate
+    at 5); the variable-eps source of Eq. 7 turns the eps_r = 50 droplet
+    prolate.  At eps_r = 5 the droplet is prolate under either source, where
+    Sec. 6 reports little deformation.  The droplet is steady
     after ~150 000 steps at n = 256; the pre-solve is 30 000 g-only sweeps."""
     W0 = W0_2MM * (d_mm / 2.0) ** 2 / kv
     O = BETA_2MM ** 2 / W0_2MM * kv * (2.0 / d_mm)

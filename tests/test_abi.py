@@ -46,7 +46,10 @@ def test_defaults_and_bytes():
     # 32 moving planes + rest of h + (phi u), each read and written once
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp32") == 2 * 32 * 4 + 2 * 8 + 2 * 8
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 2 * 32 * 2 + 2 * 3 * 8 + 2 * 8
-    assert lbm_ehd.lbm_ehd_bytes_per_lup("bf16") == 2 * 32 * 2 + 2 * 3 * 8 + 2 * 8
+    # bfloat16: two more lines, the reference momentum of f
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("bf16") == 2 * 34 * 2 + 2 * 3 * 8 + 2 * 8
+    pop, aux = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(precision="bf16"))
+    assert pop == 34 * 130 * 128 * 2 and aux == 128 * 128 * (2 * 4 + 2 * 3 * 8)
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp64") == 2 * 32 * 8 + 2 * 8 + 2 * 16
 
 

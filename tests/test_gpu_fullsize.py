@@ -72,5 +72,4 @@ def test_2048_16bit_forms_against_fp64_form_5k_steps():
               % (prec, out[prec]["D"], ref["D"], dD, dphi), flush=True)
         assert out[prec]["nonfinite"] == 0
         assert dphi <= 1e-12
-        if prec == "fp16":
-            assert dD <= 1e-3
+        assert dD <= 1e-3
