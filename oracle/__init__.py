@@ -59,6 +59,7 @@ class OracleParams(ctypes.Structure):
         ("c0", ctypes.c_double), ("q", ctypes.c_double), ("gamma_v", ctypes.c_double),
         ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
         ("s_free", ctypes.c_double), ("n_eps", ctypes.c_double),
+        ("ion_q9", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -103,9 +104,11 @@ def lib() -> ctypes.CDLL:
         L.orc_heq.argtypes = [ctypes.c_double] * 3 + [dp]
         L.orc_hforce.argtypes = [ctypes.c_double] * 6 + [dp]
         L.orc_unit_normal.argtypes = [ctypes.c_double] * 3 + [dp]
-        L.orc_ioneq.argtypes = [ctypes.c_double] * 3 + [dp]
-        L.orc_ionsrc.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int, dp]
-        L.orc_iondrift.argtypes = [ctypes.c_double] * 4 + [dp]
+        L.orc_ioneq.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3 + [dp]
+        L.orc_ionsrc.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [ctypes.c_int, dp]
+        L.orc_iondrift.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [dp]
+        L.orc_npop.argtypes = [ctypes.c_void_p]
+        L.orc_npop.restype = ctypes.c_int
         L.orc_geq.argtypes = [ctypes.c_double, dp]
         L.orc_ion_solve.argtypes = [ctypes.c_double] * 3 + [dp]
         L.orc_stencil_field.argtypes = [pp, dp, ctypes.c_int, dp, dp, dp]
@@ -191,8 +194,13 @@ class Oracle:
         lib().orc_sums(self._h, _dp(out))
         return {"sum_phi": out[0], "sum_rhoe": out[1], "sum_p": out[2], "sum_n": out[3]}
 
+    @property
+    def npop(self) -> int:
+        """Populations per cell: 33, or 41 with the ions on D2Q9."""
+        return int(lib().orc_npop(self._h))
+
     def get_state(self):
-        pop = np.empty((33, self.ny, self.nx))
+        pop = np.empty((self.npop, self.ny, self.nx))
         jp = np.empty((2, self.ny, self.nx))
         lib().orc_get_state(self._h, _dp(pop), _dp(jp))
         return pop, jp
@@ -200,7 +208,7 @@ class Oracle:
     def set_state(self, pop: np.ndarray, jprev: np.ndarray):
         pop = np.ascontiguousarray(pop, dtype=np.float64)
         jprev = np.ascontiguousarray(jprev, dtype=np.float64)
-        assert pop.shape == (33, self.ny, self.nx) and jprev.shape == (2, self.ny, self.nx)
+        assert pop.shape == (self.npop, self.ny, self.nx) and jprev.shape == (2, self.ny, self.nx)
         lib().orc_set_state(self._h, _dp(pop), _dp(jprev))
 
 
@@ -256,16 +264,17 @@ def hforce(dJx, dJy, nx, ny, phi, W):
     return _vec(lib().orc_hforce, 9, dJx, dJy, nx, ny, phi, W)
 
 
-def ioneq(c, ux, uy):
-    return _vec(lib().orc_ioneq, 5, c, ux, uy)
+def ioneq(c, ux, uy, q=5):
+    """Eq. (38) on the ion lattice of q = 5 or 9 velocities."""
+    return _vec(lib().orc_ioneq, q, int(q), c, ux, uy)
 
 
-def ionsrc(R, c, Fx, Fy, with_L=1):
-    return _vec(lib().orc_ionsrc, 5, R, c, Fx, Fy, int(with_L))
+def ionsrc(R, c, Fx, Fy, with_L=1, q=5):
+    return _vec(lib().orc_ionsrc, q, int(q), R, c, Fx, Fy, int(with_L))
 
 
-def iondrift(mu, c, gx, gy):
-    return _vec(lib().orc_iondrift, 5, mu, c, gx, gy)
+def iondrift(mu, c, gx, gy, q=5):
+    return _vec(lib().orc_iondrift, q, int(q), mu, c, gx, gy)
 
 
 def geq(psi):

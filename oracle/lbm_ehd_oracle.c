@@ -33,7 +33,9 @@
  *      test in Sec. 5.1)
  *
  * Readings taken where the paper is silent, garbled or inconsistent:
- *   - ions use the D2Q5 lattice (weights of Eq. 26, matrix N of Eq. 46);
+ *   - ions use the D2Q5 lattice (weights of Eq. 26, matrix N of Eq. 46) by
+ *     default; with ion_q9 = 1 they use D2Q9 as Eq. (34)-(38) write them
+ *     (weights of Eq. 25, matrix M of Eq. 28, s_1 = s_2 = 1/tau of Eq. 37);
  *   - which MRT rows relax with 1/tau is a per-equation bit mask; default:
  *     rows 1,2 (first moments) for h, p, n, g and rows 3,4,5 (second moments)
  *     for f, every other row relaxes with s_free (1.0 in Sec. 6);
@@ -118,9 +120,10 @@ static const double N5[25] = {
     0, 1, 0, 1, 0,
     0, 0, 1, 0, 1};
 
-/* Population sets, stored one after the other: f (9), h (9), p (5), n (5),
- * g (5). */
-enum { OF_F = 0, OF_H = 9, OF_P = 18, OF_N = 23, OF_G = 28, NPOP = 33 };
+/* Population sets, stored one after the other: f (9), h (9), p, n (5 each,
+ * or 9 each with D2Q9 ions), g (5).  The offsets of p, n and g and the
+ * number of populations are in the state (op, on, og, npop). */
+enum { OF_F = 0, OF_H = 9, OF_P = 18 };
 
 enum { WALLS_ELECTRODES = 0, WALLS_INSULATING = 1, WALLS_PERIODIC = 2 };
 
@@ -157,6 +160,8 @@ typedef struct {
   double force_x, force_y; /* external body-force density (tests) */
   double s_free;         /* rate of the free MRT rows */
   double n_eps;          /* regularisation of the unit normal (0: bare form) */
+  int32_t ion_q9;        /* 0: ions on D2Q5; 1: ions on D2Q9, Eq. (34)-(38) as printed */
+  int32_t reserved;
 } orc_params;
 
 typedef struct {
@@ -172,6 +177,8 @@ typedef struct {
   double M9i[81], N5i[25];
   int opp9[9], opp5[5];
   int mirx9[9];  /* direction with c_x reversed */
+  int qi;        /* ion lattice: 5 or 9 populations per species */
+  int op, on, og, npop; /* offsets of p, n, g; populations per cell */
 } orc_state;
 
 /* Macroscopic quantities at one node, steps 3-7. */
@@ -336,24 +343,35 @@ static void hforce(const double *dJ, const double *nhat, double phi, double W, d
   }
 }
 
-/* Eq. (38) on D2Q5. */
-static void ioneq(double c, const double *u, double *out) {
-  for (int i = 0; i < 5; ++i)
-    out[i] = W5[i] * c * (1.0 + (CX5[i] * u[0] + CY5[i] * u[1]) / CS2);
+/* The lattice of q velocities (5: D2Q5 of Eq. 26, 9: D2Q9 of Eq. 25). */
+static const int *lat_cx(int q) { return q == 9 ? CX9 : CX5; }
+static const int *lat_cy(int q) { return q == 9 ? CY9 : CY5; }
+static const double *lat_w(int q) { return q == 9 ? W9 : W5; }
+
+/* Eq. (38) on the ion lattice of q velocities. */
+static void ioneq(int q, double c, const double *u, double *out) {
+  const int *cx = lat_cx(q), *cy = lat_cy(q);
+  const double *w = lat_w(q);
+  for (int i = 0; i < q; ++i)
+    out[i] = w[i] * c * (1.0 + (cx[i] * u[0] + cy[i] * u[1]) / CS2);
 }
 
 /* Eq. (39): R_i + L_i for one species with concentration c. */
-static void ionsrc(double R, double c, const double *F, int with_L, double *out) {
-  for (int i = 0; i < 5; ++i) {
-    double L = with_L ? W5[i] * (CX5[i] * c * F[0] + CY5[i] * c * F[1]) / CS2 : 0.0;
-    out[i] = W5[i] * R + L;
+static void ionsrc(int q, double R, double c, const double *F, int with_L, double *out) {
+  const int *cx = lat_cx(q), *cy = lat_cy(q);
+  const double *w = lat_w(q);
+  for (int i = 0; i < q; ++i) {
+    double L = with_L ? w[i] * (cx[i] * c * F[0] + cy[i] * c * F[1]) / CS2 : 0.0;
+    out[i] = w[i] * R + L;
   }
 }
 
 /* Eq. (40): G_i (mobility mu, concentration c). */
-static void iondrift(double mu, double c, const double *gpsi, double *out) {
-  for (int i = 0; i < 5; ++i)
-    out[i] = W5[i] * (CX5[i] * gpsi[0] + CY5[i] * gpsi[1]) * mu * c / CS2;
+static void iondrift(int q, double mu, double c, const double *gpsi, double *out) {
+  const int *cx = lat_cx(q), *cy = lat_cy(q);
+  const double *w = lat_w(q);
+  for (int i = 0; i < q; ++i)
+    out[i] = w[i] * (cx[i] * gpsi[0] + cy[i] * gpsi[1]) * mu * c / CS2;
 }
 
 /* Eq. (45). */
@@ -419,9 +437,9 @@ static void compute_moments(orc_state *s) {
   for (size_t c = 0; c < s->nc; ++c) {
     double phi = 0.0, P = 0.0, Q = 0.0, gs = 0.0;
     for (int i = 0; i < 9; ++i) phi += s->pop[(OF_H + i) * s->nc + c];   /* Eq. (33) */
-    for (int i = 0; i < 5; ++i) P += s->pop[(OF_P + i) * s->nc + c];
-    for (int i = 0; i < 5; ++i) Q += s->pop[(OF_N + i) * s->nc + c];
-    for (int i = 1; i < 5; ++i) gs += s->pop[(OF_G + i) * s->nc + c];
+    for (int i = 0; i < s->qi; ++i) P += s->pop[(s->op + i) * s->nc + c];
+    for (int i = 0; i < s->qi; ++i) Q += s->pop[(s->on + i) * s->nc + c];
+    for (int i = 1; i < 5; ++i) gs += s->pop[(s->og + i) * s->nc + c];
     s->phi[c] = phi;
     s->sp[c] = P;
     s->sn[c] = Q;
@@ -434,7 +452,7 @@ static void compute_moments(orc_state *s) {
 static void field_from_g(const orc_state *s, size_t c, double tau_g, double *E) {
   double ex = 0.0, ey = 0.0;
   for (int i = 1; i < 5; ++i) {
-    double g = s->pop[(OF_G + i) * s->nc + c];
+    double g = s->pop[(s->og + i) * s->nc + c];
     ex += CX5[i] * g;
     ey += CY5[i] * g;
   }
@@ -552,7 +570,7 @@ static void collide_at(orc_state *s, int x, int y, mrt_memo *mm) {
   const double *A9, *B9, *A5, *B5;
   double sv[9];
   double x9[9], e9[9], d9[9], s9[9], t9[9], t9b[9];
-  double x5[5], e5[5], d5[5], s5[5], t5[5], t5b[5], g5[5];
+  double x5[5], e5[5], d5[5], t5[5];
 
   /* f, Eq. (51). */
   for (int i = 0; i < 9; ++i) x9[i] = s->pop[(OF_F + i) * nc + c];
@@ -582,43 +600,44 @@ static void collide_at(orc_state *s, int x, int y, mrt_memo *mm) {
   matvec(9, B9, s9, t9b);
   for (int i = 0; i < 9; ++i) s->post[(OF_H + i) * nc + c] = x9[i] - t9[i] + t9b[i];
 
+  /* Ions on the lattice of qi velocities, with its transformation matrix
+   * (M of Eq. 28 for D2Q9, N of Eq. 46 for D2Q5). */
+  const int qi = s->qi;
+  const double *MI = qi == 9 ? M9 : N5, *MIi = qi == 9 ? s->M9i : s->N5i;
+  const double *AI, *BI;
+  double xi[9], ei[9], di[9], si[9], gi[9], ti[9], tib[9], tig[9];
+
   /* p (cations), Eq. (34): - M^-1 S M G. */
-  for (int i = 0; i < 5; ++i) x5[i] = s->pop[(OF_P + i) * nc + c];
-  rates(5, P->mask_p, m.tau_p, P->s_free, sv);
-  mrt_cached(mm, 2, 5, N5, s->N5i, sv, &A5, &B5);
-  ioneq(m.cp, m.u, e5);
-  ionsrc(m.R, m.cp, m.F, P->ion_force, s5);
-  iondrift(m.mup, m.cp, m.gpsi, g5);
-  for (int i = 0; i < 5; ++i) d5[i] = x5[i] - e5[i];
-  matvec(5, A5, d5, t5);
-  matvec(5, B5, s5, t5b);
-  {
-    double tg[5];
-    matvec(5, A5, g5, tg);
-    for (int i = 0; i < 5; ++i) s->post[(OF_P + i) * nc + c] = x5[i] - t5[i] + t5b[i] - tg[i];
-  }
+  for (int i = 0; i < qi; ++i) xi[i] = s->pop[(s->op + i) * nc + c];
+  rates(qi, P->mask_p, m.tau_p, P->s_free, sv);
+  mrt_cached(mm, 2, qi, MI, MIi, sv, &AI, &BI);
+  ioneq(qi, m.cp, m.u, ei);
+  ionsrc(qi, m.R, m.cp, m.F, P->ion_force, si);
+  iondrift(qi, m.mup, m.cp, m.gpsi, gi);
+  for (int i = 0; i < qi; ++i) di[i] = xi[i] - ei[i];
+  matvec(qi, AI, di, ti);
+  matvec(qi, BI, si, tib);
+  matvec(qi, AI, gi, tig);
+  for (int i = 0; i < qi; ++i) s->post[(s->op + i) * nc + c] = xi[i] - ti[i] + tib[i] - tig[i];
 
   /* n (anions), Eq. (35): + M^-1 S M Gbar. */
-  for (int i = 0; i < 5; ++i) x5[i] = s->pop[(OF_N + i) * nc + c];
-  rates(5, P->mask_n, m.tau_n, P->s_free, sv);
-  mrt_cached(mm, 3, 5, N5, s->N5i, sv, &A5, &B5);
-  ioneq(m.cm, m.u, e5);
-  ionsrc(m.R, m.cm, m.F, P->ion_force, s5);
-  iondrift(m.mum, m.cm, m.gpsi, g5);
-  for (int i = 0; i < 5; ++i) d5[i] = x5[i] - e5[i];
-  matvec(5, A5, d5, t5);
-  matvec(5, B5, s5, t5b);
-  {
-    double tg[5];
-    matvec(5, A5, g5, tg);
-    for (int i = 0; i < 5; ++i) s->post[(OF_N + i) * nc + c] = x5[i] - t5[i] + t5b[i] + tg[i];
-  }
+  for (int i = 0; i < qi; ++i) xi[i] = s->pop[(s->on + i) * nc + c];
+  rates(qi, P->mask_n, m.tau_n, P->s_free, sv);
+  mrt_cached(mm, 3, qi, MI, MIi, sv, &AI, &BI);
+  ioneq(qi, m.cm, m.u, ei);
+  ionsrc(qi, m.R, m.cm, m.F, P->ion_force, si);
+  iondrift(qi, m.mum, m.cm, m.gpsi, gi);
+  for (int i = 0; i < qi; ++i) di[i] = xi[i] - ei[i];
+  matvec(qi, AI, di, ti);
+  matvec(qi, BI, si, tib);
+  matvec(qi, AI, gi, tig);
+  for (int i = 0; i < qi; ++i) s->post[(s->on + i) * nc + c] = xi[i] - ti[i] + tib[i] + tig[i];
 
   /* g, Eq. (44)-(47). */
   double Spsi = P->poisson_form
                     ? (m.rhoe + m.geps[0] * m.gpsi[0] + m.geps[1] * m.gpsi[1]) / m.eps
                     : m.rhoe / m.eps;
-  for (int i = 0; i < 5; ++i) x5[i] = s->pop[(OF_G + i) * nc + c];
+  for (int i = 0; i < 5; ++i) x5[i] = s->pop[(s->og + i) * nc + c];
   rates(5, P->mask_g, m.tau_g, P->s_free, sv);
   mrt_cached(mm, 4, 5, N5, s->N5i, sv, &A5, &B5);
   geq(m.psi, e5);
@@ -626,7 +645,7 @@ static void collide_at(orc_state *s, int x, int y, mrt_memo *mm) {
   matvec(5, A5, d5, t5);
   double wn = P->poisson_norm ? 1.0 / (1.0 - W5[0]) : 1.0;
   for (int i = 0; i < 5; ++i)
-    s->post[(OF_G + i) * nc + c] = x5[i] - t5[i] + wn * W5[i] * Spsi * P->theta;
+    s->post[(s->og + i) * nc + c] = x5[i] - t5[i] + wn * W5[i] * Spsi * P->theta;
 }
 
 /* One g-only sweep with phi and rho_e = e0 (sum p - sum n) held fixed. */
@@ -653,7 +672,7 @@ static void poisson_collide_at(orc_state *s, int x, int y, mrt_memo *mm) {
                                 : rhoe / eps;
   double sv[5], x5[5], e5[5], d5[5], t5[5];
   const double *A5, *B5;
-  for (int i = 0; i < 5; ++i) x5[i] = s->pop[(OF_G + i) * nc + c];
+  for (int i = 0; i < 5; ++i) x5[i] = s->pop[(s->og + i) * nc + c];
   rates(5, P->mask_g, tau_g, P->s_free, sv);
   mrt_cached(mm, 4, 5, N5, s->N5i, sv, &A5, &B5);
   geq(s->psi[c], e5);
@@ -661,7 +680,7 @@ static void poisson_collide_at(orc_state *s, int x, int y, mrt_memo *mm) {
   matvec(5, A5, d5, t5);
   double wn = P->poisson_norm ? 1.0 / (1.0 - W5[0]) : 1.0;
   for (int i = 0; i < 5; ++i)
-    s->post[(OF_G + i) * nc + c] = x5[i] - t5[i] + wn * W5[i] * Spsi * P->theta;
+    s->post[(s->og + i) * nc + c] = x5[i] - t5[i] + wn * W5[i] * Spsi * P->theta;
 }
 
 /* Population arriving at (x, y) along direction i of a set whose source
@@ -669,27 +688,24 @@ static void poisson_collide_at(orc_state *s, int x, int y, mrt_memo *mm) {
 static double wall_rule(const orc_state *s, int set, int i, int x, int y, int bottom) {
   size_t c = cidx(s, x, y), nc = s->nc;
   int walls = s->P.walls;
-  switch (set) {
-  case OF_F:
-  case OF_H:
+  if (set == OF_F || set == OF_H)
     return s->post[(set + s->opp9[i]) * nc + c]; /* bounce-back: u = 0, no phi flux */
-  case OF_P: {
-    double v = s->post[(OF_P + s->opp5[i]) * nc + c];
+  if (set == s->op || set == s->on) {
+    const int *opp = s->qi == 9 ? s->opp9 : s->opp5;
+    const double *w = lat_w(s->qi);
+    double v = s->post[(set + opp[i]) * nc + c];
     if (walls == WALLS_INSULATING) return v;
-    if (bottom) return -v;                       /* anode: c+ = 0 */
-    return -v + 2.0 * W5[i] * s->cp[c];          /* cathode: d c+/dn = 0 */
-  }
-  case OF_N: {
-    double v = s->post[(OF_N + s->opp5[i]) * nc + c];
-    if (walls == WALLS_INSULATING) return v;
-    if (bottom) return -v + 2.0 * W5[i] * s->cm[c]; /* anode: d c-/dn = 0 */
+    if (set == s->op) {
+      if (bottom) return -v;                     /* anode: c+ = 0 */
+      return -v + 2.0 * w[i] * s->cp[c];         /* cathode: d c+/dn = 0 */
+    }
+    if (bottom) return -v + 2.0 * w[i] * s->cm[c]; /* anode: d c-/dn = 0 */
     return -v;                                      /* cathode: c- = 0 */
   }
-  default: { /* OF_G: Dirichlet potential */
-    double v = s->post[(OF_G + s->opp5[i]) * nc + c];
+  { /* g: Dirichlet potential */
+    double v = s->post[(s->og + s->opp5[i]) * nc + c];
     double psi_w = bottom ? s->P.dpsi : 0.0;
     return -v + 2.0 * W5[i] * psi_w;
-  }
   }
 }
 
@@ -741,7 +757,7 @@ static void poisson_sweep(orc_state *s) {
     memset(mm.valid, 0, sizeof mm.valid);
     for (int x = 0; x < s->nx; ++x) poisson_collide_at(s, x, y, &mm);
   }
-  stream_set(s, OF_G, 5);
+  stream_set(s, s->og, 5);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -807,8 +823,13 @@ ORC_API orc_state *orc_create(const orc_params *p) {
   s->nx = p->nx;
   s->ny = p->ny;
   s->nc = (size_t)p->nx * p->ny;
-  s->pop = (double *)calloc(NPOP * s->nc, sizeof(double));
-  s->post = (double *)calloc(NPOP * s->nc, sizeof(double));
+  s->qi = p->ion_q9 ? 9 : 5;
+  s->op = OF_P;
+  s->on = OF_P + s->qi;
+  s->og = OF_P + 2 * s->qi;
+  s->npop = s->og + 5;
+  s->pop = (double *)calloc((size_t)s->npop * s->nc, sizeof(double));
+  s->post = (double *)calloc((size_t)s->npop * s->nc, sizeof(double));
   s->jprev = (double *)calloc(2 * s->nc, sizeof(double));
   s->phi = (double *)calloc(s->nc, sizeof(double));
   s->psi = (double *)calloc(s->nc, sizeof(double));
@@ -859,17 +880,17 @@ ORC_API void orc_init_droplet(orc_state *s, double xc, double yc, double R, doub
       double cp0 = P->c0 * (1.0 + noise * orc_noise(seed, 2 * k + 1));
       double cm0 = P->c0 * (1.0 + noise * orc_noise(seed, 2 * k + 2));
       double psi0 = P->walls == WALLS_PERIODIC ? 0.0 : P->dpsi * (s->ny - 0.5 - y) / s->ny;
-      double e9[9], e5[5];
+      double e9[9], e5[5], ei[9];
       feq(0.0, 0.0, zero_u, e9);
       for (int i = 0; i < 9; ++i) s->pop[(OF_F + i) * nc + c] = e9[i];
       heq(phi0, zero_u, e9);
       for (int i = 0; i < 9; ++i) s->pop[(OF_H + i) * nc + c] = e9[i];
-      ioneq(cp0, zero_u, e5);
-      for (int i = 0; i < 5; ++i) s->pop[(OF_P + i) * nc + c] = e5[i];
-      ioneq(cm0, zero_u, e5);
-      for (int i = 0; i < 5; ++i) s->pop[(OF_N + i) * nc + c] = e5[i];
+      ioneq(s->qi, cp0, zero_u, ei);
+      for (int i = 0; i < s->qi; ++i) s->pop[(s->op + i) * nc + c] = ei[i];
+      ioneq(s->qi, cm0, zero_u, ei);
+      for (int i = 0; i < s->qi; ++i) s->pop[(s->on + i) * nc + c] = ei[i];
       geq(psi0, e5);
-      for (int i = 0; i < 5; ++i) s->pop[(OF_G + i) * nc + c] = e5[i];
+      for (int i = 0; i < 5; ++i) s->pop[(s->og + i) * nc + c] = e5[i];
       s->jprev[c] = 0.0;
       s->jprev[nc + c] = 0.0;
     }
@@ -889,17 +910,17 @@ ORC_API void orc_init_fields(orc_state *s, const double *phi0, const double *cp0
   for (size_t c = 0; c < nc; ++c) {
     double u[2] = {ux0 ? ux0[c] : 0.0, uy0 ? uy0[c] : 0.0};
     double rho = phi0[c] * (rho_l - P->rho_v) + P->rho_v;
-    double e9[9], e5[5];
+    double e9[9], e5[5], ei[9];
     feq(0.0, rho, u, e9);
     for (int i = 0; i < 9; ++i) s->pop[(OF_F + i) * nc + c] = e9[i];
     heq(phi0[c], u, e9);
     for (int i = 0; i < 9; ++i) s->pop[(OF_H + i) * nc + c] = e9[i];
-    ioneq(cp0[c], u, e5);
-    for (int i = 0; i < 5; ++i) s->pop[(OF_P + i) * nc + c] = e5[i];
-    ioneq(cm0[c], u, e5);
-    for (int i = 0; i < 5; ++i) s->pop[(OF_N + i) * nc + c] = e5[i];
+    ioneq(s->qi, cp0[c], u, ei);
+    for (int i = 0; i < s->qi; ++i) s->pop[(s->op + i) * nc + c] = ei[i];
+    ioneq(s->qi, cm0[c], u, ei);
+    for (int i = 0; i < s->qi; ++i) s->pop[(s->on + i) * nc + c] = ei[i];
     geq(psi0[c], e5);
-    for (int i = 0; i < 5; ++i) s->pop[(OF_G + i) * nc + c] = e5[i];
+    for (int i = 0; i < 5; ++i) s->pop[(s->og + i) * nc + c] = e5[i];
     s->jprev[c] = phi0[c] * u[0];
     s->jprev[nc + c] = phi0[c] * u[1];
   }
@@ -922,9 +943,9 @@ ORC_API void orc_step(orc_state *s, int nsteps) {
     }
     stream_set(s, OF_F, 9);
     stream_set(s, OF_H, 9);
-    stream_set(s, OF_P, 5);
-    stream_set(s, OF_N, 5);
-    stream_set(s, OF_G, 5);
+    stream_set(s, s->op, s->qi);
+    stream_set(s, s->on, s->qi);
+    stream_set(s, s->og, 5);
     s->step += 1;
   }
 }
@@ -970,15 +991,18 @@ ORC_API void orc_sums(orc_state *s, double *out) {
   out[3] = cQ;
 }
 
-/* Raw state access: populations [33][ny][nx] at the current time and the
+/* Populations per cell: 33, or 41 with D2Q9 ions. */
+ORC_API int orc_npop(const orc_state *s) { return s->npop; }
+
+/* Raw state access: populations [npop][ny][nx] at the current time and the
  * previous phi*u [2][ny][nx]. */
 ORC_API void orc_get_state(const orc_state *s, double *pop, double *jprev) {
-  if (pop) memcpy(pop, s->pop, NPOP * s->nc * sizeof(double));
+  if (pop) memcpy(pop, s->pop, (size_t)s->npop * s->nc * sizeof(double));
   if (jprev) memcpy(jprev, s->jprev, 2 * s->nc * sizeof(double));
 }
 
 ORC_API void orc_set_state(orc_state *s, const double *pop, const double *jprev) {
-  if (pop) memcpy(s->pop, pop, NPOP * s->nc * sizeof(double));
+  if (pop) memcpy(s->pop, pop, (size_t)s->npop * s->nc * sizeof(double));
   if (jprev) memcpy(s->jprev, jprev, 2 * s->nc * sizeof(double));
 }
 
@@ -1021,17 +1045,18 @@ ORC_API void orc_hforce(double dJx, double dJy, double nx, double ny, double phi
   double dJ[2] = {dJx, dJy}, n[2] = {nx, ny};
   hforce(dJ, n, phi, W, out);
 }
-ORC_API void orc_ioneq(double c, double ux, double uy, double *out) {
+ORC_API void orc_ioneq(int q, double c, double ux, double uy, double *out) {
   double u[2] = {ux, uy};
-  ioneq(c, u, out);
+  ioneq(q, c, u, out);
 }
-ORC_API void orc_ionsrc(double R, double c, double Fx, double Fy, int with_L, double *out) {
+ORC_API void orc_ionsrc(int q, double R, double c, double Fx, double Fy, int with_L,
+                        double *out) {
   double F[2] = {Fx, Fy};
-  ionsrc(R, c, F, with_L, out);
+  ionsrc(q, R, c, F, with_L, out);
 }
-ORC_API void orc_iondrift(double mu, double c, double gx, double gy, double *out) {
+ORC_API void orc_iondrift(int q, double mu, double c, double gx, double gy, double *out) {
   double g[2] = {gx, gy};
-  iondrift(mu, c, g, out);
+  iondrift(q, mu, c, g, out);
 }
 ORC_API void orc_geq(double psi, double *out) { geq(psi, out); }
 ORC_API void orc_unit_normal(double gx, double gy, double n_eps, double *out) {

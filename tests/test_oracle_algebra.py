@@ -98,11 +98,12 @@ def test_equilibrium_moments(orc):
         assert math.isclose(m0, phi, rel_tol=1e-15)
         assert np.allclose(m1, phi * u, atol=1e-15)
         assert np.allclose(m2, phi * np.eye(2) / 3, atol=1e-15)
-        # Eq. (38) on D2Q5
-        m0, m1, m2 = _mom(orc.ioneq(c, *u), cx5, cy5)
-        assert math.isclose(m0, c, rel_tol=1e-15)
-        assert np.allclose(m1, c * u, atol=1e-15)
-        assert np.allclose(m2, c * np.eye(2) / 3, atol=1e-15)
+        # Eq. (38) on D2Q5 and on D2Q9 (the lattice of Eq. 34-35 as printed)
+        for q, cx, cy in ((5, cx5, cy5), (9, cx9, cy9)):
+            m0, m1, m2 = _mom(orc.ioneq(c, *u, q=q), cx, cy)
+            assert math.isclose(m0, c, rel_tol=1e-15)
+            assert np.allclose(m1, c * u, atol=1e-15)
+            assert np.allclose(m2, c * np.eye(2) / 3, atol=1e-15)
         # Eq. (45): zero sum, Eq. (49) recovers psi, second moment psi I / 3
         g = orc.geq(psi)
         m0, m1, m2 = _mom(g, cx5, cy5)
@@ -131,18 +132,19 @@ def test_forcing_moments(orc):
         assert abs(m0) < 1e-16
         assert np.allclose(m1, dJ + lam * nh / 3, atol=1e-15)
         assert np.allclose(m2, 0, atol=1e-16)
-        # Eq. (39): R, c F, R I / 3 (and no first moment without L_i)
-        m0, m1, m2 = _mom(orc.ionsrc(R, c, *F, 1), cx5, cy5)
-        assert math.isclose(m0, R, rel_tol=1e-15)
-        assert np.allclose(m1, c * F, atol=1e-15)
-        assert np.allclose(m2, R * np.eye(2) / 3, atol=1e-15)
-        m0, m1, _ = _mom(orc.ionsrc(R, c, *F, 0), cx5, cy5)
-        assert np.allclose(m1, 0, atol=1e-16)
-        # Eq. (40): G_i carries the drift flux mu c grad(psi) and nothing else
-        m0, m1, m2 = _mom(orc.iondrift(mu, c, *gr), cx5, cy5)
-        assert abs(m0) < 1e-16
-        assert np.allclose(m1, mu * c * gr, atol=1e-15)
-        assert np.allclose(m2, 0, atol=1e-16)
+        for q, cx, cy in ((5, cx5, cy5), (9, cx9, cy9)):
+            # Eq. (39): R, c F, R I / 3 (and no first moment without L_i)
+            m0, m1, m2 = _mom(orc.ionsrc(R, c, *F, 1, q=q), cx, cy)
+            assert math.isclose(m0, R, rel_tol=1e-15)
+            assert np.allclose(m1, c * F, atol=1e-15)
+            assert np.allclose(m2, R * np.eye(2) / 3, atol=1e-15)
+            m0, m1, _ = _mom(orc.ionsrc(R, c, *F, 0, q=q), cx, cy)
+            assert np.allclose(m1, 0, atol=1e-16)
+            # Eq. (40): G_i carries the drift flux mu c grad(psi) and nothing else
+            m0, m1, m2 = _mom(orc.iondrift(mu, c, *gr, q=q), cx, cy)
+            assert abs(m0) < 1e-16
+            assert np.allclose(m1, mu * c * gr, atol=1e-15)
+            assert np.allclose(m2, 0, atol=1e-16)
 
 
 def test_ion_solve_quadratic(orc):

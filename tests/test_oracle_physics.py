@@ -289,12 +289,14 @@ def test_series_dielectric(orc, form):
 # --------------------------------------------------------------------------
 # Ions (Eq. 34-43)
 # --------------------------------------------------------------------------
-def test_drift_diffusion_of_a_pulse(orc):
+@pytest.mark.parametrize("ion_q9", [0, 1])
+def test_drift_diffusion_of_a_pulse(orc, ion_q9):
     """In a uniform field a Gaussian moves at +mu+ E (cations) and -mu- E
-    (anions) and spreads as sigma^2 + 2 D t, D = v_th mu."""
+    (anions) and spreads as sigma^2 + 2 D t, D = v_th mu; on the D2Q5 ion
+    lattice and on the D2Q9 one of Eq. (34)-(38)."""
     ny, nx, dpsi, mu, vth, m = 160, 4, 1.6, 1.0, 0.025, 1.5
     o = orc.Oracle(dict(nx=nx, ny=ny, dpsi=dpsi, q=0.0, flow=0, reaction=0, mu_v=mu,
-                        v_th=vth, m_ratio=m))
+                        v_th=vth, m_ratio=m, ion_q9=ion_q9))
     y = _rows(ny, nx)
     s0, y0, T = 5.0, 79.5, 2000
     pulse = np.exp(-(y - y0) ** 2 / (2 * s0 ** 2))
@@ -316,29 +318,32 @@ def test_drift_diffusion_of_a_pulse(orc):
 _HC_CACHE = {}
 
 
-def _heterocharge(orc, W0, ny=128, nx=4, dpsi=1.0, U=0.02, alpha=0.02, beta=0.5643):
-    if W0 in _HC_CACHE:
-        return _HC_CACHE[W0]
+def _heterocharge(orc, W0, ny=128, nx=4, dpsi=1.0, U=0.02, alpha=0.02, beta=0.5643,
+                  ion_q9=0):
+    if (W0, ion_q9) in _HC_CACHE:
+        return _HC_CACHE[(W0, ion_q9)]
     mu = U * ny / dpsi
     D = alpha * mu * dpsi
     q = W0 * dpsi / ny ** 2
     gam = (beta ** 2 / W0) * ny / dpsi
     o = orc.Oracle(dict(nx=nx, ny=ny, dpsi=dpsi, mu_v=mu, v_th=D / mu, q=q, gamma_v=gam,
-                        flow=0, ion_force=0, poisson_iters=10))
+                        flow=0, ion_force=0, poisson_iters=10, ion_q9=ion_q9))
     y = _rows(ny, nx)
     o.init_fields(0.0, 1.0, 1.0, dpsi * (ny - 0.5 - y) / ny)
     o.step(15000)
     sol = bvp1d.solve(ny, dpsi, mu, mu, D, D, 1.0, q, 1.0, gam, tol=1e-7)
-    _HC_CACHE[W0] = (o.fields(), sol.sol(np.arange(ny)))
-    return _HC_CACHE[W0]
+    _HC_CACHE[(W0, ion_q9)] = (o.fields(), sol.sol(np.arange(ny)))
+    return _HC_CACHE[(W0, ion_q9)]
 
 
+@pytest.mark.parametrize("ion_q9", [0, 1])
 @pytest.mark.parametrize("W0", [1.42233, 5.6893])
-def test_heterocharge_layer_matches_independent_bvp(orc, W0):
+def test_heterocharge_layer_matches_independent_bvp(orc, W0, ion_q9):
     """Sec. 5.1: permeable electrodes, flow at rest, conduction numbers of the
     d = 1 mm and 2 mm cases (Fig. 10 caption).  The steady LB profiles match
-    a collocation solve of the same Nernst-Planck-Poisson system."""
-    f, ref = _heterocharge(orc, W0)
+    a collocation solve of the same Nernst-Planck-Poisson system, with the
+    ions on D2Q5 and on the D2Q9 lattice of Eq. (34)-(38)."""
+    f, ref = _heterocharge(orc, W0, ion_q9=ion_q9)
     cp, cm, psi, E = f["cp"][:, 0], f["cm"][:, 0], f["psi"][:, 0], f["Ey"][:, 0]
     assert np.linalg.norm(cp - ref[0]) / np.linalg.norm(ref[0]) < 2e-3
     assert np.linalg.norm(cm - ref[2]) / np.linalg.norm(ref[2]) < 2e-3
@@ -363,9 +368,10 @@ def test_heterocharge_layer_thins_as_W0_grows(orc):
 # --------------------------------------------------------------------------
 # Invariants of the coupled droplet case
 # --------------------------------------------------------------------------
-def test_conservation_of_phi_and_charge(orc):
+@pytest.mark.parametrize("ion_q9", [0, 1])
+def test_conservation_of_phi_and_charge(orc, ion_q9):
     cfg = workloads.config1()
-    p = dict(cfg["params"], walls=1)    # ion-tight walls: total charge is invariant
+    p = dict(cfg["params"], walls=1, ion_q9=ion_q9)  # ion-tight walls: charge is invariant
     o = orc.Oracle(p)
     d = cfg["droplet"]
     o.init_droplet(d["xc"], d["yc"], d["radius"], 1e-3, 5, presolve=200)
