@@ -494,6 +494,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=64)
     ap.add_argument("--cpu-steps-1t", type=int, default=4,
                     help="further oracle steps on one thread (0: skip)")
+    ap.add_argument("--inplace", action="store_true",
+                    help="in-place streaming (one population buffer, AA pattern)")
+    ap.add_argument("--ion-q9", action="store_true",
+                    help="the ion LBEs on D2Q9 instead of D2Q5")
     ap.add_argument("--no-forms", action="store_true",
                     help="leave out the batched and serving sub-objects of the default line")
     ap.add_argument("--form-requests", type=int, default=64,
@@ -560,7 +564,12 @@ def main():
     else:
         cfg = workloads.scaled(n, W=5.0)
     params, drop = cfg["params"], cfg["droplet"]
-    workload = "droplet-%d-%s" % (n, args.precision)
+    workload = "droplet-%d-%s" % (n, args.precision) + ("-inplace" if args.inplace else "") \
+        + ("-ions-d2q9" if args.ion_q9 else "")
+    if args.inplace:
+        params = dict(params, inplace=1)
+    if args.ion_q9:
+        params = dict(params, ion_q9=1)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -598,8 +607,9 @@ def main():
     # populations, reference lines) is reported beside it
     s_bytes = {"fp64": 8, "fp32": 4, "fp32f64": 4, "fp16": 2, "bf16": 2}[args.precision]
     j_bytes = 8 if args.precision in ("fp64", "fp32f64") else 4
-    alg = 2 * 33 * s_bytes + 2 * 2 * j_bytes
-    design = lbm_ehd.lbm_ehd_bytes_per_lup(args.precision)
+    npop = 41 if args.ion_q9 else 33    # the ions on D2Q9 add 2 x 4 diagonals
+    alg = 2 * npop * s_bytes + 2 * 2 * j_bytes
+    design = lbm_ehd.lbm_ehd_bytes_per_lup(args.precision) + (2 * 8 * s_bytes if args.ion_q9 else 0)
     achieved = alg * cells / (kern_ms * 1e-3) / 1e9
     diag = sim.diagnostics()
     traffic = measured_traffic(workload, waves, tile_rows)

@@ -157,6 +157,29 @@ typedef struct {
                               count of lbm_ehd_diagnostics; each check
                               synchronises the stream) and return LBM_ENONFINITE
                               as soon as a cell is not finite.  0: no checks */
+  int32_t inplace;         /* 0: two population buffers (pull streaming between them);
+                              1: one buffer, in-place streaming in the AA pattern (the
+                              populations of a node alternate between its own slots,
+                              reversed, and its neighbours' slots, step by step; wall
+                              rules written back into the node's own slots).  Halves
+                              the population memory; FP64 and FP32 storage (LBM_FP64,
+                              LBM_FP32, LBM_FP32_F64), electrodes, insulating or
+                              y-periodic walls, no side walls, no local field, no
+                              converged-Poisson mode (lbm_ehd_presolve_to is not
+                              available).  Each step adds a pre-pass that writes phi'
+                              and psi' of every node to two planes, from which the
+                              sweep takes the stencils' neighbourhoods (in place a
+                              neighbouring workgroup may already have overwritten the
+                              populations they are moments of). */
+  int32_t ion_q9;          /* 0: the ion LBEs on D2Q5 (Sec. 4.3 uses D2Q5 for them);
+                              1: on D2Q9 with the weights of Eq. (25) and the
+                              equilibria, sources and MRT rates of Eq. (34)-(38) and
+                              (47) extended to nine velocities (8 more lines per
+                              lattice row, 344 instead of 280 bytes per node update
+                              with FP32 storage).  FP64 and FP32 storage (LBM_FP64,
+                              LBM_FP32, LBM_FP32_F64), electrodes, insulating or
+                              y-periodic walls, no side walls, no local field, two
+                              buffers */
   int32_t reserved;        /* 0 */
 } lbm_ehd_params;
 
@@ -189,7 +212,8 @@ typedef struct {
 /*
  * Caller-supplied device memory and stream.  pop[0] and pop[1] each hold
  * pop_bytes (>= the size lbm_ehd_required_bytes() returns) and aux holds
- * aux_bytes; the library ping-pongs between pop[0] and pop[1].  The memory
+ * aux_bytes; the library ping-pongs between pop[0] and pop[1] (with
+ * inplace = 1 it uses pop[0] alone, and pop[1] may be NULL).  The memory
  * stays owned by the caller and must outlive the handle.  stream is a
  * hipStream_t (NULL: the null stream).
  */

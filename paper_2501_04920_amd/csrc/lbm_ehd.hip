@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "lbm_ehd.h"
-#include "lbm_ehd_kernels.hpp"
+#include "lbm_ehd_aa.hpp"
 
 using namespace lbm;
 
@@ -62,8 +62,13 @@ bool local_h(int prec) { return elem_size(prec) == 2; }
 size_t rest_bytes(int prec) { return 8 * (local_h(prec) ? 3 : 1); }
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
-// lines per lattice row of a population buffer: 33, and a 34th with bfloat16
-// storage (the second line of the reference momentum of f, see LocalF)
+// lines per lattice row of a population buffer: 33, a 34th with bfloat16
+// storage (the second line of the reference momentum of f, see LocalF), 41
+// with the ions on D2Q9 (the diagonals of both species)
+int lines_of(const lbm_ehd_params& p) {
+  if (p.ion_q9) return NPOP9;
+  return p.precision == LBM_BF16_STORE ? NPOP + 1 : NPOP;
+}
 int lines_of(int prec) { return prec == LBM_BF16_STORE ? NPOP + 1 : NPOP; }
 
 bool finite_all(std::initializer_list<double> v) {
@@ -105,15 +110,20 @@ struct lbm_ehd {
   BatchTile* d_tiles = nullptr;
   int ntiles = 0;
   int desc_cur = 0;
+  // In-place streaming (P.inplace): the orientation of f, h, p, n (par) and
+  // of g (gpar), and those the uploaded descriptor was written with.
+  int par = 0, gpar = 0;
+  int desc_par = 0, desc_gpar = 0;
   // g-only sweeps replayed from a captured graph (pre-solves): a block of
   // sweeps starting from the state buffer, per state buffer, captured on a
   // private stream (never the legacy default one)
   hipGraphExec_t pre_exec[2] = {nullptr, nullptr};
   hipStream_t cap = nullptr;
   // Blocks of RUN_BLOCK fused sweeps replayed from a captured graph
-  // (lbm_ehd_run), one per parity of cur against desc_cur; dropped when the
-  // launch shape changes.
-  hipGraphExec_t run_exec[2] = {nullptr, nullptr};
+  // (lbm_ehd_run), one per parity of cur against desc_cur (in place: of par
+  // and of gpar against the descriptor's); dropped when the launch shape
+  // changes.
+  hipGraphExec_t run_exec[4] = {nullptr, nullptr, nullptr, nullptr};
   // The batch this simulation belongs to (NULL: none).  A member is stepped
   // by its batch only.
   lbm_ehd_batch* batch = nullptr;
@@ -122,16 +132,19 @@ struct lbm_ehd {
 namespace {
 
 // Form of the sweep a simulation runs on, each compiled separately: 0 plain,
-// 1 with side walls, 2 with side walls and the local field of Eq. (50).
+// 1 with side walls, 2 with side walls and the local field of Eq. (50), 3
+// in-place streaming (plain), 4 plain with the ions on D2Q9.
 int sweep_form(const lbm_ehd_params& p) {
+  if (p.inplace) return 3;
+  if (p.ion_q9) return 4;
   return p.local_field ? 2 : (p.side_walls ? 1 : 0);
 }
 
 // Tile list of a set of simulations: larger ones first, each band by band
 // across its strips of 64 * waves columns, padded with empty tiles to a
 // multiple of 8 (the sweep gives each XCD one contiguous run of tiles).
-// `form` -1 takes every simulation (and never returns an empty list); 0, 1
-// and 2 only those on that form of the sweep (possibly none).
+// `form` -1 takes every simulation (and never returns an empty list); 0 to 4
+// only those on that form of the sweep (possibly none).
 std::vector<BatchTile> tile_list(const std::vector<const lbm_ehd*>& sims, int waves,
                                  int tile_rows, int form = -1) {
   std::vector<int> order;
@@ -191,7 +204,8 @@ KP<R> make_kp(const lbm_ehd* h) {
   k.walls = p.walls;
   k.side_walls = p.side_walls;
   k.local_field = p.local_field;
-  k.rstride = (uint32_t)(lines_of(p.precision) * h->pitch);
+  k.rstride = (uint32_t)(lines_of(p) * h->pitch);
+  k.ion_q9 = p.ion_q9;
   k.cells = (uint32_t)((long long)p.ny * h->pitch);
   k.pop_bytes = (uint32_t)h->pop_bytes;
   k.reaction = p.reaction;
@@ -264,13 +278,41 @@ struct Form {
   // h0 (then p0, n0 with 16-bit storage), one plane each.  Like the
   // populations they ping-pong between time levels (neighbouring workgroups
   // read h0 for their phi halo).
+  // In place there is one time level, which the sweep updates in place
+  // (neighbours take phi' from the pre-pass planes instead).
   static T0* h0(lbm_ehd* h, int i) {
+    if (h->P.inplace) i = 0;
     return reinterpret_cast<T0*>(static_cast<char*>(h->aux) +
                                  2 * (size_t)h->P.ny * h->pitch * sizeof(R)) +
            (size_t)i * rest_planes<S>() * h->P.ny * h->pitch;
   }
+  // In place: the phi' and psi' planes of the pre-pass (type W), after the
+  // rest population.
+  static W* phiP(lbm_ehd* h) {
+    return reinterpret_cast<W*>(h0(h, 0) + (size_t)h->P.ny * h->pitch);
+  }
+  static W* psiP(lbm_ehd* h) { return phiP(h) + (size_t)h->P.ny * h->pitch; }
 
   typedef SimDesc<S, R, T0> Desc;
+  typedef SimDescAA<S, R, T0> DescAA;
+
+  // Descriptor of an in-place simulation.
+  static DescAA desc_aa(lbm_ehd* h) {
+    DescAA d;
+    std::memset(&d, 0, sizeof d);
+    d.kp = make_kp<R>(h);
+    d.kpw = make_kp<W>(h);
+    d.pop = buf(h, 0);
+    d.jprev = jp(h);
+    d.h0 = h0(h, 0);
+    d.phiP = phiP(h);
+    d.psiP = psiP(h);
+    d.par = h->par;
+    d.gpar = h->gpar;
+    return d;
+  }
+  // 4- and 8-byte storage only (the form that has the in-place sweep)
+  static constexpr bool kAA = sizeof(S) >= 4;
 
   // Descriptor of a simulation for the tile kernel.
   static Desc desc(lbm_ehd* h) {
@@ -295,17 +337,24 @@ struct Form {
       if (e) (void)hipGraphExecDestroy(e);
       e = nullptr;
     }
-    const Desc d = desc(h);
     const std::vector<BatchTile> tl = tile_list({h}, h->waves, h->tile_rows);
     (void)hipFree(h->d_tiles);
     h->d_tiles = nullptr;
-    if (!h->d_desc) HIP_TRY(hipMalloc(&h->d_desc, sizeof(Desc)));
+    if (!h->d_desc) HIP_TRY(hipMalloc(&h->d_desc, std::max(sizeof(Desc), sizeof(DescAA))));
     HIP_TRY(hipMalloc(&h->d_tiles, tl.size() * sizeof(BatchTile)));
-    HIP_TRY(hipMemcpy(h->d_desc, &d, sizeof d, hipMemcpyHostToDevice));
+    if (h->P.inplace) {
+      const DescAA d = desc_aa(h);
+      HIP_TRY(hipMemcpy(h->d_desc, &d, sizeof d, hipMemcpyHostToDevice));
+    } else {
+      const Desc d = desc(h);
+      HIP_TRY(hipMemcpy(h->d_desc, &d, sizeof d, hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMemcpy(h->d_tiles, tl.data(), tl.size() * sizeof(BatchTile),
                       hipMemcpyHostToDevice));
     h->ntiles = (int)tl.size();
     h->desc_cur = h->cur;
+    h->desc_par = h->par;
+    h->desc_gpar = h->gpar;
     return LBM_OK;
   }
 
@@ -332,7 +381,10 @@ struct Form {
   // member's buffers.
   static lbm_status launch_tiles(int waves, int form, const void* descs,
                                  const BatchTile* tiles, int ntiles, int flip, hipStream_t st) {
-    if (form == 2)
+    if (form == 4) {
+      if constexpr (kAA)  // (4- and 8-byte storage only, as in place)
+        launch_ext<3>(waves, descs, tiles, ntiles, flip, st);
+    } else if (form == 2)
       launch_ext<2>(waves, descs, tiles, ntiles, flip, st);
     else if (form == 1)
       launch_ext<1>(waves, descs, tiles, ntiles, flip, st);
@@ -342,7 +394,41 @@ struct Form {
     return LBM_OK;
   }
 
+  // One in-place step over the tiles `tiles` of the members described by
+  // `descs` (DescAA): the phi'/psi' pre-pass, then the sweep.  `flip` /
+  // `gflip` = 1 turns every member's orientation of f, h, p, n / of g.
+  template <int NW>
+  static void launch_aa_nw(const void* descs, const BatchTile* tiles, int ntiles, int flip,
+                           int gflip, hipStream_t st) {
+    if constexpr (kAA) {
+      hipLaunchKernelGGL((k_aa_hood<S, R, T0, NW>), dim3(ntiles), dim3(64 * NW), 0, st,
+                         static_cast<const DescAA*>(descs), tiles, ntiles / 8, flip, gflip);
+      hipLaunchKernelGGL((k_sweep_aa<S, R, T0, NW>), dim3(ntiles), dim3(64 * NW), 0, st,
+                         static_cast<const DescAA*>(descs), tiles, ntiles / 8, flip, gflip);
+    }
+  }
+  static lbm_status launch_aa(int waves, const void* descs, const BatchTile* tiles, int ntiles,
+                              int flip, int gflip, hipStream_t st) {
+    if (!kAA) return fail(LBM_EINVAL, "in-place streaming needs 4- or 8-byte storage");
+    switch (waves) {
+      case 8: launch_aa_nw<8>(descs, tiles, ntiles, flip, gflip, st); break;
+      case 4: launch_aa_nw<4>(descs, tiles, ntiles, flip, gflip, st); break;
+      case 2: launch_aa_nw<2>(descs, tiles, ntiles, flip, gflip, st); break;
+      default: launch_aa_nw<1>(descs, tiles, ntiles, flip, gflip, st); break;
+    }
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+  }
+
   static lbm_status sweep(lbm_ehd* h) {
+    if (h->P.inplace) {
+      lbm_status st = launch_aa(h->waves, h->d_desc, h->d_tiles, h->ntiles,
+                                h->par ^ h->desc_par, h->gpar ^ h->desc_gpar, h->stream);
+      if (st) return st;
+      h->par ^= 1;
+      h->gpar ^= 1;
+      return LBM_OK;
+    }
     lbm_status st = launch_tiles(h->waves, sweep_form(h->P), h->d_desc, h->d_tiles,
                                  h->ntiles, h->cur ^ h->desc_cur, h->stream);
     if (st) return st;
@@ -459,7 +545,7 @@ struct Form {
   static lbm_status settle_g(lbm_ehd* h, const S* gsrc) {
     S* A = buf(h, h->cur);
     if (gsrc != A) {
-      const size_t row = (size_t)lbm::lines_of<S>() * h->pitch * sizeof(S);
+      const size_t row = (size_t)lines_of(h->P) * h->pitch * sizeof(S);
       const size_t line = (size_t)h->pitch;
       HIP_TRY(hipMemcpy2DAsync(A + QG * line, row, gsrc + QG * line, row,
                                5 * line * sizeof(S), (size_t)h->P.ny + 2,
@@ -482,6 +568,11 @@ struct Form {
       h->presolve_iters = done;
       h->presolve_residual = r;
     } else if (h->P.poisson_iters > 0) {
+      if (h->P.inplace) {
+        lbm_status st = g_sweeps_aa(h, h->P.poisson_iters);
+        if (st) return st;
+        return sweep(h);
+      }
       const S* g = nullptr;
       lbm_status st = poisson(h, h->P.poisson_iters, &g);
       if (st) return st;
@@ -489,6 +580,33 @@ struct Form {
       if (st) return st;
     }
     return sweep(h);
+  }
+
+  // `n` g-only sweeps in place (phi and rho_e held fixed), each turning the
+  // orientation of g.  The first refreshes every moment plane, the later ones
+  // psi' alone.
+  static lbm_status g_sweeps_aa(lbm_ehd* h, int n) {
+    if constexpr (kAA) {
+      if (!h->mom) HIP_TRY(hipMalloc(&h->mom, 3 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
+      const KP<R> kp = make_kp<R>(h);
+      S* A = buf(h, 0);
+      R* mom = static_cast<R*>(h->mom);
+      for (int it = 0; it < n; ++it) {
+        if (it == 0)
+          hipLaunchKernelGGL((k_aa_moments<S, R, T0>), grid2(h), dim3(64), 0, h->stream, A,
+                             h0(h, 0), mom, kp, h->par, h->gpar);
+        else
+          hipLaunchKernelGGL((k_aa_psi_plane<S, R>), grid2(h), dim3(64), 0, h->stream, A, mom,
+                             kp, h->gpar);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL((k_aa_poisson<S, R>), grid2(h), dim3(64), 0, h->stream, A, mom, kp,
+                           h->gpar);
+        HIP_TRY(hipGetLastError());
+        h->gpar ^= 1;
+      }
+      return LBM_OK;
+    }
+    return fail(LBM_EINVAL, "in-place streaming needs 4- or 8-byte storage");
   }
 
   // `n` time steps.  Steps without extra g-only sweeps are fused sweeps
@@ -506,8 +624,10 @@ struct Form {
       return LBM_OK;
     }
     if (n >= RUN_BLOCK) {
-      const int par = h->cur ^ h->desc_cur;
-      hipGraphExec_t& exec = h->run_exec[par];
+      const bool aa = h->P.inplace;
+      const int par = aa ? h->par ^ h->desc_par : h->cur ^ h->desc_cur;
+      const int gpar = aa ? h->gpar ^ h->desc_gpar : 0;
+      hipGraphExec_t& exec = h->run_exec[par | (gpar << 1)];
       if (!exec) {
         // captured (not run) on a private stream: the handle's stream may be
         // the legacy default one, which cannot be captured
@@ -515,8 +635,10 @@ struct Form {
         HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
         lbm_status cst = LBM_OK;
         for (int i = 0; i < RUN_BLOCK && !cst; ++i)
-          cst = launch_tiles(h->waves, sweep_form(h->P), h->d_desc, h->d_tiles, h->ntiles,
-                             par ^ (i & 1), h->cap);
+          cst = aa ? launch_aa(h->waves, h->d_desc, h->d_tiles, h->ntiles, par ^ (i & 1),
+                               gpar ^ (i & 1), h->cap)
+                   : launch_tiles(h->waves, sweep_form(h->P), h->d_desc, h->d_tiles,
+                                  h->ntiles, par ^ (i & 1), h->cap);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(h->cap, &g);
         if (!cst && e == hipSuccess) {
@@ -541,6 +663,7 @@ struct Form {
   }
 
   static lbm_status presolve(lbm_ehd* h, int iters) {
+    if (h->P.inplace) return g_sweeps_aa(h, iters);
     const S* g = nullptr;
     lbm_status st = poisson(h, iters, &g);
     if (st) return st;
@@ -550,8 +673,15 @@ struct Form {
   static lbm_status init(lbm_ehd* h, const InitSpec& sp) {
     const KP<R> kp = make_kp<R>(h);
     h->cur = 0;
-    hipLaunchKernelGGL((k_init<S, R, T0>), grid2(h), dim3(64), 0, h->stream, buf(h, 0), jp(h),
-                       h0(h, 0), kp, sp);
+    h->par = h->gpar = 0;
+    if (h->P.inplace) {
+      if constexpr (kAA)
+        hipLaunchKernelGGL((k_init<S, R, T0, true>), grid2(h), dim3(64), 0, h->stream, buf(h, 0),
+                           jp(h), h0(h, 0), kp, sp);
+    } else {
+      hipLaunchKernelGGL((k_init<S, R, T0>), grid2(h), dim3(64), 0, h->stream, buf(h, 0), jp(h),
+                         h0(h, 0), kp, sp);
+    }
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -560,6 +690,21 @@ struct Form {
   // derived fields (u, p, E, ...) are formed from the stored state without
   // adding FP32 rounding of their own.
   static lbm_status fields(lbm_ehd* h) {
+    if (h->P.inplace) {
+      if constexpr (kAA) {
+        if (!h->mom) HIP_TRY(hipMalloc(&h->mom, 3 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
+        if (!h->fld)
+          HIP_TRY(hipMalloc(&h->fld, 10 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
+        const KP<W> kpw = make_kp<W>(h);
+        hipLaunchKernelGGL((k_aa_moments<S, W, T0>), grid2(h), dim3(64), 0, h->stream,
+                           buf(h, 0), h0(h, 0), static_cast<W*>(h->mom), kpw, h->par, h->gpar);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL((k_aa_fields<S, W, T0>), grid2(h), dim3(64), 0, h->stream, buf(h, 0),
+                           h0(h, 0), static_cast<const W*>(h->mom), h->fld, kpw, h->par);
+        HIP_TRY(hipGetLastError());
+      }
+      return LBM_OK;
+    }
     lbm_status st = moments_as<W>(h, nullptr);
     if (st) return st;
     if (!h->fld) HIP_TRY(hipMalloc(&h->fld, 10 * (size_t)h->P.nx * h->P.ny * sizeof(double)));
@@ -576,8 +721,14 @@ struct Form {
   static lbm_status sums_into(lbm_ehd* h, double* part, double* red) {
     const KP<R> kp = make_kp<R>(h);
     const S* src = buf(h, h->cur);
-    hipLaunchKernelGGL((k_row_sums<S, R, T0>), dim3(h->P.ny), dim3(256), 0, h->stream, src,
-                       h0(h, h->cur), part, kp);
+    if (h->P.inplace) {
+      if constexpr (kAA)
+        hipLaunchKernelGGL((k_aa_row_sums<S, R, T0>), dim3(h->P.ny), dim3(256), 0, h->stream,
+                           src, h0(h, 0), part, kp, h->par, h->gpar);
+    } else {
+      hipLaunchKernelGGL((k_row_sums<S, R, T0>), dim3(h->P.ny), dim3(256), 0, h->stream, src,
+                         h0(h, h->cur), part, kp);
+    }
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, part, h->P.ny, NSUM, red);
     HIP_TRY(hipGetLastError());
@@ -654,8 +805,12 @@ struct lbm_ehd_batch {
   BatchTile* d_tiles = nullptr;
   size_t tiles_cap = 0;           // tiles
   BatchTile* h_tiles = nullptr;   // pinned staging of the tile list
-  int ntiles[3] = {0, 0, 0};      // tiles of the members on sweep form 0, 1, 2, in that
-                                  // order (each padded to a multiple of 8)
+  int ntiles[5] = {0, 0, 0, 0, 0};  // tiles of the members on sweep form 0 to 4, in that
+                                    // order (each padded to a multiple of 8)
+  // descriptors of the in-place members (form 3), indexed like the members
+  void* d_aadesc = nullptr;
+  size_t aadesc_cap = 0;          // bytes
+  void* h_aadesc = nullptr;
   bool dirty = true;              // descriptors / tiles / graph must be rebuilt
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -683,12 +838,33 @@ struct BatchForm {
       b->desc_cap = dbytes;
     }
     Desc* hd = static_cast<Desc*>(b->h_desc);
-    for (size_t i = 0; i < n; ++i) hd[i] = F::desc(b->sims[i]);
+    bool any_aa = false;
+    for (size_t i = 0; i < n; ++i) {
+      hd[i] = F::desc(b->sims[i]);
+      any_aa = any_aa || b->sims[i]->P.inplace;
+    }
+    if (any_aa) {
+      const size_t abytes = n * sizeof(typename F::DescAA);
+      if (abytes > b->aadesc_cap) {
+        (void)hipFree(b->d_aadesc);
+        (void)hipHostFree(b->h_aadesc);
+        b->d_aadesc = b->h_aadesc = nullptr;
+        b->aadesc_cap = 0;
+        HIP_TRY(hipMalloc(&b->d_aadesc, abytes));
+        HIP_TRY(hipHostMalloc(&b->h_aadesc, abytes, hipHostMallocDefault));
+        b->aadesc_cap = abytes;
+      }
+      typename F::DescAA* ha = static_cast<typename F::DescAA*>(b->h_aadesc);
+      for (size_t i = 0; i < n; ++i)
+        if (b->sims[i]->P.inplace) ha[i] = F::desc_aa(b->sims[i]);
+      HIP_TRY(hipMemcpyAsync(b->d_aadesc, b->h_aadesc, abytes, hipMemcpyHostToDevice,
+                             b->stream));
+    }
     // members on each form of the sweep get a launch of their own, so that
     // every member runs the code it runs alone (bitwise the same results)
     const std::vector<const lbm_ehd*> ms(b->sims.begin(), b->sims.end());
     std::vector<BatchTile> tl;
-    for (int form = 0; form < 3; ++form) {
+    for (int form = 0; form < 5; ++form) {
       const std::vector<BatchTile> t = tile_list(ms, b->waves, b->tile_rows, form);
       b->ntiles[form] = (int)t.size();
       tl.insert(tl.end(), t.begin(), t.end());
@@ -713,10 +889,13 @@ struct BatchForm {
 
   static lbm_status launch(lbm_ehd_batch* b, int flip) {
     int first = 0;
-    for (int form = 0; form < 3; ++form) {
+    for (int form = 0; form < 5; ++form) {
       if (b->ntiles[form] > 0) {
-        const lbm_status st = F::launch_tiles(b->waves, form, b->d_desc, b->d_tiles + first,
-                                              b->ntiles[form], flip, b->stream);
+        const lbm_status st =
+            form == 3 ? F::launch_aa(b->waves, b->d_aadesc, b->d_tiles + first, b->ntiles[form],
+                                     flip, flip, b->stream)
+                      : F::launch_tiles(b->waves, form, b->d_desc, b->d_tiles + first,
+                                        b->ntiles[form], flip, b->stream);
         if (st) return st;
       }
       first += b->ntiles[form];
@@ -755,7 +934,7 @@ lbm_status validate(const lbm_ehd_params* p) {
   if ((long long)p->nx * p->ny > (1LL << 31)) return fail(LBM_EINVAL, "grid too large");
   if (!elem_size(p->precision)) return fail(LBM_EINVAL, "unknown precision");
   // kernels address a population buffer with 32-bit byte offsets
-  if ((double)lines_of(p->precision) * (p->ny + 2) * pitch_of(p->nx) * elem_size(p->precision) >=
+  if ((double)lines_of(*p) * (p->ny + 2) * pitch_of(p->nx) * elem_size(p->precision) >=
       4294967296.0)
     return fail(LBM_EINVAL, "grid too large: a population buffer must stay below 4 GiB");
   if (p->walls < 0 || p->walls > 2) return fail(LBM_EINVAL, "unknown walls");
@@ -766,6 +945,19 @@ lbm_status validate(const lbm_ehd_params* p) {
     return fail(LBM_EINVAL, "poisson_tol > 0 needs poisson_iters >= 1 and poisson_max >= 1");
   if (p->poisson_iters < 0) return fail(LBM_EINVAL, "poisson_iters < 0");
   if (p->diag_every < 0) return fail(LBM_EINVAL, "diag_every < 0");
+  if (p->inplace != 0 && p->inplace != 1) return fail(LBM_EINVAL, "inplace: 0 or 1");
+  if (p->ion_q9 != 0 && p->ion_q9 != 1) return fail(LBM_EINVAL, "ion_q9: 0 or 1");
+  if (p->ion_q9 && (elem_size(p->precision) == 2 || p->side_walls || p->local_field ||
+                    p->inplace))
+    return fail(LBM_EINVAL,
+                "ions on D2Q9: FP64 or FP32 storage, the plain sweep (no side walls, no local "
+                "field, two buffers)");
+  if (p->inplace && elem_size(p->precision) == 2)
+    return fail(LBM_EINVAL, "in-place streaming needs FP64 or FP32 storage");
+  if (p->inplace && (p->side_walls || p->local_field || p->poisson_tol > 0))
+    return fail(LBM_EINVAL,
+                "in-place streaming covers the plain sweep: no side walls, no local field, "
+                "no converged-Poisson mode");
   if (!finite_all({p->rho_v, p->rho_r, p->eta_v, p->eta_r, p->M_phi, p->W, p->zeta, p->theta,
                    p->dpsi, p->eps_v, p->eps_r, p->mu_v, p->mu_r, p->m_ratio, p->v_th, p->c0,
                    p->q, p->gamma_v, p->force_x, p->force_y, p->s_free, p->n_eps}))
@@ -1004,10 +1196,14 @@ lbm_status lbm_ehd_required_bytes(const lbm_ehd_params* p, size_t* pop_bytes,
   if (st) return st;
   const size_t pitch = pitch_of(p->nx);
   if (pop_bytes)
-    *pop_bytes = (size_t)lines_of(p->precision) * (p->ny + 2) * pitch * elem_size(p->precision);
-  if (aux_bytes)
-    *aux_bytes =
-        (size_t)p->ny * pitch * (2 * arith_size(p->precision) + 2 * rest_bytes(p->precision));
+    *pop_bytes = (size_t)lines_of(*p) * (p->ny + 2) * pitch * elem_size(p->precision);
+  if (aux_bytes) {
+    if (p->inplace)  // (phi u), one level of the rest of h, the phi' and psi' planes (FP64)
+      *aux_bytes = (size_t)p->ny * pitch * (2 * arith_size(p->precision) + 8 + 8 + 8);
+    else
+      *aux_bytes =
+          (size_t)p->ny * pitch * (2 * arith_size(p->precision) + 2 * rest_bytes(p->precision));
+  }
   return LBM_OK;
 }
 
@@ -1019,7 +1215,7 @@ lbm_status lbm_ehd_footprint_bytes(const lbm_ehd_params* p, size_t* bytes) {
   const size_t nc = (size_t)p->nx * p->ny;
   // state + moment and field scratch (allocated on first use) + sums, lines
   // and the sweep's tile list at its largest (one wave, bands of one row)
-  *bytes = 2 * pb + ab + 3 * nc * sizeof(double) + 10 * nc * sizeof(double) +
+  *bytes = (p->inplace ? 1 : 2) * pb + ab + 3 * nc * sizeof(double) + 10 * nc * sizeof(double) +
            (size_t)p->ny * NSUM * sizeof(double) + NSUM * sizeof(double) +
            (2 * (size_t)p->ny + 2 * (size_t)p->nx) * sizeof(double) +
            ((size_t)p->ny * ((p->nx + 63) / 64) + 8) * sizeof(BatchTile) + 4096;
@@ -1048,19 +1244,20 @@ lbm_status lbm_ehd_create(const lbm_ehd_params* p, const lbm_ehd_device* dev, lb
     return fail(code, msg);
   };
   if (dev) {
-    if (!dev->pop[0] || !dev->pop[1] || !dev->aux || dev->pop[0] == dev->pop[1])
+    if (!dev->pop[0] || !dev->aux || (!p->inplace && (!dev->pop[1] || dev->pop[0] == dev->pop[1])))
       return cleanup(LBM_EINVAL, "device buffers missing or aliased");
     if (dev->pop_bytes < pb || dev->aux_bytes < ab)
       return cleanup(LBM_ERANGE, "device buffers too small (need " + std::to_string(pb) +
                                      " and " + std::to_string(ab) + " bytes)");
     h->pop[0] = dev->pop[0];
-    h->pop[1] = dev->pop[1];
+    h->pop[1] = p->inplace ? nullptr : dev->pop[1];
     h->aux = dev->aux;
     h->stream = static_cast<hipStream_t>(dev->stream);
     h->own = false;
   } else {
     h->own = true;
-    if (hipMalloc(&h->pop[0], pb) != hipSuccess || hipMalloc(&h->pop[1], pb) != hipSuccess ||
+    if (hipMalloc(&h->pop[0], pb) != hipSuccess ||
+        (!p->inplace && hipMalloc(&h->pop[1], pb) != hipSuccess) ||
         hipMalloc(&h->aux, ab) != hipSuccess)
       return cleanup(LBM_ENOMEM, "device allocation of the state failed");
   }
@@ -1158,6 +1355,9 @@ lbm_status lbm_ehd_presolve_to(lbm_ehd* h, double tol, int32_t max_iters, int32_
   if (!h->ready) return fail(LBM_ESTATE, "presolve before init");
   if (!(tol > 0) || max_iters < 1 || check_every < 1)
     return fail(LBM_EINVAL, "need tol > 0, max_iters >= 1, check_every >= 1");
+  if (h->P.inplace)
+    return fail(LBM_EINVAL, "presolve_to: the convergence residual needs two buffers "
+                            "(not available with in-place streaming)");
   int done = 0;
   double r = NAN;
   lbm_status st = dispatch(
@@ -1316,7 +1516,7 @@ namespace {
 // and the binary16 scales.  A state read with other values would stand for
 // another physical state.
 struct RefSig {
-  int32_t walls, side_walls;
+  int32_t walls, side_walls, inplace, ion_q9;
   double dpsi, c0, a_g;
   double iofs[10], sc[5];
 };
@@ -1327,6 +1527,8 @@ RefSig ref_sig(const lbm_ehd* h) {
   const KP<double> k = make_kp<double>(h);
   r.walls = h->P.walls;
   r.side_walls = h->P.side_walls;
+  r.inplace = h->P.inplace;
+  r.ion_q9 = h->P.ion_q9;
   r.dpsi = h->P.dpsi;
   r.c0 = h->P.c0;
   r.a_g = k.a_g;
@@ -1341,11 +1543,11 @@ struct SavedState {
   uint64_t magic;
   int32_t nx, ny, precision, pitch;
   int64_t step;
-  int32_t cur, reserved;
+  int32_t cur, gpar;  // the current buffer, or in place the two orientations
   uint64_t pop_bytes, aux_bytes;
   RefSig ref;
 };
-constexpr uint64_t STATE_MAGIC = 0x3230455441545345ull;  // "ESTATE02"
+constexpr uint64_t STATE_MAGIC = 0x3330455441545345ull;  // "ESTATE03"
 
 }  // namespace
 
@@ -1368,7 +1570,8 @@ lbm_status lbm_ehd_save_state(lbm_ehd* h, void* buffer, size_t bytes) {
   hd.precision = h->P.precision;
   hd.pitch = h->pitch;
   hd.step = h->step;
-  hd.cur = h->cur;
+  hd.cur = h->P.inplace ? h->par : h->cur;
+  hd.gpar = h->P.inplace ? h->gpar : 0;
   hd.pop_bytes = h->pop_bytes;
   hd.aux_bytes = h->aux_bytes;
   hd.ref = ref_sig(h);
@@ -1389,7 +1592,7 @@ lbm_status lbm_ehd_load_state(lbm_ehd* h, const void* buffer, size_t bytes) {
   if (hd.magic != STATE_MAGIC) return fail(LBM_EINVAL, "not a saved state");
   if (hd.nx != h->P.nx || hd.ny != h->P.ny || hd.precision != h->P.precision ||
       hd.pitch != h->pitch || hd.pop_bytes != h->pop_bytes || hd.aux_bytes != h->aux_bytes ||
-      (hd.cur != 0 && hd.cur != 1))
+      (hd.cur != 0 && hd.cur != 1) || (hd.gpar != 0 && hd.gpar != 1))
     return fail(LBM_EINVAL, "state of another grid, precision or layout");
   const RefSig mine = ref_sig(h);
   if (std::memcmp(&hd.ref, &mine, sizeof mine) != 0)
@@ -1400,9 +1603,14 @@ lbm_status lbm_ehd_load_state(lbm_ehd* h, const void* buffer, size_t bytes) {
     return fail(LBM_ERANGE, "state buffer too small");
   const char* in = static_cast<const char*>(buffer);
   HIP_TRY(hipStreamSynchronize(h->stream));
-  HIP_TRY(hipMemcpy(h->pop[hd.cur], in + sizeof hd, hd.pop_bytes, hipMemcpyHostToDevice));
+  const int into = h->P.inplace ? 0 : hd.cur;
+  HIP_TRY(hipMemcpy(h->pop[into], in + sizeof hd, hd.pop_bytes, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->aux, in + sizeof hd + hd.pop_bytes, hd.aux_bytes, hipMemcpyHostToDevice));
-  h->cur = hd.cur;
+  h->cur = into;
+  if (h->P.inplace) {
+    h->par = hd.cur;
+    h->gpar = hd.gpar & 1;
+  }
   h->step = hd.step;
   h->ready = true;
   return LBM_OK;
@@ -1485,8 +1693,15 @@ lbm_status batch_direct(lbm_ehd_batch* b, int64_t n) {
         dispatch_prec(b->precision, [&](auto F) { return decltype(F)::launch(b, (int)(i & 1)); });
     if (st) return st;
   }
-  if (n & 1) {  // every member's current buffer changed: record it
-    for (lbm_ehd* h : b->sims) h->cur = 1 - h->cur;
+  if (n & 1) {  // every member's current buffer (or orientation) changed: record it
+    for (lbm_ehd* h : b->sims) {
+      if (h->P.inplace) {
+        h->par ^= 1;
+        h->gpar ^= 1;
+      } else {
+        h->cur = 1 - h->cur;
+      }
+    }
     b->dirty = true;
   }
   for (lbm_ehd* h : b->sims) h->step += n;
@@ -1684,6 +1899,8 @@ lbm_status lbm_ehd_batch_destroy(lbm_ehd_batch* b) {
   (void)hipFree(b->d_tiles);
   (void)hipHostFree(b->h_desc);
   (void)hipHostFree(b->h_tiles);
+  (void)hipFree(b->d_aadesc);
+  (void)hipHostFree(b->h_aadesc);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return LBM_OK;

@@ -1,0 +1,442 @@
+// lbm_ehd_aa.hpp -- the fused sweep with in-place streaming (the AA pattern):
+// one population buffer per simulation instead of two.
+//
+// The buffer keeps the layout of the two-buffer sweep (rows of 33 lines of
+// `pitch` elements, ghost rows unused), but the populations of a node sit in
+// one of two orientations, alternating step by step:
+//   even steps: the population arriving at node x along c_i is at x, line i;
+//               the node writes its post-collision population i to x, line
+//               opp(i) (its own slots, reversed);
+//   odd steps:  the population arriving at x along c_i is at x - c_i, line
+//               opp(i) (where its sender left it); the node writes its
+//               post-collision population i to x + c_i, line i.
+// In both, every location is read and written by exactly one node, so a
+// sweep needs no second buffer and no ordering between workgroups.  At an
+// electrode the population a node sends through the wall comes back to it
+// along the opposite direction: the node writes the wall rule's value (in
+// deviation form, as in the two-buffer sweep) to its own line opp(i), which
+// at the next step is where it finds that arrival (in the even orientation
+// by definition, in the odd one because the wall is the sender).  The rest
+// populations stay in place.  The g set has its own orientation (`gpar`),
+// so that g-only sweeps (pre-solves, extra Poisson sweeps) work in place too.
+//
+// The isotropic stencils need phi' and psi' of the eight neighbours at the
+// current step, i.e. moments of their arrivals; in place, a neighbouring
+// workgroup may already have overwritten them.  A pre-pass (k_aa_hood)
+// therefore writes phi' and psi' of every node to two planes first, with the
+// arithmetic of the two-buffer sweep's stencil ring, and the sweep reads the
+// 3 x 3 neighbourhood from them.  The planes are in the working type (FP64
+// with FP32 storage, as the two-buffer sweep's rings hold them): 16 B per
+// cell of memory, and ~90 B per lattice update of traffic with FP32 storage
+// (the pre-pass reads the h and g arrivals and writes the planes, the sweep
+// reads them back).
+//
+// This form covers the plain sweep with FP64 and FP32 storage (no side walls,
+// no local field of Eq. 50, no 16-bit node-local references).
+#pragma once
+
+#include "lbm_ehd_kernels.hpp"
+
+namespace lbm {
+
+// Velocity components and opposite direction of D2Q9 direction i (the D2Q5
+// directions 0-4 are the same), as constant expressions.
+__host__ __device__ constexpr int cx_of(int i) {
+  return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int cy_of(int i) {
+  return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp_of(int i) {
+  return i == 0 ? 0 : (i <= 4 ? (i + 1) % 4 + 1 : (i - 3) % 4 + 5);
+}
+
+// A population buffer in the AA orientations.
+template <class S, class R>
+struct AAView {
+  PopView<S, R> P;
+  // the population of direction i of the set at line q0 that arrives at node
+  // (k.c, y) at this step, in orientation `par`
+  template <class K>
+  __device__ inline R in(int par, int q0, int i, K k, int y) const {
+    const uint32_t own = P.row(y + 1) + k.c;
+    if (par == 0 || i == 0) return P.at(q0 + i, own);
+    const int ny = P.kp->ny;
+    int ys = y - cy_of(i);
+    if (ys < 0 || ys >= ny) {
+      if (P.kp->walls != WALL_PERIODIC) return P.at(q0 + i, own);  // sent back by the wall
+      ys = ys < 0 ? ys + ny : ys - ny;
+    }
+    const int xs = cx_of(i) > 0 ? k.m : (cx_of(i) < 0 ? k.p : k.c);
+    return P.at(q0 + opp_of(i), P.row(ys + 1) + xs);
+  }
+  // store the post-collision population v of direction i of the set at line
+  // q0 of node (k.c, y), in orientation `par`; `vwall`: the value that comes
+  // back along opp(i) when c_i points through an electrode
+  template <class K>
+  __device__ inline void out(int par, int q0, int i, K k, int y, R v, R vwall) const {
+    const uint32_t own = P.row(y + 1) + k.c;
+    const int ny = P.kp->ny;
+    int yd = y + cy_of(i);
+    const bool through = (yd < 0 || yd >= ny) && P.kp->walls != WALL_PERIODIC;
+    if (par == 0 || i == 0 || through) {
+      P.put(q0 + opp_of(i), own, through ? vwall : v);
+      return;
+    }
+    yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+    const int xd = cx_of(i) > 0 ? k.p : (cx_of(i) < 0 ? k.m : k.c);
+    P.put(q0 + i, P.row(yd + 1) + xd, v);
+  }
+};
+
+// One member of an in-place sweep: its parameters, its population buffer,
+// (phi u)(t-1), the rest population of h (one time level, in place), the
+// phi' and psi' planes of the pre-pass (in the working type, as the stencil
+// ring of the two-buffer sweep) and the two orientations.
+template <class S, class R, class T0>
+struct SimDescAA {
+  KP<R> kp;
+  KP<typename WorkOf<S>::type> kpw;
+  S* pop;
+  R* jprev;
+  T0* h0;
+  typename WorkOf<S>::type* phiP;
+  typename WorkOf<S>::type* psiP;
+  int par, gpar;
+};
+
+// phi' / psi' neighbourhood of (k.c, y) from the planes of the pre-pass,
+// with the stencil ghosts of the two-buffer sweep at the electrodes.
+template <class W, class R, class K>
+__device__ inline void hood_aa(const W* __restrict__ phiP, const W* __restrict__ psiP,
+                               const KP<R>& kp, K k, int y, W phi9[9], W psi9[9]) {
+  const bool periodic = kp.walls == WALL_PERIODIC;
+  const int cols[3] = {k.m, k.c, k.p};
+  W ph[3][3], ps[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    int yy = y + r - 1;
+    if (yy < 0 || yy >= kp.ny) {
+      if (!periodic) continue;
+      yy = yy < 0 ? yy + kp.ny : yy - kp.ny;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      ph[r][j] = *elem(phiP, (uint32_t)yy * kp.pitch + cols[j]);
+      ps[r][j] = *elem(psiP, (uint32_t)yy * kp.pitch + cols[j]);
+    }
+  }
+  if (!periodic) {
+    if (y == 0) ghost_row(ph[1], ps[1], ph[0], ps[0]);
+    if (y == kp.ny - 1) ghost_row(ph[1], ps[1], ph[2], ps[2]);
+  }
+  nine(ph[0], ph[1], ph[2], phi9);
+  nine(ps[0], ps[1], ps[2], psi9);
+}
+
+// The pre-pass: phi' and psi' of every node of the tile at this step, the
+// same sums the two-buffer sweep forms in its stencil ring.
+template <class S, class R, class T0, int NW>
+__global__ __launch_bounds__(64 * NW) void k_aa_hood(const SimDescAA<S, R, T0>* __restrict__ sims,
+                                                     const BatchTile* __restrict__ tiles,
+                                                     int xcd_chunk, int flip, int gflip) {
+  typedef typename WorkOf<S>::type W;
+  const BatchTile tl = tiles[xcd_tile(xcd_chunk)];
+  if (tl.sim < 0) return;
+  const SimDescAA<S, R, T0>& sd = sims[tl.sim];
+  const KP<R>& kp = sd.kp;
+  const int x = tl.x0 + (int)threadIdx.x;
+  if (x >= kp.nx) return;
+  const int par = (sd.par + flip) & 1, gpar = (sd.gpar + gflip) & 1;
+  const AAView<S, R> V{PopView<S, R>{make_rsrc(sd.pop, kp.pop_bytes), &kp, false}};
+  const ColsP k = cols_for<0>(x, kp.nx, 0);
+  for (int y = tl.y0; y < tl.yend; ++y) {
+    const uint32_t jo = (uint32_t)y * kp.pitch + x;
+    R h[9], g4[4];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
+    *elem(sd.phiP, jo) = phi_of<W>((W)*elem(sd.h0, jo), h);
+    *elem(sd.psiP, jo) = psi_as<W>(g4);
+  }
+}
+
+// Per-node update of the in-place sweep: the arithmetic of update_node (the
+// two-buffer sweep, plain form, 4- and 8-byte storage) in the same order,
+// with the stores of the AA orientations.
+template <class S, class R, class T0, class K>
+__device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
+                                      R* __restrict__ jprev, T0* __restrict__ h0x,
+                                      const KP<R>& kp, const KP<typename WorkOf<S>::type>& kpw,
+                                      int x, int y, K k, const typename WorkOf<S>::type phi9[9],
+                                      const typename WorkOf<S>::type psi9[9], R f[9], R h[9],
+                                      R p[5], R n[5], R g[5]) {
+  typedef typename WorkOf<S>::type W;
+  W fw[9], pw[5], nw[5], ps9[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    fw[i] = (W)f[i];
+    ps9[i] = (W)psi9[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    pw[i] = (W)p[i];
+    nw[i] = (W)n[i];
+  }
+  const uint32_t jo = (uint32_t)y * kp.pitch + x;
+  const W Pd = pw[0] + pw[1] + pw[2] + pw[3] + pw[4];
+  const W Qd = nw[0] + nw[1] + nw[2] + nw[3] + nw[4];
+  Macro<W> m;
+  macro(phi9, ps9, Pd, Qd, fw, kpw, m);
+  const bool ins = kp.walls == WALL_INSULATING;
+  const R third = R(1) / R(3);
+
+  // f: bounce-back at the electrodes
+  collide_f(fw, m, kpw);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    f[i] = (R)fw[i];
+    V.out(par, QF, i, k, y, f[i], f[i]);
+  }
+
+  {  // g: Eq. (44)-(47); anti-bounce-back with the electrode potential
+    W gw[5] = {(W)g[0], (W)g[1], (W)g[2], (W)g[3], (W)g[4]};
+    collide_g(gw, m.psid, poisson_source<W>(m.rhoe, m.ieps, m.geps, m.gpsi, kpw), kpw);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      g[i] = (R)gw[i];
+      V.out(gpar, QG, i, k, y, g[i], -g[i]);
+    }
+  }
+
+  collide_ion(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
+  collide_ion(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
+  const R cpd = (R)m.cpd, cmd = (R)m.cmd;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    p[i] = (R)pw[i];
+    // anode (through it: direction 4): c+ = 0; cathode (direction 2): d c+/dn = 0
+    const R wp = ins ? p[i] : (i == 4 ? -p[4] - third * kp.c0 : -p[i] + third * cpd);
+    V.out(par, QP, i, k, y, p[i], wp);
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    n[i] = (R)nw[i];
+    // anode: d c-/dn = 0; cathode: c- = 0
+    const R wn = ins ? n[i] : (i == 4 ? -n[4] + third * cmd : -n[i] - third * kp.c0);
+    V.out(par, QN, i, k, y, n[i], wn);
+  }
+
+  {  // h: Eq. (27)-(32), with d(phi u)/dt of Eq. (58), in W; bounce-back
+    const uint32_t jpl = kp.cells;
+    const R Jx = (R)(m.phi * m.u[0]), Jy = (R)(m.phi * m.u[1]);
+    const W dJ[2] = {(W)Jx - (W)*elem(jprev, jo), (W)Jy - (W)*elem(jprev, jpl + jo)};
+    *elem(jprev, jo) = Jx;
+    *elem(jprev, jpl + jo) = Jy;
+    const T0 h0in = *elem(h0x, jo);
+    double mass = (double)h0in;  // exact sum of the node's incoming h
+#pragma unroll
+    for (int i = 1; i < 9; ++i) mass += (double)h[i];
+    W hw[9];
+    hw[0] = (W)h0in;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) hw[i] = (W)h[i];
+    collide_h(hw, m, dJ, kpw);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      h[i] = V.P.stored(QH + i, (R)hw[i]);
+      V.out(par, QH, i, k, y, h[i], h[i]);
+      mass -= (double)h[i];
+    }
+    // the rest population takes what the eight stored ones leave of the mass
+    *elem(h0x, jo) = (T0)mass;
+  }
+}
+
+// The fused in-place sweep: one workgroup per tile of the list (as the
+// two-buffer sweep), every node of a row of the tile independent of the
+// others (no LDS, no barrier).  `flip` / `gflip` = 1 turns every member's
+// orientation of f, h, p, n / of g (odd steps of a captured block).
+template <class S, class R, class T0, int NW>
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
+    const SimDescAA<S, R, T0>* __restrict__ sims, const BatchTile* __restrict__ tiles,
+    int xcd_chunk, int flip, int gflip) {
+  typedef typename WorkOf<S>::type W;
+  const BatchTile tl = tiles[xcd_tile(xcd_chunk)];
+  if (tl.sim < 0) return;
+  const SimDescAA<S, R, T0>& sd = sims[tl.sim];
+  const KP<R>& kp = sd.kp;
+  const int x = tl.x0 + (int)threadIdx.x;
+  if (x >= kp.nx) return;
+  const int par = (sd.par + flip) & 1, gpar = (sd.gpar + gflip) & 1;
+  constexpr bool kNT = 64 * NW * sizeof(S) >= 1024;
+  const AAView<S, R> V{PopView<S, R>{make_rsrc(sd.pop, kp.pop_bytes), &kp, kNT}};
+  const ColsP k = cols_for<0>(x, kp.nx, 0);
+  for (int y = tl.y0; y < tl.yend; ++y) {
+    W phi9[9], psi9[9];
+    hood_aa(sd.phiP, sd.psiP, kp, k, y, phi9, psi9);
+    R f[9], h[9], p[5], n[5], g[5];
+    __builtin_amdgcn_s_setprio(2);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = V.in(par, QF, i, k, y);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      p[i] = V.in(par, QP, i, k, y);
+      n[i] = V.in(par, QN, i, k, y);
+      g[i] = V.in(gpar, QG, i, k, y);
+    }
+    h[0] = R(0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
+    __builtin_amdgcn_s_setprio(0);
+    update_node_aa<S, R, T0>(V, par, gpar, sd.jprev, sd.h0, kp, sd.kpw, x, y, k, phi9, psi9, f,
+                             h, p, n, g);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Helpers of the in-place form outside the hot loop (2-D launches, one
+// thread per node).  `par` / `gpar` are the orientations of the state.
+// ---------------------------------------------------------------------------
+
+// phi', psi' and rho_e = e0 (P' - Q') of every node into compact planes (as
+// k_moments).
+template <class S, class R, class T0>
+__global__ void k_aa_moments(const S* __restrict__ src, const T0* __restrict__ h0x,
+                             R* __restrict__ mom, const KP<R> kp, int par, int gpar) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= kp.nx) return;
+  const AAView<S, R> V{PopView<S, R>{make_rsrc(src, kp.pop_bytes), &kp, false}};
+  const Cols k = cols_of(x, kp.nx, 0);
+  R h[9], g4[4];
+  h[0] = (R)*elem(h0x, (uint32_t)y * kp.pitch + x);
+  for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
+  for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
+  R Pd = R(0), Qd = R(0);
+  for (int i = 0; i < 5; ++i) {
+    Pd += V.in(par, QP, i, k, y);
+    Qd += V.in(par, QN, i, k, y);
+  }
+  const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
+  mom[c] = sum9(h);
+  mom[np + c] = psi_of(g4);
+  mom[2 * np + c] = kp.q * (Pd - Qd);
+}
+
+// psi' of every node into its moment plane (g-only sweeps).
+template <class S, class R>
+__global__ void k_aa_psi_plane(const S* __restrict__ src, R* __restrict__ mom, const KP<R> kp,
+                               int gpar) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= kp.nx) return;
+  const AAView<S, R> V{PopView<S, R>{make_rsrc(src, kp.pop_bytes), &kp, false}};
+  const Cols k = cols_of(x, kp.nx, 0);
+  R g4[4];
+  for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
+  mom[(long long)kp.nx * kp.ny + (long long)y * kp.nx + x] = psi_of(g4);
+}
+
+// One g-only sweep in place (phi and rho_e held fixed, from the moment
+// planes), orientation gpar; the g set then has the other orientation.
+template <class S, class R>
+__global__ void k_aa_poisson(S* __restrict__ buf, const R* __restrict__ mom, const KP<R> kp,
+                             int gpar) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= kp.nx) return;
+  const AAView<S, R> V{PopView<S, R>{make_rsrc(buf, kp.pop_bytes), &kp, false}};
+  const Cols k = cols_of(x, kp.nx, 0);
+  R phi9[9], psi9[9], g[5];
+  hood(mom, kp, x, y, phi9, psi9);
+  for (int i = 0; i < 5; ++i) g[i] = V.in(gpar, QG, i, k, y);
+  const long long np = (long long)kp.nx * kp.ny;
+  const long long c = (long long)y * kp.nx + x;
+  const R eps = (R(0.5) + phi9[0]) * kp.deps + kp.eps_v;
+  R gphi[2], gpsi[2];
+  grad_lap<R>(phi9, gphi, nullptr);
+  grad_lap<R>(psi9, gpsi, nullptr);
+  gpsi[1] += kp.psi_slope;
+  const R geps[2] = {kp.deps * gphi[0], kp.deps * gphi[1]};
+  collide_g(g, psi9[0], poisson_source<R>(mom[2 * np + c], recip(eps), geps, gpsi, kp), kp);
+  for (int i = 0; i < 5; ++i) V.out(gpar, QG, i, k, y, g[i], -g[i]);
+}
+
+// Macroscopic fields (FP64 output, [10][ny][nx]), as k_fields.
+template <class S, class R, class T0>
+__global__ void k_aa_fields(const S* __restrict__ src, const T0* __restrict__ h0x,
+                            const R* __restrict__ mom, double* __restrict__ out, const KP<R> kp,
+                            int par) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (x >= kp.nx) return;
+  (void)h0x;
+  const AAView<S, R> V{PopView<S, R>{make_rsrc(src, kp.pop_bytes), &kp, false}};
+  const Cols k = cols_of(x, kp.nx, 0);
+  R phi9[9], psi9[9], f[9];
+  hood(mom, kp, x, y, phi9, psi9);
+  for (int i = 0; i < 9; ++i) f[i] = V.in(par, QF, i, k, y);
+  R Pd = R(0), Qd = R(0);
+  for (int i = 0; i < 5; ++i) {
+    Pd += V.in(par, QP, i, k, y);
+    Qd += V.in(par, QN, i, k, y);
+  }
+  Macro<R> m;
+  macro(phi9, psi9, Pd, Qd, f, kp, m);
+  const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
+  const double psi_lin =
+      kp.walls == WALL_PERIODIC ? 0.0 : (double)kp.dpsi * (kp.ny - 0.5 - y) / kp.ny;
+  out[0 * np + c] = 0.5 + (double)m.phid;
+  out[1 * np + c] = psi_lin + (double)m.psid;
+  out[2 * np + c] = (double)kp.c0 + (double)m.cpd;
+  out[3 * np + c] = (double)kp.c0 + (double)m.cmd;
+  out[4 * np + c] = m.rhoe;
+  out[5 * np + c] = m.u[0];
+  out[6 * np + c] = m.u[1];
+  out[7 * np + c] = m.p;
+  out[8 * np + c] = m.E[0];
+  out[9 * np + c] = m.E[1];
+}
+
+// FP64 sums of one row, as k_row_sums (same layout and tree).
+template <class S, class R, class T0>
+__global__ __launch_bounds__(256) void k_aa_row_sums(const S* __restrict__ src,
+                                                     const T0* __restrict__ h0x,
+                                                     double* __restrict__ part, const KP<R> kp,
+                                                     int par, int gpar) {
+  __shared__ double sh[NSUM][256];
+  const int y = blockIdx.x, t = threadIdx.x;
+  const AAView<S, R> V{PopView<S, R>{make_rsrc(src, kp.pop_bytes), &kp, false}};
+  double acc[NSUM] = {0, 0, 0, 0, 0, 0, 0};
+  const double c0 = (double)kp.c0;
+  for (int x = t; x < kp.nx; x += 256) {
+    const Cols k = cols_of(x, kp.nx, 0);
+    double phid = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
+    for (int i = 1; i < 9; ++i) phid += (double)V.in(par, QH, i, k, y);
+    double Pd = 0.0, Qd = 0.0;
+    for (int i = 0; i < 5; ++i) {
+      Pd += (double)V.in(par, QP, i, k, y);
+      Qd += (double)V.in(par, QN, i, k, y);
+    }
+    R g4[4];
+    for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
+    const double phi = 0.5 + phid;
+    const double psid = (double)psi_of(g4);
+    acc[0] += phi;
+    acc[1] += (double)kp.q * (Pd - Qd);
+    acc[2] += c0 + Pd;
+    acc[3] += c0 + Qd;
+    acc[4] += phi * x;
+    acc[5] += phi * y;
+    if (!(isfinite(phid) && isfinite(Pd) && isfinite(Qd) && isfinite(psid))) acc[6] += 1.0;
+  }
+  for (int j = 0; j < NSUM; ++j) sh[j][t] = acc[j];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s)
+      for (int j = 0; j < NSUM; ++j) sh[j][t] += sh[j][t + s];
+    __syncthreads();
+  }
+  if (t < NSUM) part[(long long)y * NSUM + t] = sh[t][0];
+}
+
+}  // namespace lbm

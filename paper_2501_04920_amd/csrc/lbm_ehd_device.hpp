@@ -67,7 +67,9 @@ namespace lbm {
 constexpr int NPOP = 33;
 enum { QF = 0, QH = 9, QP = 18, QN = 23, QG = 28 };
 enum { WALL_ELECTRODES = 0, WALL_INSULATING = 1, WALL_PERIODIC = 2 };
-constexpr int RING = 5;     // rows of phi/psi kept in LDS
+// rows of phi'/psi' kept in LDS: a row's three, and the next one, written
+// before the row's barrier while slower waves may still read the last three
+constexpr int RING = 4;
 
 // Kernel constants, in the arithmetic type R.
 template <class R>
@@ -93,6 +95,7 @@ struct KP {
   R sc[5], isc[5];   // binary16 storage: power-of-two scale of each set (f h p n g)
   int side_walls;    // 1: walls at x = -1/2 and nx - 1/2 (else periodic in x)
   int local_field;   // 1: E from the g populations (Eq. 50), else -grad psi (Eq. 59)
+  int ion_q9;        // 1: the ions on D2Q9 (lines QP9, QN9 hold their diagonals)
 };
 
 // Population set of plane q: 0 f, 1 h, 2 p, 3 n, 4 g.
@@ -310,6 +313,10 @@ struct LocalF<__hip_bfloat16> {
   static constexpr bool value = true;
 };
 constexpr int QJX = QN, QJY = NPOP;
+// Ions on D2Q9 (the lattice of Eq. 34-38 as printed): directions 0-4 of each
+// species keep their lines (QP.., QN..), the diagonals 5-8 take four more
+// lines each at the end of the row, 41 lines in all.
+constexpr int QP9 = NPOP, QN9 = NPOP + 4, NPOP9 = NPOP + 8;
 // lines per lattice row of a buffer
 template <class S>
 constexpr int lines_of() {
@@ -400,11 +407,13 @@ __device__ inline T* elem(T* base, uint32_t e) {
 // above), used where absolute values enter or leave: initialisation and
 // field output.
 __device__ inline double plane_ref(int q, int y, int ny, int walls, double c0, double dpsi,
-                                  double a_g) {
+                                  double a_g, int ion_q9 = 0) {
   const double w9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   if (q < QH) return 0.0;
   if (q < QP) return 0.5 * w9[q - QH];
+  if (q >= QP9) return w9[5] * c0;  // D2Q9 ion diagonals
+  if (ion_q9 && q < QG) return w9[q < QN ? q - QP : q - QN] * c0;
   const int k = q < QN ? q - QP : (q < QG ? q - QN : q - QG);
   const double wb = k == 0 ? 1.0 / 3 : 1.0 / 6;
   if (q < QG) return wb * c0;  // the drift offsets are PopView's
@@ -727,6 +736,35 @@ __device__ inline void collide_ion(W x[5], W cd, R mu, R itau, int mask, W sign,
     mo[k] = mo[k] - s * (mo[k] - eq[k]) + (W(1) - W(0.5) * s) * so[k] + sign * s * dr[k];
   }
   inv5(mo, x);
+}
+
+// p and n on D2Q9 (Eq. 34-40 with the matrix M of Eq. 28): the same update
+// in the nine raw moments, deviations from w_i c0.  The equilibrium
+// w_i c (1 + 3 c_i.u) has the moments (c, c u, c/3, c/3, 0, c ux/3, c uy/3,
+// c/9); R_i = w_i R has (R, 0, 0, R/3, R/3, 0, 0, 0, R/9); L_i and G_i, of the
+// form w_i c_i.v / c_s^2, have v in the first moments and v/3 in moments 6, 7.
+template <class W, class R>
+__device__ inline void collide_ion9(W x[9], W cd, R mu, R itau, int mask, W sign,
+                                    const Macro<R>& m, const KP<R>& kp) {
+  W mo[9];
+  fwd9(x, mo);
+  const W third = W(1) / W(3), ninth = W(1) / W(9);
+  const W c = (W)kp.c0 + cd;
+  const W Lx = kp.ion_force ? c * (W)m.F[0] : W(0);
+  const W Ly = kp.ion_force ? c * (W)m.F[1] : W(0);
+  const W Gx = (W)mu * c * (W)m.gpsi[0], Gy = (W)mu * c * (W)m.gpsi[1];
+  const W Rr = (W)m.Rr;
+  const W ux = (W)m.u[0], uy = (W)m.u[1];
+  const W eq[9] = {cd, c * ux, c * uy, third * cd, third * cd, W(0),
+                   third * c * ux, third * c * uy, ninth * cd};
+  const W so[9] = {Rr, Lx, Ly, third * Rr, third * Rr, W(0), third * Lx, third * Ly, ninth * Rr};
+  const W dr[9] = {W(0), Gx, Gy, W(0), W(0), W(0), third * Gx, third * Gy, W(0)};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const W s = (W)rate(mask, k, itau, kp.s_free);
+    mo[k] = mo[k] - s * (mo[k] - eq[k]) + (W(1) - W(0.5) * s) * so[k] + sign * s * dr[k];
+  }
+  inv9(mo, x);
 }
 
 // Poisson source S_psi of Eq. (44) (or its variable-eps form), in W;

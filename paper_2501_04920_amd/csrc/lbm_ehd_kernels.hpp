@@ -45,12 +45,20 @@ struct ColsP {
 };
 // the form of the sweep that also has the local field of Eq. (50)
 struct ColsL : Cols {};
+// the plain form with the ions on D2Q9 (Eq. 34-38 as printed)
+struct ColsP9 : ColsP {};
 
 // Column type of sweep form EXT: 0 plain, 1 side walls, 2 side walls and the
-// local field.
+// local field, 3 plain with the ions on D2Q9.
 template <int EXT>
 using ColsOf = typename std::conditional<
-    EXT == 0, ColsP, typename std::conditional<EXT == 1, Cols, ColsL>::type>::type;
+    EXT == 0, ColsP,
+    typename std::conditional<EXT == 1, Cols,
+                              typename std::conditional<EXT == 2, ColsL, ColsP9>::type>::type>::type;
+template <class K>
+constexpr bool ion9_of() {
+  return std::is_same<K, ColsP9>::value;
+}
 
 template <int EXT>
 __device__ inline ColsOf<EXT> cols_for(int xc, int nx, int side) {
@@ -58,14 +66,34 @@ __device__ inline ColsOf<EXT> cols_for(int xc, int nx, int side) {
   k.c = xc;
   k.m = xc == 0 ? nx - 1 : xc - 1;
   k.p = xc == nx - 1 ? 0 : xc + 1;
-  if constexpr (EXT != 0) {
+  if constexpr (EXT == 1 || EXT == 2) {
     k.lw = side && xc == 0;
     k.rw = side && xc == nx - 1;
   }
   return k;
 }
 
-__device__ inline Cols cols_of(int xc, int nx, int side) { return cols_for<true>(xc, nx, side); }
+__device__ inline Cols cols_of(int xc, int nx, int side) { return cols_for<1>(xc, nx, side); }
+
+// The diagonal directions 5-8 of a D2Q9 ion set whose diagonals sit in lines
+// q9..q9+3 (no side walls): x[0..3] = directions 5..8.
+template <class S, class R, class K>
+__device__ inline void pull_diag(const PopView<S, R>& P, int q9, K k, int yy, R x[4]) {
+  const uint32_t rm = P.row(yy), rp = P.row(yy + 2);
+  x[0] = P.at(q9 + 0, rm + k.m);
+  x[1] = P.at(q9 + 1, rm + k.p);
+  x[2] = P.at(q9 + 2, rp + k.p);
+  x[3] = P.at(q9 + 3, rp + k.m);
+}
+// Deviation content of the diagonals of the ion set at line q9 (0 unless
+// the ions are on D2Q9), for the helpers outside the hot loop.
+template <class S, class R, class K>
+__device__ inline R ion_diag_sum(const PopView<S, R>& P, int q9, K k, int yy) {
+  if (!P.kp->ion_q9) return R(0);
+  R x[4];
+  pull_diag(P, q9, k, yy, x);
+  return x[0] + x[1] + x[2] + x[3];
+}
 
 // The f set of node (xc, yy).  At a side wall f bounces back (u = 0): the
 // populations coming through the wall are the node's own opposite ones,
@@ -223,6 +251,11 @@ template <class R>
 __device__ inline R psi_of(const R g4[4]) {
   return R(1.5) * (g4[0] + g4[1] + g4[2] + g4[3]);
 }
+// the same sum in the wider type T
+template <class T, class R>
+__device__ inline T psi_as(const R g4[4]) {
+  return T(1.5) * ((T)g4[0] + (T)g4[1] + (T)g4[2] + (T)g4[3]);
+}
 
 // Neighbourhood of a node from three rows (down, centre, up), each given as
 // columns (x-1, x, x+1), in velocity order.
@@ -290,14 +323,53 @@ struct Ghosts {
   }
 };
 
+// Ghost-row writes of a D2Q9 ion set (lines q0.. for directions 0-4, q9..
+// for 5-8) of a node on an electrode row (or an edge row of a y-periodic
+// box): the populations that come back through the wall, by the rule of the
+// electrode in deviation form (reference w_i c0): kind 0 ion-tight,
+// bounce-back x*_opp; kind 1, c = 0 at the wall, -x*_opp - 2 w_i c0; kind 2,
+// dc/dn = 0, -x*_opp + 2 w_i c' with c' the node's own c - c0.
+template <class S, class R, class K>
+__device__ inline void ion9_ghosts(const PopView<S, R>& D, const KP<R>& kp, int y, K k, int q0,
+                                   int q9, const R x[9], int bottom, int topk, R cd) {
+  const uint32_t top = D.row(kp.ny + 1);
+  if (kp.walls == WALL_PERIODIC) {
+    if (y == kp.ny - 1) {
+      D.put(q0 + 2, k.c, x[2]);
+      D.put(q9 + 0, k.c, x[5]);
+      D.put(q9 + 1, k.c, x[6]);
+    }
+    if (y == 0) {
+      D.put(q0 + 4, top + k.c, x[4]);
+      D.put(q9 + 2, top + k.c, x[7]);
+      D.put(q9 + 3, top + k.c, x[8]);
+    }
+    return;
+  }
+  const R a2 = R(2.0 / 9.0), d2 = R(1.0 / 18.0);  // 2 w_i, axis and diagonal
+  auto rule = [&](R v, R w2, int kind) {
+    return kind == 0 ? v : (kind == 1 ? -v - w2 * kp.c0 : -v + w2 * cd);
+  };
+  if (y == 0) {
+    D.put(q0 + 2, k.c, rule(x[4], a2, bottom));
+    D.put(q9 + 0, k.m, rule(x[7], d2, bottom));
+    D.put(q9 + 1, k.p, rule(x[8], d2, bottom));
+  }
+  if (y == kp.ny - 1) {
+    D.put(q0 + 4, top + k.c, rule(x[2], a2, topk));
+    D.put(q9 + 2, top + k.p, rule(x[5], d2, topk));
+    D.put(q9 + 3, top + k.m, rule(x[6], d2, topk));
+  }
+}
+
 // Store the post-collision g of node (x, y) (deviations, g[0..4]) with the
 // electrode rules.  psi9 is the psi' neighbourhood: with 16-bit storage each
 // moving population is stored relative to psi'~ / 6 of the node it arrives
 // at (the node itself for the populations an electrode sends back), g0
 // relative to -2/3 psi'~ of the node, and the node stores its own psi'~.
-template <class S, class R, class K>
+template <class S, class R, class K, class P9>
 __device__ inline void store_g(const PopView<S, R>& D, const KP<R>& kp, int x, int y, K k,
-                               const R g[5], const R psi9[9]) {
+                               const R g[5], const P9 psi9[9]) {
   const uint32_t o = D.row(y + 1) + x;
   const Ghosts<S, R, K> G{D, kp, y, k};
   const bool edge = y == 0 || y == kp.ny - 1;
@@ -310,7 +382,7 @@ __device__ inline void store_g(const PopView<S, R>& D, const KP<R>& kp, int x, i
   }
   R t[5];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) t[i] = D.stored(QRG, psi9[i]);
+  for (int i = 0; i < 5; ++i) t[i] = D.stored(QRG, (R)psi9[i]);
   if (k.lw) t[3] = t[0];
   if (k.rw) t[1] = t[0];
   if (kp.walls != WALL_PERIODIC) {
@@ -344,7 +416,8 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
                                    const T0* __restrict__ h0src, T0* __restrict__ h0dst,
                                    const KP<R>& kp, const KP<typename WorkOf<S>::type>& kpw, int x,
                                    int y, K k, const typename WorkOf<S>::type phi9[9],
-                                   const R psi9[9], R f[9], R p[5], R n[5], R g0,
+                                   const typename WorkOf<S>::type psi9[9], R f[9], R p[9],
+                                   R n[9], R g0,
                                    const HG& hg) {
   // Working type W: the wide type (FP64 with FP32 storage) for the
   // macroscopic quantities and all five collisions.  In FP32 the pressure
@@ -354,14 +427,17 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   // nearly steady flow (3e-5 after 160 000 steps of a droplet in a closed
   // box); in FP64 they stay at the storage's rounding.
   typedef typename WorkOf<S>::type W;
-  W fw[9], pw[5], nw[5], ps9[9];
+  // the ions on D2Q9 (Eq. 34-38 as printed): nine populations per species
+  constexpr bool I9 = ion9_of<K>();
+  constexpr int QI = I9 ? 9 : 5;
+  W fw[9], pw[QI], nw[QI], ps9[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     fw[i] = (W)f[i];
     ps9[i] = (W)psi9[i];
   }
 #pragma unroll
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < QI; ++i) {
     pw[i] = (W)p[i];
     nw[i] = (W)n[i];
   }
@@ -379,8 +455,12 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
       Qin += (double)n[i];
     }
   }
-  const W Pd = pw[0] + pw[1] + pw[2] + pw[3] + pw[4];
-  const W Qd = nw[0] + nw[1] + nw[2] + nw[3] + nw[4];
+  W Pd = pw[0] + pw[1] + pw[2] + pw[3] + pw[4];
+  W Qd = nw[0] + nw[1] + nw[2] + nw[3] + nw[4];
+  if constexpr (I9) {
+    Pd = Pd + pw[5] + pw[6] + pw[7] + pw[8];
+    Qd = Qd + nw[5] + nw[6] + nw[7] + nw[8];
+  }
   // the local field of Eq. (50), from the node's incoming g (its own form
   // of the sweep)
   W Eg[2];
@@ -432,6 +512,25 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     store_g(D, kp, x, y, k, g, psi9);
   }
 
+  if constexpr (I9) {
+    collide_ion9(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
+    collide_ion9(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      p[i] = (R)pw[i];
+      n[i] = (R)nw[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) D.put(i < 5 ? QP + i : QP9 + i - 5, o, p[i]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) D.put(i < 5 ? QN + i : QN9 + i - 5, o, n[i]);
+    if (edge) {
+      const R cpd = (R)m.cpd, cmd = (R)m.cmd;
+      // anode: c+ = 0, d c-/dn = 0; cathode: d c+/dn = 0, c- = 0
+      ion9_ghosts(D, kp, y, k, QP, QP9, p, ins ? 0 : 1, ins ? 0 : 2, cpd);
+      ion9_ghosts(D, kp, y, k, QN, QN9, n, ins ? 0 : 2, ins ? 0 : 1, cmd);
+    }
+  } else {
   collide_ion(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
   collide_ion(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
 #pragma unroll
@@ -466,13 +565,18 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   if (edge) G.set5(QP, p, ins ? p[4] : -p[4] - third * kp.c0, ins ? p[2] : -p[2] + third * cpd);
   // anode: d c-/dn = 0; cathode: c- = 0
   if (edge) G.set5(QN, n, ins ? n[4] : -n[4] + third * cmd, ins ? n[2] : -n[2] - third * kp.c0);
+  }
 
-  {  // h: Eq. (27)-(32), with d(phi u)/dt of Eq. (58), in W
+  {  // h: Eq. (27)-(32), with d(phi u)/dt of Eq. (58), in W.  (phi u)(t) is
+    // rounded to the type it is kept in before the difference is taken, so
+    // that the differences of successive steps telescope: the rounding of
+    // (phi u)(t-1) alone would enter every step with the same sign wherever
+    // the flow is steady.
     const uint32_t jpl = kp.cells;
-    const W Jx = m.phi * m.u[0], Jy = m.phi * m.u[1];
-    const W dJ[2] = {Jx - (W)*elem(jprev, jo), Jy - (W)*elem(jprev, jpl + jo)};
-    *elem(jprev, jo) = (R)Jx;
-    *elem(jprev, jpl + jo) = (R)Jy;
+    const R Jx = (R)(m.phi * m.u[0]), Jy = (R)(m.phi * m.u[1]);
+    const W dJ[2] = {(W)Jx - (W)*elem(jprev, jo), (W)Jy - (W)*elem(jprev, jpl + jo)};
+    *elem(jprev, jo) = Jx;
+    *elem(jprev, jpl + jo) = Jy;
     const T0 h0in = *elem(h0src, jo);
     R h[9];
     hg.h9(h);
@@ -536,19 +640,50 @@ struct HGLds {
   }
 };
 
-// LDS of one sweep workgroup: the phi' ring (in RP), the psi' ring and the
-// parked h1-h8, g1-g4.
-template <class R, class RP, int TW>
+// The psi' ring of a sweep workgroup, in the working type W.  With FP32
+// storage (W = FP64) it holds each value as its FP32 rounding plus the
+// bfloat16 rounding of the remainder: about 32 significant bits in 6 bytes.
+// A plain FP32 ring (24 bits), whose rounding is the same at every step where
+// the potential is steady, drove the velocity of a slow nearly steady flow
+// 2e-5 away from the oracle over 160 000 steps (1e-5, the floor of FP32
+// storage, with an FP64 ring); a full FP64 ring leaves too little LDS for
+// two 8-wave or four 4-wave workgroups per CU (-18 % / -3 % at 2048^2 on
+// MI355X).
+template <class S, class W, int TW>
+struct PsiRing {
+  W v[RING][TW + 2];
+  __device__ inline void set(int s, int c, W x) { v[s][c] = x; }
+  __device__ inline W get(int s, int c) const { return v[s][c]; }
+};
+template <int TW>
+struct PsiRing<float, double, TW> {
+  float hi[RING][TW + 2];
+  uint16_t lo[RING][TW + 2];
+  __device__ inline void set(int s, int c, double x) {
+    const float h = (float)x;
+    uint32_t b = __float_as_uint((float)(x - (double)h));
+    b += 0x7FFFu + ((b >> 16) & 1u);  // to nearest, ties to even
+    hi[s][c] = h;
+    lo[s][c] = (uint16_t)(b >> 16);
+  }
+  __device__ inline double get(int s, int c) const {
+    return (double)hi[s][c] + (double)__uint_as_float((uint32_t)lo[s][c] << 16);
+  }
+};
+
+// LDS of one sweep workgroup: the phi' ring (in the working type W), the
+// psi' ring and the parked h1-h8, g1-g4.
+template <class S, class R, int TW>
 struct SweepLds {
-  RP phi[RING][TW + 2];
-  R psi[RING][TW + 2];
+  typename WorkOf<S>::type phi[RING][TW + 2];
+  PsiRing<S, typename WorkOf<S>::type, TW> psi;
   R pull[2][12][TW];  // pulled h1-8 and g1-4 of a row, by row parity
 };
 
 // One tile of the fused sweep: columns [x0, x0 + 64 NW) of rows [y0, yend)
 // of one simulation, walked down row by row by the whole workgroup.
 template <class S, class R, class T0, int NW, int EXT>
-__device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>& L,
+__device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
                                   const S* __restrict__ src, S* __restrict__ dst,
                                   R* __restrict__ jprev, const T0* __restrict__ h0x,
                                   T0* __restrict__ h0dst, const KP<R>& kp,
@@ -606,7 +741,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
         pull_h(V, h0x, kh, ys, hh, &hh0);
         pull_g(V, kh, ys, gg);
         L.phi[sl][kcol] = phi_of<W>((W)hh0, hh);
-        L.psi[sl][kcol] = psi_of(gg);
+        L.psi.set(sl, kcol, psi_as<W>(gg));
       }
       if (valid) {
         R h[9], g4[4];
@@ -614,7 +749,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
         pull_h(V, h0x, k, ys, h, &h0);
         pull_g(V, k, ys, g4);
         L.phi[sl][lane + 1] = phi_of<W>((W)h0, h);
-        L.psi[sl][lane + 1] = psi_of(g4);
+        L.psi.set(sl, lane + 1, psi_as<W>(g4));
         const int b = (yy - y0 + 2) & 1;
 #pragma unroll
         for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = h[i];
@@ -641,7 +776,7 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
     // its ~46 loads out ahead of the arithmetic of the other waves on its
     // SIMD (measured on MI355X at 2048^2: +1.2 % FP32, +1.6 % FP16; the
     // level, 1 to 3, makes no difference).
-    R f[9], p[5], n[5], t4[4];
+    R f[9], p[9], n[9], t4[4];
     __builtin_amdgcn_s_setprio(2);
     pull_f(Ph, k, y, f);
     const uint32_t r0 = Ph.row(y + 1);
@@ -653,31 +788,36 @@ __device__ inline void sweep_tile(SweepLds<R, typename WorkOf<S>::type, 64 * NW>
     p[1] = t4[0]; p[2] = t4[1]; p[3] = t4[2]; p[4] = t4[3];
     pull4(Ph, QN, k, y, t4);
     n[1] = t4[0]; n[2] = t4[1]; n[3] = t4[2]; n[4] = t4[3];
+    if constexpr (EXT == 3) {  // the D2Q9 ions' diagonals
+      pull_diag(Ph, QP9, k, y, t4);
+      p[5] = t4[0]; p[6] = t4[1]; p[7] = t4[2]; p[8] = t4[3];
+      pull_diag(Ph, QN9, k, y, t4);
+      n[5] = t4[0]; n[6] = t4[1]; n[7] = t4[2]; n[8] = t4[3];
+    }
     if (up) ring_row(y + 1);
     __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     if (valid) {
       const int c = lane + 1, sc = slot(y);
       W phC[3] = {L.phi[sc][c - 1], L.phi[sc][c], L.phi[sc][c + 1]};
-      R psC[3] = {L.psi[sc][c - 1], L.psi[sc][c], L.psi[sc][c + 1]};
+      W psC[3] = {L.psi.get(sc, c - 1), L.psi.get(sc, c), L.psi.get(sc, c + 1)};
       W phU[3], phD[3];
-      R psU[3], psD[3];
+      W psU[3], psD[3];
       if (up) {
         const int su = slot(y + 1);
         phU[0] = L.phi[su][c - 1]; phU[1] = L.phi[su][c]; phU[2] = L.phi[su][c + 1];
-        psU[0] = L.psi[su][c - 1]; psU[1] = L.psi[su][c]; psU[2] = L.psi[su][c + 1];
+        psU[0] = L.psi.get(su, c - 1); psU[1] = L.psi.get(su, c); psU[2] = L.psi.get(su, c + 1);
       } else {
         ghost_row(phC, psC, phU, psU);
       }
       if (down) {
         const int sd = slot(y - 1);
         phD[0] = L.phi[sd][c - 1]; phD[1] = L.phi[sd][c]; phD[2] = L.phi[sd][c + 1];
-        psD[0] = L.psi[sd][c - 1]; psD[1] = L.psi[sd][c]; psD[2] = L.psi[sd][c + 1];
+        psD[0] = L.psi.get(sd, c - 1); psD[1] = L.psi.get(sd, c); psD[2] = L.psi.get(sd, c + 1);
       } else {
         ghost_row(phC, psC, phD, psD);
       }
-      W phi9[9];
-      R psi9[9];
+      W phi9[9], psi9[9];
       nine(phD, phC, phU, phi9);
       nine(psD, psC, psU, psi9);
 
@@ -736,7 +876,7 @@ __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
     const SimDesc<S, R, T0>* __restrict__ sims,
     const BatchTile* __restrict__ tiles, int xcd_chunk, int flip) {
-  __shared__ SweepLds<R, typename WorkOf<S>::type, 64 * NW> L;
+  __shared__ SweepLds<S, R, 64 * NW> L;
   const BatchTile tl = tiles[xcd_tile(xcd_chunk)];
   if (tl.sim < 0) return;
   const SimDesc<S, R, T0>& sd = sims[tl.sim];
@@ -763,9 +903,11 @@ __global__ void k_moments(const S* __restrict__ src, const S* __restrict__ gsrc,
   pull_h(Ph, h0x, k, y, h);
   pull_g(Pg, k, y, g4);
   pull4(Ph, QP, k, y, t4);
-  const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3] +
+               ion_diag_sum(Ph, QP9, k, y);
   pull4(Ph, QN, k, y, t4);
-  const R Qd = (R)ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Qd = (R)ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3] +
+               ion_diag_sum(Ph, QN9, k, y);
   const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
   mom[c] = sum9(h);
   mom[np + c] = psi_of(g4);
@@ -827,9 +969,11 @@ __global__ void k_fields(const S* __restrict__ src, const T0* __restrict__ h0x,
   hood(mom, kp, x, y, phi9, psi9);
   pull_f(Ph, k, y, f);
   pull4(Ph, QP, k, y, t4);
-  const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Pd = (R)ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3] +
+               ion_diag_sum(Ph, QP9, k, y);
   pull4(Ph, QN, k, y, t4);
-  const R Qd = (R)ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+  const R Qd = (R)ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3] +
+               ion_diag_sum(Ph, QN9, k, y);
   R Eg[2];
   const R* Eloc = nullptr;
   if (kp.local_field) {
@@ -913,8 +1057,10 @@ struct InitSpec {
 // Equilibrium initial state.  The population arriving at node (x, y) along
 // c_i at the first step is the equilibrium there, so it is written where
 // that node pulls it from: row y - c_iy, column x - c_ix, as a deviation from
-// the reference of that row.
-template <class S, class R, class T0>
+// the reference of that row.  AA: in-place streaming, whose first step reads
+// the arrivals from the node's own slots; they are written there (still as
+// deviations from the reference of the row they come from).
+template <class S, class R, class T0, bool AA = false>
 __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restrict__ h0x,
                        const KP<R> kp, const InitSpec sp) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
@@ -953,6 +1099,11 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
   const int opp5[5] = {0, 3, 4, 1, 2};
   auto put = [&](int q, int i, double v) {
     const int xs = x - cx[i], ys = y - cy[i];
+    if constexpr (AA) {
+      const double ref = plane_ref(q, ys, kp.ny, kp.walls, sp.c0, sp.dpsi, sp.a_g);
+      D.put(q, D.row(y + 1) + x, (R)(v - ref));
+      return;
+    }
     int qt = q, xt = xs, yt = ys;
     if (kp.side_walls && (xs < 0 || xs >= kp.nx)) {
       const bool corner = kp.walls != WALL_PERIODIC && (ys < 0 || ys >= kp.ny);
@@ -966,7 +1117,7 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
     } else {
       xt = xs < 0 ? xs + kp.nx : (xs >= kp.nx ? xs - kp.nx : xs);
     }
-    const double ref = plane_ref(qt, yt, kp.ny, kp.walls, sp.c0, sp.dpsi, sp.a_g);
+    const double ref = plane_ref(qt, yt, kp.ny, kp.walls, sp.c0, sp.dpsi, sp.a_g, kp.ion_q9);
     D.put(qt, D.row(yt + 1) + xt, (R)(v - ref));
   };
   // h: the rest population (which does not move) takes phi minus what the
@@ -1005,9 +1156,18 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
     D.put(QRG, D.row(y + 1) + x, t);
     tg = (double)t;
   }
+  if (kp.ion_q9) {  // the ions on D2Q9: nine populations each, weights of Eq. (25)
+    for (int i = 0; i < 9; ++i) {
+      const double cu = cx[i] * ux + cy[i] * uy;
+      put(i < 5 ? QP + i : QP9 + i - 5, i, w9[i] * cp * (1.0 + 3.0 * cu));
+      put(i < 5 ? QN + i : QN9 + i - 5, i, w9[i] * cm * (1.0 + 3.0 * cu));
+    }
+  }
   for (int i = 0; i < 5; ++i) {
     const double cu = cx[i] * ux + cy[i] * uy;
-    if (i == 0 && IonRest<S>::value) {
+    if (kp.ion_q9) {
+      // (ions written above)
+    } else if (i == 0 && IonRest<S>::value) {
       *elem(h0x, kp.cells + jo) = (T0)(w5[0] * (cp - sp.c0));
       *elem(h0x, 2 * kp.cells + jo) = (T0)(w5[0] * (cm - sp.c0));
     } else {
@@ -1039,9 +1199,11 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
     pull_h(Ph, h0x, k, y, h);
     const double h0 = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
     pull4(Ph, QP, k, y, t4);
-    const double Pd = ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+    const double Pd = ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3] +
+                      (double)ion_diag_sum(Ph, QP9, k, y);
     pull4(Ph, QN, k, y, t4);
-    const double Qd = ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3];
+    const double Qd = ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3] +
+                      (double)ion_diag_sum(Ph, QN9, k, y);
     pull_g(Ph, k, y, g4);
     double phid = h0;
     for (int i = 1; i < 9; ++i) phid += (double)h[i];

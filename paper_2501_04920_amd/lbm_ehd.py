@@ -50,7 +50,8 @@ class lbm_ehd_params(ctypes.Structure):
         ("c0", ctypes.c_double), ("q", ctypes.c_double), ("gamma_v", ctypes.c_double),
         ("force_x", ctypes.c_double), ("force_y", ctypes.c_double),
         ("s_free", ctypes.c_double), ("poisson_tol", ctypes.c_double),
-        ("n_eps", ctypes.c_double), ("diag_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_eps", ctypes.c_double), ("diag_every", ctypes.c_int32), ("inplace", ctypes.c_int32),
+        ("ion_q9", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -415,15 +416,16 @@ class Simulation:
         self.nx, self.ny = self.params.nx, self.params.ny
         pop_bytes, aux_bytes = lbm_ehd_required_bytes(self.params)
         self.device = torch.device(device)
+        nbuf = 1 if self.params.inplace else 2
         with torch.cuda.device(self.device):
             self._bufs = [torch.empty(pop_bytes, dtype=torch.uint8, device=self.device)
-                          for _ in range(2)]
+                          for _ in range(nbuf)]
             self._aux = torch.empty(aux_bytes, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
             dev = lbm_ehd_device()
             dev.stream = ctypes.c_void_p(self.stream.cuda_stream)
             dev.pop[0] = self._bufs[0].data_ptr()
-            dev.pop[1] = self._bufs[1].data_ptr()
+            dev.pop[1] = self._bufs[1].data_ptr() if nbuf == 2 else None
             dev.pop_bytes = pop_bytes
             dev.aux = self._aux.data_ptr()
             dev.aux_bytes = aux_bytes

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     # int32 block then doubles, no padding surprises
-    assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 18 * 4 + 23 * 8 + 2 * 4
+    assert ctypes.sizeof(lbm_ehd.lbm_ehd_params) == 18 * 4 + 23 * 8 + 4 * 4
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_diag) == 11 * 8
     assert ctypes.sizeof(lbm_ehd.lbm_ehd_request_info) == 8 + 4 + 4 + 2 * 8 + 3 * 8 + 8 + 11 * 8
 
@@ -57,7 +57,14 @@ def test_defaults_and_bytes():
                                  dict(theta=-0.1), dict(precision=7), dict(walls=5),
                                  dict(W=float("nan")), dict(s_free=2.0), dict(side_walls=2), dict(local_field=2), dict(poisson_tol=-1.0),
                                  dict(poisson_tol=1e-3), dict(poisson_tol=1e-3, poisson_iters=1),
-                                 dict(n_eps=-1.0), dict(diag_every=-1),
+                                 dict(n_eps=-1.0), dict(diag_every=-1), dict(inplace=2),
+                                 dict(inplace=1, precision=2), dict(inplace=1, precision=3),
+                                 dict(inplace=1, side_walls=1), dict(inplace=1, local_field=1),
+                                 dict(inplace=1, poisson_tol=1e-6, poisson_iters=1,
+                                      poisson_max=4),
+                                 dict(ion_q9=2), dict(ion_q9=1, precision=2),
+                                 dict(ion_q9=1, precision=3), dict(ion_q9=1, side_walls=1),
+                                 dict(ion_q9=1, local_field=1), dict(ion_q9=1, inplace=1),
                                  dict(nx=20000, ny=20000)])
 def test_invalid_parameters_rejected(bad):
     p = lbm_ehd.make_params(**bad)
@@ -163,3 +170,31 @@ def test_product_code_never_reaches_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert not pat.search(src), os.path.join(dirpath, f)
+
+
+def test_inplace_sizes():
+    """In-place streaming keeps one population buffer of the same size; its
+    aux holds (phi u), one level of the rest of h and the phi'/psi' planes
+    (FP64)."""
+    import ctypes
+    for prec, a in (("fp32", 4), ("fp64", 8), ("fp32f64", 8)):
+        two = lbm_ehd.make_params(precision=prec)
+        one = lbm_ehd.make_params(precision=prec, inplace=1)
+        pb2, ab2 = lbm_ehd.lbm_ehd_required_bytes(two)
+        pb1, ab1 = lbm_ehd.lbm_ehd_required_bytes(one)
+        assert pb1 == pb2 and ab1 == 128 * 128 * (2 * a + 24)
+        f1, f2 = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lbm_ehd.lib().lbm_ehd_footprint_bytes(ctypes.byref(one), ctypes.byref(f1)) == 0
+        assert lbm_ehd.lib().lbm_ehd_footprint_bytes(ctypes.byref(two), ctypes.byref(f2)) == 0
+        assert f2.value - f1.value == pb2 + ab2 - ab1
+
+
+def test_d2q9_ion_sizes():
+    """The ions on D2Q9 add their eight diagonals (four per species) to every
+    lattice row; aux is unchanged."""
+    for prec, a in (("fp32", 4), ("fp64", 8), ("fp32f64", 4)):
+        five = lbm_ehd.make_params(precision=prec)
+        nine = lbm_ehd.make_params(precision=prec, ion_q9=1)
+        pb5, ab5 = lbm_ehd.lbm_ehd_required_bytes(five)
+        pb9, ab9 = lbm_ehd.lbm_ehd_required_bytes(nine)
+        assert pb5 == 33 * 130 * 128 * a and pb9 == 41 * 130 * 128 * a and ab9 == ab5

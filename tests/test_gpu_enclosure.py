@@ -42,21 +42,22 @@ def test_enclosure_against_oracle(poisson_form):
 
 
 # After 160 000 steps (the steady droplet): D absolute, the norms of rho_e and
-# |u| and the subsampled end fields rel-L2.  FP32 storage is held to 5e-5 on
-# the fields over this run, eight times the 20 000 steps of the 2e-5 bar:
-# the slow near-steady flow carries the rounding of h into a small velocity
-# (measured: D 1.1e-6, |u| 2.5e-5, u 3.0e-5, rho_e 1.9e-5, phi 3.8e-6; FP64
-# 5.8e-11 at most).
+# |u| and the subsampled end fields rel-L2.  FP32 storage is held to the FP32
+# bar of 2e-5 on every field over this run, eight times the 20 000 steps the
+# bar was set for.  (With the h collision in FP32 arithmetic the slow, nearly
+# steady flow carried its rounding into the velocity, 3.0e-5; the collision
+# runs in FP64 since.)
 LONG_BAR = {
     "fp64": dict(D=1e-10, rhoe_l2=1e-10, u_l2=1e-10, phi=1e-10, psi=1e-10, cp=1e-10,
                  cm=1e-10, rhoe=1e-10, ux=1e-10, uy=1e-10, p=1e-10),
-    "fp32": dict(D=1e-5, rhoe_l2=5e-5, u_l2=5e-5, phi=5e-5, psi=5e-5, cp=5e-5, cm=5e-5,
-                 rhoe=5e-5, ux=5e-5, uy=5e-5, p=5e-5),
+    "fp32": dict(D=1e-5, rhoe_l2=2e-5, u_l2=2e-5, phi=2e-5, psi=2e-5, cp=2e-5, cm=2e-5,
+                 rhoe=2e-5, ux=2e-5, uy=2e-5, p=2e-5),
     "fp16": dict(D=1e-3),
 }
+LONG_BAR["fp32f64"] = LONG_BAR["fp32"]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32f64", "fp16"])
 def test_enclosure_steady_droplet_against_oracle(precision):
     case = workloads.enclosure(256)
     ref = _ref(case["name"])

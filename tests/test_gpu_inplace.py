@@ -1,0 +1,217 @@
+"""In-place streaming (AA pattern, lbm_ehd_params.inplace = 1): one population
+buffer per simulation.
+
+* FP64 against the CPU oracle on the 128^2 droplet case and on the ragged
+  variants the form covers (rel-L2 <= 1e-10 on every field, on E as a
+  vector in the ragged cases), including odd
+  pre-solve counts (the g set then has the other orientation);
+* FP32 storage against the stored oracle references of the eight 512^2
+  cases after 20 000 steps (the FP32 bar, 2e-5);
+* the same simulation with two buffers: every field agrees to rounding;
+* batches: a member gives bitwise the results it gives alone, in a batch
+  that mixes in-place and two-buffer members;
+* checkpoints, graph-replayed runs and the footprint.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from gpu_common import FIELDS8, e_vec_rel, rel_l2, run_gpu, run_oracle  # noqa: E402
+from test_gpu_long import FP32_BAR, _errors, _ref  # noqa: E402
+
+from paper_2501_04920_amd import lbm_ehd, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+ALL10 = FIELDS8 + ("Ex", "Ey")
+
+
+def _report(tag, errs):
+    print("%s: %s" % (tag, " ".join("%s=%.2e" % kv for kv in errs.items())), flush=True)
+
+
+def test_config1_droplet_inplace_fp64():
+    cfg = workloads.config1()
+    p, d = dict(cfg["params"], inplace=1), cfg["droplet"]
+    sim = run_gpu(p, "fp64", droplet=d, presolve=cfg["presolve"], steps=cfg["steps"])
+    o = run_oracle(cfg["params"], droplet=d, presolve=cfg["presolve"], steps=cfg["steps"])
+    errs = rel_l2(sim.fields(), o.fields(), p, ALL10)
+    _report("config1 inplace fp64", errs)
+    assert max(errs.values()) <= 1e-10
+    sim.close()
+
+
+def _ragged(**over):
+    p = workloads.lattice_params(70, 12.0, nx=100)
+    p.update(over)
+    d = dict(xc=49.3, yc=33.7, radius=12.0, noise=1e-3, seed=7)
+    return p, d
+
+
+VARIANTS = {
+    "base": {},
+    "periodic": dict(walls=2),
+    "insulating": dict(walls=1),
+    "poisson_iters": dict(poisson_iters=3),
+    "poisson_iters_periodic": dict(poisson_iters=2, walls=2),
+    "flow_off": dict(flow=0),
+    "reaction_off": dict(reaction=0),
+    "literal_poisson": dict(poisson_form=0, poisson_norm=0),
+    "ratios": dict(rho_r=2.0, eta_r=3.0, mu_r=0.5, m_ratio=1.5, eps_r=0.5),
+    "bgk_masks": dict(mask_f=0x1FF, mask_h=0x1FF, mask_p=0x1F, mask_n=0x1F, mask_g=0x1F),
+    "s_free": dict(s_free=1.3),
+    "body_force": dict(force_x=2e-6, force_y=-1e-6),
+}
+
+
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+@pytest.mark.parametrize("presolve", [10, 7])
+def test_ragged_variants_inplace_fp64(name, presolve):
+    """100 x 70 (a ragged strip and band), off-centre droplet, 61 steps (an
+    odd count: the state ends in the odd orientation), pre-solves of even and
+    odd length."""
+    p, d = _ragged(**VARIANTS[name])
+    sim = run_gpu(dict(p, inplace=1), "fp64", droplet=d, presolve=presolve, steps=61)
+    o = run_oracle(p, droplet=d, presolve=presolve, steps=61)
+    got, ref = sim.fields(), o.fields()
+    errs = rel_l2(got, ref, p, FIELDS8)
+    errs["E"] = e_vec_rel(got, ref)
+    _report("ragged inplace %s presolve %d" % (name, presolve), errs)
+    assert max(errs.values()) <= 1e-10
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32f64"])
+def test_inplace_agrees_with_two_buffers(precision):
+    p, d = _ragged()
+    a = run_gpu(dict(p, inplace=1), precision, droplet=d, presolve=10, steps=100)
+    b = run_gpu(p, precision, droplet=d, presolve=10, steps=100)
+    errs = rel_l2(a.fields(), b.fields(), p, ALL10)
+    _report("inplace vs two buffers %s" % precision, errs)
+    assert max(errs.values()) <= (1e-12 if precision == "fp64" else 2e-6)
+    da, db = a.diagnostics(), b.diagnostics()
+    assert abs(da["sum_phi"] / db["sum_phi"] - 1) <= 1e-13
+    a.close()
+    b.close()
+
+
+CASES = {c["name"]: c for c in workloads.config2_points()}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_inplace_fp32_20k_steps_against_oracle(name):
+    case = CASES[name]
+    ref = _ref(name)
+    p, d = dict(case["params"], inplace=1), case["droplet"]
+    sim = lbm_ehd.Simulation(dict(p, precision="fp32"), device="cuda:0")
+    sim.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"],
+                     presolve=case["presolve"])
+    t = ref["t"]
+    D, rn, un = [], [], []
+    for i, k in enumerate(t):
+        if i:
+            sim.step(int(k - t[i - 1]))
+        f = sim.fields(("phi", "rhoe", "ux", "uy"))
+        D.append(sim.diagnostics()["D"])
+        rn.append(np.linalg.norm(f["rhoe"]))
+        un.append(np.sqrt((f["ux"] ** 2 + f["uy"] ** 2).sum()))
+    fields = sim.fields()
+    sim.close()
+    e = _errors(dict(case, name=name + " inplace"), ref, np.array(D), np.array(rn),
+                np.array(un), fields)
+    assert e["D"] <= 1e-5
+    for k in ("rhoe_l2", "u_l2", "phi", "psi", "cp", "cm", "rhoe", "ux", "uy", "p"):
+        assert e[k] <= FP32_BAR[k], (k, e[k])
+
+
+def _member(nx, ny, r, seed, inplace, precision="fp32"):
+    p = workloads.lattice_params(ny, r, nx=nx)
+    s = lbm_ehd.Simulation(dict(p, precision=precision, inplace=inplace), device="cuda:0")
+    s.init_droplet((nx - 1) / 2 + 0.3, (ny - 1) / 2 - 0.2, r, 1e-3, seed, presolve=6)
+    return s
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_inplace_batch_equals_members_alone(precision):
+    shapes = [(64, 64, 10.0, 1, 1), (100, 70, 12.0, 2, 1), (128, 96, 15.0, 3, 0),
+              (37, 41, 6.0, 4, 1)]
+    steps = 37
+    alone = []
+    for nx, ny, r, seed, ip in shapes:
+        s = _member(nx, ny, r, seed, ip, precision)
+        s.step(steps)
+        alone.append(s.fields())
+        s.close()
+    sims = [_member(nx, ny, r, seed, ip, precision) for nx, ny, r, seed, ip in shapes]
+    b = lbm_ehd.Batch(sims)
+    b.set_launch(2, 8)
+    b.run(16)
+    b.set_launch(1, 4)
+    b.run(steps - 16)
+    b.synchronize()
+    for s, ref in zip(sims, alone):
+        assert s.time == steps
+        f = s.fields()
+        for k in ALL10:
+            assert np.array_equal(f[k], ref[k]), k
+    b.close()
+    for s in sims:
+        s.close()
+
+
+@pytest.mark.parametrize("steps", [50, 51])
+def test_inplace_checkpoint_and_graph_replay(steps):
+    """A saved in-place state (either orientation) loaded into a fresh
+    simulation continues bitwise; graph-replayed runs equal single steps; a
+    two-buffer simulation refuses the state."""
+    p, d = _ragged()
+    a = run_gpu(dict(p, inplace=1), "fp32", droplet=d, presolve=7, steps=steps)
+    state = a.save_state()
+    a.step(33)
+    fa = a.fields()
+    b = lbm_ehd.Simulation(dict(p, precision="fp32", inplace=1), device="cuda:0")
+    b.load_state(state)
+    assert b.time == steps
+    for _ in range(33):
+        lbm_ehd.lbm_ehd_step(b.handle)
+    fb = b.fields()
+    for k in ALL10:
+        assert np.array_equal(fa[k], fb[k]), k
+    c = lbm_ehd.Simulation(dict(p, precision="fp32"), device="cuda:0")
+    with pytest.raises(lbm_ehd.LbmError) as e:
+        c.load_state(state)
+    assert e.value.code == lbm_ehd.LBM_EINVAL
+    for s in (a, b, c):
+        s.close()
+
+
+def test_inplace_footprint_and_guards():
+    p = dict(workloads.lattice_params(512, 80.0), precision="fp32")
+    two = lbm_ehd.make_params(**p)
+    one = lbm_ehd.make_params(**dict(p, inplace=1))
+    pb2, ab2 = lbm_ehd.lbm_ehd_required_bytes(two)
+    pb1, ab1 = lbm_ehd.lbm_ehd_required_bytes(one)
+    assert pb1 == pb2
+    state2, state1 = 2 * pb2 + ab2, pb1 + ab1
+    print("state bytes per cell: two buffers %.1f, in place %.1f"
+          % (state2 / 512 ** 2, state1 / 512 ** 2), flush=True)
+    assert state1 <= 0.6 * state2
+    import ctypes
+    f1, f2 = ctypes.c_size_t(), ctypes.c_size_t()
+    lbm_ehd.lib().lbm_ehd_footprint_bytes(ctypes.byref(one), ctypes.byref(f1))
+    lbm_ehd.lib().lbm_ehd_footprint_bytes(ctypes.byref(two), ctypes.byref(f2))
+    assert f2.value - f1.value == pb2 + ab2 - ab1
+    for bad in (dict(precision="fp16"), dict(side_walls=1), dict(local_field=1),
+                dict(poisson_tol=1e-6, poisson_iters=1, poisson_max=10)):
+        with pytest.raises(lbm_ehd.LbmError) as e:
+            lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(**dict(p, inplace=1, **bad)))
+        assert e.value.code == lbm_ehd.LBM_EINVAL
+    s = lbm_ehd.Simulation(dict(p, inplace=1), device="cuda:0")
+    s.init_droplet(255.5, 255.5, 80.0)
+    with pytest.raises(lbm_ehd.LbmError) as e:
+        s.presolve_to(1e-6, 10)
+    assert e.value.code == lbm_ehd.LBM_EINVAL
+    s.close()
