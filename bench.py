@@ -391,7 +391,7 @@ def bench_enclosure(args):
     print(json.dumps(line), flush=True)
 
 
-def _serve_trace(trace, budget, block):
+def _serve_trace(trace, budget, block, precision="fp16", inplace=0):
     """Replay a trace in real time through the request server; returns
     per-request (latency s, cells x steps) and the makespan."""
     from paper_2501_04920_amd import lbm_ehd
@@ -408,8 +408,8 @@ def _serve_trace(trace, budget, block):
         while k < len(pending) and pending[k]["arrival"] <= now:
             r = pending[k]
             d = r["droplet"]
-            rid = srv.submit(dict(r["params"], precision="fp16"), d["xc"], d["yc"], d["radius"],
-                             d["noise"], d["seed"], r["steps"])
+            rid = srv.submit(dict(r["params"], precision=precision, inplace=inplace), d["xc"],
+                             d["yc"], d["radius"], d["noise"], d["seed"], r["steps"])
             ids[rid] = r
             k += 1
         running, queued = srv.advance()
@@ -435,15 +435,16 @@ def _serve_trace(trace, budget, block):
 def bench_serving(args):
     """Poisson arrivals (20 per second, seeded) of droplet requests 64^2-2048^2
     with 2k-50k steps, served with HBM-footprint admission and continuous
-    batching (FP16 storage): p50 / p99 completion latency and throughput; then
-    the same requests at a rate giving ~70 % load."""
+    batching (FP16 storage by default): p50 / p99 completion latency and
+    throughput; then the same requests at a rate giving ~70 % load."""
     import numpy as np
 
     from paper_2501_04920_amd import lbm_ehd, workloads
 
     trace = workloads.config5_trace(count=args.requests, rate=args.rate)
     budget = int(args.budget_gib * (1 << 30))
-    done, span, maxrun = _serve_trace(trace, budget, args.block)
+    prec, ip = args.serve_precision, int(args.serve_inplace)
+    done, span, maxrun = _serve_trace(trace, budget, args.block, prec, ip)
     lat = np.array([v[0] for v in done.values()])
     work = sum(v[1] for v in done.values())
     glups = work / span / 1e9
@@ -461,7 +462,7 @@ def bench_serving(args):
     sub = None
     if args.sub:
         trace2 = workloads.config5_trace(count=args.requests, rate=rate_sub)
-        done2, span2, _ = _serve_trace(trace2, budget, args.block)
+        done2, span2, _ = _serve_trace(trace2, budget, args.block, prec, ip)
         lat2 = np.array([v[0] for v in done2.values()])
         sub = {"rate_per_s": round(rate_sub, 3), "p50_s": round(float(np.percentile(lat2, 50)), 3),
                "p99_s": round(float(np.percentile(lat2, 99)), 3),
@@ -471,8 +472,10 @@ def bench_serving(args):
         "n_gpus": 1, "steps": int(sum(r["steps"] for r in trace)), "warmup": 0,
         "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "serving-%d-requests-64-2048-rate%g" % (len(trace), args.rate),
-                   "storage": "fp16", "hbm_budget_gib": args.budget_gib, "block_steps": args.block},
+        "config": {"workload": "serving-%d-requests-64-2048-rate%g" % (len(trace), args.rate)
+                   + ("-inplace" if ip else ""),
+                   "storage": prec, "inplace": ip, "hbm_budget_gib": args.budget_gib,
+                   "block_steps": args.block},
         "p50_s": round(float(np.percentile(lat, 50)), 3),
         "throughput_req_per_s": round(len(trace) / span, 3), "aggregate_glups": round(glups, 3),
         "makespan_s": round(span, 2), "max_running": maxrun, "failed": failed,
@@ -526,6 +529,10 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--serve-precision", default="fp16", choices=["fp16", "bf16", "fp32", "fp64"],
+                    help="storage of the served requests (--form serving)")
+    ap.add_argument("--serve-inplace", action="store_true",
+                    help="serve with in-place streaming (one population buffer per request)")
     ap.add_argument("--sub", type=int, default=1, help="also run the ~70 %% load trace")
     args = ap.parse_args()
     if args.summarize_pmc:

@@ -131,20 +131,29 @@ struct lbm_ehd {
 
 namespace {
 
+// The default MRT rates: rows 3-5 of f and rows 1-2 of h, p, n, g relax
+// with 1/tau, every other row with exactly 1 (s_free = 1, Sec. 6).
+bool std_rates(const lbm_ehd_params& p) {
+  return p.mask_f == 0x38 && p.mask_h == 0x6 && p.mask_p == 0x6 && p.mask_n == 0x6 &&
+         p.mask_g == 0x6 && p.s_free == 1.0;
+}
+
 // Form of the sweep a simulation runs on, each compiled separately: 0 plain,
 // 1 with side walls, 2 with side walls and the local field of Eq. (50), 3
-// in-place streaming (plain), 4 plain with the ions on D2Q9.
+// in-place streaming (plain), 4 plain with the ions on D2Q9; forms 0, 1 and
+// 4 with the default MRT rates compiled in are NFORM higher (5, 6, 9).
+constexpr int NFORM = 5;
 int sweep_form(const lbm_ehd_params& p) {
   if (p.inplace) return 3;
-  if (p.ion_q9) return 4;
-  return p.local_field ? 2 : (p.side_walls ? 1 : 0);
+  const int base = p.ion_q9 ? 4 : (p.local_field ? 2 : (p.side_walls ? 1 : 0));
+  return base + (base != 2 && std_rates(p) ? NFORM : 0);
 }
 
 // Tile list of a set of simulations: larger ones first, each band by band
 // across its strips of 64 * waves columns, padded with empty tiles to a
 // multiple of 8 (the sweep gives each XCD one contiguous run of tiles).
-// `form` -1 takes every simulation (and never returns an empty list); 0 to 4
-// only those on that form of the sweep (possibly none).
+// `form` -1 takes every simulation (and never returns an empty list); 0 to
+// 2 NFORM - 1 only those on that form of the sweep (possibly none).
 std::vector<BatchTile> tile_list(const std::vector<const lbm_ehd*>& sims, int waves,
                                  int tile_rows, int form = -1) {
   std::vector<int> order;
@@ -358,21 +367,21 @@ struct Form {
     return LBM_OK;
   }
 
-  template <int NW, int EXT>
+  template <int NW, int EXT, bool STD>
   static void launch_nw(const void* descs, const BatchTile* tiles, int ntiles, int flip,
                         hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep_batch<S, R, T0, NW, EXT>), dim3(ntiles), dim3(64 * NW), 0, st,
-                       static_cast<const Desc*>(descs), tiles, ntiles / 8, flip);
+    hipLaunchKernelGGL((k_sweep_batch<S, R, T0, NW, EXT, STD>), dim3(ntiles), dim3(64 * NW), 0,
+                       st, static_cast<const Desc*>(descs), tiles, ntiles / 8, flip);
   }
 
-  template <int EXT>
+  template <int EXT, bool STD = false>
   static void launch_ext(int waves, const void* descs, const BatchTile* tiles, int ntiles,
                         int flip, hipStream_t st) {
     switch (waves) {
-      case 8: launch_nw<8, EXT>(descs, tiles, ntiles, flip, st); break;
-      case 4: launch_nw<4, EXT>(descs, tiles, ntiles, flip, st); break;
-      case 2: launch_nw<2, EXT>(descs, tiles, ntiles, flip, st); break;
-      default: launch_nw<1, EXT>(descs, tiles, ntiles, flip, st); break;
+      case 8: launch_nw<8, EXT, STD>(descs, tiles, ntiles, flip, st); break;
+      case 4: launch_nw<4, EXT, STD>(descs, tiles, ntiles, flip, st); break;
+      case 2: launch_nw<2, EXT, STD>(descs, tiles, ntiles, flip, st); break;
+      default: launch_nw<1, EXT, STD>(descs, tiles, ntiles, flip, st); break;
     }
   }
 
@@ -381,15 +390,22 @@ struct Form {
   // member's buffers.
   static lbm_status launch_tiles(int waves, int form, const void* descs,
                                  const BatchTile* tiles, int ntiles, int flip, hipStream_t st) {
-    if (form == 4) {
-      if constexpr (kAA)  // (4- and 8-byte storage only, as in place)
-        launch_ext<3>(waves, descs, tiles, ntiles, flip, st);
-    } else if (form == 2)
-      launch_ext<2>(waves, descs, tiles, ntiles, flip, st);
-    else if (form == 1)
-      launch_ext<1>(waves, descs, tiles, ntiles, flip, st);
-    else
-      launch_ext<0>(waves, descs, tiles, ntiles, flip, st);
+    switch (form) {
+      case 4:
+      case 4 + NFORM:
+        if constexpr (kAA) {  // (4- and 8-byte storage only, as in place)
+          if (form == 4)
+            launch_ext<3>(waves, descs, tiles, ntiles, flip, st);
+          else
+            launch_ext<3, true>(waves, descs, tiles, ntiles, flip, st);
+        }
+        break;
+      case 2: launch_ext<2>(waves, descs, tiles, ntiles, flip, st); break;
+      case 1: launch_ext<1>(waves, descs, tiles, ntiles, flip, st); break;
+      case 1 + NFORM: launch_ext<1, true>(waves, descs, tiles, ntiles, flip, st); break;
+      case NFORM: launch_ext<0, true>(waves, descs, tiles, ntiles, flip, st); break;
+      default: launch_ext<0>(waves, descs, tiles, ntiles, flip, st); break;
+    }
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -805,8 +821,8 @@ struct lbm_ehd_batch {
   BatchTile* d_tiles = nullptr;
   size_t tiles_cap = 0;           // tiles
   BatchTile* h_tiles = nullptr;   // pinned staging of the tile list
-  int ntiles[5] = {0, 0, 0, 0, 0};  // tiles of the members on sweep form 0 to 4, in that
-                                    // order (each padded to a multiple of 8)
+  int ntiles[2 * NFORM] = {};  // tiles of the members on each sweep form, in the order of
+                               // the forms (each padded to a multiple of 8)
   // descriptors of the in-place members (form 3), indexed like the members
   void* d_aadesc = nullptr;
   size_t aadesc_cap = 0;          // bytes
@@ -864,7 +880,7 @@ struct BatchForm {
     // every member runs the code it runs alone (bitwise the same results)
     const std::vector<const lbm_ehd*> ms(b->sims.begin(), b->sims.end());
     std::vector<BatchTile> tl;
-    for (int form = 0; form < 5; ++form) {
+    for (int form = 0; form < 2 * NFORM; ++form) {
       const std::vector<BatchTile> t = tile_list(ms, b->waves, b->tile_rows, form);
       b->ntiles[form] = (int)t.size();
       tl.insert(tl.end(), t.begin(), t.end());
@@ -889,7 +905,7 @@ struct BatchForm {
 
   static lbm_status launch(lbm_ehd_batch* b, int flip) {
     int first = 0;
-    for (int form = 0; form < 5; ++form) {
+    for (int form = 0; form < 2 * NFORM; ++form) {
       if (b->ntiles[form] > 0) {
         const lbm_status st =
             form == 3 ? F::launch_aa(b->waves, b->d_aadesc, b->d_tiles + first, b->ntiles[form],

@@ -491,6 +491,14 @@ __device__ inline R rate(int mask, int k, R inv_tau, R s_free) {
   return ((mask >> k) & 1) ? inv_tau : s_free;
 }
 
+// The default MRT rates (Sec. 6, readings of which rows carry tau): rows
+// 3-5 of f and rows 1-2 of h, p, n and g relax with 1/tau, every other row
+// with exactly 1.  The collisions below take a compile-time flag STD for
+// this case: a row relaxing with 1 becomes its equilibrium plus half its
+// source (and its drift term), whatever its pre-collision moment, so that
+// moment is never formed and the rate selects disappear.
+constexpr int STD_MASK_F = 0x38, STD_MASK_ADE = 0x6;
+
 // ---------------------------------------------------------------------------
 // Macroscopic quantities of one node (Sec. 4: Eq. 5-9, 12-14, 33, 41-43, 49,
 // 56-57, 59, 61).  phi9 / psi9 hold phi' and psi' of the node (index 0) and
@@ -630,7 +638,7 @@ __device__ inline void macro(const RP phi9[9], const R psi9[9], R Pd, R Qd, cons
 // ---------------------------------------------------------------------------
 
 // f: Eq. (51)-(55) (reference 0).
-template <class R>
+template <bool STD = false, class R>
 __device__ inline void collide_f(R f[9], const Macro<R>& m, const KP<R>& kp) {
   if (!kp.flow) return;
   R mo[9];
@@ -660,14 +668,18 @@ __device__ inline void collide_f(R f[9], const Macro<R>& m, const KP<R>& kp) {
   fo[8] = third * ugr;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const R s = rate(kp.mask_f, k, m.itau_f, kp.s_free);
-    mo[k] = mo[k] - s * (mo[k] - eq[k]) + (R(1) - R(0.5) * s) * fo[k];
+    if (STD && !((STD_MASK_F >> k) & 1)) {
+      mo[k] = eq[k] + R(0.5) * fo[k];
+    } else {
+      const R s = STD ? m.itau_f : rate(kp.mask_f, k, m.itau_f, kp.s_free);
+      mo[k] = mo[k] - s * (mo[k] - eq[k]) + (R(1) - R(0.5) * s) * fo[k];
+    }
   }
   inv9(mo, f);
 }
 
 // h: Eq. (27)-(32) on deviations from w_i / 2.  dJ = d(phi u)/dt by Eq. (58).
-template <class R, class M>
+template <bool STD = false, class R, class M>
 __device__ inline void collide_h(R h[9], const Macro<M>& m, const R dJ[2], const KP<R>& kp) {
   R mo[9];
   fwd9(h, mo);
@@ -705,8 +717,12 @@ __device__ inline void collide_h(R h[9], const Macro<M>& m, const R dJ[2], const
   fo[8] = R(0);
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const R s = rate(kp.mask_h, k, kp.inv_tau_h, kp.s_free);
-    mo[k] = mo[k] - s * (mo[k] - eq[k]) + (R(1) - R(0.5) * s) * fo[k];
+    if (STD && !((STD_MASK_ADE >> k) & 1)) {
+      mo[k] = eq[k] + R(0.5) * fo[k];
+    } else {
+      const R s = STD ? kp.inv_tau_h : rate(kp.mask_h, k, kp.inv_tau_h, kp.s_free);
+      mo[k] = mo[k] - s * (mo[k] - eq[k]) + (R(1) - R(0.5) * s) * fo[k];
+    }
   }
   inv9(mo, h);
 }
@@ -716,7 +732,7 @@ __device__ inline void collide_h(R h[9], const Macro<M>& m, const R dJ[2], const
 // type (FP64 with FP32 storage: the drift flux mu c grad(psi) is ~10 times
 // the deviations that carry the charge, and its FP32 rounding would random-
 // walk rho_e); c = c0 + cd is formed in W.
-template <class W, class R>
+template <bool STD = false, class W, class R>
 __device__ inline void collide_ion(W x[5], W cd, R mu, R itau, int mask, W sign,
                                    const Macro<R>& m, const KP<R>& kp) {
   W mo[5];
@@ -732,8 +748,12 @@ __device__ inline void collide_ion(W x[5], W cd, R mu, R itau, int mask, W sign,
   const W dr[5] = {W(0), Gx, Gy, W(0), W(0)};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const W s = (W)rate(mask, k, itau, kp.s_free);
-    mo[k] = mo[k] - s * (mo[k] - eq[k]) + (W(1) - W(0.5) * s) * so[k] + sign * s * dr[k];
+    if (STD && !((STD_MASK_ADE >> k) & 1)) {
+      mo[k] = eq[k] + W(0.5) * so[k] + sign * dr[k];
+    } else {
+      const W s = STD ? (W)itau : (W)rate(mask, k, itau, kp.s_free);
+      mo[k] = mo[k] - s * (mo[k] - eq[k]) + (W(1) - W(0.5) * s) * so[k] + sign * s * dr[k];
+    }
   }
   inv5(mo, x);
 }
@@ -743,7 +763,7 @@ __device__ inline void collide_ion(W x[5], W cd, R mu, R itau, int mask, W sign,
 // w_i c (1 + 3 c_i.u) has the moments (c, c u, c/3, c/3, 0, c ux/3, c uy/3,
 // c/9); R_i = w_i R has (R, 0, 0, R/3, R/3, 0, 0, 0, R/9); L_i and G_i, of the
 // form w_i c_i.v / c_s^2, have v in the first moments and v/3 in moments 6, 7.
-template <class W, class R>
+template <bool STD = false, class W, class R>
 __device__ inline void collide_ion9(W x[9], W cd, R mu, R itau, int mask, W sign,
                                     const Macro<R>& m, const KP<R>& kp) {
   W mo[9];
@@ -761,8 +781,12 @@ __device__ inline void collide_ion9(W x[9], W cd, R mu, R itau, int mask, W sign
   const W dr[9] = {W(0), Gx, Gy, W(0), W(0), W(0), third * Gx, third * Gy, W(0)};
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    const W s = (W)rate(mask, k, itau, kp.s_free);
-    mo[k] = mo[k] - s * (mo[k] - eq[k]) + (W(1) - W(0.5) * s) * so[k] + sign * s * dr[k];
+    if (STD && !((STD_MASK_ADE >> k) & 1)) {
+      mo[k] = eq[k] + W(0.5) * so[k] + sign * dr[k];
+    } else {
+      const W s = STD ? (W)itau : (W)rate(mask, k, itau, kp.s_free);
+      mo[k] = mo[k] - s * (mo[k] - eq[k]) + (W(1) - W(0.5) * s) * so[k] + sign * s * dr[k];
+    }
   }
   inv9(mo, x);
 }
@@ -784,7 +808,7 @@ __device__ inline W poisson_source(R rhoe, R ieps, const R geps[2], const R gpsi
 // W is the working type: FP64 with FP32 storage, because the Poisson LBE is
 // an iterative solve whose rounding noise is amplified by the condition
 // number of the Laplacian (~ny^2); in FP32 it limits psi' to ~1e-6.
-template <class W, class R>
+template <bool STD = false, class W, class R>
 __device__ inline void collide_g(W g[5], W psid, W Spsi, const KP<R>& kp) {
   W mo[5];
   fwd5(g, mo);
@@ -792,8 +816,12 @@ __device__ inline void collide_g(W g[5], W psid, W Spsi, const KP<R>& kp) {
   const W eq[5] = {W(0), W(0), W(0), third * psid, third * psid};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const W s = (W)rate(kp.mask_g, k, kp.inv_tau_g, kp.s_free);
-    mo[k] = mo[k] - s * (mo[k] - eq[k]);
+    if (STD && !((STD_MASK_ADE >> k) & 1)) {
+      mo[k] = eq[k];
+    } else {
+      const W s = STD ? (W)kp.inv_tau_g : (W)rate(kp.mask_g, k, kp.inv_tau_g, kp.s_free);
+      mo[k] = mo[k] - s * (mo[k] - eq[k]);
+    }
   }
   inv5(mo, g);
   const W src = (W)kp.theta_src * Spsi;

@@ -411,7 +411,7 @@ __device__ inline void store_g(const PopView<S, R>& D, const KP<R>& kp, int x, i
 // -x*_opp + 2 wbar (c_w - c0), i.e. -x*_opp - c0/3 for c_w = 0 and
 // -x*_opp + c'/3 for c_w = c(node); for g the linear potential meets the
 // electrode potentials exactly, so the rule is -x*_opp.
-template <class S, class R, class T0, class HG, class K>
+template <class S, class R, class T0, bool STD, class HG, class K>
 __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev,
                                    const T0* __restrict__ h0src, T0* __restrict__ h0dst,
                                    const KP<R>& kp, const KP<typename WorkOf<S>::type>& kpw, int x,
@@ -483,7 +483,7 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   const R third = R(1) / R(3);
 
   // f first: its nine wide populations are then free for the rest
-  collide_f(fw, m, kpw);
+  collide_f<STD>(fw, m, kpw);
 #pragma unroll
   for (int i = 0; i < 9; ++i) f[i] = (R)fw[i];
   if constexpr (LocalF<S>::value) {
@@ -505,7 +505,7 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     R g4[4];
     hg.g4(g4);
     W gw[5] = {(W)g0, (W)g4[0], (W)g4[1], (W)g4[2], (W)g4[3]};
-    collide_g(gw, m.psid, poisson_source<W>(m.rhoe, m.ieps, m.geps, m.gpsi, kpw), kpw);
+    collide_g<STD>(gw, m.psid, poisson_source<W>(m.rhoe, m.ieps, m.geps, m.gpsi, kpw), kpw);
     R g[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) g[i] = (R)gw[i];
@@ -513,8 +513,8 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   }
 
   if constexpr (I9) {
-    collide_ion9(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
-    collide_ion9(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
+    collide_ion9<STD>(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
+    collide_ion9<STD>(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       p[i] = (R)pw[i];
@@ -531,8 +531,8 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
       ion9_ghosts(D, kp, y, k, QN, QN9, n, ins ? 0 : 2, ins ? 0 : 1, cmd);
     }
   } else {
-  collide_ion(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
-  collide_ion(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
+  collide_ion<STD>(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
+  collide_ion<STD>(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     p[i] = (R)pw[i];
@@ -587,7 +587,7 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     hw[0] = (W)h0in;
 #pragma unroll
     for (int i = 1; i < 9; ++i) hw[i] = (W)h[i];
-    collide_h(hw, m, dJ, kpw);
+    collide_h<STD>(hw, m, dJ, kpw);
 #pragma unroll
     for (int i = 0; i < 9; ++i) h[i] = (R)hw[i];
     // reference phase of each destination (16-bit storage; 0 otherwise):
@@ -682,7 +682,7 @@ struct SweepLds {
 
 // One tile of the fused sweep: columns [x0, x0 + 64 NW) of rows [y0, yend)
 // of one simulation, walked down row by row by the whole workgroup.
-template <class S, class R, class T0, int NW, int EXT>
+template <class S, class R, class T0, int NW, int EXT, bool STD>
 __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
                                   const S* __restrict__ src, S* __restrict__ dst,
                                   R* __restrict__ jprev, const T0* __restrict__ h0x,
@@ -822,7 +822,8 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
       nine(psD, psC, psU, psi9);
 
       const HGLds<R, TW> hg{L.pull[(y - y0 + 2) & 1], lane};
-      update_node<S, R, T0>(D, jprev, h0x, h0dst, kp, kpw, x, y, k, phi9, psi9, f, p, n, g0, hg);
+      update_node<S, R, T0, STD>(D, jprev, h0x, h0dst, kp, kpw, x, y, k, phi9, psi9, f, p, n, g0,
+                                 hg);
     }
   }
 }
@@ -862,8 +863,10 @@ struct BatchTile {
 // XCD hold neighbouring strips of the same rows and the cache lines they
 // share are fetched from HBM once.  `flip` = 1 swaps every member's buffers
 // (odd steps of a captured block).  EXT selects the form: 0 plain, 1 with
-// the side walls, 2 with the side walls and the local field of Eq. (50); a
-// launch covers members of one form.  The per-lane address and reference
+// the side walls, 2 with the side walls and the local field of Eq. (50), 3
+// plain with the ions on D2Q9; STD compiles in the default MRT rates (see
+// STD_MASK_F), which saves ~8 % of the vector instructions.  A launch covers
+// members of one form.  The per-lane address and reference
 // selects of the side walls cost 2-6 % on MI355X at 2048^2, and the local
 // field's code another ~13 % (more spills) where it is compiled in.
 //
@@ -871,7 +874,7 @@ struct BatchTile {
 // FP64 arithmetic): with the FP64 working type of FP32 storage it otherwise
 // settles on 144 VGPRs (three waves); four waves with a few spilled
 // registers are up to 18 % faster on MI355X at 2048^2.
-template <class S, class R, class T0, int NW, int EXT>
+template <class S, class R, class T0, int NW, int EXT, bool STD>
 __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
     const SimDesc<S, R, T0>* __restrict__ sims,
@@ -882,8 +885,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_batch(
   const SimDesc<S, R, T0>& sd = sims[tl.sim];
   const int a = (sd.cur + flip) & 1;
   const S* src = sd.pop[a];
-  sweep_tile<S, R, T0, NW, EXT>(L, src, sd.pop[1 - a], sd.jprev, sd.h0[a], sd.h0[1 - a], sd.kp,
-                               sd.kpw, tl.x0, tl.y0, tl.yend);
+  sweep_tile<S, R, T0, NW, EXT, STD>(L, src, sd.pop[1 - a], sd.jprev, sd.h0[a], sd.h0[1 - a],
+                                     sd.kp, sd.kpw, tl.x0, tl.y0, tl.yend);
 }
 
 // ---------------------------------------------------------------------------
