@@ -57,9 +57,13 @@ typedef int32_t lbm_status;
  * deviations from a reference state (h: w_i/2, p and n: wbar_i c0, g: the
  * equilibrium of the uncharged linear potential, f: 0; 16-bit storage adds
  * node-local references).  The rest populations that carry the conserved
- * contents (h0; with 16-bit storage also p0 and n0) are kept in FP64 in
- * every form, so that each collision conserves phi and the ion contents to
- * FP64 rounding. */
+ * contents (h0; with 16-bit storage also p0 and n0) take what a node's
+ * stored moving populations leave of its content, so that each collision
+ * conserves phi and the ion contents: they are FP64 (conserved to FP64
+ * rounding) except h0 with FP32 storage, a 32-bit fixed-point value
+ * (2^-30 units) booked in integers against the fixed-point images of the
+ * moving populations, which conserves the sum of phi over the grid
+ * exactly. */
 #define LBM_FP64 0       /* FP64 storage, FP64 arithmetic */
 #define LBM_FP32 1       /* FP32 storage.  Arithmetic: FP64 for the phase
                             ring and its stencils, the macroscopic quantities
@@ -349,7 +353,7 @@ LBM_API int64_t lbm_ehd_time(const lbm_ehd *h);
 
 /*
  * Checkpoint and resume.  The state of a simulation (its current population
- * buffer, the aux buffer with (phi u)(t-1) and the FP64 rest populations,
+ * buffer, the aux buffer with (phi u)(t-1) and the rest populations,
  * the step count) fits in *bytes of host memory.  lbm_ehd_save_state copies
  * it out (synchronises); lbm_ehd_load_state copies a saved state into a
  * simulation created with the same grid and storage precision and makes it
@@ -511,9 +515,10 @@ LBM_API const char *lbm_ehd_last_error(void);
  * item read and written once: the 32 moving populations in the storage type
  * (with 16-bit storage: 30, the rest populations of the two ions being kept
  * in FP64, plus the lines of the reference phase of h and the reference
- * potential of g), the FP64 rest populations (h0; with 16-bit storage also
- * p0 and n0) and (phi u)(t-1) in the arithmetic type.  FP64 560, FP32 288,
- * FP32 storage with FP64 arithmetic 304, FP16 and BF16 192. */
+ * potential of g), the rest populations (h0: FP64, 4 bytes with FP32
+ * storage; with 16-bit storage also p0 and n0, FP64) and (phi u)(t-1) in the
+ * arithmetic type.  FP64 560, FP32 280, FP32 storage with FP64 arithmetic
+ * 296, FP16 192, BF16 200. */
 LBM_API double lbm_ehd_bytes_per_lup(int32_t precision);
 
 /* Measurement helper, not part of the method: copy `bytes` (a multiple of

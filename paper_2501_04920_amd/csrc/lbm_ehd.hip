@@ -57,9 +57,13 @@ size_t arith_size(int prec) { return (prec == LBM_FP64 || prec == LBM_FP32_F64) 
 // 16-bit storage also reads and writes the line of h0 in the population
 // buffers (the reference phase of the moving h, see LocalH)
 bool local_h(int prec) { return elem_size(prec) == 2; }
-// bytes per cell and time level of the FP64 rest populations (see RestOf and
-// IonRest): h0, and with 16-bit storage also p0 and n0
-size_t rest_bytes(int prec) { return 8 * (local_h(prec) ? 3 : 1); }
+// bytes per cell and time level of the rest populations (see RestOf and
+// IonRest): h0 (FP64; 32-bit fixed point with FP32 storage), and with
+// 16-bit storage also p0 and n0 (FP64)
+size_t rest_bytes(int prec) {
+  if (local_h(prec)) return 3 * 8;
+  return elem_size(prec) == 4 ? 4 : 8;
+}
 
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 // lines per lattice row of a population buffer: 33, a 34th with bfloat16
@@ -1215,7 +1219,8 @@ lbm_status lbm_ehd_required_bytes(const lbm_ehd_params* p, size_t* pop_bytes,
     *pop_bytes = (size_t)lines_of(*p) * (p->ny + 2) * pitch * elem_size(p->precision);
   if (aux_bytes) {
     if (p->inplace)  // (phi u), one level of the rest of h, the phi' and psi' planes (FP64)
-      *aux_bytes = (size_t)p->ny * pitch * (2 * arith_size(p->precision) + 8 + 8 + 8);
+      *aux_bytes =
+          (size_t)p->ny * pitch * (2 * arith_size(p->precision) + rest_bytes(p->precision) + 16);
     else
       *aux_bytes =
           (size_t)p->ny * pitch * (2 * arith_size(p->precision) + 2 * rest_bytes(p->precision));
@@ -1563,7 +1568,7 @@ struct SavedState {
   uint64_t pop_bytes, aux_bytes;
   RefSig ref;
 };
-constexpr uint64_t STATE_MAGIC = 0x3330455441545345ull;  // "ESTATE03"
+constexpr uint64_t STATE_MAGIC = 0x3430455441545345ull;  // "ESTATE04"
 
 }  // namespace
 

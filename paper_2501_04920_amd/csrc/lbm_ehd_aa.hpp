@@ -157,7 +157,7 @@ __global__ __launch_bounds__(64 * NW) void k_aa_hood(const SimDescAA<S, R, T0>* 
     for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
 #pragma unroll
     for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
-    *elem(sd.phiP, jo) = phi_of<W>((W)*elem(sd.h0, jo), h);
+    *elem(sd.phiP, jo) = phi_of<W>((W)rest_val(*elem(sd.h0, jo)), h);
     *elem(sd.psiP, jo) = psi_as<W>(g4);
   }
 }
@@ -235,11 +235,12 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
     *elem(jprev, jo) = Jx;
     *elem(jprev, jpl + jo) = Jy;
     const T0 h0in = *elem(h0x, jo);
-    double mass = (double)h0in;  // exact sum of the node's incoming h
+    // the node's phi content: its rest plus its incoming h (see RestOf)
+    RestAcc<T0> mass = RestAcc<T0>::from_rest(h0in);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) mass += (double)h[i];
+    for (int i = 1; i < 9; ++i) mass.add(h[i]);
     W hw[9];
-    hw[0] = (W)h0in;
+    hw[0] = (W)rest_val(h0in);
 #pragma unroll
     for (int i = 1; i < 9; ++i) hw[i] = (W)h[i];
     collide_h(hw, m, dJ, kpw);
@@ -247,10 +248,10 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
     for (int i = 1; i < 9; ++i) {
       h[i] = V.P.stored(QH + i, (R)hw[i]);
       V.out(par, QH, i, k, y, h[i], h[i]);
-      mass -= (double)h[i];
+      mass.sub(h[i]);
     }
-    // the rest population takes what the eight stored ones leave of the mass
-    *elem(h0x, jo) = (T0)mass;
+    // the rest population takes what the eight stored ones leave of the content
+    *elem(h0x, jo) = mass.rest();
   }
 }
 
@@ -311,7 +312,7 @@ __global__ void k_aa_moments(const S* __restrict__ src, const T0* __restrict__ h
   const AAView<S, R> V{PopView<S, R>{make_rsrc(src, kp.pop_bytes), &kp, false}};
   const Cols k = cols_of(x, kp.nx, 0);
   R h[9], g4[4];
-  h[0] = (R)*elem(h0x, (uint32_t)y * kp.pitch + x);
+  h[0] = (R)rest_val(*elem(h0x, (uint32_t)y * kp.pitch + x));
   for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
   for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
   R Pd = R(0), Qd = R(0);
@@ -410,8 +411,14 @@ __global__ __launch_bounds__(256) void k_aa_row_sums(const S* __restrict__ src,
   const double c0 = (double)kp.c0;
   for (int x = t; x < kp.nx; x += 256) {
     const Cols k = cols_of(x, kp.nx, 0);
-    double phid = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
-    for (int i = 1; i < 9; ++i) phid += (double)V.in(par, QH, i, k, y);
+    RestAcc<T0> content = RestAcc<T0>::from_rest(*elem(h0x, (uint32_t)y * kp.pitch + x));
+    bool finite = true;
+    for (int i = 1; i < 9; ++i) {
+      const R hi = V.in(par, QH, i, k, y);
+      content.add(hi);
+      finite = finite && isfinite((double)hi);
+    }
+    const double phid = finite ? content.content() : NAN;
     double Pd = 0.0, Qd = 0.0;
     for (int i = 0; i < 5; ++i) {
       Pd += (double)V.in(par, QP, i, k, y);

@@ -209,15 +209,67 @@ __device__ inline float stored_as<__hip_bfloat16, float>(float x) {
   return __bfloat162float(__float2bfloat16(x));
 }
 
-// Type of the rest population of h, kept next to (phi u)(t-1): FP64 in
-// every storage form.  It absorbs the rounding of the eight moving h
-// populations of its node, so that every collision conserves phi to FP64
-// rounding.  (In FP32 the per-step changes of slowly varying cells would
-// fall below half an ulp of the rest population and be lost, always in the
-// same direction.)
+// Type of the rest population of h, kept next to (phi u)(t-1).  It absorbs
+// the rounding of the eight moving h populations of its node, so that every
+// collision conserves the node's phi.  (In FP32 the per-step changes of
+// slowly varying cells would fall below half an ulp of the rest population
+// and be lost, always in the same direction.)
+//   FP64 (FP64 and 16-bit storage): conserved to FP64 rounding.
+//   Fix32 (FP32 storage): 32-bit fixed point, value q 2^-30 (|value| < 2),
+//     booked in integers (RestAcc): a node's content is its rest plus the
+//     fixed-point images fixq() of its eight incoming populations, and its
+//     outgoing rest is that content minus the images of the eight it
+//     stores.  Streaming moves stored values unchanged, so the sum of the
+//     contents over the grid is conserved exactly, in 4 bytes instead of 8.
+//     The phase the collision sees is the rest plus the populations
+//     themselves, within 8 2^-31 of the content.
+struct Fix32 {
+  int32_t q;
+};
+constexpr double FIX_UNIT = 0x1p-30;
 template <class S>
 struct RestOf {
   typedef double type;
+};
+template <>
+struct RestOf<float> {
+  typedef Fix32 type;
+};
+__host__ __device__ inline double rest_val(double r) { return r; }
+__host__ __device__ inline double rest_val(Fix32 r) { return (double)r.q * FIX_UNIT; }
+// fixed-point image of a stored FP32 population: exact power-of-two scaling,
+// then the nearest integer
+__device__ inline int32_t fixq(float x) { return (int32_t)__builtin_rintf(x * 0x1p30f); }
+__device__ inline int32_t fixq(double x) { return (int32_t)__builtin_rint(x * 0x1p30); }
+
+// A node's phi content in the rest type's bookkeeping (see RestOf): built
+// from the rest population and the incoming moving ones, then reduced by the
+// outgoing ones to the new rest.
+template <class T0>
+struct RestAcc {
+  double m;
+  __device__ static RestAcc from_rest(T0 r) { return RestAcc{(double)r}; }
+  __device__ static RestAcc from_content(double c) { return RestAcc{c}; }
+  template <class X>
+  __device__ void add(X x) { m += (double)x; }
+  template <class X>
+  __device__ void sub(X x) { m -= (double)x; }
+  __device__ double content() const { return m; }
+  __device__ T0 rest() const { return (T0)m; }
+};
+template <>
+struct RestAcc<Fix32> {
+  uint32_t m;  // two's complement, wrapping: the end result fits in 32 bits
+  __device__ static RestAcc from_rest(Fix32 r) { return RestAcc{(uint32_t)r.q}; }
+  __device__ static RestAcc from_content(double c) {
+    return RestAcc{(uint32_t)(int32_t)__builtin_rint(c * 0x1p30)};
+  }
+  template <class X>
+  __device__ void add(X x) { m += (uint32_t)fixq(x); }
+  template <class X>
+  __device__ void sub(X x) { m -= (uint32_t)fixq(x); }
+  __device__ double content() const { return (double)(int32_t)m * FIX_UNIT; }
+  __device__ Fix32 rest() const { return Fix32{(int32_t)m}; }
 };
 
 // Working type of the sweep for a storage type: the phase ring, the
@@ -367,31 +419,38 @@ struct PopView {
   const KP<R>* kp;
   bool nt = true;
   __device__ inline uint32_t row(int r) const { return (uint32_t)r * kp->rstride; }
-  // offset of the ion lines with 16-bit storage (see the deviation form)
-  __device__ inline R ofs(int q) const {
-    if (!LocalH<S>::value || q < QP || q >= QG || q == QRG) return R(0);
-    if (LocalF<S>::value && q == QJX) return R(0);
-    return kp->iofs[q - QP];
+  // whether line q carries an offset: the ion lines with 16-bit storage
+  // (see the deviation form).  Decided where q is known at compile time:
+  // an add of a zero is no identity in IEEE arithmetic (-0 + 0 = +0), so the
+  // compiler keeps it, one vector instruction per load.  Binary16 lines keep
+  // the form scale * x + offset throughout, which is one mixed-precision
+  // multiply-add with the conversion folded in, offset or not.
+  __device__ inline bool has_ofs(int q) const {
+    return LocalH<S>::value && q >= QP && q < QG && q != QRG && !(LocalF<S>::value && q == QJX);
   }
+  __device__ inline R ofs(int q) const { return has_ofs(q) ? kp->iofs[q - QP] : R(0); }
   __device__ inline R at(int q, uint32_t off) const {
     R v = Codec<S, R>::ld(rs, off * (uint32_t)sizeof(S),
                           (uint32_t)q * kp->pitch * (uint32_t)sizeof(S), nt);
-    if (Scaled<S>::value) v *= kp->isc[line_set<S>(q)];
-    return v + ofs(q);
+    if constexpr (Scaled<S>::value) return v * kp->isc[line_set<S>(q)] + ofs(q);
+    if (has_ofs(q)) v += kp->iofs[q - QP];
+    return v;
   }
   __device__ inline void put(int q, uint32_t off, R v) const {
-    v -= ofs(q);
+    if (has_ofs(q)) v -= kp->iofs[q - QP];
     if (Scaled<S>::value) v *= kp->sc[line_set<S>(q)];
     Codec<S, R>::st(rs, off * (uint32_t)sizeof(S), (uint32_t)q * kp->pitch * (uint32_t)sizeof(S),
                     v);
   }
   // the value v takes once stored in line q (and loaded back)
   __device__ inline R stored(int q, R v) const {
-    const R o = ofs(q);
-    if (Scaled<S>::value) {
+    if constexpr (Scaled<S>::value) {
+      const R o = ofs(q);
       const int k = line_set<S>(q);
       return stored_as<S, R>((v - o) * kp->sc[k]) * kp->isc[k] + o;
     }
+    if (!has_ofs(q)) return stored_as<S, R>(v);
+    const R o = kp->iofs[q - QP];
     return stored_as<S, R>(v - o) + o;
   }
 };

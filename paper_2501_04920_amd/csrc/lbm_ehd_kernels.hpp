@@ -180,7 +180,7 @@ __device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x
   const bool bot = ywalls && yy == 0, top = ywalls && yy == P.kp->ny - 1;
   const T0 r = *elem(h0x, (uint32_t)yy * pc + k.c);
   if (h0) *h0 = r;
-  x[0] = (R)r;
+  x[0] = (R)rest_val(r);
   x[1] = P.at(QH + 1, k.lw ? own + 2 * pc : r0 + k.m);                    // <- 3
   x[2] = P.at(QH + 2, rm + k.c);
   x[3] = P.at(QH + 3, k.rw ? own - 2 * pc : r0 + k.p);                    // <- 1
@@ -205,9 +205,9 @@ __device__ inline void pull_h(const PopView<S, R>& P, const T0* __restrict__ h0x
 template <class S, class R, class T0>
 __device__ inline double ion_rest(const PopView<S, R>& P, const T0* __restrict__ h0x, int q0,
                                   int x, int y) {
-  if (IonRest<S>::value)
-    return (double)*elem(h0x, (uint32_t)(q0 == QP ? 1 : 2) * P.kp->cells +
-                                  (uint32_t)y * P.kp->pitch + x);
+  if constexpr (IonRest<S>::value)
+    return rest_val(*elem(h0x, (uint32_t)(q0 == QP ? 1 : 2) * P.kp->cells +
+                                   (uint32_t)y * P.kp->pitch + x));
   return (double)P.at(q0, P.row(y + 1) + x);
 }
 
@@ -444,9 +444,9 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
   const uint32_t jo = (uint32_t)y * kp.pitch + x;
   // exact incoming ion content of the node (FP64 ion rest populations)
   double Pin = 0.0, Qin = 0.0;
-  if (IonRest<S>::value) {
-    Pin = (double)*elem(h0src, kp.cells + jo);
-    Qin = (double)*elem(h0src, 2 * kp.cells + jo);
+  if constexpr (IonRest<S>::value) {
+    Pin = rest_val(*elem(h0src, kp.cells + jo));
+    Qin = rest_val(*elem(h0src, 2 * kp.cells + jo));
     pw[0] = (W)Pin;
     nw[0] = (W)Qin;
 #pragma unroll
@@ -538,7 +538,7 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     p[i] = (R)pw[i];
     n[i] = (R)nw[i];
   }
-  if (IonRest<S>::value) {
+  if constexpr (IonRest<S>::value) {
     // the collision adds the reaction term to each ion's content (Eq. 41);
     // the rest populations take what the stored moving ones leave of it
     double Pout = Pin + (double)m.Rr, Qout = Qin + (double)m.Rr;
@@ -580,11 +580,12 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     const T0 h0in = *elem(h0src, jo);
     R h[9];
     hg.h9(h);
-    double mass = (double)h0in;  // exact sum of the node's incoming h
+    // the node's phi content: its rest plus its incoming h (see RestOf)
+    RestAcc<T0> mass = RestAcc<T0>::from_rest(h0in);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) mass += (double)h[i];
+    for (int i = 1; i < 9; ++i) mass.add(h[i]);
     W hw[9];
-    hw[0] = (W)h0in;
+    hw[0] = (W)rest_val(h0in);
 #pragma unroll
     for (int i = 1; i < 9; ++i) hw[i] = (W)h[i];
     collide_h<STD>(hw, m, dJ, kpw);
@@ -614,10 +615,10 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
     for (int i = 1; i < 9; ++i) {
       h[i] = D.stored(QH + i, h[i] - (R)W9F[i] * t[i]);
       D.put(QH + i, o, h[i]);
-      mass -= (double)h_from(h[i], i, t[i]);
+      mass.sub(h_from(h[i], i, t[i]));
     }
-    // the rest population takes what the eight stored ones leave of the mass
-    *elem(h0dst, jo) = (T0)mass;
+    // the rest population takes what the eight stored ones leave of the content
+    *elem(h0dst, jo) = mass.rest();
     if (edge) G.set9(QH, h);
   }
 
@@ -740,7 +741,7 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
         T0 hh0;
         pull_h(V, h0x, kh, ys, hh, &hh0);
         pull_g(V, kh, ys, gg);
-        L.phi[sl][kcol] = phi_of<W>((W)hh0, hh);
+        L.phi[sl][kcol] = phi_of<W>((W)rest_val(hh0), hh);
         L.psi.set(sl, kcol, psi_as<W>(gg));
       }
       if (valid) {
@@ -748,7 +749,7 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
         T0 h0;
         pull_h(V, h0x, k, ys, h, &h0);
         pull_g(V, k, ys, g4);
-        L.phi[sl][lane + 1] = phi_of<W>((W)h0, h);
+        L.phi[sl][lane + 1] = phi_of<W>((W)rest_val(h0), h);
         L.psi.set(sl, lane + 1, psi_as<W>(g4));
         const int b = (yy - y0 + 2) & 1;
 #pragma unroll
@@ -1125,7 +1126,7 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
   };
   // h: the rest population (which does not move) takes phi minus what the
   // eight stored moving populations hold, so that phi is exact from the start
-  double hrest = phi - 0.5;
+  RestAcc<T0> hrest = RestAcc<T0>::from_content(phi - 0.5);
   R tref = R(0);  // this node's reference phase (16-bit storage)
   if (LocalH<S>::value) {
     tref = D.stored(QH, (R)(phi - 0.5));
@@ -1139,10 +1140,10 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
       const double dev = w9[i] * phi * (1.0 + 3.0 * cu) - 0.5 * w9[i];
       const R st = D.stored(QH + i, (R)(dev - (double)W9F[i] * (double)tref));
       put(QH + i, i, (double)st + 0.5 * w9[i]);
-      hrest -= (double)h_from(st, i, tref);
+      hrest.sub(h_from(st, i, tref));
     }
   }
-  *elem(h0x, (uint32_t)y * kp.pitch + x) = (T0)hrest;
+  *elem(h0x, (uint32_t)y * kp.pitch + x) = hrest.rest();
   const uint32_t jo = (uint32_t)y * kp.pitch + x;
   // bfloat16 storage: every node's reference momentum starts at 0, so the
   // initial f above are stored relative to 0 as written
@@ -1171,8 +1172,10 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
     if (kp.ion_q9) {
       // (ions written above)
     } else if (i == 0 && IonRest<S>::value) {
-      *elem(h0x, kp.cells + jo) = (T0)(w5[0] * (cp - sp.c0));
-      *elem(h0x, 2 * kp.cells + jo) = (T0)(w5[0] * (cm - sp.c0));
+      if constexpr (IonRest<S>::value) {
+        *elem(h0x, kp.cells + jo) = (T0)(w5[0] * (cp - sp.c0));
+        *elem(h0x, 2 * kp.cells + jo) = (T0)(w5[0] * (cm - sp.c0));
+      }
     } else {
       put(QP + i, i, w5[i] * cp * (1.0 + 3.0 * cu));
       put(QN + i, i, w5[i] * cm * (1.0 + 3.0 * cu));
@@ -1200,7 +1203,10 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
     const Cols k = cols_of(x, kp.nx, kp.side_walls);
     R h[9], t4[4], g4[4];
     pull_h(Ph, h0x, k, y, h);
-    const double h0 = (double)*elem(h0x, (uint32_t)y * kp.pitch + x);
+    // the node's phi content in the bookkeeping of the rest type (exact
+    // integer sums with the fixed-point rest of FP32 storage)
+    RestAcc<T0> content = RestAcc<T0>::from_rest(*elem(h0x, (uint32_t)y * kp.pitch + x));
+    for (int i = 1; i < 9; ++i) content.add(h[i]);
     pull4(Ph, QP, k, y, t4);
     const double Pd = ion_rest(Ph, h0x, QP, x, y) + t4[0] + t4[1] + t4[2] + t4[3] +
                       (double)ion_diag_sum(Ph, QP9, k, y);
@@ -1208,8 +1214,10 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
     const double Qd = ion_rest(Ph, h0x, QN, x, y) + t4[0] + t4[1] + t4[2] + t4[3] +
                       (double)ion_diag_sum(Ph, QN9, k, y);
     pull_g(Ph, k, y, g4);
-    double phid = h0;
-    for (int i = 1; i < 9; ++i) phid += (double)h[i];
+    double phid = content.content();
+    // a non-finite population has no fixed-point image
+    for (int i = 1; i < 9; ++i)
+      if (!isfinite((double)h[i])) phid = (double)h[i];
     const double phi = 0.5 + phid;
     const double psid = (double)psi_of(g4);
     acc[0] += phi;

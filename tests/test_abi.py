@@ -38,13 +38,14 @@ def test_defaults_and_bytes():
     assert (p.nx, p.ny, p.precision, p.walls) == (128, 128, 1, 0)
     assert p.mask_f == 0b111000 and p.mask_h == 0b110 and p.theta == 0.3
     pop, aux = lbm_ehd.lbm_ehd_required_bytes(p)
-    # (phi u)(t-1) in FP32 and two time levels of the rest population of h in FP64
-    assert pop == 33 * 130 * 128 * 4 and aux == 128 * 128 * (2 * 4 + 2 * 8)
+    # (phi u)(t-1) in FP32 and two time levels of the rest population of h in
+    # 32-bit fixed point
+    assert pop == 33 * 130 * 128 * 4 and aux == 128 * 128 * (2 * 4 + 2 * 4)
     # 16-bit storage: two time levels of the rest populations of h, p and n
     pop, aux = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(precision="fp16"))
     assert pop == 33 * 130 * 128 * 2 and aux == 128 * 128 * (2 * 4 + 2 * 3 * 8)
     # 32 moving planes + rest of h + (phi u), each read and written once
-    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp32") == 2 * 32 * 4 + 2 * 8 + 2 * 8
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp32") == 2 * 32 * 4 + 2 * 4 + 2 * 8 == 280
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp16") == 2 * 32 * 2 + 2 * 3 * 8 + 2 * 8
     # bfloat16: two more lines, the reference momentum of f
     assert lbm_ehd.lbm_ehd_bytes_per_lup("bf16") == 2 * 34 * 2 + 2 * 3 * 8 + 2 * 8
@@ -177,12 +178,12 @@ def test_inplace_sizes():
     aux holds (phi u), one level of the rest of h and the phi'/psi' planes
     (FP64)."""
     import ctypes
-    for prec, a in (("fp32", 4), ("fp64", 8), ("fp32f64", 8)):
+    for prec, a, r in (("fp32", 4, 4), ("fp64", 8, 8), ("fp32f64", 8, 4)):
         two = lbm_ehd.make_params(precision=prec)
         one = lbm_ehd.make_params(precision=prec, inplace=1)
         pb2, ab2 = lbm_ehd.lbm_ehd_required_bytes(two)
         pb1, ab1 = lbm_ehd.lbm_ehd_required_bytes(one)
-        assert pb1 == pb2 and ab1 == 128 * 128 * (2 * a + 24)
+        assert pb1 == pb2 and ab1 == 128 * 128 * (2 * a + r + 16)
         f1, f2 = ctypes.c_size_t(), ctypes.c_size_t()
         assert lbm_ehd.lib().lbm_ehd_footprint_bytes(ctypes.byref(one), ctypes.byref(f1)) == 0
         assert lbm_ehd.lib().lbm_ehd_footprint_bytes(ctypes.byref(two), ctypes.byref(f2)) == 0
