@@ -144,12 +144,13 @@ bool std_rates(const lbm_ehd_params& p) {
 
 // Form of the sweep a simulation runs on, each compiled separately: 0 plain,
 // 1 with side walls, 2 with side walls and the local field of Eq. (50), 3
-// in-place streaming (plain), 4 plain with the ions on D2Q9; forms 0, 1 and
-// 4 with the default MRT rates compiled in are NFORM higher (5, 6, 9).
+// in-place streaming (plain), 4 plain with the ions on D2Q9; forms 0, 1, 3
+// and 4 with the default MRT rates compiled in are NFORM higher (5, 6, 8,
+// 9).
 constexpr int NFORM = 5;
 int sweep_form(const lbm_ehd_params& p) {
-  if (p.inplace) return 3;
-  const int base = p.ion_q9 ? 4 : (p.local_field ? 2 : (p.side_walls ? 1 : 0));
+  const int base =
+      p.inplace ? 3 : (p.ion_q9 ? 4 : (p.local_field ? 2 : (p.side_walls ? 1 : 0)));
   return base + (base != 2 && std_rates(p) ? NFORM : 0);
 }
 
@@ -417,32 +418,41 @@ struct Form {
   // One in-place step over the tiles `tiles` of the members described by
   // `descs` (DescAA): the phi'/psi' pre-pass, then the sweep.  `flip` /
   // `gflip` = 1 turns every member's orientation of f, h, p, n / of g.
-  template <int NW>
+  template <int NW, bool STD>
   static void launch_aa_nw(const void* descs, const BatchTile* tiles, int ntiles, int flip,
                            int gflip, hipStream_t st) {
     if constexpr (kAA) {
       hipLaunchKernelGGL((k_aa_hood<S, R, T0, NW>), dim3(ntiles), dim3(64 * NW), 0, st,
                          static_cast<const DescAA*>(descs), tiles, ntiles / 8, flip, gflip);
-      hipLaunchKernelGGL((k_sweep_aa<S, R, T0, NW>), dim3(ntiles), dim3(64 * NW), 0, st,
+      hipLaunchKernelGGL((k_sweep_aa<S, R, T0, NW, STD>), dim3(ntiles), dim3(64 * NW), 0, st,
                          static_cast<const DescAA*>(descs), tiles, ntiles / 8, flip, gflip);
     }
   }
-  static lbm_status launch_aa(int waves, const void* descs, const BatchTile* tiles, int ntiles,
-                              int flip, int gflip, hipStream_t st) {
-    if (!kAA) return fail(LBM_EINVAL, "in-place streaming needs 4- or 8-byte storage");
+  template <bool STD>
+  static void launch_aa_std(int waves, const void* descs, const BatchTile* tiles, int ntiles,
+                            int flip, int gflip, hipStream_t st) {
     switch (waves) {
-      case 8: launch_aa_nw<8>(descs, tiles, ntiles, flip, gflip, st); break;
-      case 4: launch_aa_nw<4>(descs, tiles, ntiles, flip, gflip, st); break;
-      case 2: launch_aa_nw<2>(descs, tiles, ntiles, flip, gflip, st); break;
-      default: launch_aa_nw<1>(descs, tiles, ntiles, flip, gflip, st); break;
+      case 8: launch_aa_nw<8, STD>(descs, tiles, ntiles, flip, gflip, st); break;
+      case 4: launch_aa_nw<4, STD>(descs, tiles, ntiles, flip, gflip, st); break;
+      case 2: launch_aa_nw<2, STD>(descs, tiles, ntiles, flip, gflip, st); break;
+      default: launch_aa_nw<1, STD>(descs, tiles, ntiles, flip, gflip, st); break;
     }
+  }
+  // `std`: the members have the default MRT rates (sweep form 3 + NFORM)
+  static lbm_status launch_aa(int waves, bool std, const void* descs, const BatchTile* tiles,
+                              int ntiles, int flip, int gflip, hipStream_t st) {
+    if (!kAA) return fail(LBM_EINVAL, "in-place streaming needs 4- or 8-byte storage");
+    if (std)
+      launch_aa_std<true>(waves, descs, tiles, ntiles, flip, gflip, st);
+    else
+      launch_aa_std<false>(waves, descs, tiles, ntiles, flip, gflip, st);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
 
   static lbm_status sweep(lbm_ehd* h) {
     if (h->P.inplace) {
-      lbm_status st = launch_aa(h->waves, h->d_desc, h->d_tiles, h->ntiles,
+      lbm_status st = launch_aa(h->waves, std_rates(h->P), h->d_desc, h->d_tiles, h->ntiles,
                                 h->par ^ h->desc_par, h->gpar ^ h->desc_gpar, h->stream);
       if (st) return st;
       h->par ^= 1;
@@ -655,8 +665,8 @@ struct Form {
         HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
         lbm_status cst = LBM_OK;
         for (int i = 0; i < RUN_BLOCK && !cst; ++i)
-          cst = aa ? launch_aa(h->waves, h->d_desc, h->d_tiles, h->ntiles, par ^ (i & 1),
-                               gpar ^ (i & 1), h->cap)
+          cst = aa ? launch_aa(h->waves, std_rates(h->P), h->d_desc, h->d_tiles, h->ntiles,
+                               par ^ (i & 1), gpar ^ (i & 1), h->cap)
                    : launch_tiles(h->waves, sweep_form(h->P), h->d_desc, h->d_tiles,
                                   h->ntiles, par ^ (i & 1), h->cap);
         hipGraph_t g = nullptr;
@@ -912,7 +922,9 @@ struct BatchForm {
     for (int form = 0; form < 2 * NFORM; ++form) {
       if (b->ntiles[form] > 0) {
         const lbm_status st =
-            form == 3 ? F::launch_aa(b->waves, b->d_aadesc, b->d_tiles + first, b->ntiles[form],
+            form % NFORM == 3
+                ? F::launch_aa(b->waves, form >= NFORM, b->d_aadesc, b->d_tiles + first,
+                               b->ntiles[form],
                                      flip, flip, b->stream)
                       : F::launch_tiles(b->waves, form, b->d_desc, b->d_tiles + first,
                                         b->ntiles[form], flip, b->stream);

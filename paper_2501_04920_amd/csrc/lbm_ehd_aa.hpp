@@ -165,7 +165,7 @@ __global__ __launch_bounds__(64 * NW) void k_aa_hood(const SimDescAA<S, R, T0>* 
 // Per-node update of the in-place sweep: the arithmetic of update_node (the
 // two-buffer sweep, plain form, 4- and 8-byte storage) in the same order,
 // with the stores of the AA orientations.
-template <class S, class R, class T0, class K>
+template <class S, class R, class T0, bool STD, class K>
 __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
                                       R* __restrict__ jprev, T0* __restrict__ h0x,
                                       const KP<R>& kp, const KP<typename WorkOf<S>::type>& kpw,
@@ -193,7 +193,7 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
   const R third = R(1) / R(3);
 
   // f: bounce-back at the electrodes
-  collide_f(fw, m, kpw);
+  collide_f<STD>(fw, m, kpw);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     f[i] = (R)fw[i];
@@ -202,7 +202,7 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
 
   {  // g: Eq. (44)-(47); anti-bounce-back with the electrode potential
     W gw[5] = {(W)g[0], (W)g[1], (W)g[2], (W)g[3], (W)g[4]};
-    collide_g(gw, m.psid, poisson_source<W>(m.rhoe, m.ieps, m.geps, m.gpsi, kpw), kpw);
+    collide_g<STD>(gw, m.psid, poisson_source<W>(m.rhoe, m.ieps, m.geps, m.gpsi, kpw), kpw);
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       g[i] = (R)gw[i];
@@ -210,8 +210,8 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
     }
   }
 
-  collide_ion(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
-  collide_ion(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
+  collide_ion<STD>(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
+  collide_ion<STD>(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
   const R cpd = (R)m.cpd, cmd = (R)m.cmd;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -243,7 +243,7 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
     hw[0] = (W)rest_val(h0in);
 #pragma unroll
     for (int i = 1; i < 9; ++i) hw[i] = (W)h[i];
-    collide_h(hw, m, dJ, kpw);
+    collide_h<STD>(hw, m, dJ, kpw);
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       h[i] = V.P.stored(QH + i, (R)hw[i]);
@@ -258,8 +258,9 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
 // The fused in-place sweep: one workgroup per tile of the list (as the
 // two-buffer sweep), every node of a row of the tile independent of the
 // others (no LDS, no barrier).  `flip` / `gflip` = 1 turns every member's
-// orientation of f, h, p, n / of g (odd steps of a captured block).
-template <class S, class R, class T0, int NW>
+// orientation of f, h, p, n / of g (odd steps of a captured block).  STD:
+// the default MRT rates compiled in, as in the two-buffer sweep.
+template <class S, class R, class T0, int NW, bool STD>
 __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
     const SimDescAA<S, R, T0>* __restrict__ sims, const BatchTile* __restrict__ tiles,
@@ -292,7 +293,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
 #pragma unroll
     for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
     __builtin_amdgcn_s_setprio(0);
-    update_node_aa<S, R, T0>(V, par, gpar, sd.jprev, sd.h0, kp, sd.kpw, x, y, k, phi9, psi9, f,
+    update_node_aa<S, R, T0, STD>(V, par, gpar, sd.jprev, sd.h0, kp, sd.kpw, x, y, k, phi9, psi9, f,
                              h, p, n, g);
   }
 }
