@@ -21,15 +21,15 @@
 // so that g-only sweeps (pre-solves, extra Poisson sweeps) work in place too.
 //
 // The isotropic stencils need phi' and psi' of the eight neighbours at the
-// current step, i.e. moments of their arrivals; in place, a neighbouring
-// workgroup may already have overwritten them.  A pre-pass (k_aa_hood)
-// therefore writes phi' and psi' of every node to two planes first, with the
-// arithmetic of the two-buffer sweep's stencil ring, and the sweep reads the
-// 3 x 3 neighbourhood from them.  The planes are in the working type (FP64
-// with FP32 storage, as the two-buffer sweep's rings hold them): 16 B per
-// cell of memory, and ~90 B per lattice update of traffic with FP32 storage
-// (the pre-pass reads the h and g arrivals and writes the planes, the sweep
-// reads them back).
+// current step, i.e. moments of their arrivals.  The sweep forms them for its
+// own rows in an LDS ring one row ahead, as the two-buffer sweep does; but in
+// place a neighbouring workgroup may already have overwritten the arrivals of
+// the nodes beyond the tile.  A pre-pass (k_aa_hood) therefore writes phi'
+// and psi' of every tile's edge nodes (first and last row of each band, first
+// and last column of each strip) to two planes first, with the same
+// arithmetic, and the sweep takes its halo from them.  The planes are in the
+// working type (FP64 with FP32 storage): 16 B per cell of memory; the
+// pre-pass reads the h and g arrivals of about 2 / band height of the nodes.
 //
 // This form covers the plain sweep with FP64 and FP32 storage (no side walls,
 // no local field of Eq. 50, no 16-bit node-local references).
@@ -105,37 +105,12 @@ struct SimDescAA {
   int par, gpar;
 };
 
-// phi' / psi' neighbourhood of (k.c, y) from the planes of the pre-pass,
-// with the stencil ghosts of the two-buffer sweep at the electrodes.
-template <class W, class R, class K>
-__device__ inline void hood_aa(const W* __restrict__ phiP, const W* __restrict__ psiP,
-                               const KP<R>& kp, K k, int y, W phi9[9], W psi9[9]) {
-  const bool periodic = kp.walls == WALL_PERIODIC;
-  const int cols[3] = {k.m, k.c, k.p};
-  W ph[3][3], ps[3][3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    int yy = y + r - 1;
-    if (yy < 0 || yy >= kp.ny) {
-      if (!periodic) continue;
-      yy = yy < 0 ? yy + kp.ny : yy - kp.ny;
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      ph[r][j] = *elem(phiP, (uint32_t)yy * kp.pitch + cols[j]);
-      ps[r][j] = *elem(psiP, (uint32_t)yy * kp.pitch + cols[j]);
-    }
-  }
-  if (!periodic) {
-    if (y == 0) ghost_row(ph[1], ps[1], ph[0], ps[0]);
-    if (y == kp.ny - 1) ghost_row(ph[1], ps[1], ph[2], ps[2]);
-  }
-  nine(ph[0], ph[1], ph[2], phi9);
-  nine(ps[0], ps[1], ps[2], psi9);
-}
-
-// The pre-pass: phi' and psi' of every node of the tile at this step, the
-// same sums the two-buffer sweep forms in its stencil ring.
+// The pre-pass: phi' and psi' at this step of the nodes that a neighbouring
+// tile's stencils reach, i.e. the first and last row of every band and the
+// first and last column of every strip (the sweep forms the others itself in
+// its LDS ring, one row ahead), with the sums of the two-buffer sweep's
+// ring.  In place, a neighbouring workgroup may overwrite such a node's
+// arrivals before the stencil needs them.
 template <class S, class R, class T0, int NW>
 __global__ __launch_bounds__(64 * NW) void k_aa_hood(const SimDescAA<S, R, T0>* __restrict__ sims,
                                                      const BatchTile* __restrict__ tiles,
@@ -145,12 +120,16 @@ __global__ __launch_bounds__(64 * NW) void k_aa_hood(const SimDescAA<S, R, T0>* 
   if (tl.sim < 0) return;
   const SimDescAA<S, R, T0>& sd = sims[tl.sim];
   const KP<R>& kp = sd.kp;
-  const int x = tl.x0 + (int)threadIdx.x;
+  const int lane = (int)threadIdx.x;
+  const int x = tl.x0 + lane;
   if (x >= kp.nx) return;
+  const int w = min(64 * NW, kp.nx - tl.x0);
+  const bool edge_col = lane == 0 || lane == w - 1;
   const int par = (sd.par + flip) & 1, gpar = (sd.gpar + gflip) & 1;
   const AAView<S, R> V{PopView<S, R>{make_rsrc(sd.pop, kp.pop_bytes), &kp, false}};
   const ColsP k = cols_for<0>(x, kp.nx, 0);
   for (int y = tl.y0; y < tl.yend; ++y) {
+    if (!(edge_col || y == tl.y0 || y == tl.yend - 1)) continue;
     const uint32_t jo = (uint32_t)y * kp.pitch + x;
     R h[9], g4[4];
 #pragma unroll
@@ -165,13 +144,13 @@ __global__ __launch_bounds__(64 * NW) void k_aa_hood(const SimDescAA<S, R, T0>* 
 // Per-node update of the in-place sweep: the arithmetic of update_node (the
 // two-buffer sweep, plain form, 4- and 8-byte storage) in the same order,
 // with the stores of the AA orientations.
-template <class S, class R, class T0, bool STD, class K>
+template <class S, class R, class T0, bool STD, class HG, class K>
 __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
                                       R* __restrict__ jprev, T0* __restrict__ h0x,
                                       const KP<R>& kp, const KP<typename WorkOf<S>::type>& kpw,
                                       int x, int y, K k, const typename WorkOf<S>::type phi9[9],
-                                      const typename WorkOf<S>::type psi9[9], R f[9], R h[9],
-                                      R p[5], R n[5], R g[5]) {
+                                      const typename WorkOf<S>::type psi9[9], R f[9], R p[5],
+                                      R n[5], R g0, const HG& hg) {
   typedef typename WorkOf<S>::type W;
   W fw[9], pw[5], nw[5], ps9[9];
 #pragma unroll
@@ -201,6 +180,9 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
   }
 
   {  // g: Eq. (44)-(47); anti-bounce-back with the electrode potential
+    R g[5];
+    g[0] = g0;
+    hg.g4(g + 1);
     W gw[5] = {(W)g[0], (W)g[1], (W)g[2], (W)g[3], (W)g[4]};
     collide_g<STD>(gw, m.psid, poisson_source<W>(m.rhoe, m.ieps, m.geps, m.gpsi, kpw), kpw);
 #pragma unroll
@@ -235,6 +217,8 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
     *elem(jprev, jo) = Jx;
     *elem(jprev, jpl + jo) = Jy;
     const T0 h0in = *elem(h0x, jo);
+    R h[9];
+    hg.h9(h);
     // the node's phi content: its rest plus its incoming h (see RestOf)
     RestAcc<T0> mass = RestAcc<T0>::from_rest(h0in);
 #pragma unroll
@@ -255,46 +239,121 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
   }
 }
 
-// The fused in-place sweep: one workgroup per tile of the list (as the
-// two-buffer sweep), every node of a row of the tile independent of the
-// others (no LDS, no barrier).  `flip` / `gflip` = 1 turns every member's
-// orientation of f, h, p, n / of g (odd steps of a captured block).  STD:
-// the default MRT rates compiled in, as in the two-buffer sweep.
+// The fused in-place sweep: one workgroup per tile of the list, walking its
+// band row by row as the two-buffer sweep does.  phi' and psi' of the
+// tile's own rows come from its LDS ring, formed one row ahead from the
+// arrivals, whose h1-h8 and g1-g4 are parked in LDS for the row's update;
+// those of the rows and columns beyond the tile (its neighbours' edge nodes,
+// which they may already have updated in place) from the pre-pass planes.
+// A node reads and writes only its own slots of the buffer (the AA
+// pattern), so updating a row leaves the arrivals of the next one intact.
+// `flip` / `gflip` = 1 turns every member's orientation of f, h, p, n / of g
+// (odd steps of a captured block).  STD: the default MRT rates compiled in.
 template <class S, class R, class T0, int NW, bool STD>
 __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
     const SimDescAA<S, R, T0>* __restrict__ sims, const BatchTile* __restrict__ tiles,
     int xcd_chunk, int flip, int gflip) {
   typedef typename WorkOf<S>::type W;
+  constexpr int TW = 64 * NW;
+  __shared__ SweepLds<S, R, TW> L;
   const BatchTile tl = tiles[xcd_tile(xcd_chunk)];
   if (tl.sim < 0) return;
   const SimDescAA<S, R, T0>& sd = sims[tl.sim];
   const KP<R>& kp = sd.kp;
-  const int x = tl.x0 + (int)threadIdx.x;
-  if (x >= kp.nx) return;
+  const int nx = kp.nx, ny = kp.ny, x0 = tl.x0, y0 = tl.y0, yend = tl.yend;
+  const int w = min(TW, nx - x0);
+  const int lane = (int)threadIdx.x;
+  const bool valid = lane < w;
+  const int x = x0 + (valid ? lane : 0);
+  const bool periodic = kp.walls == WALL_PERIODIC;
   const int par = (sd.par + flip) & 1, gpar = (sd.gpar + gflip) & 1;
   constexpr bool kNT = 64 * NW * sizeof(S) >= 1024;
   const AAView<S, R> V{PopView<S, R>{make_rsrc(sd.pop, kp.pop_bytes), &kp, kNT}};
-  const ColsP k = cols_for<0>(x, kp.nx, 0);
-  for (int y = tl.y0; y < tl.yend; ++y) {
-    W phi9[9], psi9[9];
-    hood_aa(sd.phiP, sd.psiP, kp, k, y, phi9, psi9);
-    R f[9], h[9], p[5], n[5], g[5];
-    __builtin_amdgcn_s_setprio(2);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = V.in(par, QF, i, k, y);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      p[i] = V.in(par, QP, i, k, y);
-      n[i] = V.in(par, QN, i, k, y);
-      g[i] = V.in(gpar, QG, i, k, y);
+  const ColsP k = cols_for<0>(x, nx, 0);
+  // halo columns (lanes 0 and 1): x0 - 1 and x0 + w, periodic in x
+  const int xh = lane == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + w == nx ? 0 : x0 + w);
+  const int kcol = lane == 0 ? 0 : w + 1;
+  auto slot = [&](int yy) { return (yy - y0 + 1) % RING; };
+  // phi', psi' of row yy into the ring: the tile's own rows from the
+  // arrivals (parked for the update), the rows beyond the band and the halo
+  // columns from the planes
+  auto ring_row = [&](int yy) {
+    const int ys = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+    const int sl = slot(yy);
+    if (lane < 2) {
+      const uint32_t jo = (uint32_t)ys * kp.pitch + xh;
+      L.phi[sl][kcol] = *elem(sd.phiP, jo);
+      L.psi.set(sl, kcol, *elem(sd.psiP, jo));
     }
-    h[0] = R(0);
+    if (!valid) return;
+    const uint32_t jo = (uint32_t)ys * kp.pitch + x;
+    if (yy < y0 || yy >= yend) {
+      L.phi[sl][lane + 1] = *elem(sd.phiP, jo);
+      L.psi.set(sl, lane + 1, *elem(sd.psiP, jo));
+      return;
+    }
+    R h[9], g4[4];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
+    for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, ys);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, ys);
+    L.phi[sl][lane + 1] = phi_of<W>((W)rest_val(*elem(sd.h0, jo)), h);
+    L.psi.set(sl, lane + 1, psi_as<W>(g4));
+    const int b = (yy - y0 + 2) & 1;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = h[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = g4[i];
+  };
+
+  if (y0 > 0 || periodic) ring_row(y0 - 1);
+  ring_row(y0);
+  for (int y = y0; y < yend; ++y) {
+    const bool up = y + 1 < ny || periodic;
+    const bool down = y > 0 || periodic;
+    R f[9], p[5], n[5];
+    R g0 = R(0);
+    __builtin_amdgcn_s_setprio(2);
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = V.in(par, QF, i, k, y);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        p[i] = V.in(par, QP, i, k, y);
+        n[i] = V.in(par, QN, i, k, y);
+      }
+      g0 = V.in(gpar, QG, 0, k, y);
+    }
+    if (up) ring_row(y + 1);
     __builtin_amdgcn_s_setprio(0);
-    update_node_aa<S, R, T0, STD>(V, par, gpar, sd.jprev, sd.h0, kp, sd.kpw, x, y, k, phi9, psi9, f,
-                             h, p, n, g);
+    __syncthreads();
+    if (valid) {
+      const int c = lane + 1, sc = slot(y);
+      W phC[3] = {L.phi[sc][c - 1], L.phi[sc][c], L.phi[sc][c + 1]};
+      W psC[3] = {L.psi.get(sc, c - 1), L.psi.get(sc, c), L.psi.get(sc, c + 1)};
+      W phU[3], phD[3], psU[3], psD[3];
+      if (up) {
+        const int su = slot(y + 1);
+        phU[0] = L.phi[su][c - 1]; phU[1] = L.phi[su][c]; phU[2] = L.phi[su][c + 1];
+        psU[0] = L.psi.get(su, c - 1); psU[1] = L.psi.get(su, c); psU[2] = L.psi.get(su, c + 1);
+      } else {
+        ghost_row(phC, psC, phU, psU);
+      }
+      if (down) {
+        const int sd0 = slot(y - 1);
+        phD[0] = L.phi[sd0][c - 1]; phD[1] = L.phi[sd0][c]; phD[2] = L.phi[sd0][c + 1];
+        psD[0] = L.psi.get(sd0, c - 1); psD[1] = L.psi.get(sd0, c); psD[2] = L.psi.get(sd0, c + 1);
+      } else {
+        ghost_row(phC, psC, phD, psD);
+      }
+      W phi9[9], psi9[9];
+      nine(phD, phC, phU, phi9);
+      nine(psD, psC, psU, psi9);
+      const HGLds<R, TW> hg{L.pull[(y - y0 + 2) & 1], lane};
+      update_node_aa<S, R, T0, STD>(V, par, gpar, sd.jprev, sd.h0, kp, sd.kpw, x, y, k, phi9,
+                                    psi9, f, p, n, g0, hg);
+    }
   }
 }
 
