@@ -175,15 +175,16 @@ typedef struct {
                               sweep takes the stencils' neighbourhoods (in place a
                               neighbouring workgroup may already have overwritten the
                               populations they are moments of). */
-  int32_t ion_q9;          /* 0: the ion LBEs on D2Q5 (Sec. 4.3 uses D2Q5 for them);
-                              1: on D2Q9 with the weights of Eq. (25) and the
-                              equilibria, sources and MRT rates of Eq. (34)-(38) and
-                              (47) extended to nine velocities (8 more lines per
-                              lattice row, 344 instead of 280 bytes per node update
-                              with FP32 storage).  FP64 and FP32 storage (LBM_FP64,
-                              LBM_FP32, LBM_FP32_F64), electrodes, insulating or
-                              y-periodic walls, no side walls, no local field, two
-                              buffers */
+  int32_t ion_q9;          /* 0: the ion LBEs on D2Q5 (weights of Eq. (26), matrix N
+                              of Eq. (46); 33 populations per node, the default);
+                              1: on D2Q9 as Eq. (34)-(38) write them, with the
+                              weights of Eq. (25) and the matrix M of Eq. (28) (8
+                              more lines per lattice row, 344 instead of 280 bytes
+                              per node update with FP32 storage).  FP64 and FP32
+                              storage (LBM_FP64, LBM_FP32, LBM_FP32_F64), electrodes,
+                              insulating or y-periodic walls, with or without side
+                              walls (where the ions bounce back), no local field,
+                              two buffers */
   int32_t reserved;        /* 0 */
 } lbm_ehd_params;
 

@@ -144,13 +144,14 @@ bool std_rates(const lbm_ehd_params& p) {
 
 // Form of the sweep a simulation runs on, each compiled separately: 0 plain,
 // 1 with side walls, 2 with side walls and the local field of Eq. (50), 3
-// in-place streaming (plain), 4 plain with the ions on D2Q9; forms 0, 1, 3
-// and 4 with the default MRT rates compiled in are NFORM higher (5, 6, 8,
-// 9).
-constexpr int NFORM = 5;
+// in-place streaming (plain), 4 plain with the ions on D2Q9, 5 side walls
+// with the ions on D2Q9; all but 2 with the default MRT rates compiled in
+// are NFORM higher.
+constexpr int NFORM = 6;
 int sweep_form(const lbm_ehd_params& p) {
-  const int base =
-      p.inplace ? 3 : (p.ion_q9 ? 4 : (p.local_field ? 2 : (p.side_walls ? 1 : 0)));
+  const int base = p.inplace ? 3
+                 : p.ion_q9  ? (p.side_walls ? 5 : 4)
+                             : (p.local_field ? 2 : (p.side_walls ? 1 : 0));
   return base + (base != 2 && std_rates(p) ? NFORM : 0);
 }
 
@@ -398,11 +399,17 @@ struct Form {
     switch (form) {
       case 4:
       case 4 + NFORM:
+      case 5:
+      case 5 + NFORM:
         if constexpr (kAA) {  // (4- and 8-byte storage only, as in place)
           if (form == 4)
             launch_ext<3>(waves, descs, tiles, ntiles, flip, st);
-          else
+          else if (form == 4 + NFORM)
             launch_ext<3, true>(waves, descs, tiles, ntiles, flip, st);
+          else if (form == 5)
+            launch_ext<4>(waves, descs, tiles, ntiles, flip, st);
+          else
+            launch_ext<4, true>(waves, descs, tiles, ntiles, flip, st);
         }
         break;
       case 2: launch_ext<2>(waves, descs, tiles, ntiles, flip, st); break;
@@ -979,11 +986,9 @@ lbm_status validate(const lbm_ehd_params* p) {
   if (p->diag_every < 0) return fail(LBM_EINVAL, "diag_every < 0");
   if (p->inplace != 0 && p->inplace != 1) return fail(LBM_EINVAL, "inplace: 0 or 1");
   if (p->ion_q9 != 0 && p->ion_q9 != 1) return fail(LBM_EINVAL, "ion_q9: 0 or 1");
-  if (p->ion_q9 && (elem_size(p->precision) == 2 || p->side_walls || p->local_field ||
-                    p->inplace))
+  if (p->ion_q9 && (elem_size(p->precision) == 2 || p->local_field || p->inplace))
     return fail(LBM_EINVAL,
-                "ions on D2Q9: FP64 or FP32 storage, the plain sweep (no side walls, no local "
-                "field, two buffers)");
+                "ions on D2Q9: FP64 or FP32 storage, two buffers, no local field");
   if (p->inplace && elem_size(p->precision) == 2)
     return fail(LBM_EINVAL, "in-place streaming needs FP64 or FP32 storage");
   if (p->inplace && (p->side_walls || p->local_field || p->poisson_tol > 0))

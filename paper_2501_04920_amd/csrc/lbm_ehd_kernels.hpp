@@ -10,7 +10,7 @@
 // draw ~15 % more bandwidth than independent single-wave strips).  phi and
 // psi, needed at the eight neighbours for the isotropic stencils (Eq. 59),
 // are the moments of the *pulled* h and g of those neighbours, so the
-// workgroup computes them one row ahead into a small LDS ring (5 rows x
+// workgroup computes them one row ahead into a small LDS ring (4 rows x
 // 64 NW + 2 columns, the two halo columns by threads 0 and 1) and each thread
 // parks the pulled h and g of its node in LDS for the row's own update.
 // Every population is read once and written once per step; only h and g of
@@ -45,19 +45,25 @@ struct ColsP {
 };
 // the form of the sweep that also has the local field of Eq. (50)
 struct ColsL : Cols {};
-// the plain form with the ions on D2Q9 (Eq. 34-38 as printed)
+// the plain form with the ions on D2Q9 (Eq. 34-38 as printed), and the form
+// with side walls and the ions on D2Q9
 struct ColsP9 : ColsP {};
+struct ColsS9 : Cols {};
 
 // Column type of sweep form EXT: 0 plain, 1 side walls, 2 side walls and the
-// local field, 3 plain with the ions on D2Q9.
+// local field, 3 plain with the ions on D2Q9, 4 side walls with the ions on
+// D2Q9.
 template <int EXT>
 using ColsOf = typename std::conditional<
     EXT == 0, ColsP,
-    typename std::conditional<EXT == 1, Cols,
-                              typename std::conditional<EXT == 2, ColsL, ColsP9>::type>::type>::type;
+    typename std::conditional<
+        EXT == 1, Cols,
+        typename std::conditional<
+            EXT == 2, ColsL,
+            typename std::conditional<EXT == 3, ColsP9, ColsS9>::type>::type>::type>::type;
 template <class K>
 constexpr bool ion9_of() {
-  return std::is_same<K, ColsP9>::value;
+  return std::is_same<K, ColsP9>::value || std::is_same<K, ColsS9>::value;
 }
 
 template <int EXT>
@@ -66,7 +72,7 @@ __device__ inline ColsOf<EXT> cols_for(int xc, int nx, int side) {
   k.c = xc;
   k.m = xc == 0 ? nx - 1 : xc - 1;
   k.p = xc == nx - 1 ? 0 : xc + 1;
-  if constexpr (EXT == 1 || EXT == 2) {
+  if constexpr (EXT == 1 || EXT == 2 || EXT == 4) {
     k.lw = side && xc == 0;
     k.rw = side && xc == nx - 1;
   }
@@ -76,14 +82,17 @@ __device__ inline ColsOf<EXT> cols_for(int xc, int nx, int side) {
 __device__ inline Cols cols_of(int xc, int nx, int side) { return cols_for<1>(xc, nx, side); }
 
 // The diagonal directions 5-8 of a D2Q9 ion set whose diagonals sit in lines
-// q9..q9+3 (no side walls): x[0..3] = directions 5..8.
+// q9..q9+3: x[0..3] = directions 5..8.  At a side wall the ions bounce back:
+// a diagonal coming through the wall is the node's own opposite one, read
+// through the same load two lines up or down (lines are pitch apart).
 template <class S, class R, class K>
 __device__ inline void pull_diag(const PopView<S, R>& P, int q9, K k, int yy, R x[4]) {
-  const uint32_t rm = P.row(yy), rp = P.row(yy + 2);
-  x[0] = P.at(q9 + 0, rm + k.m);
-  x[1] = P.at(q9 + 1, rm + k.p);
-  x[2] = P.at(q9 + 2, rp + k.p);
-  x[3] = P.at(q9 + 3, rp + k.m);
+  const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
+  const uint32_t pc = P.kp->pitch, own = r0 + k.c;
+  x[0] = P.at(q9 + 0, k.lw ? own + 2 * pc : rm + k.m);  // <- 7
+  x[1] = P.at(q9 + 1, k.rw ? own + 2 * pc : rm + k.p);  // <- 8
+  x[2] = P.at(q9 + 2, k.rw ? own - 2 * pc : rp + k.p);  // <- 5
+  x[3] = P.at(q9 + 3, k.lw ? own - 2 * pc : rp + k.m);  // <- 6
 }
 // Deviation content of the diagonals of the ion set at line q9 (0 unless
 // the ions are on D2Q9), for the helpers outside the hot loop.
@@ -789,7 +798,7 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
     p[1] = t4[0]; p[2] = t4[1]; p[3] = t4[2]; p[4] = t4[3];
     pull4(Ph, QN, k, y, t4);
     n[1] = t4[0]; n[2] = t4[1]; n[3] = t4[2]; n[4] = t4[3];
-    if constexpr (EXT == 3) {  // the D2Q9 ions' diagonals
+    if constexpr (EXT == 3 || EXT == 4) {  // the D2Q9 ions' diagonals
       pull_diag(Ph, QP9, k, y, t4);
       p[5] = t4[0]; p[6] = t4[1]; p[7] = t4[2]; p[8] = t4[3];
       pull_diag(Ph, QN9, k, y, t4);
@@ -1114,8 +1123,8 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
       xt = x;
       if (q >= QH && q < QP && !corner) {
         qt = q - i + mir9[i];
-      } else {
-        qt = q - i + (q < QP ? opp9[i] : opp5[i]);
+      } else {  // (lines from QP9 on: the diagonals of D2Q9 ions, direction i - 5)
+        qt = q - i + ((q < QP || q >= QP9) ? opp9[i] : opp5[i]);
         yt = y;
       }
     } else {

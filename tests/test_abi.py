@@ -64,7 +64,7 @@ def test_defaults_and_bytes():
                                  dict(inplace=1, poisson_tol=1e-6, poisson_iters=1,
                                       poisson_max=4),
                                  dict(ion_q9=2), dict(ion_q9=1, precision=2),
-                                 dict(ion_q9=1, precision=3), dict(ion_q9=1, side_walls=1),
+                                 dict(ion_q9=1, precision=3),
                                  dict(ion_q9=1, local_field=1), dict(ion_q9=1, inplace=1),
                                  dict(nx=20000, ny=20000)])
 def test_invalid_parameters_rejected(bad):

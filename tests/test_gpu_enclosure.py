@@ -44,9 +44,10 @@ def test_enclosure_against_oracle(poisson_form):
 # After 160 000 steps (the steady droplet): D absolute, the norms of rho_e and
 # |u| and the subsampled end fields rel-L2.  FP32 storage is held to the FP32
 # bar of 2e-5 on every field over this run, eight times the 20 000 steps the
-# bar was set for.  (With the h collision in FP32 arithmetic the slow, nearly
-# steady flow carried its rounding into the velocity, 3.0e-5; the collision
-# runs in FP64 since.)
+# bar was set for.  (The slow, nearly steady flow integrates any rounding that
+# is the same at every step: with the h collision in FP32 arithmetic it
+# carried 3.0e-5 into the velocity, with the psi' stencil ring rounded to
+# FP32 2.0e-5; both are kept to FP64 precision since.)
 LONG_BAR = {
     "fp64": dict(D=1e-10, rhoe_l2=1e-10, u_l2=1e-10, phi=1e-10, psi=1e-10, cp=1e-10,
                  cm=1e-10, rhoe=1e-10, ux=1e-10, uy=1e-10, p=1e-10),

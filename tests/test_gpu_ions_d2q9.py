@@ -1,9 +1,11 @@
 """The ion LBEs on D2Q9 (lbm_ehd_params.ion_q9 = 1) against the CPU oracle
 run with the same option.
 
-* FP64 storage on the 128^2 droplet case and on ragged variants of the
-  plain sweep (rel-L2 <= 1e-10 on every field);
-* FP32 storage on the ragged case (the FP32 bar, 2e-5, after 200 steps);
+* FP64 storage on the 128^2 droplet case, on ragged variants with and
+  without side walls, and on the enclosure of Sec. 6 (rel-L2 <= 1e-10 on
+  every field);
+* FP32 storage on the ragged case with and without side walls and on the
+  enclosure (the FP32 bar, 2e-5);
 * D2Q9 ions differ from D2Q5 ions (the option is not a no-op) while phi is
   conserved to rounding;
 * batches that mix D2Q9 and D2Q5 members give every member bitwise its
@@ -57,6 +59,10 @@ VARIANTS = {
     "ratios": dict(rho_r=2.0, eta_r=3.0, mu_r=0.5, m_ratio=1.5, eps_r=0.5),
     "bgk_masks": dict(mask_f=0x1FF, mask_h=0x1FF, mask_p=0x1FF, mask_n=0x1FF, mask_g=0x1F),
     "s_free": dict(s_free=1.3),
+    "side_walls": dict(side_walls=1),
+    "side_walls_insulating": dict(side_walls=1, walls=1),
+    "side_walls_periodic": dict(side_walls=1, walls=2),
+    "side_walls_bgk": dict(side_walls=1, mask_p=0x1FF, mask_n=0x1FF),
 }
 
 
@@ -72,14 +78,29 @@ def test_ragged_variants_ions_d2q9_fp64(name):
     sim.close()
 
 
+@pytest.mark.parametrize("side_walls", [0, 1])
 @pytest.mark.parametrize("precision", ["fp32", "fp32f64"])
-def test_ragged_ions_d2q9_fp32_storage(precision):
-    p, d = _ragged()
+def test_ragged_ions_d2q9_fp32_storage(precision, side_walls):
+    p, d = _ragged(side_walls=side_walls)
     sim = run_gpu(p, precision, droplet=d, presolve=10, steps=200)
     o = run_oracle(p, droplet=d, presolve=10, steps=200)
     errs = rel_l2(sim.fields(), o.fields(), p, ALL10)
-    _report("ragged ions d2q9 %s" % precision, errs)
+    _report("ragged ions d2q9 %s side walls %d" % (precision, side_walls), errs)
     assert max(errs.values()) <= 2e-5
+    sim.close()
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_enclosure_ions_d2q9(precision, bar):
+    """The enclosure of Sec. 6 (256^2, side walls, electrodes) with the ions
+    on D2Q9: 2000 pre-solve sweeps and 1000 steps against the oracle."""
+    case = workloads.enclosure(256)
+    p, d = dict(case["params"], ion_q9=1), case["droplet"]
+    sim = run_gpu(p, precision, droplet=d, presolve=2000, steps=1000)
+    o = run_oracle(p, droplet=d, presolve=2000, steps=1000)
+    errs = rel_l2(sim.fields(), o.fields(), p, ALL10)
+    _report("enclosure ions d2q9 %s" % precision, errs)
+    assert max(errs.values()) <= bar
     sim.close()
 
 
@@ -100,25 +121,27 @@ def test_d2q9_ions_differ_from_d2q5_and_conserve():
         s.close()
 
 
-def _member(nx, ny, r, seed, q9, precision):
+def _member(nx, ny, r, seed, q9, precision, side=0):
     p = workloads.lattice_params(ny, r, nx=nx)
-    s = lbm_ehd.Simulation(dict(p, precision=precision, ion_q9=q9), device="cuda:0")
+    s = lbm_ehd.Simulation(dict(p, precision=precision, ion_q9=q9, side_walls=side),
+                           device="cuda:0")
     s.init_droplet((nx - 1) / 2 + 0.3, (ny - 1) / 2 - 0.2, r, 1e-3, seed, presolve=6)
     return s
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_ions_d2q9_batch_equals_members_alone(precision):
-    shapes = [(64, 64, 10.0, 1, 1), (100, 70, 12.0, 2, 0), (128, 96, 15.0, 3, 1),
-              (37, 41, 6.0, 4, 1)]
+    shapes = [(64, 64, 10.0, 1, 1, 0), (100, 70, 12.0, 2, 0, 0), (128, 96, 15.0, 3, 1, 1),
+              (37, 41, 6.0, 4, 1, 0), (90, 60, 11.0, 5, 0, 1)]
     steps = 37
     alone = []
-    for nx, ny, r, seed, q9 in shapes:
-        s = _member(nx, ny, r, seed, q9, precision)
+    for nx, ny, r, seed, q9, side in shapes:
+        s = _member(nx, ny, r, seed, q9, precision, side)
         s.step(steps)
         alone.append(s.fields())
         s.close()
-    sims = [_member(nx, ny, r, seed, q9, precision) for nx, ny, r, seed, q9 in shapes]
+    sims = [_member(nx, ny, r, seed, q9, precision, side)
+            for nx, ny, r, seed, q9, side in shapes]
     b = lbm_ehd.Batch(sims)
     b.set_launch(2, 8)
     b.run(16)
