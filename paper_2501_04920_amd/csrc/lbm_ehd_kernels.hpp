@@ -733,16 +733,18 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
 
   auto slot = [&](int yy) { return (yy - y0 + 1) % RING; };
   // phi', psi' of row yy into the ring; each thread's own pulls are parked
-  // in LDS.  The h and g lines of the ring rows are loaded cached with 4-byte
-  // storage, and with 8-byte storage those of the two ring rows at each end
-  // of the band, which the neighbouring band (put on the same XCD soon after
-  // by the tile order) pulls too; the others non-temporal.  Measured on
+  // in LDS.  The h and g lines of the ring rows are loaded cached with FP32
+  // storage and arithmetic; with FP64 storage, or FP32 storage and FP64
+  // arithmetic, those of the two ring rows at each end of the band, which the
+  // neighbouring band (put on the same XCD soon after by the tile order) pulls
+  // too; the others non-temporal.  Measured on
   // MI355X at 2048^2 against all non-temporal: the end rows cached, FP32
   // +1.7 % (bands of 16) / +3.1 % (bands of 8), FP64 +1.1 %, FP16 -0.4 % (and
   // -7 % for the batched FP16 droplets of 128^2 to 1024^2, whose short bands
   // make most ring rows edge rows); every ring row cached, FP32 +2.7 %, FP16
-  // -2.6 %, FP64 -4 % (and FP32 +0.8 % over the end rows only, with the
-  // specialised sweep and 280 B/LUP).
+  // -2.6 %, FP64 -4 % (and, with the specialised sweep and 280 B/LUP, FP32
+  // +0.8 % but FP32 storage with FP64 arithmetic -2.6 % over the end rows
+  // only).
   auto ring_row = [&](int yy) {
     const int ys = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
     const int sl = slot(yy);
@@ -769,7 +771,7 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
         for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = g4[i];
       }
     };
-    if (kNT && (sizeof(S) == 4 || (sizeof(S) == 8 && (yy <= y0 || yy >= yend - 1))))
+    if (kNT && ((sizeof(S) == 4 && sizeof(R) == 4) || (sizeof(S) >= 4 && (yy <= y0 || yy >= yend - 1))))
       pulls(Pc);
     else
       pulls(Ph);
