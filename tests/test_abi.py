@@ -52,6 +52,23 @@ def test_defaults_and_bytes():
     pop, aux = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(precision="bf16"))
     assert pop == 34 * 130 * 128 * 2 and aux == 128 * 128 * (2 * 4 + 2 * 3 * 8)
     assert lbm_ehd.lbm_ehd_bytes_per_lup("fp64") == 2 * 32 * 8 + 2 * 8 + 2 * 16
+    # FP32 storage with FP64 arithmetic: the fixed-point rest, (phi u) in FP64
+    assert lbm_ehd.lbm_ehd_bytes_per_lup("fp32f64") == 2 * 32 * 4 + 2 * 4 + 2 * 16 == 296
+    pop, aux = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(precision="fp32f64"))
+    assert pop == 33 * 130 * 128 * 4 and aux == 128 * 128 * (2 * 8 + 2 * 4)
+
+
+def test_buffer_sizes_follow_the_layout():
+    """The population buffer grows by the eight diagonal lines with D2Q9
+    ions, keeps its size in place, and doubles with 8-byte storage."""
+    sizes = {}
+    for name, kw in (("fp32", {}), ("fp32_q9", dict(ion_q9=1)), ("fp32_inplace", dict(inplace=1)),
+                     ("fp64", dict(precision="fp64")),
+                     ("fp32_q9_side", dict(ion_q9=1, side_walls=1))):
+        sizes[name] = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(**kw))
+    assert sizes["fp32_q9"][0] == sizes["fp32"][0] * 41 // 33 == sizes["fp32_q9_side"][0]
+    assert sizes["fp32_inplace"][0] == sizes["fp32"][0]
+    assert sizes["fp64"][0] == 2 * sizes["fp32"][0]
 
 
 @pytest.mark.parametrize("bad", [dict(nx=1), dict(v_th=0.0), dict(eta_v=0.0), dict(M_phi=0.0),
