@@ -442,6 +442,13 @@ struct PopView {
     Codec<S, R>::st(rs, off * (uint32_t)sizeof(S), (uint32_t)q * kp->pitch * (uint32_t)sizeof(S),
                     v);
   }
+  // the 16-bit pattern stored in line q (16-bit storage only)
+  __device__ inline unsigned short bits(int q, uint32_t off) const {
+    static_assert(sizeof(S) == 2, "a 16-bit storage type");
+    const uint32_t v = off * 2u, s = (uint32_t)q * kp->pitch * 2u;
+    return nt ? __builtin_amdgcn_raw_buffer_load_b16(rs, v, s, LD_NT)
+              : __builtin_amdgcn_raw_buffer_load_b16(rs, v, s, 0);
+  }
   // the value v takes once stored in line q (and loaded back)
   __device__ inline R stored(int q, R v) const {
     if constexpr (Scaled<S>::value) {

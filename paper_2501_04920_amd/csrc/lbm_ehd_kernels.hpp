@@ -129,10 +129,10 @@ __device__ inline void pull9(const PopView<S, R>& P, int q0, K k, int yy, R x[9]
 // QJX, QJY); 0 for populations that come through a ghost row; for one
 // reflected at a side wall (the node's own population of the opposite
 // direction) the node's own reference of that direction.
-template <class S, class R, class K>
+template <class S, class R, class K, bool REFS = true>
 __device__ inline void pull_f(const PopView<S, R>& P, K k, int yy, R x[9]) {
   pull9(P, QF, k, yy, x);
-  if constexpr (LocalF<S>::value) {
+  if constexpr (LocalF<S>::value && REFS) {
     const uint32_t rm = P.row(yy), r0 = P.row(yy + 1), rp = P.row(yy + 2);
     const bool gd = yy == 0, gu = yy == P.kp->ny - 1;  // sources in a ghost row
     const uint32_t own = r0 + k.c;
@@ -159,6 +159,48 @@ __device__ inline void pull_f(const PopView<S, R>& P, K k, int yy, R x[9]) {
     add(7, rp + k.p, gu, k.rw, 5);
     add(8, rp + k.m, gu, k.lw, 6);
   }
+}
+
+// J~ of the nodes of the sweep's ring rows with bfloat16 storage: the 16-bit
+// patterns of lines QJX (low half) and QJY (high half) of each node, loaded
+// once per row of a band instead of once per receiving neighbour (16 loads
+// per node otherwise).  Other storage types keep no J~.
+template <bool ON, int TW>
+struct JRing {};
+template <int TW>
+struct JRing<true, TW> {
+  uint32_t v[RING][TW + 2];
+};
+template <class S, class R>
+__device__ inline uint32_t j_bits(const PopView<S, R>& P, int yy, int xc) {
+  const uint32_t o = P.row(yy + 1) + xc;
+  return (uint32_t)P.bits(QJX, o) | ((uint32_t)P.bits(QJY, o) << 16);
+}
+// The references of pull_f added to an f set pulled without them, with each
+// sender's J~ taken from the ring: column c of slots sd, sc, su (rows yy - 1,
+// yy, yy + 1).  The same sums, in the same order, as pull_f.
+template <int TW, class K>
+__device__ inline void add_f_refs(const JRing<true, TW>& J, int sd, int sc, int su, int c,
+                                  int yy, int ny, K k, float x[9]) {
+  const bool gd = yy == 0, gu = yy == ny - 1;  // sources in a ghost row
+  const uint32_t own = J.v[sc][c];
+  auto jx = [](uint32_t b) { return __uint_as_float(b << 16); };
+  auto jy = [](uint32_t b) { return __uint_as_float(b & 0xFFFF0000u); };
+  auto one = [&](int i, uint32_t b, bool ghost, bool bb, int opp) {
+    if (bb) {
+      x[i] += f_ref(opp, jx(own), jy(own));
+    } else if (!ghost) {
+      x[i] += f_ref(i, jx(b), jy(b));
+    }
+  };
+  one(1, J.v[sc][c - 1], false, k.lw, 3);
+  one(2, J.v[sd][c], gd, false, 4);
+  one(3, J.v[sc][c + 1], false, k.rw, 1);
+  one(4, J.v[su][c], gu, false, 2);
+  one(5, J.v[sd][c - 1], gd, k.lw, 7);
+  one(6, J.v[sd][c + 1], gd, k.rw, 8);
+  one(7, J.v[su][c + 1], gu, k.rw, 5);
+  one(8, J.v[su][c - 1], gu, k.lw, 6);
 }
 
 // Directions 1..4 of a D2Q5 set (the rest population is pulled separately).
@@ -682,12 +724,13 @@ struct PsiRing<float, double, TW> {
 };
 
 // LDS of one sweep workgroup: the phi' ring (in the working type W), the
-// psi' ring and the parked h1-h8, g1-g4.
+// psi' ring, the parked h1-h8, g1-g4 and, with bfloat16 storage, the J~ ring.
 template <class S, class R, int TW>
 struct SweepLds {
   typename WorkOf<S>::type phi[RING][TW + 2];
   PsiRing<S, typename WorkOf<S>::type, TW> psi;
   R pull[2][12][TW];  // pulled h1-8 and g1-4 of a row, by row parity
+  JRing<LocalF<S>::value, TW> jref;
 };
 
 // One tile of the fused sweep: columns [x0, x0 + 64 NW) of rows [y0, yend)
@@ -756,6 +799,7 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
         pull_g(V, kh, ys, gg);
         L.phi[sl][kcol] = phi_of<W>((W)rest_val(hh0), hh);
         L.psi.set(sl, kcol, psi_as<W>(gg));
+        if constexpr (LocalF<S>::value) L.jref.v[sl][kcol] = j_bits(V, ys, kh.c);
       }
       if (valid) {
         R h[9], g4[4];
@@ -764,6 +808,7 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
         pull_g(V, k, ys, g4);
         L.phi[sl][lane + 1] = phi_of<W>((W)rest_val(h0), h);
         L.psi.set(sl, lane + 1, psi_as<W>(g4));
+        if constexpr (LocalF<S>::value) L.jref.v[sl][lane + 1] = j_bits(V, ys, k.c);
         const int b = (yy - y0 + 2) & 1;
 #pragma unroll
         for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = h[i];
@@ -792,7 +837,7 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
     // level, 1 to 3, makes no difference).
     R f[9], p[9], n[9], t4[4];
     __builtin_amdgcn_s_setprio(2);
-    pull_f(Ph, k, y, f);
+    pull_f<S, R, ColsOf<EXT>, false>(Ph, k, y, f);  // (references: after the barrier)
     const uint32_t r0 = Ph.row(y + 1);
     // (the ion rest populations of 16-bit storage are read by the update)
     p[0] = IonRest<S>::value ? R(0) : Ph.at(QP, r0 + x);
@@ -834,6 +879,8 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
       W phi9[9], psi9[9];
       nine(phD, phC, phU, phi9);
       nine(psD, psC, psU, psi9);
+      if constexpr (LocalF<S>::value)
+        add_f_refs(L.jref, slot(y - 1), sc, slot(y + 1), c, y, ny, k, f);
 
       const HGLds<R, TW> hg{L.pull[(y - y0 + 2) & 1], lane};
       update_node<S, R, T0, STD>(D, jprev, h0x, h0dst, kp, kpw, x, y, k, phi9, psi9, f, p, n, g0,
