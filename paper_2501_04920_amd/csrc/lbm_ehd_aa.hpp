@@ -469,7 +469,7 @@ __global__ __launch_bounds__(256) void k_aa_row_sums(const S* __restrict__ src,
                                                      const T0* __restrict__ h0x,
                                                      double* __restrict__ part, const KP<R> kp,
                                                      int par, int gpar) {
-  __shared__ double sh[NSUM][256];
+  __shared__ double sh[NSUM][4];
   const int y = blockIdx.x, t = threadIdx.x;
   const AAView<S, R> V{PopView<S, R>{make_rsrc(src, kp.pop_bytes), &kp, false}};
   double acc[NSUM] = {0, 0, 0, 0, 0, 0, 0};
@@ -501,14 +501,8 @@ __global__ __launch_bounds__(256) void k_aa_row_sums(const S* __restrict__ src,
     acc[5] += phi * y;
     if (!(isfinite(phid) && isfinite(Pd) && isfinite(Qd) && isfinite(psid))) acc[6] += 1.0;
   }
-  for (int j = 0; j < NSUM; ++j) sh[j][t] = acc[j];
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s)
-      for (int j = 0; j < NSUM; ++j) sh[j][t] += sh[j][t + s];
-    __syncthreads();
-  }
-  if (t < NSUM) part[(long long)y * NSUM + t] = sh[t][0];
+  const double r = block_sums<NSUM>(sh, acc, t);
+  if (t < NSUM) part[(long long)y * NSUM + t] = r;
 }
 
 }  // namespace lbm

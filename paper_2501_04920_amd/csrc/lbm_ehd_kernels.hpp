@@ -1246,15 +1246,36 @@ __global__ void k_init(S* __restrict__ dst, R* __restrict__ jprev, T0* __restric
   *elem(jprev, kp.cells + jo) = (R)(phi * uy);
 }
 
+// Sum over the 64 lanes of a wave by a butterfly of lane exchanges, the same
+// fixed order in every call (every lane ends with the sum).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+// The N sums over a 256-thread workgroup of acc[0..N-1]: each wave's by
+// wave_sum, then the four waves' partials (sh: N x 4 doubles of LDS) in a
+// fixed order.  Thread j < N returns sum j.
+template <int N>
+__device__ inline double block_sums(double (*sh)[4], const double acc[N], int t) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double v = wave_sum(acc[j]);
+    if ((t & 63) == 0) sh[j][t >> 6] = v;
+  }
+  __syncthreads();
+  return t < N ? (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]) : 0.0;
+}
+
 // FP64 sums of one row: [phi, rho_e, sum p, sum n, phi x, phi y, nonfinite].
-// One workgroup per row, fixed-shape tree reduction: the result depends on
-// nx and ny only.
+// One 256-thread workgroup per row; wavefront reductions of fixed shape: the
+// result depends on nx and ny only.
 constexpr int NSUM = 7;
 template <class S, class R, class T0>
 __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
                                                   const T0* __restrict__ h0x,
                                                   double* __restrict__ part, const KP<R> kp) {
-  __shared__ double sh[NSUM][256];
+  __shared__ double sh[NSUM][4];
   const int y = blockIdx.x, t = threadIdx.x;
   const PopView<S, R> Ph{make_rsrc(src, kp.pop_bytes), &kp};
   double acc[NSUM] = {0, 0, 0, 0, 0, 0, 0};
@@ -1288,14 +1309,8 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
     acc[5] += phi * y;
     if (!(isfinite(phid) && isfinite(Pd) && isfinite(Qd) && isfinite(psid))) acc[6] += 1.0;
   }
-  for (int j = 0; j < NSUM; ++j) sh[j][t] = acc[j];
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s)
-      for (int j = 0; j < NSUM; ++j) sh[j][t] += sh[j][t + s];
-    __syncthreads();
-  }
-  if (t < NSUM) part[(long long)y * NSUM + t] = sh[t][0];
+  const double r = block_sums<NSUM>(sh, acc, t);
+  if (t < NSUM) part[(long long)y * NSUM + t] = r;
 }
 
 // Column sums of the per-row partial sums [ny][ncol] (ncol <= 64), rows in
@@ -1311,14 +1326,14 @@ __global__ void k_sum_rows(const double* __restrict__ part, int ny, int ncol,
 
 // FP64 sums of one row for the convergence residual of the g-only sweeps:
 // [sum (psi_new - psi_old)^2, sum psi_new^2], psi from the g sets of two
-// buffers (the latest sweep and the one before).  Same fixed-shape tree as
-// k_row_sums.
+// buffers (the latest sweep and the one before).  Same fixed-shape
+// reductions as k_row_sums.
 template <class S, class R>
 __global__ __launch_bounds__(256) void k_psi_change_rows(const S* __restrict__ gnew,
                                                          const S* __restrict__ gold,
                                                          double* __restrict__ part,
                                                          const KP<R> kp) {
-  __shared__ double sh[2][256];
+  __shared__ double sh[2][4];
   const int y = blockIdx.x, t = threadIdx.x;
   const PopView<S, R> Pn{make_rsrc(gnew, kp.pop_bytes), &kp};
   const PopView<S, R> Po{make_rsrc(gold, kp.pop_bytes), &kp};
@@ -1334,17 +1349,9 @@ __global__ __launch_bounds__(256) void k_psi_change_rows(const S* __restrict__ g
     dd += (pn - po) * (pn - po);
     nn += pn * pn;
   }
-  sh[0][t] = dd;
-  sh[1][t] = nn;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) {
-      sh[0][t] += sh[0][t + s];
-      sh[1][t] += sh[1][t + s];
-    }
-    __syncthreads();
-  }
-  if (t < 2) part[(long long)y * 2 + t] = sh[t][0];
+  const double acc[2] = {dd, nn};
+  const double r = block_sums<2>(sh, acc, t);
+  if (t < 2) part[(long long)y * 2 + t] = r;
 }
 
 // Plain copy through buffer descriptors (measurement helper).  Each lane
