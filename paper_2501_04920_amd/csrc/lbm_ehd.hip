@@ -1046,16 +1046,19 @@ void free_scratch(lbm_ehd* h) {
 // two waves fit on a SIMD, and eight-wave workgroups lose 9 %).  Bands are
 // the tallest (the h and g rows just outside a band are read twice) that
 // still put four wavefronts per SIMD in flight (4096 on the 256 CUs), eight
-// per SIMD with FP32 storage.  Measured on MI355X at 2048^2 (GLUPS; waves x
-// rows per band): FP32 18.1 (8 x 8), 17.9 (4 x 8), 17.5 (4 x 4), 17.4 (8 x 4),
-// 15.8 (2 x 8), 14.9 (1 x 8); FP32 storage with FP64 arithmetic 16.9 (4 x 8),
-// 15.5 (8 x 8); FP16 24.1 (8 x 16), 24.0 (4 x 16), 23.4 (8 x 8), 18.3
-// (4 x 32); BF16 24.5 (8 x 16), 24.2 (4 x 16); FP64 10.0 (4 x 16), 9.8 (8 x 16).
+// per SIMD with FP32 storage and arithmetic.  Measured on MI355X at 2048^2
+// (GLUPS; waves x rows per band): FP32 20.1 (8 x 8), 19.9 (8 x 16), 19.9
+// (4 x 8), 19.6 (4 x 4), 19.3 (8 x 4), 17.4 (2 x 8); FP32 storage with FP64
+// arithmetic 19.2 (4 x 16), 18.5 (4 x 8), 17.0 (8 x 16), 16.8 (8 x 8); FP16
+// 26.5 (8 x 16), 25.9 (8 x 8), 24.5 (4 x 16), 20.0 (4 x 32); BF16 25.9
+// (8 x 16), 25.1 (8 x 8), 23.1 (4 x 16); FP64 10.8 (4 x 16), 10.8 (8 x 16),
+// 10.7 (4 x 8), 10.6 (8 x 8).
 void default_launch(const lbm_ehd_params* p, int* waves, int* tile_rows) {
   *waves = p->nx >= 256 ? 4 : (p->nx >= 128 ? 2 : 1);
   if (arith_size(p->precision) == 4 && p->nx >= 512) *waves = 8;
   const long long strips = (p->nx + 64 * *waves - 1) / (64 * *waves);
-  const long long want = elem_size(p->precision) == 4 ? 8192 : 4096;
+  const long long want =
+      elem_size(p->precision) == 4 && arith_size(p->precision) == 4 ? 8192 : 4096;
   int rows = 32;
   while (rows > 2 && strips * *waves * ((p->ny + rows - 1) / rows) < want) rows /= 2;
   *tile_rows = std::min(rows, p->ny);
