@@ -1042,23 +1042,27 @@ void free_scratch(lbm_ehd* h) {
 
 // Default launch shape of the sweep for a grid.  Strips are 64 columns per
 // wave: four waves (256 columns) where the grid is that wide, eight (512)
-// with FP32 arithmetic where the grid is that wide (with FP64 arithmetic only
-// two waves fit on a SIMD, and eight-wave workgroups lose 9 %).  Bands are
-// the tallest (the h and g rows just outside a band are read twice) that
-// still put four wavefronts per SIMD in flight (4096 on the 256 CUs), eight
-// per SIMD with FP32 storage and arithmetic.  Measured on MI355X at 2048^2
-// (GLUPS; waves x rows per band): FP32 20.1 (8 x 8), 19.9 (8 x 16), 19.9
-// (4 x 8), 19.6 (4 x 4), 19.3 (8 x 4), 17.4 (2 x 8); FP32 storage with FP64
-// arithmetic 19.2 (4 x 16), 18.5 (4 x 8), 17.0 (8 x 16), 16.8 (8 x 8); FP16
+// where the grid is that wide and eight-wave workgroups fit twice on a CU
+// (FP32 arithmetic, or FP32 storage with its pulls parked in LDS as FP32 in
+// the plain two-buffer sweep with the default MRT rates; the other forms
+// take more than 128 registers with FP64 arithmetic, three waves per SIMD).
+// Bands are the tallest (the h and g rows just outside a band are read
+// twice) that still put four wavefronts per SIMD in flight (4096 on the 256
+// CUs), eight per SIMD with FP32 storage.  Measured on
+// MI355X at 2048^2 (GLUPS; waves x rows per band): FP32 20.1 (8 x 8), 19.9
+// (8 x 16), 19.9 (4 x 8), 19.6 (4 x 4), 19.3 (8 x 4), 17.4 (2 x 8); FP32
+// storage with FP64 arithmetic 19.6 (8 x 8), 19.4 (8 x 16), 19.3 (4 x 8),
+// 19.0 (4 x 16), in place 12.7 (4 x 8), 11.1 (8 x 8), 10.7 (4 x 16); FP16
 // 26.5 (8 x 16), 25.9 (8 x 8), 24.5 (4 x 16), 20.0 (4 x 32); BF16 25.9
 // (8 x 16), 25.1 (8 x 8), 23.1 (4 x 16); FP64 10.8 (4 x 16), 10.8 (8 x 16),
 // 10.7 (4 x 8), 10.6 (8 x 8).
 void default_launch(const lbm_ehd_params* p, int* waves, int* tile_rows) {
   *waves = p->nx >= 256 ? 4 : (p->nx >= 128 ? 2 : 1);
-  if (arith_size(p->precision) == 4 && p->nx >= 512) *waves = 8;
+  const bool fp32_store = elem_size(p->precision) == 4;
+  if (p->nx >= 512 && (arith_size(p->precision) == 4 || (fp32_store && sweep_form(*p) == NFORM)))
+    *waves = 8;
   const long long strips = (p->nx + 64 * *waves - 1) / (64 * *waves);
-  const long long want =
-      elem_size(p->precision) == 4 && arith_size(p->precision) == 4 ? 8192 : 4096;
+  const long long want = fp32_store ? 8192 : 4096;
   int rows = 32;
   while (rows > 2 && strips * *waves * ((p->ny + rows - 1) / rows) < want) rows /= 2;
   *tile_rows = std::min(rows, p->ny);

@@ -307,9 +307,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
     L.psi.set(sl, lane + 1, psi_as<W>(g4));
     const int b = (yy - y0 + 2) & 1;
 #pragma unroll
-    for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = h[i];
+    for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = (typename ParkOf<S, R>::type)h[i];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = g4[i];
+    for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = (typename ParkOf<S, R>::type)g4[i];
   };
 
   if (y0 > 0 || periodic) ring_row(y0 - 1);
@@ -355,7 +355,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
       W phi9[9], psi9[9];
       nine(phD, phC, phU, phi9);
       nine(psD, psC, psU, psi9);
-      const HGLds<R, TW> hg{L.pull[(y - y0 + 2) & 1], lane};
+      const HGLds<R, typename ParkOf<S, R>::type, TW> hg{L.pull[(y - y0 + 2) & 1], lane};
       update_node_aa<S, R, T0, STD>(V, par, gpar, sd.jprev, sd.h0, kp, sd.kpw, x, y, k, phi9,
                                     psi9, f, p, n, g0, hg);
     }

@@ -675,20 +675,32 @@ __device__ inline void update_node(const PopView<S, R>& D, R* __restrict__ jprev
 
 }
 
+// Type the pulled h1-h8 and g1-g4 are parked in: the storage type where the
+// pulls are its values widened (FP32 storage with FP64 arithmetic: exact, and
+// half the LDS, so that four workgroups of four waves fit on a CU instead of
+// two), else the pull type.
+template <class S, class R>
+struct ParkOf {
+  typedef R type;
+};
+template <>
+struct ParkOf<float, double> {
+  typedef float type;
+};
 // h1-h8 and g1-g4 of one node parked in LDS, one column per thread (h0 is
 // read again from the rest plane in its wider type).
-template <class R, int TW>
+template <class R, class P, int TW>
 struct HGLds {
-  const R (*s)[TW];
+  const P (*s)[TW];
   int lane;
   __device__ inline void h9(R o[9]) const {
     o[0] = R(0);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) o[i] = s[i - 1][lane];
+    for (int i = 1; i < 9; ++i) o[i] = (R)s[i - 1][lane];
   }
   __device__ inline void g4(R o[4]) const {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) o[i] = s[8 + i][lane];
+    for (int i = 0; i < 4; ++i) o[i] = (R)s[8 + i][lane];
   }
 };
 
@@ -729,7 +741,7 @@ template <class S, class R, int TW>
 struct SweepLds {
   typename WorkOf<S>::type phi[RING][TW + 2];
   PsiRing<S, typename WorkOf<S>::type, TW> psi;
-  R pull[2][12][TW];  // pulled h1-8 and g1-4 of a row, by row parity
+  typename ParkOf<S, R>::type pull[2][12][TW];  // pulled h1-8 and g1-4 of a row, by row parity
   JRing<LocalF<S>::value, TW> jref;
 };
 
@@ -811,9 +823,9 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
         if constexpr (LocalF<S>::value) L.jref.v[sl][lane + 1] = j_bits(V, ys, k.c);
         const int b = (yy - y0 + 2) & 1;
 #pragma unroll
-        for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = h[i];
+        for (int i = 1; i < 9; ++i) L.pull[b][i - 1][lane] = (typename ParkOf<S, R>::type)h[i];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = g4[i];
+        for (int i = 0; i < 4; ++i) L.pull[b][8 + i][lane] = (typename ParkOf<S, R>::type)g4[i];
       }
     };
     if (kNT && ((sizeof(S) == 4 && sizeof(R) == 4) || (sizeof(S) >= 4 && (yy <= y0 || yy >= yend - 1))))
@@ -882,7 +894,7 @@ __device__ inline void sweep_tile(SweepLds<S, R, 64 * NW>& L,
       if constexpr (LocalF<S>::value)
         add_f_refs(L.jref, slot(y - 1), sc, slot(y + 1), c, y, ny, k, f);
 
-      const HGLds<R, TW> hg{L.pull[(y - y0 + 2) & 1], lane};
+      const HGLds<R, typename ParkOf<S, R>::type, TW> hg{L.pull[(y - y0 + 2) & 1], lane};
       update_node<S, R, T0, STD>(D, jprev, h0x, h0dst, kp, kpw, x, y, k, phi9, psi9, f, p, n, g0,
                                  hg);
     }
