@@ -375,7 +375,7 @@ LBM_API lbm_status lbm_ehd_state_bytes(const lbm_ehd *h, size_t *bytes);
 LBM_API lbm_status lbm_ehd_save_state(lbm_ehd *h, void *buffer, size_t bytes);
 LBM_API lbm_status lbm_ehd_load_state(lbm_ehd *h, const void *buffer, size_t bytes);
 
-/* Launch shape of the fused sweep: `waves` wavefronts per workgroup (1, 2 or
+/* Launch shape of the fused sweep: `waves` wavefronts per workgroup (1, 2, 4
  * or 8; a workgroup owns a strip of 64 * waves columns and walks down a band of
  * `tile_rows` rows, tile_rows >= 1, clamped to ny).  Results do not depend on
  * the shape (every node runs the same arithmetic), only the speed does.
