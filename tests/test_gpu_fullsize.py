@@ -2,8 +2,9 @@
 launch shape the throughput benchmark times (the library's default for this
 grid).
 
-* FP64 and FP32 storage against the CPU oracle after 20 steps, every field of
-  every node (the oracle does this size in seconds with its threads).
+* FP64 and FP32 storage (FP32 also with FP64 arithmetic, and the in-place
+  sweeps) against the CPU oracle after 20 steps, every field of every node
+  (the oracle does this size in seconds with its threads).
 * 16-bit storage against the FP64 storage form of this library after 5000
   steps (a consistency check between forms, not an oracle comparison: the
   oracle would need hours for 5000 steps at this size): the deformation
@@ -51,6 +52,29 @@ def test_2048_against_oracle_20_steps(oracle_20, precision, bar):
     sim.close()
     print("2048 %s: %s" % (precision, " ".join("%s=%.2e" % kv for kv in errs.items())),
           flush=True)
+    for k, e in errs.items():
+        assert e <= bar, k
+
+
+# The other forms at full size in their default launch shapes: FP32 storage
+# with FP64 arithmetic (its pulls parked in LDS as FP32, eight-wave strips),
+# and the in-place sweeps.
+OTHER_FORMS = [("fp32f64", 0, (8, 8)), ("fp32", 1, (8, 8)), ("fp32f64", 1, (4, 8)),
+               ("fp64", 1, (4, 16))]
+
+
+@pytest.mark.parametrize("precision,inplace,launch", OTHER_FORMS)
+def test_2048_other_forms_against_oracle_20_steps(oracle_20, precision, inplace, launch):
+    p, d = _case()
+    sim = run_gpu(dict(p, inplace=inplace), precision, droplet=d)
+    assert sim.launch == launch
+    sim.step(20)
+    errs = rel_l2(sim.fields(), oracle_20, p, ALL10)
+    sim.close()
+    print("2048 %s inplace %d: %s" % (precision, inplace,
+                                      " ".join("%s=%.2e" % kv for kv in errs.items())),
+          flush=True)
+    bar = 1e-10 if precision == "fp64" else 2e-5
     for k, e in errs.items():
         assert e <= bar, k
 
