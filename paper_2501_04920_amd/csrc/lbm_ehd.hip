@@ -767,7 +767,7 @@ struct Form {
                          h0(h, h->cur), part, kp);
     }
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, part, h->P.ny, NSUM, red);
+    hipLaunchKernelGGL(k_sum_rows, dim3(NSUM), dim3(256), 0, h->stream, part, h->P.ny, NSUM, red);
     HIP_TRY(hipGetLastError());
     return LBM_OK;
   }
@@ -799,7 +799,7 @@ struct Form {
       hipLaunchKernelGGL((k_psi_change_rows<S, W>), dim3(h->P.ny), dim3(256), 0, h->stream,
                          from, older, h->part, kpw);
       HIP_TRY(hipGetLastError());
-      hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, h->stream, h->part, h->P.ny, 2,
+      hipLaunchKernelGGL(k_sum_rows, dim3(2), dim3(256), 0, h->stream, h->part, h->P.ny, 2,
                          h->red);
       HIP_TRY(hipGetLastError());
       double sums[2];

@@ -1325,15 +1325,18 @@ __global__ __launch_bounds__(256) void k_row_sums(const S* __restrict__ src,
   if (t < NSUM) part[(long long)y * NSUM + t] = r;
 }
 
-// Column sums of the per-row partial sums [ny][ncol] (ncol <= 64), rows in
-// order.
-__global__ void k_sum_rows(const double* __restrict__ part, int ny, int ncol,
-                           double* __restrict__ out) {
-  if ((int)threadIdx.x < ncol) {
-    double a = 0.0;
-    for (int y = 0; y < ny; ++y) a += part[(long long)y * ncol + threadIdx.x];
-    out[threadIdx.x] = a;
-  }
+// Column sums of the per-row partial sums [ny][ncol]: one 256-thread
+// workgroup per column, thread t summing rows t, t + 256, ... in order, then
+// the reductions of block_sums (a fixed shape: the result depends on ny only).
+// One thread walking all rows took 270 us at ny = 2048, more than a sweep.
+__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ part, int ny,
+                                                  int ncol, double* __restrict__ out) {
+  __shared__ double sh[1][4];
+  const int j = blockIdx.x, t = threadIdx.x;
+  double a[1] = {0.0};
+  for (int y = t; y < ny; y += 256) a[0] += part[(long long)y * ncol + j];
+  const double r = block_sums<1>(sh, a, t);
+  if (t == 0) out[j] = r;
 }
 
 // FP64 sums of one row for the convergence residual of the g-only sweeps:
