@@ -7,8 +7,9 @@
 // Memory layout (structure of arrays per lattice row; the rest population
 // of h lives in the aux buffer, see RestOf):
 //   a buffer is ny + 2 lattice rows, each 33 lines of `pitch` elements, one
-//   line per population: population q of row r, column x is element
-//   (r * 33 + q) * pitch + x.  Line q of row r = y + 1 holds, at column x,
+//   line per population (34 with bfloat16 storage, 41 with the ions on
+//   D2Q9; the row stride is `rstride`): population q of row r, column x is
+//   element (r * 33 + q) * pitch + x.  Line q of row r = y + 1 holds, at column x,
 //   the post-collision population q of node (x, y) from the previous step,
 //   so that the population arriving at (x, y) along c_q is read ("pulled")
 //   at row y - c_qy + 1, column (x - c_qx) mod nx.  Rows 0 and ny + 1 are

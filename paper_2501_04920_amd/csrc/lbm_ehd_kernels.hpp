@@ -12,7 +12,8 @@
 // are the moments of the *pulled* h and g of those neighbours, so the
 // workgroup computes them one row ahead into a small LDS ring (4 rows x
 // 64 NW + 2 columns, the two halo columns by threads 0 and 1) and each thread
-// parks the pulled h and g of its node in LDS for the row's own update.
+// parks the pulled h and g of its node in LDS for the row's own update (with
+// bfloat16 storage a third ring holds each node's momentum reference J~).
 // Every population is read once and written once per step; only h and g of
 // the two halo columns and of the rows just outside a band are read twice.
 #pragma once
