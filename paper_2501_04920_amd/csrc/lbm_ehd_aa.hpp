@@ -286,24 +286,36 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
   auto ring_row = [&](int yy) {
     const int ys = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
     const int sl = slot(yy);
+    const uint32_t jo = (uint32_t)ys * kp.pitch + x;
+    const bool own = valid && yy >= y0 && yy < yend;
+    // With the pulls in the storage type (FP32, FP64) a thread's own loads
+    // are issued before the halo lanes' plane loads, so that the wave holding
+    // those lanes waits once for both (measured on MI355X at 2048^2: FP64
+    // +3.0 %, FP32 +0.7 %; FP32 storage with FP64 arithmetic -2.6 %).
+    constexpr bool kOwnFirst = sizeof(S) == sizeof(R);
+    R h[9], g4[4];
+    T0 h0v{};
+    auto own_loads = [&]() {
+#pragma unroll
+      for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, ys);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, ys);
+      h0v = *elem(sd.h0, jo);
+    };
+    if (kOwnFirst && own) own_loads();
     if (lane < 2) {
-      const uint32_t jo = (uint32_t)ys * kp.pitch + xh;
-      L.phi[sl][kcol] = *elem(sd.phiP, jo);
-      L.psi.set(sl, kcol, *elem(sd.psiP, jo));
+      const uint32_t jh = (uint32_t)ys * kp.pitch + xh;
+      L.phi[sl][kcol] = *elem(sd.phiP, jh);
+      L.psi.set(sl, kcol, *elem(sd.psiP, jh));
     }
     if (!valid) return;
-    const uint32_t jo = (uint32_t)ys * kp.pitch + x;
-    if (yy < y0 || yy >= yend) {
+    if (!own) {
       L.phi[sl][lane + 1] = *elem(sd.phiP, jo);
       L.psi.set(sl, lane + 1, *elem(sd.psiP, jo));
       return;
     }
-    R h[9], g4[4];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, ys);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, ys);
-    L.phi[sl][lane + 1] = phi_of<W>((W)rest_val(*elem(sd.h0, jo)), h);
+    if (!kOwnFirst) own_loads();
+    L.phi[sl][lane + 1] = phi_of<W>((W)rest_val(h0v), h);
     L.psi.set(sl, lane + 1, psi_as<W>(g4));
     const int b = (yy - y0 + 2) & 1;
 #pragma unroll
