@@ -335,6 +335,23 @@ def test_diagnostics_sums_and_deformation(precision):
     assert abs(g["D"] - D) <= dtol and abs(g["L"] - L) <= 1e3 * dtol
 
 
+@pytest.mark.parametrize("inplace", [0, 1])
+def test_diagnostics_sums_ragged_grid_fp64(inplace):
+    """The FP64 invariant sums on a grid wider than a 256-thread row
+    workgroup and taller than the 256-thread column sum (300 x 270, neither a
+    multiple of 64), two-buffer and in place, against the oracle's sums."""
+    p = workloads.lattice_params(270, 40.0, nx=300)
+    d = dict(xc=151.3, yc=133.7, radius=40.0, noise=1e-3, seed=11)
+    sim = run_gpu(dict(p, inplace=inplace), "fp64", droplet=d, presolve=10, steps=21)
+    o = run_oracle(p, droplet=d, presolve=10, steps=21)
+    g, s = sim.diagnostics(), o.sums()
+    sim.close()
+    assert g["nonfinite"] == 0 and g["step"] == 21
+    for k in ("sum_phi", "sum_p", "sum_n"):
+        assert abs(g[k] / s[k] - 1) <= 1e-12, k
+    assert abs(g["sum_rhoe"] - s["sum_rhoe"]) <= 1e-12 * p["q"] * s["sum_p"]
+
+
 def test_bitwise_repeatable_fp32():
     cfg = workloads.config1()
     p, d = cfg["params"], cfg["droplet"]
