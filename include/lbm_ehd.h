@@ -171,10 +171,12 @@ typedef struct {
                               y-periodic walls, no side walls, no local field, no
                               converged-Poisson mode (lbm_ehd_presolve_to is not
                               available).  Each step adds a pre-pass that writes phi'
-                              and psi' of every node to two planes, from which the
-                              sweep takes the stencils' neighbourhoods (in place a
-                              neighbouring workgroup may already have overwritten the
-                              populations they are moments of). */
+                              and psi' of the nodes at the edges of the sweep's tiles
+                              (first and last row of each band, first and last
+                              column of each strip) to two planes, from which the
+                              sweep takes the stencils' halo (in place a neighbouring
+                              workgroup may already have overwritten the populations
+                              they are moments of). */
   int32_t ion_q9;          /* 0: the ion LBEs on D2Q5 (weights of Eq. (26), matrix N
                               of Eq. (46); 33 populations per node, the default);
                               1: on D2Q9 as Eq. (34)-(38) write them, with the
