@@ -99,7 +99,11 @@ typedef int32_t lbm_status;
  * every property is interpolated linearly in phi (Eq. 61).
  */
 typedef struct {
-  int32_t nx, ny;          /* grid; nx >= 2, ny >= 2 */
+  int32_t nx, ny;          /* grid; nx >= 2, 2 <= ny <= 65536 (one row of workgroups
+                              per lattice row in the helper kernels), and a
+                              population buffer below 4 GiB (32-bit byte offsets:
+                              lines x (ny + 2) x pitch x element size, pitch = nx
+                              rounded up to 64); LBM_EINVAL otherwise */
   int32_t precision;       /* LBM_FP64, LBM_FP32, LBM_FP16_STORE, LBM_BF16_STORE,
                               LBM_FP32_F64 */
   int32_t walls;           /* LBM_ELECTRODES, LBM_INSULATING, LBM_PERIODIC */

@@ -971,6 +971,8 @@ lbm_status validate(const lbm_ehd_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 2 || p->ny < 2) return fail(LBM_EINVAL, "nx and ny must be >= 2");
   if ((long long)p->nx * p->ny > (1LL << 31)) return fail(LBM_EINVAL, "grid too large");
+  // the helper kernels launch one row of workgroups per lattice row
+  if (p->ny > 65536) return fail(LBM_EINVAL, "ny must be at most 65536");
   if (!elem_size(p->precision)) return fail(LBM_EINVAL, "unknown precision");
   // kernels address a population buffer with 32-bit byte offsets
   if ((double)lines_of(*p) * (p->ny + 2) * pitch_of(p->nx) * elem_size(p->precision) >=

@@ -83,11 +83,38 @@ def test_buffer_sizes_follow_the_layout():
                                  dict(ion_q9=2), dict(ion_q9=1, precision=2),
                                  dict(ion_q9=1, precision=3),
                                  dict(ion_q9=1, local_field=1), dict(ion_q9=1, inplace=1),
-                                 dict(nx=20000, ny=20000)])
+                                 dict(nx=20000, ny=20000), dict(nx=64, ny=65537)])
 def test_invalid_parameters_rejected(bad):
     p = lbm_ehd.make_params(**bad)
     with pytest.raises(lbm_ehd.LbmError) as e:
         lbm_ehd.lbm_ehd_required_bytes(p)
+    assert e.value.code == lbm_ehd.LBM_EINVAL
+
+
+# The largest grid of each layout: a population buffer of `lines` lines per
+# lattice row must stay below 4 GiB (the kernels' 32-bit byte offsets).
+LARGEST = [("fp64", {}, 33, 8), ("fp32", {}, 33, 4), ("fp16", {}, 33, 2), ("bf16", {}, 34, 2),
+           ("fp32", {"ion_q9": 1}, 41, 4)]
+
+
+def largest_ny(nx, lines, size):
+    pitch = (nx + 63) // 64 * 64
+    ny = (1 << 32) // (lines * pitch * size) - 2
+    while lines * (ny + 2) * pitch * size >= 1 << 32:
+        ny -= 1
+    return ny
+
+
+@pytest.mark.parametrize("precision,extra,lines,size", LARGEST)
+def test_largest_grid_accepted_one_row_more_refused(precision, extra, lines, size):
+    nx = 2048
+    ny = largest_ny(nx, lines, size)
+    pop, _ = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(precision=precision, nx=nx,
+                                                                ny=ny, **extra))
+    assert pop == lines * (ny + 2) * nx * size < 1 << 32  # bytes of one buffer
+    with pytest.raises(lbm_ehd.LbmError) as e:
+        lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(precision=precision, nx=nx,
+                                                           ny=ny + 1, **extra))
     assert e.value.code == lbm_ehd.LBM_EINVAL
 
 
