@@ -99,6 +99,27 @@ def test_autotune_and_membership_changes():
     b.close()
 
 
+def test_empty_batch():
+    """A batch with no members runs, autotunes and synchronises as a no-op;
+    a member added to it, run and removed again advances as it would
+    alone."""
+    b = lbm_ehd.Batch()
+    assert len(b) == 0
+    b.run(10)
+    assert b.autotune(4)[2] == 0
+    b.synchronize()
+    s, _ = _member(0, "fp32")
+    b.add(s).run(5)
+    b.remove(s)
+    assert len(b) == 0
+    b.run(5)
+    b.synchronize()
+    assert s.time == 5
+    _same(s.fields(), _alone(0, "fp32", 5), "member of a batch emptied again")
+    b.close()
+    s.close()
+
+
 def test_batched_member_matches_oracle_fp64():
     sims = [_member(i, "fp64")[0] for i in (4, 1)]
     b = lbm_ehd.Batch(sims).set_launch(1, 4)
