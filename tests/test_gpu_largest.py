@@ -1,6 +1,6 @@
 """The largest grids the population buffers allow (below 4 GiB each: the
 kernels address a buffer with 32-bit byte offsets), at 2048 columns in FP64,
-FP32 and FP16 storage.
+FP32 and FP16 storage, and FP32 with in-place streaming.
 
 An x-uniform state (a flat heavy layer between the electrodes, ion and
 potential profiles in y only) stays x-uniform: every column of the GPU result
@@ -33,9 +33,9 @@ def largest_ny(nx, lines, size):
     return ny
 
 
-@pytest.mark.parametrize("precision,size,bar", [("fp64", 8, 1e-10), ("fp32", 4, 2e-5),
-                                                ("fp16", 2, 3e-3)])
-def test_largest_grid_x_uniform_state(precision, size, bar):
+@pytest.mark.parametrize("precision,size,bar,inplace", [("fp64", 8, 1e-10, 0), ("fp32", 4, 2e-5, 0),
+                                                        ("fp16", 2, 3e-3, 0), ("fp32", 4, 2e-5, 1)])
+def test_largest_grid_x_uniform_state(precision, size, bar, inplace):
     nx = 2048
     ny = largest_ny(nx, 33, size)
     p = workloads.lattice_params(ny, 20.0, nx=nx)
@@ -46,10 +46,10 @@ def test_largest_grid_x_uniform_state(precision, size, bar):
     cm = p["c0"] * (1 - 1e-3 * np.sin(2 * np.pi * y / 61.0))
     psi = p["dpsi"] * (ny - 0.5 - y) / ny
     steps = 20
-    print("largest %s grid: %d x %d" % (precision, nx, ny), flush=True)
+    print("largest %s grid: %d x %d, in place %d" % (precision, nx, ny, inplace), flush=True)
     o = run_oracle(dict(p, nx=2), fields=(phi, cp, cm, psi), steps=steps)
     ref = {k: v[:, :1] for k, v in o.fields().items()}
-    sim = run_gpu(p, precision, fields=(phi, cp, cm, psi), steps=steps)
+    sim = run_gpu(dict(p, inplace=inplace), precision, fields=(phi, cp, cm, psi), steps=steps)
     got = sim.fields(NAMES)
     sim.close()
     for k in NAMES:
