@@ -94,6 +94,10 @@ VARIANTS = {
     "no_ion_force": dict(ion_force=0),
     "s_free": dict(s_free=1.3),
     "body_force": dict(force_x=2e-6, force_y=-1e-6),
+    # degenerate cases: no charge (the ions decouple from the flow and the
+    # potential), no applied voltage (electrodes at one potential)
+    "uncharged": dict(q=0.0),
+    "no_voltage": dict(dpsi=0.0),
     "side_walls": dict(side_walls=1),
     "side_walls_insulating": dict(side_walls=1, walls=1),
     "side_walls_periodic_y": dict(side_walls=1, walls=2, force_y=1e-6),
