@@ -128,7 +128,7 @@ def test_ragged_grid_variants_fp64(name):
 # after 300 steps: fields <= 2e-3 (FP16), <= 4e-2 (BF16).
 VARIANTS_16 = ("base", "periodic", "insulating", "poisson_iters", "literal_poisson",
                "side_walls", "side_walls_periodic_y", "local_field", "local_field_periodic",
-               "local_field_side_walls")
+               "local_field_side_walls", "uncharged", "no_voltage")
 
 
 @pytest.mark.parametrize("precision,bar", [("fp16", 1e-2), ("bf16", 0.1)])
