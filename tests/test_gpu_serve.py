@@ -18,10 +18,10 @@ REQUESTS = [(64, 64, 10.0, 2.0, 1.0, 0.5, 30), (100, 70, 12.0, 0.5, 2.0, 0.25, 5
             (96, 96, 14.0, 1.0, 1.0, 0.5, 101), (37, 41, 6.0, 1.0, 1.0, 0.5, 0)]
 
 
-def _params(i, precision):
+def _params(i, precision, inplace=0):
     nx, ny, r, er, mr, ca, _ = REQUESTS[i]
     p = workloads.lattice_params(ny, r, nx=nx, eps_r=er, mu_r=mr, Ca_E=ca)
-    return lbm_ehd.make_params(**dict(p, precision=precision))
+    return lbm_ehd.make_params(**dict(p, precision=precision, inplace=inplace))
 
 
 def _drop(i):
@@ -29,8 +29,8 @@ def _drop(i):
     return dict(xc=(nx - 1) / 2 + 0.25, yc=(ny - 1) / 2, radius=r, noise=1e-3, seed=100 + i)
 
 
-def _alone(i, precision):
-    sim = lbm_ehd.Simulation(_params(i, precision), device="cuda:0")
+def _alone(i, precision, inplace=0):
+    sim = lbm_ehd.Simulation(_params(i, precision, inplace), device="cuda:0")
     d = _drop(i)
     sim.init_droplet(d["xc"], d["yc"], d["radius"], d["noise"], d["seed"])
     sim.step(REQUESTS[i][6])
@@ -39,9 +39,10 @@ def _alone(i, precision):
     return f
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16"])
-def test_each_result_is_the_same_alone_and_in_the_mix(precision):
-    fps = [lbm_ehd.lbm_ehd_footprint_bytes(_params(i, precision)) for i in range(len(REQUESTS))]
+@pytest.mark.parametrize("precision,inplace", [("fp32", 0), ("fp16", 0), ("fp32", 1)])
+def test_each_result_is_the_same_alone_and_in_the_mix(precision, inplace):
+    fps = [lbm_ehd.lbm_ehd_footprint_bytes(_params(i, precision, inplace))
+           for i in range(len(REQUESTS))]
     budget = sorted(fps)[-1] + sorted(fps)[-2]      # two large ones at most at a time
     srv = lbm_ehd.Server(budget, block_steps=16)
     ids, got, infos = [], {}, {}
@@ -53,7 +54,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix(precision):
         if pending and rounds % 2 == 0:
             i = pending.pop(0)
             d = _drop(i)
-            ids.append(srv.submit(_params(i, precision), d["xc"], d["yc"], d["radius"],
+            ids.append(srv.submit(_params(i, precision, inplace), d["xc"], d["yc"], d["radius"],
                                   d["noise"], d["seed"], REQUESTS[i][6]))
         running, queued = srv.advance()
         assert srv.used_bytes <= budget
@@ -79,7 +80,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix(precision):
         inf = infos[i]
         assert inf["steps_done"] == REQUESTS[i][6]
         assert inf["t_submit"] <= inf["t_start"] <= inf["t_done"]
-        want = _alone(i, precision)
+        want = _alone(i, precision, inplace)
         for k in ALL10:
             assert np.array_equal(got[i][k], want[k]), (i, k)
     srv.close()
