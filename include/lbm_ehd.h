@@ -170,8 +170,12 @@ typedef struct {
                               populations of a node alternate between its own slots,
                               reversed, and its neighbours' slots, step by step; wall
                               rules written back into the node's own slots).  Halves
-                              the population memory; FP64 and FP32 storage (LBM_FP64,
-                              LBM_FP32, LBM_FP32_F64), electrodes, insulating or
+                              the population memory; FP64, FP32 and binary16 storage
+                              (LBM_FP64, LBM_FP32, LBM_FP32_F64, LBM_FP16_STORE; binary16
+                              keeps its node-local references of h and g in the node's
+                              own rest slots and its ion rest populations in their
+                              FP64 planes, as with two buffers; not LBM_BF16_STORE),
+                              electrodes, insulating or
                               y-periodic walls, no side walls, no local field, no
                               converged-Poisson mode (lbm_ehd_presolve_to is not
                               available).  Each step adds a pre-pass that writes phi'

@@ -304,7 +304,7 @@ struct Form {
   // In place: the phi' and psi' planes of the pre-pass (type W), after the
   // rest population.
   static W* phiP(lbm_ehd* h) {
-    return reinterpret_cast<W*>(h0(h, 0) + (size_t)h->P.ny * h->pitch);
+    return reinterpret_cast<W*>(h0(h, 0) + rest_planes<S>() * (size_t)h->P.ny * h->pitch);
   }
   static W* psiP(lbm_ehd* h) { return phiP(h) + (size_t)h->P.ny * h->pitch; }
 
@@ -326,8 +326,10 @@ struct Form {
     d.gpar = h->gpar;
     return d;
   }
-  // 4- and 8-byte storage only (the form that has the in-place sweep)
-  static constexpr bool kAA = sizeof(S) >= 4;
+  // the storage types that have the in-place sweep (not bfloat16)
+  static constexpr bool kAA = !LocalF<S>::value;
+  // ... and the sweep with the ions on D2Q9 (4- and 8-byte storage)
+  static constexpr bool kQ9 = sizeof(S) >= 4;
 
   // Descriptor of a simulation for the tile kernel.
   static Desc desc(lbm_ehd* h) {
@@ -401,7 +403,7 @@ struct Form {
       case 4 + NFORM:
       case 5:
       case 5 + NFORM:
-        if constexpr (kAA) {  // (4- and 8-byte storage only, as in place)
+        if constexpr (kQ9) {
           if (form == 4)
             launch_ext<3>(waves, descs, tiles, ntiles, flip, st);
           else if (form == 4 + NFORM)
@@ -448,7 +450,7 @@ struct Form {
   // `std`: the members have the default MRT rates (sweep form 3 + NFORM)
   static lbm_status launch_aa(int waves, bool std, const void* descs, const BatchTile* tiles,
                               int ntiles, int flip, int gflip, hipStream_t st) {
-    if (!kAA) return fail(LBM_EINVAL, "in-place streaming needs 4- or 8-byte storage");
+    if (!kAA) return fail(LBM_EINVAL, "in-place streaming needs FP64, FP32 or FP16 storage");
     if (std)
       launch_aa_std<true>(waves, descs, tiles, ntiles, flip, gflip, st);
     else
@@ -643,7 +645,7 @@ struct Form {
       }
       return LBM_OK;
     }
-    return fail(LBM_EINVAL, "in-place streaming needs 4- or 8-byte storage");
+    return fail(LBM_EINVAL, "in-place streaming needs FP64, FP32 or FP16 storage");
   }
 
   // `n` time steps.  Steps without extra g-only sweeps are fused sweeps
@@ -991,8 +993,8 @@ lbm_status validate(const lbm_ehd_params* p) {
   if (p->ion_q9 && (elem_size(p->precision) == 2 || p->local_field || p->inplace))
     return fail(LBM_EINVAL,
                 "ions on D2Q9: FP64 or FP32 storage, two buffers, no local field");
-  if (p->inplace && elem_size(p->precision) == 2)
-    return fail(LBM_EINVAL, "in-place streaming needs FP64 or FP32 storage");
+  if (p->inplace && p->precision == LBM_BF16_STORE)
+    return fail(LBM_EINVAL, "in-place streaming needs FP64, FP32 or FP16 storage");
   if (p->inplace && (p->side_walls || p->local_field || p->poisson_tol > 0))
     return fail(LBM_EINVAL,
                 "in-place streaming covers the plain sweep: no side walls, no local field, "

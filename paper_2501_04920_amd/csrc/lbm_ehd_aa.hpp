@@ -31,8 +31,14 @@
 // working type (FP64 with FP32 storage): 16 B per cell of memory; the
 // pre-pass reads the h and g arrivals of about 2 / band height of the nodes.
 //
-// This form covers the plain sweep with FP64 and FP32 storage (no side walls,
-// no local field of Eq. 50, no 16-bit node-local references).
+// This form covers the plain sweep (no side walls, no local field of Eq. 50)
+// with FP64, FP32 and binary16 storage.  With binary16 the node-local
+// references stay where the two-buffer layout keeps them: each node's phi'~
+// in its own slot of line QH and its psi'~ in its own slot of line QRG (the
+// rest populations of h, p and n live in their planes, so those slots are
+// free in both orientations), and every population is stored relative to the
+// reference of the node it arrives at, which in either orientation is the
+// node that reads it.
 #pragma once
 
 #include "lbm_ehd_kernels.hpp"
@@ -74,7 +80,7 @@ struct AAView {
     const int ys = y1 < 0 ? y1 + ny : (y1 >= ny ? y1 - ny : y1);
     const bool self = par == 0 || i == 0 || (beyond && P.kp->walls != WALL_PERIODIC);
     const int xs = cx_of(i) > 0 ? k.m : (cx_of(i) < 0 ? k.p : k.c);
-    return P.at(self ? q0 + i : q0 + opp_of(i), self ? own : P.row(ys + 1) + xs);
+    return load_as(self ? q0 + i : q0 + opp_of(i), q0 + i, self ? own : P.row(ys + 1) + xs);
   }
   // store the post-collision population v of direction i of the set at line
   // q0 of node (k.c, y), in orientation `par`; `vwall`: the value that comes
@@ -88,9 +94,81 @@ struct AAView {
     const int yd = y1 < 0 ? y1 + ny : (y1 >= ny ? y1 - ny : y1);
     const bool self = par == 0 || i == 0 || through;
     const int xd = cx_of(i) > 0 ? k.p : (cx_of(i) < 0 ? k.m : k.c);
-    P.put(self ? q0 + opp_of(i) : q0 + i, self ? own : P.row(yd + 1) + xd, through ? vwall : v);
+    const int qi = q0 + i, qo = q0 + opp_of(i);
+    R x = through ? vwall : v;
+    // the reflected value travels along opp(i), the others along i (a line
+    // pair of one set: both or neither carry an offset)
+    if (P.has_ofs(qi)) x -= through ? P.kp->iofs[qo - QP] : P.kp->iofs[qi - QP];
+    if (Scaled<S>::value) x *= P.kp->sc[line_set<S>(qi)];
+    Codec<S, R>::st(P.rs, (self ? own : P.row(yd + 1) + xd) * (uint32_t)sizeof(S),
+                    line_bytes(self ? qo : qi), x);
+  }
+  // In place a population spends every other step in the slot of the
+  // opposite direction, but it keeps the encoding of its own: the per-line
+  // offset of the 16-bit ion lines (the drifting bulk, which differs between
+  // +y and -y) is that of its direction, so that it rounds as with two
+  // buffers and the FP64 rest populations book exactly what is stored.  The
+  // same as PopView::at where q == c.
+  __device__ inline R load_as(int q, int c, uint32_t off) const {
+    R v = Codec<S, R>::ld(P.rs, off * (uint32_t)sizeof(S), line_bytes(q), P.nt);
+    if constexpr (Scaled<S>::value) return v * P.kp->isc[line_set<S>(c)] + P.ofs(c);
+    if (P.has_ofs(c)) v += P.kp->iofs[c - QP];
+    return v;
+  }
+  // Byte offset of line q, the scalar operand of the buffer access.  The
+  // line depends on the orientation, the direction and the row only, which
+  // every lane of a wave shares (one lattice row per wave in every kernel
+  // that streams in place); without the broadcast the compiler, which sees
+  // the line selected inside branches on the lane, wraps each access in a
+  // loop over the distinct values.
+  __device__ inline uint32_t line_bytes(int q) const {
+    return (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)((uint32_t)q * P.kp->pitch * (uint32_t)sizeof(S)));
   }
 };
+
+// The arrivals of node (k.c, y) with the node-local references of binary16
+// storage added back (h: w_i phi'~, g: psi'~ / 6 of the node itself; see the
+// header); a no-op for the other storage types.
+template <class S, class R, class K>
+__device__ inline void aa_refs_h(const AAView<S, R>& V, K k, int y, R h[9]) {
+  if constexpr (LocalH<S>::value) {
+    const R t = V.P.at(QH, V.P.row(y + 1) + k.c);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) h[i] = h_from(h[i], i, t);
+  }
+}
+template <class S, class R, class K>
+__device__ inline void aa_refs_g(const AAView<S, R>& V, K k, int y, R g4[4]) {
+  if constexpr (LocalG<S>::value) {
+    const R t = V.P.at(QRG, V.P.row(y + 1) + k.c) * R(1.0 / 6.0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g4[i] += t;
+  }
+}
+// g0 of node (k.c, y) in orientation gpar, as a deviation (g_rest)
+template <class S, class R, class K>
+__device__ inline R aa_g0(const AAView<S, R>& V, int gpar, K k, int y) {
+  R g0 = V.in(gpar, QG, 0, k, y);
+  if constexpr (LocalG<S>::value) g0 -= R(2.0 / 3.0) * V.P.at(QRG, V.P.row(y + 1) + k.c);
+  return g0;
+}
+// The ion content of node (x, y) in orientation par, summed in type A: its
+// rest population (the FP64 plane with binary16 storage) plus its four
+// arrivals, in the order of the two-buffer helpers.
+template <class A, class S, class R, class T0, class K>
+__device__ inline A aa_ion(const AAView<S, R>& V, const T0* __restrict__ h0x, int par, int q0,
+                           K k, int x, int y) {
+  A c;
+  if constexpr (IonRest<S>::value)
+    c = (A)rest_val(*elem(h0x, (uint32_t)(q0 == QP ? 1 : 2) * V.P.kp->cells +
+                                  (uint32_t)y * V.P.kp->pitch + x));
+  else
+    c = (A)V.in(par, q0, 0, k, y);
+#pragma unroll
+  for (int i = 1; i < 5; ++i) c += (A)V.in(par, q0, i, k, y);
+  return c;
+}
 
 // One member of an in-place sweep: its parameters, its population buffer,
 // (phi u)(t-1), the rest population of h (one time level, in place), the
@@ -139,14 +217,16 @@ __global__ __launch_bounds__(64 * NW) void k_aa_hood(const SimDescAA<S, R, T0>* 
     for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
 #pragma unroll
     for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
+    aa_refs_h(V, k, y, h);
+    aa_refs_g(V, k, y, g4);
     *elem(sd.phiP, jo) = phi_of<W>((W)rest_val(*elem(sd.h0, jo)), h);
     *elem(sd.psiP, jo) = psi_as<W>(g4);
   }
 }
 
 // Per-node update of the in-place sweep: the arithmetic of update_node (the
-// two-buffer sweep, plain form, 4- and 8-byte storage) in the same order,
-// with the stores of the AA orientations.
+// two-buffer sweep, plain form) in the same order, with the stores of the AA
+// orientations.
 template <class S, class R, class T0, bool STD, class HG, class K>
 __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
                                       R* __restrict__ jprev, T0* __restrict__ h0x,
@@ -167,6 +247,20 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
     nw[i] = (W)n[i];
   }
   const uint32_t jo = (uint32_t)y * kp.pitch + x;
+  const uint32_t own = V.P.row(y + 1) + x;
+  // exact incoming ion content of the node (FP64 ion rest populations)
+  double Pin = 0.0, Qin = 0.0;
+  if constexpr (IonRest<S>::value) {
+    Pin = rest_val(*elem(h0x, kp.cells + jo));
+    Qin = rest_val(*elem(h0x, 2 * kp.cells + jo));
+    pw[0] = (W)Pin;
+    nw[0] = (W)Qin;
+#pragma unroll
+    for (int i = 1; i < 5; ++i) {
+      Pin += (double)p[i];
+      Qin += (double)n[i];
+    }
+  }
   const W Pd = pw[0] + pw[1] + pw[2] + pw[3] + pw[4];
   const W Qd = nw[0] + nw[1] + nw[2] + nw[3] + nw[4];
   Macro<W> m;
@@ -188,29 +282,65 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
     hg.g4(g + 1);
     W gw[5] = {(W)g[0], (W)g[1], (W)g[2], (W)g[3], (W)g[4]};
     collide_g<STD>(gw, m.psid, poisson_source<W>(m.rhoe, m.ieps, m.geps, m.gpsi, kpw), kpw);
+    if constexpr (LocalG<S>::value) {
+      // relative to psi'~ / 6 of the node each population arrives at (the
+      // node itself for one reflected at an electrode), g0 relative to
+      // -2/3 psi'~ of its own node (store_g of the two-buffer sweep)
+      R t[5];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      g[i] = (R)gw[i];
-      V.out(gpar, QG, i, k, y, g[i], -g[i]);
+      for (int i = 0; i < 5; ++i) t[i] = V.P.stored(QRG, (R)psi9[i]);
+      if (kp.walls != WALL_PERIODIC) {
+        if (y == 0) t[4] = t[0];
+        if (y == kp.ny - 1) t[2] = t[0];
+      }
+      V.P.put(QRG, own, t[0]);
+      const R sixth = R(1.0 / 6.0);
+      g[0] = (R)gw[0];
+      V.out(gpar, QG, 0, k, y, g[0] + R(2.0 / 3.0) * t[0], g[0]);
+#pragma unroll
+      for (int i = 1; i < 5; ++i) {
+        g[i] = (R)gw[i];
+        V.out(gpar, QG, i, k, y, g[i] - t[i] * sixth, -g[i] - t[0] * sixth);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        g[i] = (R)gw[i];
+        V.out(gpar, QG, i, k, y, g[i], -g[i]);
+      }
     }
   }
 
   collide_ion<STD>(pw, m.cpd, m.mup, m.itau_p, kpw.mask_p, W(-1), m, kpw);
   collide_ion<STD>(nw, m.cmd, m.mum, m.itau_n, kpw.mask_n, W(1), m, kpw);
   const R cpd = (R)m.cpd, cmd = (R)m.cmd;
+  // the rest populations of binary16 storage live in their FP64 planes
+  constexpr int I0 = IonRest<S>::value ? 1 : 0;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     p[i] = (R)pw[i];
+    n[i] = (R)nw[i];
+  }
+  // the collision adds the reaction term to each ion's content (Eq. 41); with
+  // FP64 rest populations those take what the stored moving ones leave of it
+  double Pout = Pin + (double)m.Rr, Qout = Qin + (double)m.Rr;
+#pragma unroll
+  for (int i = I0; i < 5; ++i) {
     // anode (through it: direction 4): c+ = 0; cathode (direction 2): d c+/dn = 0
     const R wp = ins ? p[i] : (i == 4 ? -p[4] - third * kp.c0 : -p[i] + third * cpd);
     V.out(par, QP, i, k, y, p[i], wp);
+    if constexpr (IonRest<S>::value) Pout -= (double)V.P.stored(QP + i, p[i]);
   }
 #pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    n[i] = (R)nw[i];
+  for (int i = I0; i < 5; ++i) {
     // anode: d c-/dn = 0; cathode: c- = 0
     const R wn = ins ? n[i] : (i == 4 ? -n[4] + third * cmd : -n[i] - third * kp.c0);
     V.out(par, QN, i, k, y, n[i], wn);
+    if constexpr (IonRest<S>::value) Qout -= (double)V.P.stored(QN + i, n[i]);
+  }
+  if constexpr (IonRest<S>::value) {
+    *elem(h0x, kp.cells + jo) = (T0)Pout;
+    *elem(h0x, 2 * kp.cells + jo) = (T0)Qout;
   }
 
   {  // h: Eq. (27)-(32), with d(phi u)/dt of Eq. (58), in W; bounce-back
@@ -231,11 +361,30 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
 #pragma unroll
     for (int i = 1; i < 9; ++i) hw[i] = (W)h[i];
     collide_h<STD>(hw, m, dJ, kpw);
+    if constexpr (LocalH<S>::value) {
+      // relative to w_i phi'~ of the node each population arrives at (the node
+      // itself for one reflected at an electrode)
+      R t[9];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      h[i] = V.P.stored(QH + i, (R)hw[i]);
-      V.out(par, QH, i, k, y, h[i], h[i]);
-      mass.sub(h[i]);
+      for (int i = 0; i < 9; ++i) t[i] = V.P.stored(QH, (R)phi9[i]);
+      if (kp.walls != WALL_PERIODIC) {
+        if (y == 0) t[4] = t[7] = t[8] = t[0];
+        if (y == kp.ny - 1) t[2] = t[5] = t[6] = t[0];
+      }
+      V.P.put(QH, own, t[0]);  // this node's reference for the next step
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        h[i] = V.P.stored(QH + i, (R)hw[i] - (R)W9F[i] * t[i]);
+        V.out(par, QH, i, k, y, h[i], h[i]);
+        mass.sub(h_from(h[i], i, t[i]));
+      }
+    } else {
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        h[i] = V.P.stored(QH + i, (R)hw[i]);
+        V.out(par, QH, i, k, y, h[i], h[i]);
+        mass.sub(h[i]);
+      }
     }
     // the rest population takes what the eight stored ones leave of the content
     *elem(h0x, jo) = mass.rest();
@@ -252,17 +401,14 @@ __device__ inline void update_node_aa(const AAView<S, R>& V, int par, int gpar,
 // pattern), so updating a row leaves the arrivals of the next one intact.
 // `flip` / `gflip` = 1 turns every member's orientation of f, h, p, n / of g
 // (odd steps of a captured block).  STD: the default MRT rates compiled in.
-template <class S, class R, class T0, int NW, bool STD>
-__global__ __launch_bounds__(64 * NW)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
-    const SimDescAA<S, R, T0>* __restrict__ sims, const BatchTile* __restrict__ tiles,
-    int xcd_chunk, int flip, int gflip) {
+//
+// The tile's walk in the orientations PAR (f, h, p, n) and GPAR (g).
+template <class S, class R, class T0, int NW, bool STD, int PAR, int GPAR>
+__device__ __forceinline__ void sweep_aa_tile(SweepLds<S, R, 64 * NW>& L,
+                                              const SimDescAA<S, R, T0>& sd,
+                                              const BatchTile& tl) {
   typedef typename WorkOf<S>::type W;
   constexpr int TW = 64 * NW;
-  __shared__ SweepLds<S, R, TW> L;
-  const BatchTile tl = tiles[xcd_tile(xcd_chunk)];
-  if (tl.sim < 0) return;
-  const SimDescAA<S, R, T0>& sd = sims[tl.sim];
   const KP<R>& kp = sd.kp;
   const int nx = kp.nx, ny = kp.ny, x0 = tl.x0, y0 = tl.y0, yend = tl.yend;
   const int w = min(TW, nx - x0);
@@ -270,7 +416,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
   const bool valid = lane < w;
   const int x = x0 + (valid ? lane : 0);
   const bool periodic = kp.walls == WALL_PERIODIC;
-  const int par = (sd.par + flip) & 1, gpar = (sd.gpar + gflip) & 1;
+  constexpr int par = PAR, gpar = GPAR;
   // Loads are cached: in place a node writes the lines it has just read, and
   // the non-temporal loads of the two-buffer sweep cost 4.5 % here (MI355X,
   // 2048^2, FP32).
@@ -300,6 +446,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
       for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, ys);
 #pragma unroll
       for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, ys);
+      aa_refs_h(V, k, ys, h);
+      aa_refs_g(V, k, ys, g4);
       h0v = *elem(sd.h0, jo);
     };
     if (kOwnFirst && own) own_loads();
@@ -335,12 +483,15 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
     if (valid) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = V.in(par, QF, i, k, y);
+      // (with binary16 storage the ion rest populations are read by the update)
+      p[0] = IonRest<S>::value ? R(0) : V.in(par, QP, 0, k, y);
+      n[0] = IonRest<S>::value ? R(0) : V.in(par, QN, 0, k, y);
 #pragma unroll
-      for (int i = 0; i < 5; ++i) {
+      for (int i = 1; i < 5; ++i) {
         p[i] = V.in(par, QP, i, k, y);
         n[i] = V.in(par, QN, i, k, y);
       }
-      g0 = V.in(gpar, QG, 0, k, y);
+      g0 = aa_g0(V, gpar, k, y);
     }
     if (up) ring_row(y + 1);
     __builtin_amdgcn_s_setprio(0);
@@ -374,6 +525,35 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
   }
 }
 
+template <class S, class R, class T0, int NW, bool STD>
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void k_sweep_aa(
+    const SimDescAA<S, R, T0>* __restrict__ sims, const BatchTile* __restrict__ tiles,
+    int xcd_chunk, int flip, int gflip) {
+  __shared__ SweepLds<S, R, 64 * NW> L;
+  const BatchTile tl = tiles[xcd_tile(xcd_chunk)];
+  if (tl.sim < 0) return;
+  const SimDescAA<S, R, T0>& sd = sims[tl.sim];
+  // The orientations are the member's, the same for the whole workgroup:
+  // one compiled walk for each pair, in which every line and slot of the AA
+  // addressing is a constant.  With the orientation a run-time value, the
+  // selects of line and offset in every access cost a third of the binary16
+  // sweep's time and a tenth of the FP32 one's (MI355X, 2048^2, a node's
+  // own slots: 225 against 157 us, 232 against 204 us).
+  const int par = (sd.par + flip) & 1, gpar = (sd.gpar + gflip) & 1;
+  if (par == 0) {
+    if (gpar == 0)
+      sweep_aa_tile<S, R, T0, NW, STD, 0, 0>(L, sd, tl);
+    else
+      sweep_aa_tile<S, R, T0, NW, STD, 0, 1>(L, sd, tl);
+  } else {
+    if (gpar == 0)
+      sweep_aa_tile<S, R, T0, NW, STD, 1, 0>(L, sd, tl);
+    else
+      sweep_aa_tile<S, R, T0, NW, STD, 1, 1>(L, sd, tl);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Helpers of the in-place form outside the hot loop (2-D launches, one
 // thread per node).  `par` / `gpar` are the orientations of the state.
@@ -392,11 +572,10 @@ __global__ void k_aa_moments(const S* __restrict__ src, const T0* __restrict__ h
   h[0] = (R)rest_val(*elem(h0x, (uint32_t)y * kp.pitch + x));
   for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
   for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
-  R Pd = R(0), Qd = R(0);
-  for (int i = 0; i < 5; ++i) {
-    Pd += V.in(par, QP, i, k, y);
-    Qd += V.in(par, QN, i, k, y);
-  }
+  aa_refs_h(V, k, y, h);
+  aa_refs_g(V, k, y, g4);
+  const R Pd = aa_ion<R>(V, h0x, par, QP, k, x, y);
+  const R Qd = aa_ion<R>(V, h0x, par, QN, k, x, y);
   const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
   mom[c] = sum9(h);
   mom[np + c] = psi_of(g4);
@@ -413,6 +592,7 @@ __global__ void k_aa_psi_plane(const S* __restrict__ src, R* __restrict__ mom, c
   const Cols k = cols_of(x, kp.nx, 0);
   R g4[4];
   for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
+  aa_refs_g(V, k, y, g4);
   mom[(long long)kp.nx * kp.ny + (long long)y * kp.nx + x] = psi_of(g4);
 }
 
@@ -427,7 +607,9 @@ __global__ void k_aa_poisson(S* __restrict__ buf, const R* __restrict__ mom, con
   const Cols k = cols_of(x, kp.nx, 0);
   R phi9[9], psi9[9], g[5];
   hood(mom, kp, x, y, phi9, psi9);
-  for (int i = 0; i < 5; ++i) g[i] = V.in(gpar, QG, i, k, y);
+  g[0] = aa_g0(V, gpar, k, y);
+  for (int i = 1; i < 5; ++i) g[i] = V.in(gpar, QG, i, k, y);
+  aa_refs_g(V, k, y, g + 1);
   const long long np = (long long)kp.nx * kp.ny;
   const long long c = (long long)y * kp.nx + x;
   const R eps = (R(0.5) + phi9[0]) * kp.deps + kp.eps_v;
@@ -437,7 +619,20 @@ __global__ void k_aa_poisson(S* __restrict__ buf, const R* __restrict__ mom, con
   gpsi[1] += kp.psi_slope;
   const R geps[2] = {kp.deps * gphi[0], kp.deps * gphi[1]};
   collide_g(g, psi9[0], poisson_source<R>(mom[2 * np + c], recip(eps), geps, gpsi, kp), kp);
-  for (int i = 0; i < 5; ++i) V.out(gpar, QG, i, k, y, g[i], -g[i]);
+  if constexpr (LocalG<S>::value) {  // the references of the sweep's g store
+    R t[5];
+    for (int i = 0; i < 5; ++i) t[i] = V.P.stored(QRG, psi9[i]);
+    if (kp.walls != WALL_PERIODIC) {
+      if (y == 0) t[4] = t[0];
+      if (y == kp.ny - 1) t[2] = t[0];
+    }
+    V.P.put(QRG, V.P.row(y + 1) + x, t[0]);
+    const R sixth = R(1.0 / 6.0);
+    V.out(gpar, QG, 0, k, y, g[0] + R(2.0 / 3.0) * t[0], g[0]);
+    for (int i = 1; i < 5; ++i) V.out(gpar, QG, i, k, y, g[i] - t[i] * sixth, -g[i] - t[0] * sixth);
+  } else {
+    for (int i = 0; i < 5; ++i) V.out(gpar, QG, i, k, y, g[i], -g[i]);
+  }
 }
 
 // Macroscopic fields (FP64 output, [10][ny][nx]), as k_fields.
@@ -447,17 +642,13 @@ __global__ void k_aa_fields(const S* __restrict__ src, const T0* __restrict__ h0
                             int par) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
   if (x >= kp.nx) return;
-  (void)h0x;
   const AAView<S, R> V{PopView<S, R>{make_rsrc(src, kp.pop_bytes), &kp, false}};
   const Cols k = cols_of(x, kp.nx, 0);
   R phi9[9], psi9[9], f[9];
   hood(mom, kp, x, y, phi9, psi9);
   for (int i = 0; i < 9; ++i) f[i] = V.in(par, QF, i, k, y);
-  R Pd = R(0), Qd = R(0);
-  for (int i = 0; i < 5; ++i) {
-    Pd += V.in(par, QP, i, k, y);
-    Qd += V.in(par, QN, i, k, y);
-  }
+  const R Pd = aa_ion<R>(V, h0x, par, QP, k, x, y);
+  const R Qd = aa_ion<R>(V, h0x, par, QN, k, x, y);
   Macro<R> m;
   macro(phi9, psi9, Pd, Qd, f, kp, m);
   const long long c = (long long)y * kp.nx + x, np = (long long)kp.nx * kp.ny;
@@ -489,20 +680,20 @@ __global__ __launch_bounds__(256) void k_aa_row_sums(const S* __restrict__ src,
   for (int x = t; x < kp.nx; x += 256) {
     const Cols k = cols_of(x, kp.nx, 0);
     RestAcc<T0> content = RestAcc<T0>::from_rest(*elem(h0x, (uint32_t)y * kp.pitch + x));
+    R h[9];
+    for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
+    aa_refs_h(V, k, y, h);
     bool finite = true;
     for (int i = 1; i < 9; ++i) {
-      const R hi = V.in(par, QH, i, k, y);
-      content.add(hi);
-      finite = finite && isfinite((double)hi);
+      content.add(h[i]);
+      finite = finite && isfinite((double)h[i]);
     }
     const double phid = finite ? content.content() : NAN;
-    double Pd = 0.0, Qd = 0.0;
-    for (int i = 0; i < 5; ++i) {
-      Pd += (double)V.in(par, QP, i, k, y);
-      Qd += (double)V.in(par, QN, i, k, y);
-    }
+    const double Pd = aa_ion<double>(V, h0x, par, QP, k, x, y);
+    const double Qd = aa_ion<double>(V, h0x, par, QN, k, x, y);
     R g4[4];
     for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
+    aa_refs_g(V, k, y, g4);
     const double phi = 0.5 + phid;
     const double psid = (double)psi_of(g4);
     acc[0] += phi;

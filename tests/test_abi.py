@@ -60,14 +60,18 @@ def test_defaults_and_bytes():
 
 def test_buffer_sizes_follow_the_layout():
     """The population buffer grows by the eight diagonal lines with D2Q9
-    ions, keeps its size in place, and doubles with 8-byte storage."""
+    ions, keeps its size in place (binary16 too), and
+    doubles with 8-byte storage."""
     sizes = {}
     for name, kw in (("fp32", {}), ("fp32_q9", dict(ion_q9=1)), ("fp32_inplace", dict(inplace=1)),
                      ("fp64", dict(precision="fp64")),
-                     ("fp32_q9_side", dict(ion_q9=1, side_walls=1))):
+                     ("fp32_q9_side", dict(ion_q9=1, side_walls=1)),
+                     ("fp16", dict(precision="fp16")),
+                     ("fp16_inplace", dict(precision="fp16", inplace=1))):
         sizes[name] = lbm_ehd.lbm_ehd_required_bytes(lbm_ehd.make_params(**kw))
     assert sizes["fp32_q9"][0] == sizes["fp32"][0] * 41 // 33 == sizes["fp32_q9_side"][0]
     assert sizes["fp32_inplace"][0] == sizes["fp32"][0]
+    assert sizes["fp16_inplace"][0] == sizes["fp16"][0]
     assert sizes["fp64"][0] == 2 * sizes["fp32"][0]
 
 
@@ -76,7 +80,7 @@ def test_buffer_sizes_follow_the_layout():
                                  dict(W=float("nan")), dict(s_free=2.0), dict(side_walls=2), dict(local_field=2), dict(poisson_tol=-1.0),
                                  dict(poisson_tol=1e-3), dict(poisson_tol=1e-3, poisson_iters=1),
                                  dict(n_eps=-1.0), dict(diag_every=-1), dict(inplace=2),
-                                 dict(inplace=1, precision=2), dict(inplace=1, precision=3),
+                                 dict(inplace=1, precision=3),
                                  dict(inplace=1, side_walls=1), dict(inplace=1, local_field=1),
                                  dict(inplace=1, poisson_tol=1e-6, poisson_iters=1,
                                       poisson_max=4),

@@ -39,7 +39,7 @@ def _alone(i, precision, inplace=0):
     return f
 
 
-@pytest.mark.parametrize("precision,inplace", [("fp32", 0), ("fp16", 0), ("fp32", 1)])
+@pytest.mark.parametrize("precision,inplace", [("fp32", 0), ("fp16", 0), ("fp32", 1), ("fp16", 1)])
 def test_each_result_is_the_same_alone_and_in_the_mix(precision, inplace):
     fps = [lbm_ehd.lbm_ehd_footprint_bytes(_params(i, precision, inplace))
            for i in range(len(REQUESTS))]
