@@ -1,6 +1,6 @@
 """The largest grids the population buffers allow (below 4 GiB each: the
 kernels address a buffer with 32-bit byte offsets), at 2048 columns in FP64,
-FP32 and FP16 storage, and FP32 with in-place streaming.
+FP32 and FP16 storage, and FP32 and FP16 with in-place streaming.
 
 An x-uniform state (a flat heavy layer between the electrodes, ion and
 potential profiles in y only) stays x-uniform: every column of the GPU result
@@ -34,7 +34,8 @@ def largest_ny(nx, lines, size):
 
 
 @pytest.mark.parametrize("precision,size,bar,inplace", [("fp64", 8, 1e-10, 0), ("fp32", 4, 2e-5, 0),
-                                                        ("fp16", 2, 3e-3, 0), ("fp32", 4, 2e-5, 1)])
+                                                        ("fp16", 2, 3e-3, 0), ("fp32", 4, 2e-5, 1),
+                                                        ("fp16", 2, 3e-3, 1)])
 def test_largest_grid_x_uniform_state(precision, size, bar, inplace):
     nx = 2048
     ny = largest_ny(nx, 33, size)
