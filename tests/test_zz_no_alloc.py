@@ -2,7 +2,8 @@
 lbm_ehd_diagnostics, against lbm_ehd_diagnostics itself through the C ABI:
 the same sums bitwise (same kernels, same summation order), on two calls in
 a row whose second grid is smaller than the first (the static scratch keeps
-the first call's rows), and its guards."""
+the first call's rows), with two population buffers and in place, and its
+guards."""
 import ctypes
 import math
 
@@ -22,8 +23,8 @@ def _noalloc(sim):
     return code, d
 
 
-def _sim(nx, ny, precision, steps):
-    p = dict(workloads.lattice_params(ny, ny / 6.0, nx=nx), precision=precision)
+def _sim(nx, ny, precision, steps, inplace=0):
+    p = dict(workloads.lattice_params(ny, ny / 6.0, nx=nx), precision=precision, inplace=inplace)
     s = lbm_ehd.Simulation(p, device="cuda:0")
     s.init_droplet((nx - 1) / 2, (ny - 1) / 2, ny / 6.0, 1e-4, 3, presolve=20)
     s.step(steps)
@@ -31,12 +32,15 @@ def _sim(nx, ny, precision, steps):
 
 
 def test_noalloc_invariants_equal_diagnostics_on_two_calls():
-    for nx, ny, prec in ((320, 288, "fp32"), (96, 72, "fp16")):
-        sim = _sim(nx, ny, prec, 21)
+    # two-buffer states, then in-place ones (in the odd orientation after 21
+    # steps), each pair with a smaller second grid
+    for nx, ny, prec, ip in ((320, 288, "fp32", 0), (96, 72, "fp16", 0),
+                             (200, 150, "fp16", 1), (80, 60, "fp32", 1)):
+        sim = _sim(nx, ny, prec, 21, ip)
         code, d = _noalloc(sim)
         ref = lbm_ehd.lbm_ehd_diagnostics(sim.handle)
-        print("%dx%d %s: sum_phi %.17g vs %.17g" % (nx, ny, prec, d.sum_phi, ref.sum_phi),
-              flush=True)
+        print("%dx%d %s in place %d: sum_phi %.17g vs %.17g"
+              % (nx, ny, prec, ip, d.sum_phi, ref.sum_phi), flush=True)
         assert code == lbm_ehd.LBM_OK
         for k in SUMS:
             assert getattr(d, k) == getattr(ref, k), k
