@@ -82,6 +82,25 @@ struct AAView {
     const int xs = cx_of(i) > 0 ? k.m : (cx_of(i) < 0 ? k.p : k.c);
     return load_as(self ? q0 + i : q0 + opp_of(i), q0 + i, self ? own : P.row(ys + 1) + xs);
   }
+  // The same for lanes that may sit in different rows: the line goes into the
+  // lane's own offset instead of the wave's scalar one.
+  template <class K>
+  __device__ inline R in_lane(int par, int q0, int i, K k, int y) const {
+    const uint32_t own = P.row(y + 1) + k.c;
+    const int ny = P.kp->ny;
+    const int y1 = y - cy_of(i);
+    const bool beyond = y1 < 0 || y1 >= ny;
+    const int ys = y1 < 0 ? y1 + ny : (y1 >= ny ? y1 - ny : y1);
+    const bool self = par == 0 || i == 0 || (beyond && P.kp->walls != WALL_PERIODIC);
+    const int xs = cx_of(i) > 0 ? k.m : (cx_of(i) < 0 ? k.p : k.c);
+    const uint32_t q = self ? q0 + i : q0 + opp_of(i);
+    const uint32_t off = (self ? own : P.row(ys + 1) + xs) + q * (uint32_t)P.kp->pitch;
+    const int c = q0 + i;
+    R v = Codec<S, R>::ld(P.rs, off * (uint32_t)sizeof(S), 0u, P.nt);
+    if constexpr (Scaled<S>::value) return v * P.kp->isc[line_set<S>(c)] + P.ofs(c);
+    if (P.has_ofs(c)) v += P.kp->iofs[c - QP];
+    return v;
+  }
   // store the post-collision population v of direction i of the set at line
   // q0 of node (k.c, y), in orientation `par`; `vwall`: the value that comes
   // back along opp(i) when c_i points through an electrode
@@ -201,22 +220,34 @@ __global__ __launch_bounds__(64 * NW) void k_aa_hood(const SimDescAA<S, R, T0>* 
   if (tl.sim < 0) return;
   const SimDescAA<S, R, T0>& sd = sims[tl.sim];
   const KP<R>& kp = sd.kp;
-  const int lane = (int)threadIdx.x;
-  const int x = tl.x0 + lane;
-  if (x >= kp.nx) return;
-  const int w = min(64 * NW, kp.nx - tl.x0);
-  const bool edge_col = lane == 0 || lane == w - 1;
+  const int w = min(64 * NW, kp.nx - tl.x0), hb = tl.yend - tl.y0;
+  // The tile's edge nodes, each once (also in one-row bands and one-column
+  // strips): its first and last row, then the first and last column of the
+  // rows between.  A thread takes every (64 NW)-th of them, so that all of
+  // them are loaded in a few rounds (a walk down the band, in which only the
+  // edge columns' lanes work on the inner rows, made as many dependent
+  // rounds as the band has rows).
+  const int nrow = hb > 1 ? 2 : 1, ncol = w > 1 ? 2 : 1, inner = max(hb - 2, 0);
+  const int count = nrow * w + ncol * inner;
   const int par = (sd.par + flip) & 1, gpar = (sd.gpar + gflip) & 1;
   const AAView<S, R> V{PopView<S, R>{make_rsrc(sd.pop, kp.pop_bytes), &kp, false}};
-  const ColsP k = cols_for<0>(x, kp.nx, 0);
-  for (int y = tl.y0; y < tl.yend; ++y) {
-    if (!(edge_col || y == tl.y0 || y == tl.yend - 1)) continue;
+  for (int j = (int)threadIdx.x; j < count; j += 64 * NW) {
+    int x, y;
+    if (j < nrow * w) {
+      x = tl.x0 + (j < w ? j : j - w);
+      y = j < w ? tl.y0 : tl.yend - 1;
+    } else {
+      const int r = j - nrow * w;
+      x = r < inner ? tl.x0 : tl.x0 + w - 1;
+      y = tl.y0 + 1 + (r < inner ? r : r - inner);
+    }
+    const ColsP k = cols_for<0>(x, kp.nx, 0);
     const uint32_t jo = (uint32_t)y * kp.pitch + x;
     R h[9], g4[4];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) h[i] = V.in(par, QH, i, k, y);
+    for (int i = 1; i < 9; ++i) h[i] = V.in_lane(par, QH, i, k, y);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) g4[i] = V.in(gpar, QG, i + 1, k, y);
+    for (int i = 0; i < 4; ++i) g4[i] = V.in_lane(gpar, QG, i + 1, k, y);
     aa_refs_h(V, k, y, h);
     aa_refs_g(V, k, y, g4);
     *elem(sd.phiP, jo) = phi_of<W>((W)rest_val(*elem(sd.h0, jo)), h);
