@@ -142,6 +142,42 @@ def test_ragged_variants_inplace_fp16(name, presolve):
     sim.close()
 
 
+# Grids narrower than a strip or shorter than a band, in launch shapes that
+# leave a one-column strip or a one-row band, where the pre-pass must take
+# each tile edge node exactly once: (nx, ny), (waves, rows per band).
+SHAPES = [((2, 8), (1, 8)), ((3, 17), (1, 8)), ((65, 9), (1, 8)), ((128, 3), (2, 2)),
+          ((129, 33), (2, 16)), ((65, 41), (1, 4))]
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("fp16", 1e-2)])
+@pytest.mark.parametrize("shape,launch", SHAPES)
+def test_small_and_odd_shapes_inplace(shape, launch, precision, bar):
+    nx, ny = shape
+    p = workloads.lattice_params(ny, 2.0, nx=nx)
+    p.update(walls=2 if ny < 8 else 0)
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    x = np.ones((ny, 1)) * np.arange(nx)[None, :]
+    rng = np.random.default_rng(nx * 1000 + ny)
+    # no grid-symmetric extremum of phi (see the two-buffer test of these shapes)
+    phi = 0.5 * (1 + np.tanh(np.sin(2 * np.pi * (x + 0.3) / nx) * 2
+                             + np.cos(2 * np.pi * (y + 0.3) / ny)))
+    cp = 1 + 0.01 * rng.uniform(-1, 1, (ny, nx))
+    cm = 1 + 0.01 * rng.uniform(-1, 1, (ny, nx))
+    psi = p["dpsi"] * (ny - 0.5 - y) / ny
+    fields = (phi, cp, cm, psi)
+    sim = lbm_ehd.Simulation(dict(p, precision=precision, inplace=1), device="cuda:0")
+    sim.init_fields(*fields)
+    sim.set_launch(*launch)
+    assert sim.launch == launch
+    sim.step(21)
+    o = run_oracle(p, fields=fields, steps=21)
+    names = ALL10 if precision == "fp64" else FIELDS8
+    errs = rel_l2(sim.fields(), o.fields(), p, names)
+    _report("shape %s launch %s inplace %s" % (shape, launch, precision), errs)
+    assert max(errs.values()) <= bar
+    sim.close()
+
+
 # In place and with two buffers the arithmetic is the same; the compiler
 # fuses a few multiply-adds differently where the in-place pre-pass forms
 # phi' and psi' of the tile edge nodes, which changes roundings at a few
