@@ -20,22 +20,23 @@ def _droplet_fields(n, p):
     return phi, psi
 
 
-def test_watchdog_stops_a_run_at_the_first_check_after_a_nan():
+@pytest.mark.parametrize("precision,inplace", [("fp32", 0), ("fp16", 1), ("fp64", 1)])
+def test_watchdog_stops_a_run_at_the_first_check_after_a_nan(precision, inplace):
     """With diag_every = 8 a NaN in one cell of the initial phi stops the
     run with LBM_ENONFINITE at step 8 (the first check), and the step count
     says so; with the watchdog off the same run completes, and a clean state
-    passes every check."""
+    passes every check (two buffers and in place)."""
     n = 64
-    p = workloads.lattice_params(n, 10.0)
+    p = dict(workloads.lattice_params(n, 10.0), precision=precision, inplace=inplace)
     phi, psi = _droplet_fields(n, p)
-    clean = lbm_ehd.Simulation(dict(p, precision="fp32", diag_every=8), device="cuda:0")
+    clean = lbm_ehd.Simulation(dict(p, diag_every=8), device="cuda:0")
     clean.init_fields(phi, 1.0, 1.0, psi)
     clean.step(40)
     assert clean.time == 40
     clean.close()
     phi[20, 30] = np.nan
     for every in (8, 0):
-        sim = lbm_ehd.Simulation(dict(p, precision="fp32", diag_every=every), device="cuda:0")
+        sim = lbm_ehd.Simulation(dict(p, diag_every=every), device="cuda:0")
         sim.init_fields(phi, 1.0, 1.0, psi)
         code = lbm_ehd.lib().lbm_ehd_run(sim.handle, 40)
         if every:
