@@ -136,8 +136,9 @@ struct AAView {
   }
   // Byte offset of line q, the scalar operand of the buffer access.  The
   // line depends on the orientation, the direction and the row only, which
-  // every lane of a wave shares (one lattice row per wave in every kernel
-  // that streams in place); without the broadcast the compiler, which sees
+  // every lane of a wave shares wherever in() and out() are called (one
+  // lattice row per wave; the pre-pass, whose lanes sit in different rows,
+  // loads through in_lane); without the broadcast the compiler, which sees
   // the line selected inside branches on the lane, wraps each access in a
   // loop over the distinct values.
   __device__ inline uint32_t line_bytes(int q) const {
