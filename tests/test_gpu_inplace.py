@@ -124,10 +124,14 @@ def test_ragged_variants_inplace_fp64(name, presolve):
 # The switches that change what binary16 storage keeps in place: periodic and
 # ion-tight walls (the node-local references of h and g of the boundary rows),
 # Poisson sub-iterations (the g set and its reference line re-stored between
-# steps), the literal Poisson form and the degenerate cases.  Measured after
-# 61 steps: fields <= 9.2e-4.
+# steps), the literal Poisson form and the degenerate cases; then the
+# general-rate sweep and the other switches.  Measured after 61 steps:
+# fields <= 9.2e-4.
 VARIANTS_FP16 = ("base", "periodic", "insulating", "poisson_iters", "poisson_iters_periodic",
-                 "literal_poisson", "uncharged", "no_voltage")
+                 "literal_poisson", "uncharged", "no_voltage",
+                 # the general-rate sweep (other MRT masks, another free rate)
+                 # and the other switches of the arithmetic
+                 "bgk_masks", "s_free", "ratios", "body_force", "flow_off", "reaction_off")
 
 
 @pytest.mark.parametrize("name", VARIANTS_FP16)
