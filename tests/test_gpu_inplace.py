@@ -182,6 +182,22 @@ def test_small_and_odd_shapes_inplace(shape, launch, precision, bar):
     sim.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp32f64"])
+@pytest.mark.parametrize("name", ["bgk_masks", "s_free", "ratios", "insulating",
+                                  "poisson_iters_periodic"])
+def test_ragged_variants_inplace_fp32(name, precision):
+    """FP32 storage in place on the general-rate sweep (other MRT masks,
+    another free rate) and on switches of the arithmetic and the walls,
+    against the oracle at the FP32 bar."""
+    p, d = _ragged(**VARIANTS[name])
+    sim = run_gpu(dict(p, inplace=1), precision, droplet=d, presolve=7, steps=61)
+    o = run_oracle(p, droplet=d, presolve=7, steps=61)
+    errs = rel_l2(sim.fields(), o.fields(), p, ALL10)
+    _report("ragged inplace %s %s" % (precision, name), errs)
+    assert max(errs.values()) <= 2e-5
+    sim.close()
+
+
 # In place and with two buffers the arithmetic is the same; the compiler
 # fuses a few multiply-adds differently where the in-place pre-pass forms
 # phi' and psi' of the tile edge nodes, which changes roundings at a few
