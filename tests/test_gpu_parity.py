@@ -128,7 +128,9 @@ def test_ragged_grid_variants_fp64(name):
 # after 300 steps: fields <= 2e-3 (FP16), <= 4e-2 (BF16).
 VARIANTS_16 = ("base", "periodic", "insulating", "poisson_iters", "literal_poisson",
                "side_walls", "side_walls_periodic_y", "local_field", "local_field_periodic",
-               "local_field_side_walls", "uncharged", "no_voltage")
+               "local_field_side_walls", "uncharged", "no_voltage",
+               # the general-rate sweep (other MRT masks, another free rate)
+               "bgk_masks", "s_free")
 
 
 @pytest.mark.parametrize("precision,bar", [("fp16", 1e-2), ("bf16", 0.1)])
@@ -142,16 +144,19 @@ def test_ragged_grid_variants_16bit(name, precision, bar):
     assert max(errs.values()) <= bar
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp32f64"])
 @pytest.mark.parametrize("name", ["side_walls", "side_walls_periodic_y", "local_field",
-                                  "local_field_side_walls"])
-def test_ragged_extended_sweep_fp32(name):
-    """FP32 storage (FP64 working type) on the extended sweep (side walls,
-    the local field of Eq. 50) against the oracle: the FP32 bar."""
+                                  "local_field_side_walls", "bgk_masks", "s_free", "ratios"])
+def test_ragged_extended_sweep_fp32(name, precision):
+    """FP32 storage on the extended sweep (side walls, the local field of
+    Eq. 50) and on the plain sweep's general-rate form (other MRT masks,
+    another free rate), with FP32 and FP64 arithmetic, against the oracle:
+    the FP32 bar."""
     p, d = _ragged(**VARIANTS[name])
-    sim = run_gpu(p, "fp32", droplet=d, presolve=20, steps=300)
+    sim = run_gpu(p, precision, droplet=d, presolve=20, steps=300)
     o = run_oracle(p, droplet=d, presolve=20, steps=300)
     errs = rel_l2(sim.fields(), o.fields(), p, ALL10)
-    _report("ragged fp32 %s" % name, errs)
+    _report("ragged %s %s" % (precision, name), errs)
     assert max(errs.values()) <= 2e-5
 
 
