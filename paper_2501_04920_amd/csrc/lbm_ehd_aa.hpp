@@ -57,6 +57,38 @@ __host__ __device__ constexpr int opp_of(int i) {
   return i == 0 ? 0 : (i <= 4 ? (i + 1) % 4 + 1 : (i - 3) % 4 + 5);
 }
 
+// Stores of the odd steps, which scatter to the neighbours' slots, with 4-
+// and 2-byte storage: the non-temporal hint without device scope (SC1),
+// where the codec's stores (even steps, a node's own slots, the two-buffer
+// sweep, and 8-byte storage) carry both.  Measured on MI355X at 2048^2, a
+// step in place: +4.1 % FP32, +3.2 % binary16, +0.5 % FP32 storage with FP64
+// arithmetic, -1.1 % FP64 (so FP64 keeps the codec's); the same hint on even
+// steps cost 7 %.  The same conversions as the codec's stores.
+constexpr int ST_AA_ODD = 2;  // NT
+template <class S, class R>
+struct OddStore;
+template <>
+struct OddStore<float, float> {
+  __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, v, s,
+                                          ST_AA_ODD);
+  }
+};
+template <>
+struct OddStore<float, double> {
+  __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, double x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, (float)x), r, v, s,
+                                          ST_AA_ODD);
+  }
+};
+template <>
+struct OddStore<__half, float> {
+  __device__ static inline void st(Rsrc r, uint32_t v, uint32_t s, float x) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(x)),
+                                          r, v, s, ST_AA_ODD);
+  }
+};
+
 // A population buffer in the AA orientations.  The choices between a node's
 // own slot and a neighbour's (the orientation, an electrode in the way) are
 // selects of the line and the offset, not branches: the row and the
@@ -119,8 +151,15 @@ struct AAView {
     // pair of one set: both or neither carry an offset)
     if (P.has_ofs(qi)) x -= through ? P.kp->iofs[qo - QP] : P.kp->iofs[qi - QP];
     if (Scaled<S>::value) x *= P.kp->sc[line_set<S>(qi)];
-    Codec<S, R>::st(P.rs, (self ? own : P.row(yd + 1) + xd) * (uint32_t)sizeof(S),
-                    line_bytes(self ? qo : qi), x);
+    const uint32_t vo = (self ? own : P.row(yd + 1) + xd) * (uint32_t)sizeof(S);
+    if constexpr (sizeof(S) == 8) {
+      Codec<S, R>::st(P.rs, vo, line_bytes(self ? qo : qi), x);
+    } else {
+      if (par == 0)
+        Codec<S, R>::st(P.rs, vo, line_bytes(self ? qo : qi), x);
+      else
+        OddStore<S, R>::st(P.rs, vo, line_bytes(self ? qo : qi), x);
+    }
   }
   // In place a population spends every other step in the slot of the
   // opposite direction, but it keeps the encoding of its own: the per-line
