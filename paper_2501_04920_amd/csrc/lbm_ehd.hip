@@ -1045,8 +1045,9 @@ void free_scratch(lbm_ehd* h) {
 }
 
 // Default launch shape of the sweep for a grid.  Strips are 64 columns per
-// wave: four waves (256 columns) where the grid is that wide, eight (512)
-// where the grid is that wide and eight-wave workgroups fit twice on a CU
+// wave: one wave on grids narrower than 512 columns, four waves (256
+// columns) on wider ones, eight (512) where eight-wave workgroups fit twice
+// on a CU
 // (FP32 arithmetic, or FP32 storage with its pulls parked in LDS as FP32 in
 // the plain two-buffer sweep with the default MRT rates; the other forms
 // take more than 128 registers with FP64 arithmetic, three waves per SIMD).
@@ -1059,9 +1060,12 @@ void free_scratch(lbm_ehd* h) {
 // 19.0 (4 x 16), in place 12.7 (4 x 8), 11.1 (8 x 8), 10.7 (4 x 16); FP16
 // 26.5 (8 x 16), 25.9 (8 x 8), 24.5 (4 x 16), 20.0 (4 x 32); BF16 25.9
 // (8 x 16), 25.1 (8 x 8), 23.1 (4 x 16); FP64 10.8 (4 x 16), 10.8 (8 x 16),
-// 10.7 (4 x 8), 10.6 (8 x 8).
+// 10.7 (4 x 8), 10.6 (8 x 8).  On narrow grids many small tiles fill the
+// chip first (MLUPS at 256^2, FP32 / FP16 / FP64: 5158 / 5080 / 4923 with
+// (1 x 2) against 4908 / 5057 / 4541 with (4 x 2); at 128^2 1378 / 1399 /
+// 1544 against 1335 / 1348 / 1438 with (2 x 2)).
 void default_launch(const lbm_ehd_params* p, int* waves, int* tile_rows) {
-  *waves = p->nx >= 256 ? 4 : (p->nx >= 128 ? 2 : 1);
+  *waves = p->nx >= 512 ? 4 : 1;
   const bool fp32_store = elem_size(p->precision) == 4;
   if (p->nx >= 512 && (arith_size(p->precision) == 4 || (fp32_store && sweep_form(*p) == NFORM)))
     *waves = 8;
