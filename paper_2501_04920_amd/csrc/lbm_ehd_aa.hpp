@@ -489,11 +489,14 @@ __device__ __forceinline__ void sweep_aa_tile(SweepLds<S, R, 64 * NW>& L,
   const bool periodic = kp.walls == WALL_PERIODIC;
   constexpr int par = PAR, gpar = GPAR;
   // Loads carry the non-temporal hint of the two-buffer sweep on even steps
-  // (a node's own slots) and are cached on odd ones, which gather from and
-  // scatter to the neighbours' slots: measured on MI355X at 2048^2 against
-  // cached loads in both, +2.4 % FP64, +1.0 % FP32, +0.5 % binary16 per
-  // step; the hint on odd steps too cost 10 % there.
-  const AAView<S, R> V{PopView<S, R>{make_rsrc(sd.pop, kp.pop_bytes), &kp, PAR == 0}};
+  // (a node's own slots): measured on MI355X at 2048^2 against cached loads,
+  // +2.4 % FP64, +1.0 % FP32, +0.5 % binary16 per step.  On odd steps, which
+  // gather from and scatter to the neighbours' slots, they carry it where the
+  // storage is narrower than the arithmetic (with the odd steps' store hint:
+  // +5.4 % binary16, +3.0 % FP32 storage with FP64 arithmetic) and are cached
+  // otherwise (the hint cost FP32 0.5 % and FP64 3.1 %).
+  constexpr bool kLoadNT = PAR == 0 || sizeof(S) < sizeof(R);
+  const AAView<S, R> V{PopView<S, R>{make_rsrc(sd.pop, kp.pop_bytes), &kp, kLoadNT}};
   const ColsP k = cols_for<0>(x, nx, 0);
   // halo columns (lanes 0 and 1): x0 - 1 and x0 + w, periodic in x
   const int xh = lane == 0 ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + w == nx ? 0 : x0 + w);
