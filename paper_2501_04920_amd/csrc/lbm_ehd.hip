@@ -1070,7 +1070,11 @@ void default_launch(const lbm_ehd_params* p, int* waves, int* tile_rows) {
   if (p->nx >= 512 && (arith_size(p->precision) == 4 || (fp32_store && sweep_form(*p) == NFORM)))
     *waves = 8;
   const long long strips = (p->nx + 64 * *waves - 1) / (64 * *waves);
-  const long long want = fp32_store ? 8192 : 4096;
+  // FP32 storage and arithmetic in place takes the taller bands of four
+  // wavefronts per SIMD (18.3 GLUPS with 8 x 16 against 17.9 with 8 x 8 at
+  // 2048^2; its pre-pass covers the band edges)
+  const bool fp32_inplace = p->inplace && fp32_store && arith_size(p->precision) == 4;
+  const long long want = fp32_store && !fp32_inplace ? 8192 : 4096;
   int rows = 32;
   while (rows > 2 && strips * *waves * ((p->ny + rows - 1) / rows) < want) rows /= 2;
   *tile_rows = std::min(rows, p->ny);

@@ -61,7 +61,7 @@ def test_2048_against_oracle_20_steps(oracle_20, precision, bar):
 # The other forms at full size in their default launch shapes: FP32 storage
 # with FP64 arithmetic (its pulls parked in LDS as FP32, eight-wave strips),
 # and the in-place sweeps.
-OTHER_FORMS = [("fp32f64", 0, (8, 8)), ("fp32", 1, (8, 8)), ("fp32f64", 1, (4, 8)),
+OTHER_FORMS = [("fp32f64", 0, (8, 8)), ("fp32", 1, (8, 16)), ("fp32f64", 1, (4, 8)),
                ("fp64", 1, (4, 16))]
 
 
