@@ -1057,7 +1057,7 @@ void free_scratch(lbm_ehd* h) {
 // MI355X at 2048^2 (GLUPS; waves x rows per band): FP32 20.1 (8 x 8), 19.9
 // (8 x 16), 19.9 (4 x 8), 19.6 (4 x 4), 19.3 (8 x 4), 17.4 (2 x 8); FP32
 // storage with FP64 arithmetic 19.6 (8 x 8), 19.4 (8 x 16), 19.3 (4 x 8),
-// 19.0 (4 x 16), in place 12.7 (4 x 8), 11.1 (8 x 8), 10.7 (4 x 16); FP16
+// 19.0 (4 x 16), in place 17.1 (4 x 8), 17.0 (8 x 8), 17.0 (4 x 16); FP16
 // 26.5 (8 x 16), 25.9 (8 x 8), 24.5 (4 x 16), 20.0 (4 x 32); BF16 25.9
 // (8 x 16), 25.1 (8 x 8), 23.1 (4 x 16); FP64 10.8 (4 x 16), 10.8 (8 x 16),
 // 10.7 (4 x 8), 10.6 (8 x 8).  On narrow grids many small tiles fill the
